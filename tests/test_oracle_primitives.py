@@ -1,0 +1,290 @@
+"""Pins of the oracle's building blocks against what the paper and mathematics fix.
+
+- Philox4x32-10 against the published known-answer vectors (and rocRAND's
+  implementation when hipcc is present);
+- the uniform mapping's exactness;
+- the normalized time coefficients against numerical integration of the
+  paper's epsilon_alpha(t), Eq. (13), over [0, dt] (Eq. (16), Eq. (48));
+- half-range moments, microslopes (Eqs. (20), (22)) and the time-averaged
+  fluxes (Eqs. (49), (50)) against brute-force velocity-space quadrature;
+- the GTS form, Eqs. (23), (31), as the equal-step special case.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from tests import quadrature as Q
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answers():
+    n = 0
+    for line in open(os.path.join(GOLD, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        assert oracle.philox(w[0:4], w[4:6]) == w[6:10]
+        n += 1
+    assert n == 3
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand(tmp_path):
+    """rocRAND's host-callable Philox4x32-10 rounds on a sweep of counters."""
+    src = tmp_path / "p.cpp"
+    src.write_text(r'''
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+struct probe : rocrand_device::philox4x32_10_engine {
+  using rocrand_device::philox4x32_10_engine::ten_rounds;
+};
+int main(){
+  probe e;
+  for (unsigned i = 0; i < 2000; ++i) {
+    uint4 c = {i * 2654435761u, i ^ 0x5bd1e995u, i * 97u + 13u, (2u << 24) | (i & 7u)};
+    uint2 k = {0x12345678u ^ i, 0x9abcdef0u + i};
+    uint4 o = e.ten_rounds(c, k);
+    std::printf("%u %u %u %u %u %u %u %u %u %u\n", c.x, c.y, c.z, c.w, k.x, k.y, o.x, o.y, o.z, o.w);
+  }
+}
+''')
+    exe = tmp_path / "p"
+    r = subprocess.run(["hipcc", "--offload-arch=gfx950", "-O1", "-o", str(exe), str(src)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("could not build the rocRAND probe: " + r.stderr[-300:])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    rows = [list(map(int, ln.split())) for ln in out if ln.strip()]
+    assert len(rows) == 2000
+    for w in rows:
+        assert oracle.philox(w[0:4], w[4:6]) == w[6:10]
+
+
+def test_uniform_mapping_exact_and_open():
+    lo = oracle.uniform(0, 0)
+    hi = oracle.uniform(0xFFFFFFFF, 0xFFFFFFFF)
+    assert lo == 2.0 ** -53
+    assert hi == 1.0 - 2.0 ** -53
+    rng = np.random.default_rng(3)
+    for a, b in rng.integers(0, 2 ** 32, size=(500, 2)):
+        e = oracle.uniform(int(a), int(b))
+        k = (int(a) << 20) | (int(b) >> 12)
+        assert e == (k + 0.5) / 2.0 ** 52  # exact: (2k+1) 2^-53 has <= 53 significant bits
+        assert 0.0 < e < 1.0
+
+
+def _eps_integrals(dt, tau):
+    """Eq. (13) integrated over [0, dt] at 50 digits, divided by dt."""
+    mpmath.mp.dps = 50
+    dt, tau = mpmath.mpf(dt), mpmath.mpf(tau)
+    ex = lambda t: mpmath.exp(-t / tau)
+    eps = [
+        lambda t: 1 - ex(t),
+        lambda t: t * ex(t) - tau * (1 - ex(t)),
+        lambda t: t - tau * (1 - ex(t)),
+        lambda t: ex(t),
+        lambda t: -t * ex(t),
+    ]
+    d = [mpmath.quad(f, [0, dt]) / dt for f in eps]
+    E = ex(dt)
+    return [d[0], d[1], d[2], d[3], d[4], E, d[3] - E, d[4] + dt * E / 2]
+
+
+@pytest.mark.parametrize("x", [1e-9, 1e-5, 1e-3, 0.05, 0.3, 0.999, 1.0, 1.001, 2.5, 17.0, 300.0])
+@pytest.mark.parametrize("tau", [0.7, 3e-4])
+def test_time_coefficients_match_integrated_eps(x, tau):
+    dt = x * tau
+    got = oracle.time_coeffs(dt, tau)
+    ref = _eps_integrals(dt, tau)
+    names = ["abar", "bbar", "cbar", "dbar", "ebar", "E", "dbar-E", "ebar+dtE/2"]
+    for name, g, r in zip(names, got, ref):
+        r = float(r)
+        scale = abs(r) if r != 0 else 1.0
+        assert abs(g - r) <= 5e-14 * scale + 1e-300, (name, x, g, r)
+
+
+def test_time_coefficients_gks_and_collisionless_limits():
+    # x -> infinity: abar -> 1, dbar -> 0 (pure equilibrium); x -> 0: abar -> 0, dbar -> 1.
+    big = oracle.time_coeffs(1e4, 1.0)
+    assert abs(big[0] - (1 - 1e-4)) < 1e-15 and abs(big[3] - 1e-4) < 1e-18 and big[5] == 0.0
+    small = oracle.time_coeffs(1e-12, 1.0)
+    assert small[0] < 1e-12 and abs(small[3] - 1.0) < 1e-12
+    # abar + dbar = 1 and the free-transport coefficients vanish at x -> 0
+    for x in [1e-6, 0.5, 0.99, 1.0, 4.0]:
+        c = oracle.time_coeffs(x, 1.0)
+        assert abs(c[0] + c[3] - 1.0) <= 2e-16
+
+
+@pytest.mark.parametrize("U,lam", [(0.0, 0.5), (1.3, 0.5), (-2.1, 0.2), (19.4, 0.5), (-0.4, 3.0)])
+def test_half_range_moments_quadrature(U, lam):
+    f = lambda u, k: u ** k * math.sqrt(lam / math.pi) * math.exp(-lam * (u - U) ** 2)
+    sig = math.sqrt(0.5 / lam)
+    for sign in (+1, -1, 0):
+        M = oracle.moments_n(U, lam, sign)
+        for k in range(7):
+            if sign > 0:
+                a, b = 0.0, max(U, 0.0) + 40 * sig
+            elif sign < 0:
+                a, b = min(U, 0.0) - 40 * sig, 0.0
+            else:
+                a, b = U - 40 * sig, U + 40 * sig
+            pts = [U] if a < U < b else None
+            ref = integrate.quad(f, a, b, args=(k,), points=pts, epsabs=0, epsrel=1e-13, limit=400)[0]
+            # relative accuracy, floored at 1e-14 of the full-range absolute moment
+            # (far half-range tails of a fast drift cancel in the recursion)
+            full = integrate.quad(lambda u: abs(f(u, k)), U - 40 * sig, U + 40 * sig, points=[U], limit=400)[0]
+            assert abs(M[k] - ref) <= 1e-12 * abs(ref) + 1e-14 * full, (sign, k, M[k], ref)
+
+
+def _rand_state(rng, K):
+    rho = rng.uniform(0.3, 3.0)
+    U, V, T = rng.uniform(-2, 2), rng.uniform(-1.5, 1.5), rng.uniform(0.4, 3.0)
+    return Q.maxwell_W(rho, U, V, T, K)
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_microslope_solves_moment_system(K):
+    """Pr = 1: <Psi g a> = dW (Eq. (20)); compatibility <Psi g A> = -<Psi g a u_n> (Eq. (22))."""
+    rng = np.random.default_rng(10 + K)
+    for _ in range(4):
+        W = _rand_state(rng, K)
+        dW = rng.normal(size=4) * np.array([0.5, 1.0, 1.0, 3.0])
+        a = oracle.microslope(W, dW, K, 1.0)
+        got = Q.moment(W, K, 0, Q.poly(a))
+        assert np.allclose(got, dW, rtol=1e-11, atol=1e-11 * np.abs(dW).max())
+        a_ref = Q.solve_slope(W, dW, K)
+        assert np.allclose(a, a_ref, rtol=1e-9, atol=1e-10 * np.abs(a_ref).max())
+
+
+def test_microslope_prandtl_fix_scales_temperature_slope():
+    """Sec. III.A: a(Pr) is the ln-derivative of the Maxwellian whose lambda slope
+    is divided by Pr, other primitive slopes unchanged."""
+    K, Pr = 1, 2.0 / 3.0
+    rng = np.random.default_rng(7)
+    W = _rand_state(rng, K)
+    dW = rng.normal(size=4)
+    rho, U, V, lam = Q.state(W, K)
+    # primitive derivatives by finite differences of the conservative map
+    def prim(Wv):
+        r, u, v, l = Q.state(Wv, K)
+        return np.array([r, u, v, l])
+    h = 1e-6
+    dp = (prim(W + h * dW) - prim(W - h * dW)) / (2 * h)
+    dp[3] /= Pr
+
+    def cons(p):
+        r, u, v, l = p
+        T = 1.0 / (2.0 * l)
+        return Q.maxwell_W(r, u, v, T, K)
+    p0 = prim(W)
+    dW_pr = (cons(p0 + h * dp) - cons(p0 - h * dp)) / (2 * h)
+    a = oracle.microslope(W, dW, K, Pr)
+    got = Q.moment(W, K, 0, Q.poly(a))
+    assert np.allclose(got, dW_pr, rtol=1e-7, atol=1e-7 * np.abs(dW_pr).max())
+
+
+def _brute_flux(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K):
+    """Eqs. (17), (20), (22), (49), (50) by quadrature and linear solves."""
+    W0 = Q.moment(WL, K, +1) + Q.moment(WR, K, -1)
+    a = Q.solve_slope(W0, dW0, K)
+    Wt = -Q.moment(W0, K, 0, lambda un, ut, x2: Q.poly(a)(un, ut, x2) * un)
+    A = Q.solve_slope(W0, Wt, K)
+    F = np.zeros(4)
+    Ffr = np.zeros(4)
+    for half, dt, tau, Wh, dWh in ((+1, dtL, tauL, WhL, dWhL), (-1, dtR, tauR, WhR, dWhR)):
+        da, db, dc, dd, de, E = Q.delta_coeffs(dt, tau)
+        F += (da * Q.moment(W0, K, half, power=1)
+              + db * Q.moment(W0, K, half, Q.poly(a), power=2)
+              + dc * Q.moment(W0, K, half, Q.poly(A), power=1)) / dt
+        if Wh is not None:
+            ah = Q.solve_slope(Wh, dWh, K)
+            Ffr += ((dd - dt * E) * Q.moment(Wh, K, half, power=1)
+                    + (de + 0.5 * dt * dt * E) * Q.moment(Wh, K, half, Q.poly(ah), power=2)) / dt
+    return F, Ffr
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_face_flux_matches_quadrature(case):
+    K = 1
+    rng = np.random.default_rng(100 + case)
+    WL, WR = _rand_state(rng, K), _rand_state(rng, K)
+    dW0 = (WR - WL) / rng.uniform(0.5, 2.0)
+    WhL = WL * rng.uniform(0.1, 0.9)
+    WhR = WR * rng.uniform(0.1, 0.9)
+    dWhL = rng.normal(size=4) * 0.3 * np.abs(WhL)
+    dWhR = rng.normal(size=4) * 0.3 * np.abs(WhR)
+    tauL, tauR = rng.uniform(0.05, 1.0), rng.uniform(0.05, 1.0)
+    dtL, dtR = tauL * rng.uniform(0.05, 5.0), tauR * rng.uniform(0.05, 5.0)
+    if case == 0:
+        WhR = None
+    Feq, Ffr = oracle.flux_interior(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K, 1.0)
+    Feq_ref, Ffr_ref = _brute_flux(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K)
+    s = np.abs(Feq_ref).max()
+    assert np.allclose(Feq, Feq_ref, rtol=1e-10, atol=1e-10 * s), (Feq, Feq_ref)
+    s = max(np.abs(Ffr_ref).max(), 1e-300)
+    assert np.allclose(Ffr, Ffr_ref, rtol=1e-10, atol=1e-10 * s), (Ffr, Ffr_ref)
+
+
+def test_equal_steps_recover_gts_flux():
+    """Sec. IV.B: with dt_L = dt_R = dt_G, dt_G * Fbar equals the GTS fluxes of
+    Eqs. (23) and (31) built from the un-normalized coefficients."""
+    K = 1
+    rng = np.random.default_rng(5)
+    WL, WR = _rand_state(rng, K), _rand_state(rng, K)
+    dW0 = (WR - WL) * 0.8
+    WhL, WhR = WL * 0.4, WR * 0.7
+    dWh = np.zeros(4)
+    dt, tauL, tauR = 0.02, 0.03, 0.5
+    Feq, Ffr = oracle.flux_interior(WL, WR, dW0, WhL, WhR, dWh, dWh, dt, tauL, dt, tauR, K, 1.0)
+    W0 = Q.moment(WL, K, +1) + Q.moment(WR, K, -1)
+    a = Q.solve_slope(W0, dW0, K)
+    A = Q.solve_slope(W0, -Q.moment(W0, K, 0, lambda un, ut, x2: Q.poly(a)(un, ut, x2) * un), K)
+    Fg, Ffg = np.zeros(4), np.zeros(4)
+    for half, tau, Wh in ((+1, tauL, WhL), (-1, tauR, WhR)):
+        da, db, dc, dd, de, E = Q.delta_coeffs(dt, tau)
+        Fg += da * Q.moment(W0, K, half, power=1) + db * Q.moment(W0, K, half, Q.poly(a), power=2) \
+            + dc * Q.moment(W0, K, half, Q.poly(A), power=1)
+        Ffg += (dd - dt * E) * Q.moment(Wh, K, half, power=1)
+    assert np.allclose(dt * Feq, Fg, rtol=1e-10, atol=1e-12)
+    assert np.allclose(dt * Ffr, Ffg, rtol=1e-10, atol=1e-12)
+
+
+def test_wall_flux_zero_mass_and_quadrature():
+    K = 1
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        W = _rand_state(rng, K)
+        Wh = W * 0.6
+        dt, tau, Tw = 0.01, 0.02, rng.uniform(0.2, 2.0)
+        F = oracle.flux_wall(W, Wh, dt, tau, Tw, 1.0, K)
+        assert abs(F[0]) <= 1e-14 * abs(W[0]) * 10
+        da, db, dc, dd, de, E = Q.delta_coeffs(dt, tau)
+        Fin = (da / dt) * Q.moment(W, K, +1, power=1) + (dd / dt - E) * Q.moment(Wh, K, +1, power=1)
+        wall = Q.maxwell_W(1.0, 0.0, 0.0, Tw, K)
+        refl = Q.moment(wall, K, -1, power=1)
+        ref = Fin + (Fin[0] / -refl[0]) * refl
+        assert np.allclose(F[1:], ref[1:], rtol=1e-10)
+
+
+def test_lts_counterexample_values():
+    """Sec. IV.A: the printed 4/3 vs 3/2 of Eq. (46)."""
+    from fractions import Fraction as Fr
+    vals = {}
+    for line in open(os.path.join(GOLD, "lts_counterexample.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        vals[k] = v
+    M = int(vals["M"][0])
+    dL = [Fr(v) for v in vals["dt_L"]]
+    dR = [Fr(v) for v in vals["dt_R"]]
+    lhs = sum(dR) / sum(dL)
+    rhs = sum(r / l for r, l in zip(dR, dL)) / M
+    assert lhs == Fr(vals["lhs"][0]) and rhs == Fr(vals["rhs"][0]) and lhs != rhs

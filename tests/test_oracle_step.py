@@ -1,0 +1,304 @@
+"""Whole-step pins of the oracle against invariants, limits and brute force.
+
+- Eq. (33): local time steps on rectangles (closed form);
+- uniform Maxwellian preserved in the continuum (GKS) limit on graded meshes;
+- Eqs. (41), (43): time-weighted content sum_i Omega_i W_i / dt_i conserved
+  through LTS crossings in closed specular boxes, and m/dt invariant per crossing;
+- tracking against exact rational arithmetic (1D) and sub-stepped point
+  location (2D);
+- Eq. (25): the new particles carry exactly W^hp (mass by Eq. (26), momentum
+  and energy by the moment-matching reading);
+- collisionless limit: two-reservoir steady state (closed form, erfc);
+- continuum limit: Rankine-Hugoniot plateaus of a Ma 3 shock.
+"""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+from scipy.special import erfc
+
+import oracle
+import workloads as wl
+
+
+def cell_volumes(w):
+    if w["dim"] == 1:
+        return np.diff(w["nodes"][:, 0])
+    nodes = w["nodes"]
+    cn = w["cell_nodes"].reshape(-1, 4)
+    p = nodes[cn]
+    return 0.5 * np.sum(p[:, :, 0] * np.roll(p[:, :, 1], -1, 1) - np.roll(p[:, :, 0], -1, 1) * p[:, :, 1], axis=1)
+
+
+def test_cfl_time_step_closed_form():
+    xs = wl.graded(4, 1.5)
+    ys = wl.graded(3, 2.0, 0.5)
+    m = wl.uniform2d(wl.box2d(xs, ys, wl.BC_SYMMETRY), rho=1.3, ux=0.4, uy=-0.3, T=2.0)
+    o = oracle.Oracle(m)
+    dt = o.dt()
+    k = 0
+    for j in range(3):
+        for i in range(4):
+            hx, hy = xs[i + 1] - xs[i], ys[j + 1] - ys[j]
+            ref = 0.8 * hx * hy / ((0.5 + 3 * math.sqrt(2.0)) * (2 * hx + 2 * hy))
+            assert abs(dt[k] - ref) <= 1e-15 * ref
+            k += 1
+    m["lts"] = 0
+    assert np.all(oracle.Oracle(m).dt() == dt.min())
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_uniform_state_preserved_gks_limit(dim):
+    """Continuum limit (tau -> 0: E = 0, no particles): a uniform flow is a
+    steady solution on graded LTS meshes up to round-off."""
+    if dim == 1:
+        m = wl.uniform1d(wl.graded(12, 1.25), rho=1.2, U=0.7, T=1.5, mu_ref=1e-12)
+    else:
+        box = wl.box2d(wl.graded(6, 1.3), wl.graded(5, 1.5, 0.3), wl.BC_FARFIELD, [1.2, 0.7, -0.4, 1.5])
+        m = wl.uniform2d(box, rho=1.2, ux=0.7, uy=-0.4, T=1.5, mu_ref=1e-12)
+    o = oracle.Oracle(m)
+    W0 = o.fields()
+    o.step(10)
+    cnt, info = o.counts()
+    assert info["total"] == 0
+    assert np.max(np.abs(o.fields() - W0) / np.abs(W0).max(axis=0)) < 1e-13
+
+
+def _closed_box(dim, seed=0, mu=0.05):
+    if dim == 1:
+        m = wl.uniform1d(wl.graded(10, 1.3), bc=wl.BC_SYMMETRY, mu_ref=mu, n_ref=40, seed=seed)
+    else:
+        box = wl.box2d(wl.graded(5, 1.35), wl.graded(4, 1.6, 0.4), wl.BC_SYMMETRY)
+        m = wl.uniform2d(box, mu_ref=mu, n_ref=40, seed=seed)
+    rng = np.random.default_rng(seed)
+    n = m["n_cells"]
+    rho = rng.uniform(0.6, 1.6, n)
+    ux = rng.uniform(-0.5, 0.5, n)
+    uy = rng.uniform(-0.5, 0.5, n) if dim == 2 else 0.0
+    T = rng.uniform(0.7, 1.4, n)
+    m["W0"] = wl.conservative(rho, ux, uy, T, dim)
+    return m
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_time_weighted_content_conserved_lts(dim):
+    """Eq. (43) with Eq. (53): fixed dt_i and m <- m dt_R/dt_L make
+    I = sum_i Omega_i W_i / dt_i invariant (mass and energy in a specular box),
+    while the plain sum_i Omega_i W_i is not."""
+    m = _closed_box(dim)
+    o = oracle.Oracle(m)
+    vol = cell_volumes(m)
+    dt = o.dt()
+    assert dt.max() / dt.min() > 3.0
+    comps = [0, dim + 1]
+    I0 = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+    P0 = (vol[:, None] * o.fields()).sum(0)
+    drift = 0.0
+    for _ in range(25):
+        o.step(1)
+        I = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+        for c in comps:
+            assert abs(I[c] - I0[c]) <= 2e-13 * abs(I0[c]), (c, I[c], I0[c])
+        P = (vol[:, None] * o.fields()).sum(0)
+        drift = max(drift, abs(P[0] - P0[0]) / P0[0])
+    assert o.counts()[1]["total"] > 0
+    assert drift > 1e-8  # LTS does not conserve the plain content
+
+
+def test_crossing_scales_mass_and_time_exactly():
+    """Eqs. (41), (52) against exact rational arithmetic on a graded 1D mesh."""
+    x = wl.graded(6, 1.4)
+    m = wl.uniform1d(x, bc=wl.BC_FARFIELD)
+    o = oracle.Oracle(m)
+    dt = o.dt()
+    rng = np.random.default_rng(1)
+    for trial in range(40):
+        cell = int(rng.integers(0, 6))
+        x0 = x[cell] + rng.uniform(0.05, 0.95) * (x[cell + 1] - x[cell])
+        u = np.array([rng.choice([-1, 1]) * rng.uniform(0.5, 8.0), rng.normal(), rng.normal()])
+        t = rng.uniform(0.2, 3.0) * dt[cell]
+        m0 = 0.37
+        r = o.track_one(12345, 0, cell, [x0], u, m0, t)
+        # exact: walk cell by cell with Fractions of the same float inputs
+        X, U, Tm, M, c = Fr(x0), Fr(u[0]), Fr(t), Fr(m0), cell
+        left = False
+        while True:
+            edge = Fr(x[c + 1]) if U > 0 else Fr(x[c])
+            te = (edge - X) / U
+            if te >= Tm:
+                X += U * Tm
+                break
+            X, Tm = edge, Tm - te
+            nxt = c + (1 if U > 0 else -1)
+            if nxt < 0 or nxt >= 6:
+                left = True
+                break
+            ratio = Fr(dt[nxt]) / Fr(dt[c])
+            Tm *= ratio
+            M *= ratio
+            c = nxt
+        assert r["rc"] == (1 if left else 0)
+        assert r["cell"] == c
+        if not left:
+            assert abs(r["m"] - float(M)) <= 1e-14 * float(M)
+            assert abs(r["x"][0] - float(X)) <= 1e-12 * max(1.0, abs(float(X)))
+            assert abs(r["m"] / dt[c] - m0 / dt[cell]) <= 1e-14 * m0 / dt[cell]
+
+
+def _locate(nodes, quads, p):
+    for k, q in enumerate(quads):
+        v = nodes[q]
+        inside = True
+        for a in range(4):
+            b = (a + 1) % 4
+            cr = (v[b, 0] - v[a, 0]) * (p[1] - v[a, 1]) - (v[b, 1] - v[a, 1]) * (p[0] - v[a, 0])
+            if cr < 0:
+                inside = False
+                break
+        if inside:
+            return k
+    return -1
+
+
+def test_tracking_2d_matches_substepped_location():
+    """Crossing detection in 2D against brute-force sub-stepping with point
+    location on a skewed graded quad mesh (far-field: particles may leave)."""
+    xs = wl.graded(4, 1.5)
+    ys = wl.graded(3, 1.7, 0.6)
+    box = wl.box2d(xs, ys, wl.BC_FARFIELD, [1, 0, 0, 1])
+    # skew the interior nodes a little (cells stay convex)
+    nodes = box["nodes"].copy()
+    rng = np.random.default_rng(4)
+    nodes[:, 0] += 0.08 * np.sin(3.1 * nodes[:, 1])
+    box["nodes"] = nodes
+    m = wl.uniform2d(box)
+    o = oracle.Oracle(m)
+    dt = o.dt()
+    quads = m["cell_nodes"].reshape(-1, 4)
+    for trial in range(25):
+        cell = int(rng.integers(0, 12))
+        v = nodes[quads[cell]]
+        w = rng.dirichlet([1, 1, 1, 1])
+        p0 = (w[:, None] * v).sum(0)
+        ang = rng.uniform(0, 2 * np.pi)
+        spd = rng.uniform(1, 10)
+        u = np.array([spd * np.cos(ang), spd * np.sin(ang), 0.3])
+        t = rng.uniform(0.5, 4.0) * dt[cell]
+        r = o.track_one(7, 0, cell, p0, u, 1.0, t)
+        # brute force: small steps, locate, scale remaining time by dt ratio
+        n_sub = 4000
+        h = t / n_sub
+        p, c, rem, mass = p0.copy(), cell, t, 1.0
+        while rem > 1e-15 * t:
+            step = min(h, rem)
+            q = p + u[:2] * step
+            k = _locate(nodes, quads, q)
+            if k == c:
+                p, rem = q, rem - step
+                continue
+            if k < 0:
+                c = -1
+                break
+            # refine the crossing time by bisection, then scale
+            lo, hi = 0.0, step
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                if _locate(nodes, quads, p + u[:2] * mid) == c:
+                    lo = mid
+                else:
+                    hi = mid
+            p = p + u[:2] * hi
+            rem = (rem - hi) * dt[k] / dt[c]
+            mass *= dt[k] / dt[c]
+            c = k
+        if c < 0:
+            assert r["rc"] == 1
+        else:
+            assert r["rc"] == 0 and r["cell"] == c
+            assert np.allclose(r["x"], p, atol=1e-9 * max(1.0, spd * t))
+            assert abs(r["m"] - mass) <= 1e-12 * mass
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_new_particles_carry_w_hp_exactly(dim):
+    """Eqs. (25)-(26): at n = 0 (W^p = 0, W^h = W) the pre-transport tally of
+    each cell is exactly e^{-dt/tau} W Omega (mass, momentum, energy)."""
+    m = _closed_box(dim, seed=3, mu=0.2)
+    o = oracle.Oracle(m)
+    W = o.fields()
+    vol = cell_volumes(m)
+    dt = o.dt()
+    o.step(1)
+    Sm, Sp = o.tally()
+    rho, ux = W[:, 0], W[:, 1] / W[:, 0]
+    uy = W[:, 2] / W[:, 0] if dim == 2 else 0.0
+    e = W[:, dim + 1] - 0.5 * rho * (ux ** 2 + uy ** 2)
+    T = 2 * e / (3 * rho)
+    tau = m["gas"]["mu_ref"] * T ** m["gas"]["omega"] / (rho * T)
+    E = np.exp(-dt / tau)
+    ref = (E * vol)[:, None] * W
+    N = np.ceil(E * m["n_ref"])
+    assert np.allclose(Sm[:, 0], ref[:, 0], rtol=1e-13, atol=0)
+    multi = N >= 2  # a single particle cannot carry the thermal energy exactly
+    assert multi.sum() >= 3
+    assert np.allclose(Sm[multi], ref[multi], rtol=1e-13, atol=1e-15 * np.abs(ref).max())
+
+
+def test_collisionless_two_reservoir_steady_state():
+    """tau -> infinity: wave fluxes vanish and the steady state between two
+    far-field reservoirs on a graded LTS mesh is the sum of their half-range
+    Maxwellians, W = rho_A <Psi>^{u>0}_A + rho_B <Psi>^{u<0}_B."""
+    A = (1.0, 0.4, 1.0)
+    B = (0.6, -0.3, 1.8)
+    x = wl.graded(8, 1.25)
+    m = wl.uniform1d(x, rho=A[0], U=A[1], T=A[2], mu_ref=1e8, n_ref=300, seed=11,
+                     left=[A[0], A[1], 0.0, A[2]], right=[B[0], B[1], 0.0, B[2]])
+    o = oracle.Oracle(m)
+    o.step(700)
+    acc, n = [], 900
+    for _ in range(n):
+        o.step(1)
+        acc.append(o.fields())
+    acc = np.array(acc)
+    mean = acc.mean(0)
+    # batch-means standard error
+    nb = 30
+    bm = acc.reshape(nb, n // nb, *acc.shape[1:]).mean(1)
+    se = bm.std(0, ddof=1) / math.sqrt(nb)
+
+    def half(rho, U, T, sign):
+        lam = 1 / (2 * T)
+        s = math.sqrt(lam)
+        if sign > 0:
+            m0 = 0.5 * erfc(-s * U)
+            m1 = U * m0 + math.exp(-lam * U * U) / (2 * math.sqrt(math.pi * lam))
+        else:
+            m0 = 0.5 * erfc(s * U)
+            m1 = U * m0 - math.exp(-lam * U * U) / (2 * math.sqrt(math.pi * lam))
+        m2 = U * m1 + m0 / (2 * lam)
+        # energy: u^2/2 + two transverse components with T each
+        return rho * np.array([m0, m1, 0.5 * m2 + m0 * T])
+    ref = half(*A, +1) + half(*B, -1)
+    z = (mean - ref[None, :]) / np.maximum(se, 1e-12)
+    assert np.all(np.abs(z) < 5.0), (mean, ref, z)
+
+
+def test_shock_plateaus_continuum_limit():
+    """tau -> 0: a Ma 3 shock started from its Rankine-Hugoniot states relaxes
+    to a steady shock: every face carries the same mass flux rho_1 U_1 and the
+    plateaus keep the jump rho_2/rho_1 = 3, T_2/T_1 = 11/3."""
+    m = wl.shock1d(Kn=1e-9)
+    o = oracle.Oracle(m)
+    o.step(4000)
+    assert o.residual()[0] < 1e-9
+    W = o.fields()
+    U1 = 3 * math.sqrt(5 / 3)
+    Fs = o.face_flux()
+    assert np.max(np.abs(np.abs(Fs[:, 0]) - U1)) < 1e-8 * U1  # boundary face 0 points to -x
+    far = np.r_[0:40, 60:100]
+    assert np.max(np.abs(W[far, 1] - U1)) < 1e-6 * U1
+    assert abs(W[0, 0] - 1.0) < 1e-8 and abs(W[-1, 0] - 3.0) < 1e-8
+    T = lambda k: (2 * (W[k, 2] - 0.5 * W[k, 1] ** 2 / W[k, 0])) / (3 * W[k, 0])
+    assert abs(T(-1) / T(0) - 11 / 3) < 1e-8
+    assert o.counts()[1]["total"] == 0
