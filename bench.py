@@ -1,0 +1,165 @@
+"""Benchmark of the UGKWP-LTS hot path on one MI355X.
+
+Workload (the one the metric is quoted on): hypersonic flow past a cylinder,
+argon-like VHS gas (omega 0.81, Pr 2/3), Ma 15, Kn 0.01 on the radius,
+isothermal diffuse wall T_w/T_inf = 0.2, structured O-grid 200 x 150 to 15 R
+with first-layer height 1e-4 R, N_ref 400, local time stepping, FP64.  Inputs
+are synthetic (uniform freestream start), resident in HBM before timing.
+
+A step is one whole UGKWP-LTS step (cell preparation, resampling, transport
+with LTS scaling, tally and re-sort, wave fluxes, update, wall quantities).
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process;
+the domain-decomposition design is described with the code).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transport_cylinder_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2607_09552_amd", "csrc", "kernels.hip")
+
+
+def workload(kn=0.01):
+    return workloads.cylinder(n_theta=200, n_r=150, Ma=15.0, Kn=kn, omega=0.81, Pr=2.0 / 3.0, Tw=0.2, n_ref=400,
+                              lts=1, seed=1)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per transport launch from committed rocprofv3 counters, if
+    they were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(kn, steps):
+    """The CPU oracle, as it stands, on the first `steps` steps of the same
+    workload (single thread)."""
+    import oracle
+    w = workload(kn)
+    o = oracle.Oracle(w)
+    n_upd = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(1)
+        n_upd += o.counts()[1]["total"]
+    dt = time.perf_counter() - t0
+    o.close()
+    return dict(value=n_upd / dt, unit="particle updates/s", cores=1, kind="oracle",
+                sample=f"first {steps} steps of the same cylinder workload from the freestream start, "
+                       f"{n_upd} particle updates in {dt:.1f} s, 1 thread")
+
+
+def copy_probe(gib=1.0, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--kn", type=float, default=0.01)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is a "
+              "domain-decomposition design, not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if a.copy_probe:
+        copy_probe()
+        return
+    from paper_2607_09552_amd import Solver
+
+    w = workload(a.kn)
+    s = Solver(w)
+    print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
+    s.step(a.warmup)
+    torch.cuda.synchronize()
+    s.profile(True)
+    n_upd = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        s.step(1)
+        n_upd += s.counts()[1]["total"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    print(f"# timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    tr = prof["transport"]
+    avg_ms = tr["ms"] / max(tr["launches"], 1)
+    bytes_per_launch = tr["bytes"] / max(tr["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_per_launch()
+    kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),
+                    GBs=round(v["bytes"] / max(v["ms"], 1e-12) * 1e-6, 1) if v["ms"] > 0 else None)
+            for k, v in prof.items() if v["launches"] > 0}
+    value = n_upd / elapsed
+    out = {
+        "metric": "particle updates/s",
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
+                               f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, FP64, Philox seed 1",
+                   "cells": int(w["n_cells"]),
+                   "particles_per_step": n_upd / a.steps,
+                   "cell_steps_per_s": w["n_cells"] * a.steps / elapsed},
+        "roofline": {"bound": "hbm", "kernel": "transport", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms},
+        "kernels": kern,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.kn, a.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

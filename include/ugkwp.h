@@ -1,0 +1,157 @@
+/*
+ * ugkwp.h - C ABI of the MI355X (gfx950) library for the hot path of one
+ * UGKWP-LTS time step (Guo, Cao, Long, Xu, arXiv 2607.09552, Secs. III-IV).
+ *
+ * One call to ugkwp_step advances every cell by its own fixed local time step
+ * (Eq. (33)), doing on the GPU:
+ *   - the wave-particle decomposition W = W^h + W^p (Eq. (24)) with the LTS
+ *     collisionless fraction e^{-dt_i/tau_i} and resampling of new particles
+ *     (Eqs. (25)-(26), Sec. IV.B);
+ *   - the free-transport time of retained particles (Eq. (51));
+ *   - free transport and tracking through the mesh with mass and remaining
+ *     time scaled by dt_R/dt_L at every crossing (Eqs. (41), (52));
+ *   - the before/after particle tally (Eqs. (29)-(30)) and removal of
+ *     collided particles, with the store re-sorted by cell;
+ *   - the time-averaged equilibrium and analytic free-transport wave fluxes
+ *     (Eqs. (49)-(50)) on every face;
+ *   - the conservative update (Eq. (53)).
+ *
+ * Conventions for every call:
+ *   - Units are nondimensional; layouts are row-major [item][component];
+ *     W = (rho, rho U_x[, rho U_y], rho E) has dim + 2 components.
+ *   - Ownership: every input array is copied at init; the caller keeps it.
+ *     Outputs go to caller buffers (host unless the name says device).
+ *   - All GPU work is ordered on the stream given at init (NULL = the
+ *     library's own stream).  Getters synchronize that stream.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Every call returns UGKWP_OK or a negative error code;
+ *     ugkwp_last_error() gives a text.  After an error from ugkwp_step the
+ *     fields and particles are unspecified: free the context.
+ *   - The library requires a gfx950 device; it has no CPU fallback.
+ */
+#ifndef UGKWP_H
+#define UGKWP_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  UGKWP_OK = 0,
+  UGKWP_EINVAL = -1,    /* bad argument, mesh or parameter */
+  UGKWP_ENOMEM = -2,    /* device or host allocation failed */
+  UGKWP_EDEVICE = -3,   /* HIP runtime error or no usable device */
+  UGKWP_EOVERFLOW = -4, /* particle capacity or a caller buffer too small */
+  UGKWP_ENUMERIC = -5,  /* non-finite or invalid state, runaway tracking */
+  UGKWP_ESTATE = -6     /* call not valid in the current state */
+};
+
+enum { /* boundary face types */
+  UGKWP_BC_FARFIELD = 1,     /* fixed ghost state; injects particles */
+  UGKWP_BC_OUTFLOW = 2,      /* ghost = copy of the interior cell; injects */
+  UGKWP_BC_WALL_DIFFUSE = 3, /* isothermal wall, diffuse reflection */
+  UGKWP_BC_SYMMETRY = 4      /* mirror ghost, specular particles */
+};
+
+typedef struct ugkwp_ctx ugkwp_ctx;
+
+/* Mesh of cells Omega_i with faces s_j and unit normals n_j (Sec. III). */
+typedef struct {
+  int32_t dim;                /* 1 or 2 */
+  int64_t n_nodes;
+  const double *nodes;        /* [n_nodes*dim]; 1D: increasing x_0..x_N */
+  int64_t n_cells;            /* 1D: n_nodes - 1 */
+  const int64_t *cell_ptr;    /* 2D: CSR of strictly convex CCW polygons (3..8 vertices); NULL in 1D */
+  const int64_t *cell_nodes;  /* 2D: node ids, [cell_ptr[n_cells]] */
+  int64_t n_bfaces;           /* every open edge (2D) / both end nodes (1D) */
+  const int64_t *bface_nodes; /* [n_bfaces*dim] node ids of each boundary face */
+  const int32_t *bface_type;  /* UGKWP_BC_* */
+  const double *bface_data;   /* [n_bfaces*8]: far field rho, U_x, U_y, T; wall T_w; else unused */
+} ugkwp_mesh;
+
+/* Gas (Sec. II: tau = mu/p, mu = mu_ref (T/T_ref)^omega), time stepping
+ * (Eq. (33) CFL number, Eq. (34) GTS when lts = 0), sampling (Eq. (26) N_ref),
+ * the Philox seed, and the freestream used for C_p, C_F, C_Q, C_d (Sec. V). */
+typedef struct {
+  double R, omega, mu_ref, T_ref, Pr;
+  int32_t D;                  /* internal degrees of freedom (0: monatomic) */
+  double cfl;
+  int32_t n_ref;
+  int32_t lts;                /* 1 local time steps, 0 global dt_G = min dt_i */
+  uint64_t seed;
+  double rho_inf, u_inf_x, u_inf_y, T_inf, L_ref;
+  int64_t particle_capacity;  /* 0 = automatic; grows on demand */
+  void *stream;               /* hipStream_t or NULL */
+} ugkwp_params;
+
+/* Builds faces and geometry, uploads the state and computes the local time
+ * steps dt_i from W0 (Eq. (33)), fixed for the whole run; the particle set
+ * starts empty (W^p = 0, Sec. III.C).  W0 is [n_cells*(dim+2)] host memory.
+ * Errors: EINVAL (mesh not matching its boundary list, non-convex or
+ * clockwise cell, bad parameters), ENUMERIC (invalid W0), EDEVICE, ENOMEM. */
+int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double *W0, ugkwp_ctx **out);
+
+/* Advances n_steps UGKWP-LTS steps (Secs. III.C, IV.B).  Errors: ENUMERIC
+ * (invalid cell state at the start of a step, runaway tracking), EOVERFLOW
+ * (more than 2^20 particles born in one cell), ENOMEM, EDEVICE. */
+int ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps);
+
+/* Residuals after the last step (the paper defines none; reading): r_inst is
+ * the area-weighted RMS of the last density change over rho_inf, r_avg the
+ * same for the running mean of the density over all steps.  step = steps done. */
+int ugkwp_residual(ugkwp_ctx *ctx, double *r_inst, double *r_avg, int64_t *step);
+
+/* Wall quantities of Sec. V (diffuse-wall faces in boundary-list order):
+ * out[w*6 + 0..5] = face midpoint x, y, length, C_p, C_F, C_Q, and the drag
+ * coefficient C_d = F_d / (rho_inf U_inf^2 L_ref / 2) (Sec. V.B).
+ * mode 0: last step; 1: mean over all steps; 2: exponential moving average
+ * with alpha = 2/1001 (Sec. V.A).  out may be NULL to query n_wall.
+ * Errors: ESTATE before the first step, EOVERFLOW if cap < n_wall. */
+int ugkwp_surface(ugkwp_ctx *ctx, int32_t mode, double *out, int64_t cap, int64_t *n_wall, double *Cd);
+
+/* Host copy of W, [n_cells*(dim+2)]. */
+int ugkwp_get_fields(ugkwp_ctx *ctx, double *W);
+/* Stream-ordered device-to-device copy of W into d_W (device pointer). */
+int ugkwp_get_fields_device(ugkwp_ctx *ctx, void *d_W);
+/* Local time steps dt_i, [n_cells]. */
+int ugkwp_get_dt(ugkwp_ctx *ctx, double *dt);
+/* Retained particles per cell after the last step and step totals:
+ * transported (retained + new + entered from ghosts), new, removed
+ * (collided), exited, and cells reset by the vacuum guard.  Any pointer may
+ * be NULL. */
+int ugkwp_get_counts(ugkwp_ctx *ctx, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
+                     int64_t *n_exited, int64_t *n_guard);
+/* Retained particles sorted by pid: pid = step << 44 | birth cell << 20 | j
+ * (birth cell >= n_cells marks a boundary face), cell, mass, position
+ * [n*dim], velocity [n*3].  Pointers may be NULL; *n is set even when
+ * cap is too small (then EOVERFLOW). */
+int ugkwp_get_particles(ugkwp_ctx *ctx, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x,
+                        double *u, int64_t *n);
+/* Replaces the retained set (host arrays as in ugkwp_get_particles). */
+int ugkwp_set_particles(ugkwp_ctx *ctx, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
+                        const double *x, const double *u);
+/* Restart support: replace W ([n_cells*(dim+2)] host; the local time steps
+ * stay those of the initial field, Eq. (33)) and the step counter that keys
+ * the random numbers.  With ugkwp_set_particles this restores a state saved
+ * with the getters. */
+int ugkwp_set_fields(ugkwp_ctx *ctx, const double *W);
+int ugkwp_set_step(ugkwp_ctx *ctx, int64_t step);
+/* Last step's particle tallies sum_k m_k Psi_k before (W^{p,-} Omega) and
+ * after (W^{p,+} Omega) transport, Eq. (30), [n_cells*(dim+2)] each. */
+int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
+
+/* Per-kernel timing with HIP events on the library's stream.  enable = 1
+ * starts accumulating (and resets), 0 stops.  ugkwp_profile_read returns up
+ * to cap entries: name, total milliseconds, launches and the algorithmic
+ * bytes moved (the byte model of each kernel). */
+int ugkwp_profile(ugkwp_ctx *ctx, int32_t enable);
+int ugkwp_profile_read(ugkwp_ctx *ctx, int32_t cap, const char **names, double *ms, int64_t *launches,
+                       double *bytes, int32_t *n);
+
+const char *ugkwp_last_error(const ugkwp_ctx *ctx);
+void ugkwp_free(ugkwp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -77,6 +77,8 @@ def lib():
         L.ref_n_faces.restype = C.c_int64
         L.ref_n_guard.argtypes = [C.c_void_p]
         L.ref_n_guard.restype = C.c_int64
+        L.ref_set_step.argtypes = [C.c_void_p, C.c_int64]
+        L.ref_set_step.restype = None
         L.ref_last_error.argtypes = [C.c_void_p]
         L.ref_last_error.restype = C.c_char_p
         L.ref_free.argtypes = [C.c_void_p]
@@ -255,6 +257,9 @@ class Oracle:
         m, x, u = _f64(m), _f64(x), _f64(u)
         self._check(lib().ref_set_particles(self.h, len(pid), _p(pid, C.c_uint64), _p(cell, C.c_int32), _p(m),
                                             _p(x), _p(u)))
+
+    def set_step(self, n):
+        lib().ref_set_step(self.h, n)
 
     def residual(self):
         a, b, n = C.c_double(), C.c_double(), C.c_int64()

@@ -1606,3 +1606,4 @@ int ref_get_face_flux(const ref_ctx *c, double *Fs) {
 
 int64_t ref_n_faces(const ref_ctx *c) { return c->nf; }
 int64_t ref_n_guard(const ref_ctx *c) { return c->n_guard; }
+void ref_set_step(ref_ctx *c, int64_t step) { c->step = step; }

@@ -77,6 +77,7 @@ int ref_get_tally(const ref_ctx *c, double *Sminus, double *Splus); /* last step
 int ref_get_face_flux(const ref_ctx *c, double *Fs);               /* last step, [nf*(dim+2)] */
 int64_t ref_n_faces(const ref_ctx *c);
 int64_t ref_n_guard(const ref_ctx *c); /* cells reset by the vacuum guard in the last step */
+void ref_set_step(ref_ctx *c, int64_t step); /* step counter that keys the RNG */
 const char *ref_last_error(const ref_ctx *c);
 void ref_free(ref_ctx *c);
 

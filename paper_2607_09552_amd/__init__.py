@@ -1,0 +1,244 @@
+"""UGKWP-LTS hot path on MI355X (gfx950): Python binding of libugkwp.so.
+
+The binding only marshals arguments; every step of the method runs in the HIP
+kernels of the library.  There is no CPU fallback: without the built library
+(``python -m paper_2607_09552_amd.build``) or without a GPU, constructing a
+Solver raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libugkwp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
+
+# Every entry point declared in include/ugkwp.h.
+ABI_SYMBOLS = (
+    "ugkwp_init", "ugkwp_step", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
+    "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_particles",
+    "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
+    "ugkwp_last_error", "ugkwp_free",
+)
+
+
+class UgkwpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ugkwp error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n_nodes", C.c_int64), ("nodes", C.c_void_p), ("n_cells", C.c_int64),
+        ("cell_ptr", C.c_void_p), ("cell_nodes", C.c_void_p), ("n_bfaces", C.c_int64),
+        ("bface_nodes", C.c_void_p), ("bface_type", C.c_void_p), ("bface_data", C.c_void_p),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("R", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double), ("T_ref", C.c_double),
+        ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32), ("lts", C.c_int32),
+        ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double), ("u_inf_y", C.c_double),
+        ("T_inf", C.c_double), ("L_ref", C.c_double), ("particle_capacity", C.c_int64), ("stream", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libugkwp.so and declare its ABI.  Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_09552_amd.build`")
+    L = C.CDLL(path)
+    vp, dp, i64p, i32p, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)
+    L.ugkwp_init.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.POINTER(vp)]
+    L.ugkwp_step.argtypes = [vp, C.c_int32]
+    L.ugkwp_residual.argtypes = [vp, dp, dp, i64p]
+    L.ugkwp_surface.argtypes = [vp, C.c_int32, dp, C.c_int64, i64p, dp]
+    L.ugkwp_get_fields.argtypes = [vp, dp]
+    L.ugkwp_get_fields_device.argtypes = [vp, vp]
+    L.ugkwp_get_dt.argtypes = [vp, dp]
+    L.ugkwp_get_counts.argtypes = [vp, i32p, i64p, i64p, i64p, i64p, i64p]
+    L.ugkwp_get_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp, i64p]
+    L.ugkwp_set_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp]
+    L.ugkwp_get_tally.argtypes = [vp, dp, dp]
+    L.ugkwp_set_fields.argtypes = [vp, dp]
+    L.ugkwp_set_step.argtypes = [vp, C.c_int64]
+    L.ugkwp_profile.argtypes = [vp, C.c_int32]
+    L.ugkwp_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_char_p), dp, i64p, dp, i32p]
+    L.ugkwp_last_error.argtypes = [vp]
+    L.ugkwp_last_error.restype = C.c_char_p
+    L.ugkwp_free.argtypes = [vp]
+    L.ugkwp_free.restype = None
+    _lib = L
+    return L
+
+
+def _ptr(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def _vp(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+class Solver:
+    """One UGKWP-LTS problem resident on the GPU.
+
+    ``wl`` is a workload dict (see the ``workloads`` module).  ``stream`` is a
+    raw hipStream_t handle (e.g. ``torch.cuda.current_stream().cuda_stream``)
+    or None for the library's own stream.
+    """
+
+    def __init__(self, wl, W0=None, stream=None, particle_capacity=0):
+        L = load_library()
+        self.dim = int(wl["dim"])
+        self.nw = self.dim + 2
+        self.nc = int(wl["n_cells"])
+        keep = []
+
+        def arr(a, dt):
+            x = np.ascontiguousarray(a, dtype=dt)
+            keep.append(x)
+            return x
+
+        m = _Mesh()
+        m.dim = self.dim
+        nodes = arr(wl["nodes"], np.float64).ravel()
+        m.n_nodes = len(nodes) // self.dim
+        m.nodes = _vp(nodes)
+        m.n_cells = self.nc
+        if self.dim == 2:
+            m.cell_ptr = _vp(arr(wl["cell_ptr"], np.int64))
+            m.cell_nodes = _vp(arr(wl["cell_nodes"], np.int64))
+        bt = arr(wl["bface_type"], np.int32)
+        m.n_bfaces = len(bt)
+        m.bface_nodes = _vp(arr(wl["bface_nodes"], np.int64).ravel())
+        m.bface_type = _vp(bt)
+        m.bface_data = _vp(arr(wl["bface_data"], np.float64).ravel())
+        g, r = wl["gas"], wl["ref"]
+        p = _Params(R=g["R"], omega=g["omega"], mu_ref=g["mu_ref"], T_ref=g["T_ref"], Pr=g["Pr"], D=g["D"],
+                    cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
+                    u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
+                    particle_capacity=particle_capacity, stream=stream)
+        W = arr(wl["W0"] if W0 is None else W0, np.float64).ravel()
+        h = C.c_void_p()
+        rc = L.ugkwp_init(C.byref(m), C.byref(p), _ptr(W), C.byref(h))
+        self.h = h
+        if rc != OK:
+            msg = L.ugkwp_last_error(h).decode() if h.value else ""
+            self.close()
+            raise UgkwpError(rc, msg)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise UgkwpError(rc, load_library().ugkwp_last_error(self.h).decode())
+
+    def step(self, n=1):
+        self._check(load_library().ugkwp_step(self.h, n))
+
+    def fields(self):
+        W = np.zeros((self.nc, self.nw))
+        self._check(load_library().ugkwp_get_fields(self.h, _ptr(W)))
+        return W
+
+    def fields_device(self):
+        """W as a float64 torch tensor on the GPU (stream-ordered copy)."""
+        import torch
+        out = torch.empty((self.nc, self.nw), dtype=torch.float64, device="cuda")
+        self._check(load_library().ugkwp_get_fields_device(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def dt(self):
+        d = np.zeros(self.nc)
+        self._check(load_library().ugkwp_get_dt(self.h, _ptr(d)))
+        return d
+
+    def counts(self):
+        cnt = np.zeros(self.nc, dtype=np.int32)
+        v = [C.c_int64() for _ in range(5)]
+        self._check(load_library().ugkwp_get_counts(self.h, _ptr(cnt, C.c_int32), *[C.byref(x) for x in v]))
+        return cnt, dict(total=v[0].value, new=v[1].value, removed=v[2].value, exited=v[3].value, guard=v[4].value)
+
+    def particles(self):
+        L = load_library()
+        n = C.c_int64()
+        L.ugkwp_get_particles(self.h, 0, None, None, None, None, None, C.byref(n))
+        k = n.value
+        pid = np.zeros(k, dtype=np.uint64)
+        cell = np.zeros(k, dtype=np.int32)
+        m = np.zeros(k)
+        x = np.zeros((k, self.dim))
+        u = np.zeros((k, 3))
+        self._check(L.ugkwp_get_particles(self.h, k, _ptr(pid, C.c_uint64), _ptr(cell, C.c_int32), _ptr(m), _ptr(x),
+                                          _ptr(u), C.byref(n)))
+        return dict(pid=pid, cell=cell, m=m, x=x, u=u)
+
+    def set_particles(self, pid, cell, m, x, u):
+        pid = np.ascontiguousarray(pid, dtype=np.uint64)
+        cell = np.ascontiguousarray(cell, dtype=np.int32)
+        m, x, u = (np.ascontiguousarray(a, dtype=np.float64) for a in (m, x, u))
+        self._check(load_library().ugkwp_set_particles(self.h, len(pid), _ptr(pid, C.c_uint64),
+                                                       _ptr(cell, C.c_int32), _ptr(m), _ptr(x), _ptr(u)))
+
+    def set_fields(self, W):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        self._check(load_library().ugkwp_set_fields(self.h, _ptr(W)))
+
+    def set_step(self, n):
+        self._check(load_library().ugkwp_set_step(self.h, n))
+
+    def residual(self):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        self._check(load_library().ugkwp_residual(self.h, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
+
+    def surface(self, mode=0):
+        L = load_library()
+        nw, cd = C.c_int64(), C.c_double()
+        self._check(L.ugkwp_surface(self.h, mode, None, 0, C.byref(nw), C.byref(cd)))
+        out = np.zeros((nw.value, 6))
+        self._check(L.ugkwp_surface(self.h, mode, _ptr(out), nw.value, C.byref(nw), C.byref(cd)))
+        return out, cd.value
+
+    def tally(self):
+        Sm = np.zeros((self.nc, self.nw))
+        Sp = np.zeros((self.nc, self.nw))
+        self._check(load_library().ugkwp_get_tally(self.h, _ptr(Sm), _ptr(Sp)))
+        return Sm, Sp
+
+    def profile(self, enable=True):
+        self._check(load_library().ugkwp_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        L = load_library()
+        cap = 32
+        names = (C.c_char_p * cap)()
+        ms = np.zeros(cap)
+        nl = np.zeros(cap, dtype=np.int64)
+        by = np.zeros(cap)
+        n = C.c_int32()
+        self._check(L.ugkwp_profile_read(self.h, cap, names, _ptr(ms), _ptr(nl, C.c_int64), _ptr(by), C.byref(n)))
+        return {names[k].decode(): dict(ms=ms[k], launches=int(nl[k]), bytes=by[k]) for k in range(n.value)}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load_library().ugkwp_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

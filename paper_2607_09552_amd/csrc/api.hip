@@ -1,0 +1,1039 @@
+// Host side of the UGKWP-LTS library: mesh tables, device memory, the step
+// sequence on one HIP stream, getters and per-kernel event timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ugkwp.h"
+#include "kernels.h"
+
+using namespace ugk;
+
+namespace {
+
+enum KernelId {
+  kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKHeatFlux, kKSampleCells, kKSampleGhosts, kKTransport,
+  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCount
+};
+const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "heat_flux",
+                                     "sample_cells", "sample_ghosts", "transport", "face_flux", "update",
+                                     "surface",   "finish",    "scatter"};
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct ugkwp_ctx {
+  int dim = 0, nw = 0, NV = 0;
+  int64_t nc = 0, nf = 0, nb = 0, nwall = 0;
+  Params P{};
+  int lts = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // host copies needed by getters
+  std::vector<double> h_face_mid;  // [nf*2]
+  std::vector<int> h_wall_b, h_bcell, h_bk, h_lface;
+  std::vector<double> h_lfn;       // [nc*NV*4]
+  // device geometry
+  double4 *lfn = nullptr;
+  int *lnb = nullptr, *lface = nullptr, *nv = nullptr;
+  double *ratio = nullptr, *vol = nullptr;
+  double2 *cverts = nullptr;
+  int *fL = nullptr, *fR = nullptr, *fLL = nullptr, *fRR = nullptr;
+  double2 *fn = nullptr;
+  double *fs = nullptr;
+  double4 *fxi = nullptr;
+  int *bcell = nullptr, *bk = nullptr, *btype = nullptr, *wall_b = nullptr;
+  double *bdata = nullptr;
+  // state
+  State S{};
+  Store A{}, B{};
+  int64_t cap = 0, n_ret = 0, step = 0;
+  int64_t last_total = 0, last_new = 0;
+  int64_t *scan_tmp = nullptr;   // block sums
+  int64_t scan_tmp_n = 0;
+  int64_t *pinned = nullptr;     // host pinned mailbox
+  std::vector<void *> allocs;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRec> prof_pending;
+  double prof_ms[kKCount] = {0};
+  int64_t prof_n[kKCount] = {0};
+  double prof_bytes[kKCount] = {0};
+  Geo geo() const {
+    Geo g;
+    g.NV = NV;
+    g.nc = nc;
+    g.nf = nf;
+    g.nb = nb;
+    g.nwall = nwall;
+    g.lfn = lfn;
+    g.lnb = lnb;
+    g.ratio = ratio;
+    g.lface = lface;
+    g.vol = vol;
+    g.cverts = cverts;
+    g.nv = nv;
+    g.fL = fL;
+    g.fR = fR;
+    g.fLL = fLL;
+    g.fRR = fRR;
+    g.fn = fn;
+    g.fs = fs;
+    g.fxi = fxi;
+    g.bcell = bcell;
+    g.bk = bk;
+    g.btype = btype;
+    g.bdata = bdata;
+    g.wall_b = wall_b;
+    return g;
+  }
+};
+
+namespace {
+
+int set_err(ugkwp_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(call)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      return set_err(c, e_ == hipErrorOutOfMemory ? UGKWP_ENOMEM : UGKWP_EDEVICE, "%s: %s", #call,      \
+                     hipGetErrorString(e_));                                                           \
+  } while (0)
+
+template <class T>
+int dalloc(ugkwp_ctx *c, T **p, size_t n) {
+  void *q = nullptr;
+  HIPCHK(hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return UGKWP_OK;
+}
+
+void dfree(ugkwp_ctx *c, void *p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+template <class T>
+int upload(ugkwp_ctx *c, T **p, const std::vector<T> &h) {
+  int rc = dalloc(c, p, h.size());
+  if (rc) return rc;
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return UGKWP_OK;
+}
+
+inline unsigned nblk(int64_t n, int t) { return static_cast<unsigned>(std::max<int64_t>(1, (n + t - 1) / t)); }
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+hipEvent_t ev_get(ugkwp_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  ugkwp_ctx *c;
+  int id;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(ugkwp_ctx *c_, int id_, double bytes_) : c(c_), id(id_), bytes(bytes_) {
+    if (c->prof) {
+      a = ev_get(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof && a) {
+      hipEvent_t b = ev_get(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->prof_pending.push_back({id, a, b, bytes});
+      }
+    }
+  }
+};
+
+void prof_harvest(ugkwp_ctx *c) {
+  for (auto &r : c->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_ms[r.id] += ms;
+      c->prof_n[r.id] += 1;
+      c->prof_bytes[r.id] += r.bytes;
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// mesh tables
+// ---------------------------------------------------------------------------
+struct HostMesh {
+  int NV = 0;
+  int64_t nc = 0, nf = 0, nb = 0;
+  std::vector<double> vol, cen;        // cen [nc*2]
+  std::vector<double> lfn;             // [nc*NV*4]
+  std::vector<int> lnb, lface, nv;     // [nc*NV], [nc*NV], [nc]
+  std::vector<double> cverts;          // [nc*NV*2]
+  std::vector<int> fL, fR, fkL, fkR, fLL, fRR;
+  std::vector<double> fn, fs, fmid, fxi;
+  std::vector<int> bcell, bk;
+};
+
+// Geometry by fan triangulation from vertex 0 (area, centroid); CCW edge
+// d = v_{k+1} - v_k has outward unit normal (d_y, -d_x)/|d|, length |d| and
+// offset n . v_k.  Faces are numbered in order of first appearance over
+// (cell, local face); L is that first cell and n its outward normal.
+int build_mesh(ugkwp_ctx *c, const ugkwp_mesh *m, HostMesh &h) {
+  const int dim = m->dim;
+  const int64_t nc = m->n_cells, nb = m->n_bfaces;
+  h.nc = nc;
+  h.nb = nb;
+  if (dim == 1) {
+    if (m->n_nodes != nc + 1) return set_err(c, UGKWP_EINVAL, "1D mesh needs n_nodes = n_cells + 1");
+    h.NV = 2;
+  } else {
+    if (!m->cell_ptr || !m->cell_nodes) return set_err(c, UGKWP_EINVAL, "2D mesh needs cell_ptr/cell_nodes");
+    int mx = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+      const int64_t nvv = m->cell_ptr[i + 1] - m->cell_ptr[i];
+      if (nvv < 3 || nvv > 8) return set_err(c, UGKWP_EINVAL, "cell %lld has %lld vertices", (long long)i, (long long)nvv);
+      mx = std::max<int>(mx, static_cast<int>(nvv));
+    }
+    h.NV = mx;
+  }
+  const int NV = h.NV;
+  h.vol.assign(nc, 0.0);
+  h.cen.assign(nc * 2, 0.0);
+  h.lfn.assign(nc * NV * 4, 0.0);
+  h.lnb.assign(nc * NV, kPad);
+  h.lface.assign(nc * NV, kNoFace);
+  h.nv.assign(nc, 0);
+  h.cverts.assign(nc * NV * 2, 0.0);
+  h.bcell.assign(nb, -1);
+  h.bk.assign(nb, -1);
+  const double *v = m->nodes;
+  if (dim == 1) {
+    for (int64_t i = 0; i < nc; ++i) {
+      const double xl = v[i], xr = v[i + 1];
+      if (!(xr > xl)) return set_err(c, UGKWP_EINVAL, "1D nodes not increasing at %lld", (long long)i);
+      h.vol[i] = xr - xl;
+      h.cen[2 * i] = 0.5 * (xl + xr);
+      h.nv[i] = 2;
+      double *f0 = &h.lfn[(i * NV + 0) * 4], *f1 = &h.lfn[(i * NV + 1) * 4];
+      f0[0] = -1.0; f0[1] = 0.0; f0[2] = -xl; f0[3] = 1.0;
+      f1[0] = 1.0;  f1[1] = 0.0; f1[2] = xr;  f1[3] = 1.0;
+      h.lnb[i * NV + 0] = static_cast<int>(i - 1);
+      h.lnb[i * NV + 1] = static_cast<int>(i + 1);
+      h.cverts[(i * NV + 0) * 2] = xl;
+      h.cverts[(i * NV + 1) * 2] = xr;
+    }
+    int seen0 = 0, seen1 = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t nd = m->bface_nodes[b];
+      if (nd == 0) {
+        h.lnb[0] = static_cast<int>(-(b + 1)); h.bcell[b] = 0; h.bk[b] = 0; ++seen0;
+      } else if (nd == nc) {
+        h.lnb[(nc - 1) * NV + 1] = static_cast<int>(-(b + 1)); h.bcell[b] = static_cast<int>(nc - 1); h.bk[b] = 1; ++seen1;
+      } else {
+        return set_err(c, UGKWP_EINVAL, "1D boundary face on interior node %lld", (long long)nd);
+      }
+    }
+    if (seen0 != 1 || seen1 != 1) return set_err(c, UGKWP_EINVAL, "1D mesh needs one boundary face at each end");
+  } else {
+    struct Edge {
+      int64_t a, b, cell, k;
+    };
+    std::vector<Edge> E;
+    E.reserve(m->cell_ptr[nc]);
+    for (int64_t i = 0; i < nc; ++i) {
+      const int64_t s0 = m->cell_ptr[i];
+      const int nvv = static_cast<int>(m->cell_ptr[i + 1] - s0);
+      const int64_t *id = m->cell_nodes + s0;
+      for (int k = 0; k < nvv; ++k)
+        if (id[k] < 0 || id[k] >= m->n_nodes) return set_err(c, UGKWP_EINVAL, "cell %lld node out of range", (long long)i);
+      h.nv[i] = nvv;
+      const double x0 = v[2 * id[0]], y0 = v[2 * id[0] + 1];
+      double area = 0.0, cx = 0.0, cy = 0.0;
+      for (int t = 0; t + 2 < nvv; ++t) {
+        const double xa = v[2 * id[t + 1]], ya = v[2 * id[t + 1] + 1];
+        const double xb = v[2 * id[t + 2]], yb = v[2 * id[t + 2] + 1];
+        const double At = 0.5 * ((xa - x0) * (yb - y0) - (xb - x0) * (ya - y0));
+        area += At;
+        cx += At * ((x0 + xa + xb) / 3.0);
+        cy += At * ((y0 + ya + yb) / 3.0);
+      }
+      if (!(area > 0.0)) return set_err(c, UGKWP_EINVAL, "cell %lld has non-positive area (not CCW?)", (long long)i);
+      h.vol[i] = area;
+      h.cen[2 * i] = cx / area;
+      h.cen[2 * i + 1] = cy / area;
+      for (int k = 0; k < nvv; ++k) {
+        const int64_t a = id[k], b = id[(k + 1) % nvv], bb = id[(k + 2) % nvv];
+        const double dx = v[2 * b] - v[2 * a], dy = v[2 * b + 1] - v[2 * a + 1];
+        const double ex = v[2 * bb] - v[2 * b], ey = v[2 * bb + 1] - v[2 * b + 1];
+        if (!(dx * ey - dy * ex > 0.0)) return set_err(c, UGKWP_EINVAL, "cell %lld is not strictly convex/CCW", (long long)i);
+        const double len = std::sqrt(dx * dx + dy * dy);
+        const double nx = dy / len, ny = -dx / len;
+        double *f = &h.lfn[(i * NV + k) * 4];
+        f[0] = nx;
+        f[1] = ny;
+        f[2] = nx * v[2 * a] + ny * v[2 * a + 1];
+        f[3] = len;
+        h.cverts[(i * NV + k) * 2] = v[2 * a];
+        h.cverts[(i * NV + k) * 2 + 1] = v[2 * a + 1];
+        E.push_back({std::min(a, b), std::max(a, b), i, k});
+      }
+    }
+    std::sort(E.begin(), E.end(), [](const Edge &p, const Edge &q) {
+      if (p.a != q.a) return p.a < q.a;
+      if (p.b != q.b) return p.b < q.b;
+      if (p.cell != q.cell) return p.cell < q.cell;
+      return p.k < q.k;
+    });
+    std::vector<Edge> Bv(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t a = m->bface_nodes[2 * b], d = m->bface_nodes[2 * b + 1];
+      Bv[b] = {std::min(a, d), std::max(a, d), b, 0};
+    }
+    std::sort(Bv.begin(), Bv.end(), [](const Edge &p, const Edge &q) { return p.a != q.a ? p.a < q.a : p.b < q.b; });
+    size_t ib = 0;
+    for (size_t e = 0; e < E.size();) {
+      if (e + 1 < E.size() && E[e + 1].a == E[e].a && E[e + 1].b == E[e].b) {
+        if (e + 2 < E.size() && E[e + 2].a == E[e].a && E[e + 2].b == E[e].b)
+          return set_err(c, UGKWP_EINVAL, "edge shared by more than two cells");
+        h.lnb[E[e].cell * NV + E[e].k] = static_cast<int>(E[e + 1].cell);
+        h.lnb[E[e + 1].cell * NV + E[e + 1].k] = static_cast<int>(E[e].cell);
+        e += 2;
+      } else {
+        while (ib < Bv.size() && (Bv[ib].a < E[e].a || (Bv[ib].a == E[e].a && Bv[ib].b < E[e].b))) ++ib;
+        if (ib >= Bv.size() || Bv[ib].a != E[e].a || Bv[ib].b != E[e].b)
+          return set_err(c, UGKWP_EINVAL, "open edge (%lld,%lld) not in the boundary list", (long long)E[e].a, (long long)E[e].b);
+        const int64_t b = Bv[ib].cell;
+        h.lnb[E[e].cell * NV + E[e].k] = static_cast<int>(-(b + 1));
+        h.bcell[b] = static_cast<int>(E[e].cell);
+        h.bk[b] = static_cast<int>(E[e].k);
+        ++e;
+      }
+    }
+  }
+  for (int64_t b = 0; b < nb; ++b)
+    if (h.bcell[b] < 0) return set_err(c, UGKWP_EINVAL, "boundary face %lld matches no cell edge", (long long)b);
+  // global faces
+  std::vector<int> lf(nc * NV, -1);
+  int64_t nf = 0;
+  for (int64_t i = 0; i < nc; ++i) {
+    for (int k = 0; k < h.nv[i]; ++k) {
+      const int64_t l = i * NV + k;
+      if (lf[l] >= 0) continue;
+      const int f = static_cast<int>(nf++);
+      lf[l] = f;
+      h.lface[l] = f;
+      h.fL.push_back(static_cast<int>(i));
+      h.fkL.push_back(k);
+      h.fn.push_back(h.lfn[l * 4]);
+      h.fn.push_back(h.lfn[l * 4 + 1]);
+      h.fs.push_back(h.lfn[l * 4 + 3]);
+      if (dim == 1) {
+        h.fmid.push_back(k == 0 ? v[i] : v[i + 1]);
+        h.fmid.push_back(0.0);
+      } else {
+        const int kn = (k + 1) % h.nv[i];
+        h.fmid.push_back(0.5 * (h.cverts[l * 2] + h.cverts[(i * NV + kn) * 2]));
+        h.fmid.push_back(0.5 * (h.cverts[l * 2 + 1] + h.cverts[(i * NV + kn) * 2 + 1]));
+      }
+      const int nbr = h.lnb[l];
+      if (nbr >= 0) {
+        int found = -1;
+        for (int k2 = 0; k2 < h.nv[nbr]; ++k2)
+          if (h.lnb[static_cast<int64_t>(nbr) * NV + k2] == i && lf[static_cast<int64_t>(nbr) * NV + k2] < 0) {
+            found = k2;
+            break;
+          }
+        if (found < 0) return set_err(c, UGKWP_EINVAL, "inconsistent neighbour table");
+        lf[static_cast<int64_t>(nbr) * NV + found] = f;
+        h.lface[static_cast<int64_t>(nbr) * NV + found] = ~f;
+        h.fR.push_back(nbr);
+        h.fkR.push_back(found);
+      } else {
+        h.fR.push_back(nbr);
+        h.fkR.push_back(-1);
+      }
+    }
+  }
+  h.nf = nf;
+  // reconstruction stencil: the cell across the opposite face (1D: 1-k; quads: k+2)
+  auto opposite = [&](int cell, int k) -> int {
+    int ko;
+    if (dim == 1) ko = 1 - k;
+    else if (h.nv[cell] == 4) ko = (k + 2) % 4;
+    else return -1;
+    const int nb2 = h.lnb[static_cast<int64_t>(cell) * NV + ko];
+    return nb2 >= 0 ? nb2 : -1;
+  };
+  h.fLL.resize(nf);
+  h.fRR.resize(nf);
+  h.fxi.assign(nf * 4, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int L = h.fL[f], R = h.fR[f];
+    const double nx = h.fn[2 * f], ny = h.fn[2 * f + 1];
+    const double mx = h.fmid[2 * f], my = h.fmid[2 * f + 1];
+    auto xi = [&](int cell) { return (h.cen[2 * cell] - mx) * nx + (h.cen[2 * cell + 1] - my) * ny; };
+    h.fLL[f] = R >= 0 ? opposite(L, h.fkL[f]) : -1;
+    h.fRR[f] = R >= 0 ? opposite(R, h.fkR[f]) : -1;
+    h.fxi[4 * f + 1] = xi(L);
+    if (R >= 0) h.fxi[4 * f + 2] = xi(R);
+    if (h.fLL[f] >= 0) h.fxi[4 * f + 0] = xi(h.fLL[f]);
+    if (h.fRR[f] >= 0) h.fxi[4 * f + 3] = xi(h.fRR[f]);
+  }
+  return UGKWP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scan helper: out[0..n] = exclusive scan of in[0..n), out[n] = total
+// ---------------------------------------------------------------------------
+int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
+  const int64_t nblocks = std::max<int64_t>(1, (n + kScanBlock) / kScanBlock);
+  if (nblocks + 1 > c->scan_tmp_n) {
+    dfree(c, c->scan_tmp);
+    c->scan_tmp = nullptr;
+    int rc = dalloc(c, &c->scan_tmp, static_cast<size_t>(nblocks + 1));
+    if (rc) return rc;
+    c->scan_tmp_n = nblocks + 1;
+  }
+  ProfScope ps(c, kKScan, 12.0 * static_cast<double>(n));
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanBlock), 0, c->stream, in, n, out, c->scan_tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, c->stream, c->scan_tmp, nblocks,
+                     c->scan_tmp + nblocks);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, c->stream, out, n, c->scan_tmp,
+                     c->scan_tmp + nblocks);
+  HIPCHK(hipGetLastError());
+  return UGKWP_OK;
+}
+
+int alloc_store(ugkwp_ctx *c, Store &s, int64_t n) {
+  int rc = 0;
+  rc |= dalloc(c, &s.x, n);
+  if (c->dim == 2) rc |= dalloc(c, &s.y, n);
+  rc |= dalloc(c, &s.ux, n);
+  rc |= dalloc(c, &s.uy, n);
+  rc |= dalloc(c, &s.uz, n);
+  rc |= dalloc(c, &s.m, n);
+  rc |= dalloc(c, &s.pid, n);
+  rc |= dalloc(c, &s.cell, n);
+  return rc ? UGKWP_ENOMEM : UGKWP_OK;
+}
+
+void free_store(ugkwp_ctx *c, Store &s) {
+  dfree(c, s.x);
+  dfree(c, s.y);
+  dfree(c, s.ux);
+  dfree(c, s.uy);
+  dfree(c, s.uz);
+  dfree(c, s.m);
+  dfree(c, s.pid);
+  dfree(c, s.cell);
+  s = Store{};
+}
+
+int copy_store(ugkwp_ctx *c, const Store &from, const Store &to, int64_t n) {
+  if (n <= 0) return UGKWP_OK;
+  const size_t d8 = n * sizeof(double);
+  HIPCHK(hipMemcpyAsync(to.x, from.x, d8, hipMemcpyDeviceToDevice, c->stream));
+  if (c->dim == 2) HIPCHK(hipMemcpyAsync(to.y, from.y, d8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.ux, from.ux, d8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.uy, from.uy, d8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.uz, from.uz, d8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.m, from.m, d8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.pid, from.pid, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.cell, from.cell, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+  return UGKWP_OK;
+}
+
+// Grow the particle buffers to hold at least `need` particles (retained kept).
+int ensure_capacity(ugkwp_ctx *c, int64_t need) {
+  if (need <= c->cap) return UGKWP_OK;
+  const int64_t ncap = std::max<int64_t>(need + need / 4 + 1024, c->cap + c->cap / 2);
+  Store A2{}, B2{};
+  int rc = alloc_store(c, A2, ncap);
+  if (!rc) rc = alloc_store(c, B2, ncap);
+  if (rc) return set_err(c, UGKWP_ENOMEM, "cannot grow particle store to %lld", (long long)ncap);
+  rc = copy_store(c, c->A, A2, c->n_ret);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  free_store(c, c->A);
+  free_store(c, c->B);
+  dfree(c, c->S.rank);
+  dfree(c, c->S.tghost);
+  c->S.rank = nullptr;
+  c->S.tghost = nullptr;
+  if (dalloc(c, &c->S.rank, ncap) || dalloc(c, &c->S.tghost, ncap))
+    return set_err(c, UGKWP_ENOMEM, "cannot grow particle work arrays");
+  c->A = A2;
+  c->B = B2;
+  c->cap = ncap;
+  return UGKWP_OK;
+}
+
+template <int DIM>
+int do_step(ugkwp_ctx *c) {
+  const int NW = DIM + 2;
+  const Geo g = c->geo();
+  State &S = c->S;
+  const int64_t nc = c->nc, nb = c->nb;
+  // zero per-step accumulators
+  HIPCHK(hipMemsetAsync(S.Sp, 0, nc * NW * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Sretn, 0, nc * NW * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.wimp, 0, std::max<int64_t>(nb, 1) * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.resid, 0, 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.cdsum, 0, sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.stats, 0, kStatN * sizeof(int64_t), c->stream));
+  if (c->P.Pr != 1.0) {
+    HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
+    ProfScope ps(c, kKHeatFlux, 44.0 * c->n_ret);
+    hipLaunchKernelGGL(k_heat_flux<DIM>, dim3(nblk(c->n_ret, 256)), dim3(256), 0, c->stream, c->P, c->A, S.W,
+                       c->n_ret, S.Q);
+  }
+  {
+    ProfScope ps(c, kKCellPrep, 160.0 * nc);
+    hipLaunchKernelGGL(k_cell_prep<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
+  }
+  if (nb > 0) {
+    ProfScope ps(c, kKGhostPrep, 200.0 * nb);
+    hipLaunchKernelGGL(k_ghost_prep<DIM>, dim3(nblk(nb, 256)), dim3(256), 0, c->stream, g, c->P, S);
+  }
+  int rc = scan(c, S.ncount, nc + nb, S.noff);
+  if (rc) return rc;
+  HIPCHK(hipGetLastError());
+  // one host sync per step: totals of the new sets and error flags
+  HIPCHK(hipMemcpyAsync(&c->pinned[0], S.noff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&c->pinned[1], S.noff + nc + nb, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&c->pinned[2], S.flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) prof_harvest(c);
+  const int flags = static_cast<int>(c->pinned[2] & 0xffffffff);
+  if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state at step %lld", (long long)c->step);
+  if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking before step %lld", (long long)c->step);
+  if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+  const int64_t n_cellnew = c->pinned[0];
+  const int64_t n_newall = c->pinned[1];
+  rc = ensure_capacity(c, c->n_ret + n_newall);
+  if (rc) return rc;
+  const int64_t n_max = c->n_ret + n_newall;
+  const double rec = DIM == 2 ? 60.0 : 52.0;  // bytes of one particle record
+  {
+    ProfScope ps(c, kKSampleCells, rec * n_cellnew);
+    hipLaunchKernelGGL(k_sample_cells<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+                       c->n_ret, c->step);
+  }
+  if (nb > 0) {
+    ProfScope ps(c, kKSampleGhosts, rec * (n_newall - n_cellnew));
+    hipLaunchKernelGGL(k_sample_ghosts<DIM>, dim3(nblk(nb * 64, 256)), dim3(256), 0, c->stream, g, c->P, S,
+                       c->A, c->n_ret + n_cellnew, c->step);
+  }
+  {
+    // transport reads a record and writes x, (y), m, cell and the rank
+    const double wr = DIM == 2 ? 32.0 : 24.0;
+    ProfScope ps(c, kKTransport, (rec + wr) * (c->n_ret + n_cellnew));
+    hipLaunchKernelGGL(k_transport<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+                       c->n_ret, n_cellnew, c->step);
+  }
+  {
+    ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
+    hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, 256)), dim3(256), 0, c->stream, g, c->P, S);
+  }
+  {
+    ProfScope ps(c, kKUpdate, 350.0 * nc);
+    hipLaunchKernelGGL(k_update<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S, c->step);
+  }
+  if (c->nwall > 0) {
+    ProfScope ps(c, kKSurface, 150.0 * c->nwall);
+    hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S, c->step);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, c->stream, c->P, S, c->step);
+  rc = scan(c, S.count, nc, S.coff);
+  if (rc) return rc;
+  {
+    ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->n_ret);
+    hipLaunchKernelGGL(k_scatter<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, c->A, c->B, S.rank,
+                       S.coff, c->n_ret, n_cellnew, S.nghost);
+  }
+  HIPCHK(hipGetLastError());
+  std::swap(c->A, c->B);
+  std::swap(S.Sret, S.Sretn);
+  // the retained count is needed for the next launch sizes
+  HIPCHK(hipMemcpyAsync(&c->pinned[3], S.coff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&c->pinned[4], S.nghost, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int64_t prev_ret = c->n_ret;
+  c->n_ret = c->pinned[3];
+  c->last_new = n_cellnew + c->pinned[4];
+  c->last_total = prev_ret + c->last_new;
+  c->step += 1;
+  return UGKWP_OK;
+}
+
+int check_flags(ugkwp_ctx *c) {
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, c->S.flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state");
+  if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking");
+  if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+  return UGKWP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, ugkwp_ctx **out) {
+  if (!out) return UGKWP_EINVAL;
+  *out = nullptr;
+  ugkwp_ctx *c = new (std::nothrow) ugkwp_ctx();
+  if (!c) return UGKWP_ENOMEM;
+  *out = c;
+  if (!mesh || !par || !W0) return set_err(c, UGKWP_EINVAL, "null argument");
+  if (mesh->dim != 1 && mesh->dim != 2) return set_err(c, UGKWP_EINVAL, "dim must be 1 or 2");
+  if (mesh->n_cells <= 0 || mesh->n_cells >= (1 << 24) - 1 - mesh->n_bfaces)
+    return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces must be in [1, 2^24)");
+  if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
+        par->D >= 0 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0))
+    return set_err(c, UGKWP_EINVAL, "invalid parameters");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return set_err(c, UGKWP_EDEVICE, "no HIP device");
+  c->dim = mesh->dim;
+  c->nw = mesh->dim + 2;
+  c->lts = par->lts;
+  Params &P = c->P;
+  P.R = par->R;
+  P.omega = par->omega;
+  P.mu_ref = par->mu_ref;
+  P.T_ref = par->T_ref;
+  P.Pr = par->Pr;
+  P.Nd = static_cast<double>(3 + par->D);
+  P.NR = P.Nd * par->R;
+  P.K = 1 + par->D;
+  P.cfl = par->cfl;
+  P.n_ref = par->n_ref;
+  P.seed = par->seed;
+  P.rho_inf = par->rho_inf;
+  P.u_inf_x = par->u_inf_x;
+  P.u_inf_y = par->u_inf_y;
+  P.U_inf = std::sqrt(par->u_inf_x * par->u_inf_x + par->u_inf_y * par->u_inf_y);
+  P.T_inf = par->T_inf;
+  P.L_ref = par->L_ref;
+  if (!(P.U_inf > 0)) return set_err(c, UGKWP_EINVAL, "u_inf must be nonzero");
+  if (par->stream) {
+    c->stream = static_cast<hipStream_t>(par->stream);
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  for (int64_t b = 0; b < mesh->n_bfaces; ++b)
+    if (mesh->bface_type[b] < 1 || mesh->bface_type[b] > 4)
+      return set_err(c, UGKWP_EINVAL, "boundary face %lld has unknown type", (long long)b);
+  HostMesh h;
+  int rc = build_mesh(c, mesh, h);
+  if (rc) return rc;
+  c->NV = h.NV;
+  c->nc = h.nc;
+  c->nf = h.nf;
+  c->nb = h.nb;
+  const int64_t nc = c->nc, nb = c->nb, nw = c->nw;
+  c->h_face_mid = h.fmid;
+  c->h_bcell = h.bcell;
+  c->h_bk = h.bk;
+  c->h_lfn = h.lfn;
+  c->h_lface = h.lface;
+  std::vector<int> wall_b, btype(mesh->bface_type, mesh->bface_type + nb);
+  for (int64_t b = 0; b < nb; ++b)
+    if (btype[b] == UGKWP_BC_WALL_DIFFUSE) wall_b.push_back(static_cast<int>(b));
+  c->h_wall_b = wall_b;
+  c->nwall = static_cast<int64_t>(wall_b.size());
+  // device geometry
+  std::vector<double4> lfn4(nc * c->NV);
+  for (int64_t l = 0; l < nc * c->NV; ++l) lfn4[l] = make_double4(h.lfn[4 * l], h.lfn[4 * l + 1], h.lfn[4 * l + 2], h.lfn[4 * l + 3]);
+  std::vector<double2> cv2(nc * c->NV), fn2(c->nf);
+  for (int64_t l = 0; l < nc * c->NV; ++l) cv2[l] = make_double2(h.cverts[2 * l], h.cverts[2 * l + 1]);
+  for (int64_t f = 0; f < c->nf; ++f) fn2[f] = make_double2(h.fn[2 * f], h.fn[2 * f + 1]);
+  std::vector<double4> fxi4(c->nf);
+  for (int64_t f = 0; f < c->nf; ++f) fxi4[f] = make_double4(h.fxi[4 * f], h.fxi[4 * f + 1], h.fxi[4 * f + 2], h.fxi[4 * f + 3]);
+  std::vector<double> bdata(mesh->bface_data, mesh->bface_data + nb * 8);
+  if ((rc = upload(c, &c->lfn, lfn4)) || (rc = upload(c, &c->lnb, h.lnb)) || (rc = upload(c, &c->lface, h.lface)) ||
+      (rc = upload(c, &c->nv, h.nv)) || (rc = upload(c, &c->vol, h.vol)) || (rc = upload(c, &c->cverts, cv2)) ||
+      (rc = upload(c, &c->fL, h.fL)) || (rc = upload(c, &c->fR, h.fR)) || (rc = upload(c, &c->fLL, h.fLL)) ||
+      (rc = upload(c, &c->fRR, h.fRR)) || (rc = upload(c, &c->fn, fn2)) || (rc = upload(c, &c->fs, h.fs)) ||
+      (rc = upload(c, &c->fxi, fxi4)) || (rc = upload(c, &c->bcell, h.bcell)) || (rc = upload(c, &c->bk, h.bk)) ||
+      (rc = upload(c, &c->btype, btype)) || (rc = upload(c, &c->bdata, bdata)) || (rc = upload(c, &c->wall_b, wall_b)))
+    return rc;
+  if ((rc = dalloc(c, &c->ratio, nc * c->NV))) return rc;
+  // state
+  State &S = c->S;
+  std::vector<double> W(W0, W0 + nc * nw);
+  if ((rc = upload(c, &S.W, W))) return rc;
+  const size_t ncw = nc * nw, nbw = std::max<int64_t>(nb, 1) * nw;
+  if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.E, nc) ||
+      dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) || dalloc(c, &S.Sm, ncw) ||
+      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.ncount, nc + nb) ||
+      dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
+      dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, std::max<int64_t>(nb, 1)) ||
+      dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
+      dalloc(c, &S.nghost, 1) || dalloc(c, &S.count, nc) || dalloc(c, &S.coff, nc + 1) || dalloc(c, &S.Fs, c->nf * nw) ||
+      dalloc(c, &S.rho_prev, nc) || dalloc(c, &S.rho_sum, nc) || dalloc(c, &S.rho_mean_prev, nc) ||
+      dalloc(c, &S.resid, 3) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
+      dalloc(c, &S.wlast, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.wsum, std::max<int64_t>(c->nwall, 1) * 3) ||
+      dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, 1) || dalloc(c, &S.scal, kScalN) ||
+      dalloc(c, &S.stats, kStatN) || dalloc(c, &S.flags, 1))
+    return set_err(c, UGKWP_ENOMEM, "device allocation failed");
+  HIPCHK(hipMemsetAsync(S.Sret, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Sm, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.rho_sum, 0, nc * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.rho_mean_prev, 0, nc * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wsum, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wlast, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wema, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.scal, 0, kScalN * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.stats, 0, kStatN * sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.flags, 0, sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
+  // rho_prev = initial density
+  {
+    std::vector<double> r(nc);
+    for (int64_t i = 0; i < nc; ++i) r[i] = W0[i * nw];
+    HIPCHK(hipMemcpyAsync(S.rho_prev, r.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  void *pin = nullptr;
+  HIPCHK(hipHostMalloc(&pin, 8 * sizeof(int64_t), hipHostMallocDefault));
+  c->pinned = static_cast<int64_t *>(pin);
+  // a1: local time steps
+  const Geo g = c->geo();
+  {
+    ProfScope ps(c, kKInitDt, 80.0 * nc);
+    if (c->dim == 1)
+      hipLaunchKernelGGL(k_init_dt<1>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, S.W, S.dt, S.flags);
+    else
+      hipLaunchKernelGGL(k_init_dt<2>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, S.W, S.dt, S.flags);
+  }
+  HIPCHK(hipGetLastError());
+  if ((rc = check_flags(c))) return set_err(c, UGKWP_ENUMERIC, "invalid initial state");
+  if (!c->lts) {
+    std::vector<double> dt(nc);
+    HIPCHK(hipMemcpy(dt.data(), S.dt, nc * sizeof(double), hipMemcpyDeviceToHost));
+    const double m = *std::min_element(dt.begin(), dt.end());
+    std::fill(dt.begin(), dt.end(), m);
+    HIPCHK(hipMemcpy(S.dt, dt.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+  }
+  Geo g2 = c->geo();
+  hipLaunchKernelGGL(k_init_ratio, dim3(nblk(nc * c->NV, 256)), dim3(256), 0, c->stream, g2, S.dt, c->ratio);
+  HIPCHK(hipGetLastError());
+  const int64_t cap0 = par->particle_capacity > 0 ? par->particle_capacity
+                                                  : std::max<int64_t>(4096, 2 * static_cast<int64_t>(par->n_ref) * nc);
+  if ((rc = ensure_capacity(c, cap0))) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
+  if (!c || n_steps < 0) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (c->step >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+    const int rc = c->dim == 1 ? do_step<1>(c) : do_step<2>(c);
+    if (rc) return rc;
+  }
+  return check_flags(c);
+}
+
+int ugkwp_residual(ugkwp_ctx *c, double *r_inst, double *r_avg, int64_t *step) {
+  if (!c) return UGKWP_EINVAL;
+  double s[kScalN];
+  HIPCHK(hipMemcpyAsync(s, c->S.scal, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (r_inst) *r_inst = s[kScalRinst];
+  if (r_avg) *r_avg = s[kScalRavg];
+  if (step) *step = c->step;
+  return UGKWP_OK;
+}
+
+int ugkwp_surface(ugkwp_ctx *c, int32_t mode, double *out, int64_t cap, int64_t *n_wall, double *Cd) {
+  if (!c || mode < 0 || mode > 2) return UGKWP_EINVAL;
+  if (n_wall) *n_wall = c->nwall;
+  if (c->step == 0) return set_err(c, UGKWP_ESTATE, "no step done yet");
+  double s[kScalN];
+  HIPCHK(hipMemcpyAsync(s, c->S.scal, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> w(std::max<int64_t>(c->nwall, 1) * 3);
+  const double *src = mode == 0 ? c->S.wlast : mode == 1 ? c->S.wsum : c->S.wema;
+  HIPCHK(hipMemcpyAsync(w.data(), src, w.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (Cd) *Cd = mode == 0 ? s[kScalCdLast] : mode == 1 ? s[kScalCdSum] / static_cast<double>(c->step) : s[kScalCdEma];
+  if (!out) return UGKWP_OK;
+  if (cap < c->nwall) return set_err(c, UGKWP_EOVERFLOW, "surface buffer too small");
+  const Params &P = c->P;
+  const double qd = 0.5 * P.rho_inf * P.U_inf * P.U_inf;
+  const double pinf = P.rho_inf * P.R * P.T_inf;
+  const double scale = mode == 1 ? 1.0 / static_cast<double>(c->step) : 1.0;
+  for (int64_t k = 0; k < c->nwall; ++k) {
+    const int b = c->h_wall_b[k];
+    const int64_t l = static_cast<int64_t>(c->h_bcell[b]) * c->NV + c->h_bk[b];
+    const int fs = c->h_lface[l];
+    const int f = fs >= 0 ? fs : ~fs;
+    const double mx = c->h_face_mid[2 * f], my = c->h_face_mid[2 * f + 1];
+    out[6 * k + 0] = mx;
+    out[6 * k + 1] = my;
+    out[6 * k + 2] = c->h_lfn[l * 4 + 3];
+    out[6 * k + 3] = (w[3 * k] * scale - pinf) / qd;
+    out[6 * k + 4] = w[3 * k + 1] * scale / qd;
+    out[6 * k + 5] = w[3 * k + 2] * scale / (qd * P.U_inf);
+  }
+  return UGKWP_OK;
+}
+
+int ugkwp_get_fields(ugkwp_ctx *c, double *W) {
+  if (!c || !W) return UGKWP_EINVAL;
+  HIPCHK(hipMemcpyAsync(W, c->S.W, c->nc * c->nw * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_get_fields_device(ugkwp_ctx *c, void *d_W) {
+  if (!c || !d_W) return UGKWP_EINVAL;
+  HIPCHK(hipMemcpyAsync(d_W, c->S.W, c->nc * c->nw * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_get_dt(ugkwp_ctx *c, double *dt) {
+  if (!c || !dt) return UGKWP_EINVAL;
+  HIPCHK(hipMemcpyAsync(dt, c->S.dt, c->nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_get_counts(ugkwp_ctx *c, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
+                     int64_t *n_exited, int64_t *n_guard) {
+  if (!c) return UGKWP_EINVAL;
+  int64_t st[kStatN];
+  HIPCHK(hipMemcpyAsync(st, c->S.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  if (count) HIPCHK(hipMemcpyAsync(count, c->S.count, c->nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (n_total) *n_total = c->last_total;
+  if (n_new) *n_new = c->last_new;
+  if (n_removed) *n_removed = st[kStatRemoved];
+  if (n_exited) *n_exited = st[kStatExited];
+  if (n_guard) *n_guard = st[kStatGuard];
+  return UGKWP_OK;
+}
+
+int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x, double *u,
+                        int64_t *n) {
+  if (!c || !n) return UGKWP_EINVAL;
+  const int64_t np = c->n_ret;
+  *n = np;
+  if (cap < np) return set_err(c, UGKWP_EOVERFLOW, "particle buffer too small");
+  std::vector<uint64_t> P(np);
+  std::vector<int> C(np);
+  std::vector<double> X(np), Y(c->dim == 2 ? np : 0), U0(np), U1(np), U2(np), M(np);
+  const Store &s = c->A;
+  if (np > 0) {
+    HIPCHK(hipMemcpyAsync(P.data(), s.pid, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(C.data(), s.cell, np * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(X.data(), s.x, np * 8, hipMemcpyDeviceToHost, c->stream));
+    if (c->dim == 2) HIPCHK(hipMemcpyAsync(Y.data(), s.y, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(U0.data(), s.ux, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(U1.data(), s.uy, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(U2.data(), s.uz, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(M.data(), s.m, np * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<int64_t> order(np);
+  for (int64_t k = 0; k < np; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return P[a] < P[b]; });
+  for (int64_t j = 0; j < np; ++j) {
+    const int64_t k = order[j];
+    if (pid) pid[j] = P[k];
+    if (cell) cell[j] = C[k];
+    if (m) m[j] = M[k];
+    if (x) {
+      x[j * c->dim] = X[k];
+      if (c->dim == 2) x[j * 2 + 1] = Y[k];
+    }
+    if (u) {
+      u[3 * j] = U0[k];
+      u[3 * j + 1] = U1[k];
+      u[3 * j + 2] = U2[k];
+    }
+  }
+  return UGKWP_OK;
+}
+
+int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
+                        const double *x, const double *u) {
+  if (!c || n < 0 || (n > 0 && (!pid || !cell || !m || !x || !u))) return UGKWP_EINVAL;
+  std::vector<int64_t> order(n);
+  for (int64_t k = 0; k < n; ++k) {
+    if (cell[k] < 0 || cell[k] >= c->nc) return set_err(c, UGKWP_EINVAL, "particle cell out of range");
+    order[k] = k;
+  }
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return cell[a] != cell[b] ? cell[a] < cell[b] : pid[a] < pid[b];
+  });
+  int rc = ensure_capacity(c, n);
+  if (rc) return rc;
+  std::vector<uint64_t> P(n);
+  std::vector<int> C(n);
+  std::vector<double> X(n), Y(n), U0(n), U1(n), U2(n), M(n);
+  std::vector<double> Sr(c->nc * c->nw, 0.0);
+  std::vector<int> cnt(c->nc, 0);
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t k = order[j];
+    P[j] = pid[k];
+    C[j] = cell[k];
+    M[j] = m[k];
+    X[j] = x[k * c->dim];
+    Y[j] = c->dim == 2 ? x[k * 2 + 1] : 0.0;
+    U0[j] = u[3 * k];
+    U1[j] = u[3 * k + 1];
+    U2[j] = u[3 * k + 2];
+    const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]);
+    double *sr = &Sr[C[j] * c->nw];
+    sr[0] += M[j];
+    sr[1] += M[j] * U0[j];
+    if (c->dim == 2) sr[2] += M[j] * U1[j];
+    sr[c->nw - 1] += M[j] * e;
+    cnt[C[j]]++;
+  }
+  const Store &s = c->A;
+  if (n > 0) {
+    HIPCHK(hipMemcpy(s.pid, P.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.cell, C.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.x, X.data(), n * 8, hipMemcpyHostToDevice));
+    if (c->dim == 2) HIPCHK(hipMemcpy(s.y, Y.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.ux, U0.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.uy, U1.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.uz, U2.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.m, M.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(c->S.Sret, Sr.data(), Sr.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->S.count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
+  c->n_ret = n;
+  return UGKWP_OK;
+}
+
+int ugkwp_set_fields(ugkwp_ctx *c, const double *W) {
+  if (!c || !W) return UGKWP_EINVAL;
+  HIPCHK(hipMemcpy(c->S.W, W, c->nc * c->nw * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<double> r(c->nc);
+  for (int64_t i = 0; i < c->nc; ++i) r[i] = W[i * c->nw];
+  HIPCHK(hipMemcpy(c->S.rho_prev, r.data(), c->nc * sizeof(double), hipMemcpyHostToDevice));
+  return UGKWP_OK;
+}
+
+int ugkwp_set_step(ugkwp_ctx *c, int64_t step) {
+  if (!c || step < 0 || step >= (1 << 20)) return UGKWP_EINVAL;
+  c->step = step;
+  return UGKWP_OK;
+}
+
+int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
+  if (!c) return UGKWP_EINVAL;
+  const size_t bytes = c->nc * c->nw * sizeof(double);
+  if (Sminus) HIPCHK(hipMemcpyAsync(Sminus, c->S.Sm, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (Splus) HIPCHK(hipMemcpyAsync(Splus, c->S.Sp, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_profile(ugkwp_ctx *c, int32_t enable) {
+  if (!c) return UGKWP_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  prof_harvest(c);
+  if (enable) {
+    for (int k = 0; k < kKCount; ++k) {
+      c->prof_ms[k] = 0.0;
+      c->prof_n[k] = 0;
+      c->prof_bytes[k] = 0.0;
+    }
+  }
+  c->prof = enable != 0;
+  return UGKWP_OK;
+}
+
+int ugkwp_profile_read(ugkwp_ctx *c, int32_t cap, const char **names, double *ms, int64_t *launches, double *bytes,
+                       int32_t *n) {
+  if (!c) return UGKWP_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  prof_harvest(c);
+  if (n) *n = kKCount;
+  for (int k = 0; k < kKCount && k < cap; ++k) {
+    if (names) names[k] = kKernelNames[k];
+    if (ms) ms[k] = c->prof_ms[k];
+    if (launches) launches[k] = c->prof_n[k];
+    if (bytes) bytes[k] = c->prof_bytes[k];
+  }
+  return UGKWP_OK;
+}
+
+const char *ugkwp_last_error(const ugkwp_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+void ugkwp_free(ugkwp_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &r : c->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Device data layout and kernel declarations of the UGKWP-LTS library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+
+namespace ugk {
+
+constexpr int kPad = INT32_MIN;      // padding local face (cells with fewer faces)
+constexpr int kNoFace = INT32_MIN;   // lface entry of a padding local face
+constexpr int kScanBlock = 1024;
+constexpr int kMaxCross = 10000;
+
+enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4 };
+enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4 };
+enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
+enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalN };
+
+// Mesh tables (device pointers).  Local faces are padded to NV per cell:
+// local face l = cell * NV + k.
+struct Geo {
+  int NV;
+  int64_t nc, nf, nb, nwall;
+  const double4 *lfn;    // [nc*NV] outward unit normal (x, y), offset c = n . v_k (z), length s (w)
+  const int *lnb;        // [nc*NV] neighbour cell, -(b+1) for boundary face b, kPad for padding
+  const double *ratio;   // [nc*NV] dt_neighbour / dt_cell (1 at boundaries)
+  const int *lface;      // [nc*NV] global face id f (cell is L) or ~f (cell is R); kNoFace for padding
+  const double *vol;     // [nc]
+  const double2 *cverts; // [nc*NV] vertex coordinates (1D: x of left/right node)
+  const int *nv;         // [nc] vertex count
+  const int *fL, *fR;    // [nf] face cells; fR = -(b+1) on the boundary
+  const int *fLL, *fRR;  // [nf] cell across the opposite face of L / R (quads, 1D) or -1
+  const double2 *fn;     // [nf] unit normal, outward of L
+  const double *fs;      // [nf] face length
+  const double4 *fxi;    // [nf] centroid coordinates along n from the face midpoint: LL, L, R, RR
+  const int *bcell, *bk, *btype; // [nb] interior cell, its local face, BC type
+  const double *bdata;   // [nb*8]
+  const int *wall_b;     // [nwall] boundary face id of each wall face
+};
+
+struct Params {
+  double R, omega, mu_ref, T_ref, Pr;
+  double Nd;   // 3 + D velocity-like degrees of freedom
+  double NR;   // Nd * R
+  int K;       // lumped degrees of freedom in the face frame, 1 + D
+  double cfl;
+  int n_ref;
+  uint64_t seed;
+  double rho_inf, u_inf_x, u_inf_y, U_inf, T_inf, L_ref;
+};
+
+// Per-step and persistent state (device pointers).
+struct State {
+  double *W, *Wh, *dt, *tau, *E;
+  int *hvalid;
+  double *Sret, *Sretn, *Sm, *Sp, *Q;   // tallies sum_k m_k Psi_k [nc*NW], heat flux [nc*2]
+  int *ncount;                          // [nc + nb] new particles per cell / boundary face
+  int64_t *noff;                        // [nc + nb + 1] exclusive scan of ncount
+  double *mnew;                         // [nc + nb] mass of each new particle
+  double *gW, *gWh, *gtau, *gdepth;     // [nb*NW], [nb*NW], [nb], [nb]
+  int *ghvalid;                         // [nb]
+  int64_t *nghost;                      // entered ghost particles this step
+  double *tghost;                       // remaining time of entered ghost particles
+  int *count;                           // [nc] kept particles per cell
+  int64_t *coff;                        // [nc + 1] exclusive scan of count
+  int *rank;                            // [cap] rank of a kept particle in its cell, -1 removed
+  double *Fs;                           // [nf*NW] time-averaged face flux times s_j
+  double *rho_prev, *rho_sum, *rho_mean_prev;
+  double *resid;                        // [3] residual sums
+  double *wimp;                         // [nb*3] particle impulse x, y and energy at walls
+  double *wlast, *wsum, *wema;          // [nwall*3] p, tau, q
+  double *cdsum;                        // drag of the step
+  double *scal;                         // [kScalN]
+  int64_t *stats;                       // [kStatN]
+  int *flags;
+};
+
+struct Store {
+  double *x, *y, *ux, *uy, *uz, *m;
+  uint64_t *pid;
+  int *cell;
+};
+
+template <int DIM> __global__ void k_init_dt(Geo, Params, const double *, double *, int *);
+__global__ void k_init_ratio(Geo, const double *, double *);
+template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
+template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
+__global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *);
+__global__ void k_scan_sums(int64_t *, int64_t, int64_t *);
+__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *);
+template <int DIM> __global__ void k_sample_cells(Geo, Params, State, Store, int64_t, int64_t);
+template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t, int64_t);
+template <int DIM> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+template <int DIM>
+__global__ void k_scatter(Store, Store, const int *, const int64_t *, int64_t, int64_t, const int64_t *);
+template <int DIM> __global__ void k_heat_flux(Params, Store, const double *, int64_t, double *);
+template <int DIM> __global__ void k_face_flux(Geo, Params, State);
+template <int DIM> __global__ void k_update(Geo, Params, State, int64_t);
+template <int DIM> __global__ void k_surface(Geo, Params, State, int64_t);
+__global__ void k_finish(Params, State, int64_t);
+
+}  // namespace ugk

@@ -1,0 +1,990 @@
+// HIP kernels of the UGKWP-LTS step for gfx950 (CDNA4, 64-lane wavefronts).
+//
+// Particle store: structure of arrays (x, y, ux, uy, uz, m: f64; pid: u64;
+// cell: i32), double-buffered, sorted by cell at the start of every step.
+// The pre-transport set is [retained | new from cells | entered from ghosts].
+#include "kernels.h"
+
+namespace ugk {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+template <int DIM>
+struct Prim {
+  double rho, ux, uy, T, e;
+};
+
+// rho, U from W; e = rho E - rho |U|^2 / 2; T = 2 e / (N R rho), N = 3 + D.
+template <int DIM>
+__device__ __forceinline__ Prim<DIM> prim(const double *W, double NR) {
+  Prim<DIM> s;
+  s.rho = W[0];
+  s.ux = W[1] / s.rho;
+  s.uy = DIM == 2 ? W[2] / s.rho : 0.0;
+  const double ke = 0.5 * s.rho * (s.ux * s.ux + s.uy * s.uy);
+  s.e = W[DIM + 1] - ke;
+  s.T = (2.0 * s.e) / (NR * s.rho);
+  return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool prim_ok(const Prim<DIM> &s) {
+  return s.rho > 0.0 && s.e > 0.0 && isfinite(s.rho) && isfinite(s.e);
+}
+
+// tau = mu / p (Eq. (3)), mu = mu_ref (T / T_ref)^omega.
+__device__ __forceinline__ double relax_time(const Params &p, double rho, double T) {
+  const double mu = p.mu_ref * pow(T / p.T_ref, p.omega);
+  return mu / (rho * p.R * T);
+}
+
+template <int DIM>
+__device__ __forceinline__ void to_frame(const double *W, double nx, double ny, double o[4]) {
+  o[0] = W[0];
+  if (DIM == 2) {
+    o[1] = W[1] * nx + W[2] * ny;
+    o[2] = W[2] * nx - W[1] * ny;
+    o[3] = W[3];
+  } else {
+    o[1] = W[1] * nx;
+    o[2] = 0.0;
+    o[3] = W[2];
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void from_frame(const double F[4], double nx, double ny, double *o) {
+  o[0] = F[0];
+  if (DIM == 2) {
+    o[1] = F[1] * nx - F[2] * ny;
+    o[2] = F[1] * ny + F[2] * nx;
+    o[3] = F[3];
+  } else {
+    o[1] = F[1] * nx;
+    o[2] = F[3];
+  }
+}
+
+// Wavefront-aggregated tally: lanes with equal key (cell id >= 0) are reduced
+// in registers and one lane per key adds to global memory.  Lanes pass a
+// value vector and two membership flags: `all` adds v to A[key], `keep` adds
+// v to B[key] and counts into cnt[key], returning each kept lane's rank among
+// the kept particles of its cell.  Every lane of the wave must call this.
+template <int NW>
+__device__ __forceinline__ int wave_tally(int key, bool all, bool keep, const double v[NW], double *A, double *B,
+                                          int *cnt) {
+  int rank = -1;
+  uint64_t todo = __ballot(key >= 0 && (all || keep));
+  while (todo) {
+    const int leader = __ffsll(static_cast<long long>(todo)) - 1;
+    const int k = __shfl(key, leader, 64);
+    const bool mine = key == k && (all || keep);
+    const uint64_t same = __ballot(mine);
+    const uint64_t kmask = __ballot(mine && keep);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const double sa = wave_sum(mine && all ? v[q] : 0.0);
+      const double sb = wave_sum(mine && keep ? v[q] : 0.0);
+      if (lane_id() == leader) {
+        if (A && sa != 0.0) atomicAdd(&A[static_cast<int64_t>(k) * NW + q], sa);
+        if (B && sb != 0.0) atomicAdd(&B[static_cast<int64_t>(k) * NW + q], sb);
+      }
+    }
+    int base = 0;
+    if (lane_id() == leader && kmask) base = atomicAdd(&cnt[k], __popcll(kmask));
+    base = __shfl(base, leader, 64);
+    if (mine && keep) rank = base + popc_below(kmask);
+    todo &= ~same;
+  }
+  return rank;
+}
+
+// ---------------------------------------------------------------------------
+// a1: local time step from the initial field, Eq. (33), and Eq. (34)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_init_dt(Geo g, Params p, const double *__restrict__ W, double *__restrict__ dt,
+                          int *__restrict__ flags) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= g.nc) return;
+  const Prim<DIM> s = prim<DIM>(W + i * (DIM + 2), p.NR);
+  if (!prim_ok(s)) {
+    atomicOr(flags, kFlagInvalid);
+    dt[i] = 0.0;
+    return;
+  }
+  const double speed = DIM == 2 ? sqrt(s.ux * s.ux + s.uy * s.uy) : fabs(s.ux);
+  const double a = speed + 3.0 * sqrt(p.R * s.T);
+  double S = 0.0;
+  for (int k = 0; k < g.NV; ++k) {
+    const int64_t l = i * g.NV + k;
+    if (g.lnb[l] == kPad) continue;
+    S += g.lfn[l].w;
+  }
+  dt[i] = (p.cfl * g.vol[i]) / (a * S);
+}
+
+// dt_i <- min_j dt_j under GTS; directed crossing ratios dt_R / dt_L (Eq. (41)).
+__global__ void k_init_ratio(Geo g, const double *__restrict__ dt, double *__restrict__ ratio) {
+  const int64_t l = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (l >= g.nc * g.NV) return;
+  const int64_t i = l / g.NV;
+  const int nb = g.lnb[l];
+  ratio[l] = nb >= 0 ? dt[nb] / dt[i] : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// a2: cell preparation.  tau_i, E_i = e^{-dt_i/tau_i}, W^h = W - W^p
+// (Eq. (24)), and the count of new particles N = ceil(rho^hp / rho N_ref)
+// with rho^hp = rho^h E_i and mass m = rho^hp Omega_i / N (Eqs. (25)-(26)).
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_cell_prep(Geo g, Params p, State st) {
+  constexpr int NW = DIM + 2;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= g.nc) return;
+  const double *W = st.W + i * NW;
+  const Prim<DIM> s = prim<DIM>(W, p.NR);
+  int N = 0;
+  double mk = 0.0;
+  if (!prim_ok(s)) {
+    atomicOr(st.flags, kFlagInvalid);
+    st.tau[i] = 1.0;
+    st.E[i] = 0.0;
+    st.hvalid[i] = 0;
+  } else {
+    const double tau = relax_time(p, s.rho, s.T);
+    const double E = exp(-(st.dt[i] / tau));
+    st.tau[i] = tau;
+    st.E[i] = E;
+    double Wh[NW];
+    const double vol = g.vol[i];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      Wh[q] = W[q] - st.Sret[i * NW + q] / vol;
+      st.Wh[i * NW + q] = Wh[q];
+    }
+    const Prim<DIM> h = prim<DIM>(Wh, p.NR);
+    const bool hv = prim_ok(h);
+    st.hvalid[i] = hv ? 1 : 0;
+    if (hv) {
+      const double rho_hp = Wh[0] * E;
+      if (rho_hp > 0.0) {
+        const double ratio = rho_hp / W[0];
+        const double Nd = ceil(ratio * static_cast<double>(p.n_ref));
+        if (Nd > 1048575.0) {
+          atomicOr(st.flags, kFlagOverflow);
+        } else {
+          N = static_cast<int>(Nd);
+          mk = (rho_hp * vol) / static_cast<double>(N);
+        }
+      }
+    }
+  }
+  st.ncount[i] = N;
+  st.mnew[i] = mk;
+}
+
+// Ghost states of boundary faces (both sides use dt_i, Sec. IV.B): far field
+// fixed, outflow = copy of W_i, symmetry = mirror of W_i and W^h_i.  For far
+// field and outflow, the injection slab of depth dt_i (U_in + 6 sqrt(R T_g))
+// behind the face and its particle count relative to Omega_i.
+template <int DIM>
+__global__ void k_ghost_prep(Geo g, Params p, State st) {
+  constexpr int NW = DIM + 2;
+  const int64_t b = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (b >= g.nb) return;
+  const int i = g.bcell[b];
+  const int ty = g.btype[b];
+  const double4 f = g.lfn[static_cast<int64_t>(i) * g.NV + g.bk[b]];
+  double W[4] = {0, 0, 0, 0}, Wh[4] = {0, 0, 0, 0};
+  int hv = 0;
+  double tau = st.tau[i];
+  if (ty == kBcFarfield) {
+    const double *d = g.bdata + 8 * b;
+    const double ke = 0.5 * d[0] * (d[1] * d[1] + (DIM == 2 ? d[2] * d[2] : 0.0));
+    W[0] = d[0];
+    W[1] = d[0] * d[1];
+    if (DIM == 2) W[2] = d[0] * d[2];
+    W[DIM + 1] = ke + 0.5 * p.Nd * d[0] * p.R * d[3];
+    for (int q = 0; q < NW; ++q) Wh[q] = W[q];
+    hv = 1;
+    tau = relax_time(p, d[0], d[3]);
+  } else if (ty == kBcOutflow) {
+    for (int q = 0; q < NW; ++q) Wh[q] = W[q] = st.W[static_cast<int64_t>(i) * NW + q];
+    hv = 1;
+  } else if (ty == kBcSymmetry) {
+    for (int q = 0; q < NW; ++q) {
+      W[q] = st.W[static_cast<int64_t>(i) * NW + q];
+      Wh[q] = st.Wh[static_cast<int64_t>(i) * NW + q];
+    }
+    if (DIM == 2) {
+      const double mn = W[1] * f.x + W[2] * f.y;
+      const double w1 = W[1] - 2.0 * mn * f.x, w2 = W[2] - 2.0 * mn * f.y;
+      W[1] = w1;
+      W[2] = w2;
+      const double hn = Wh[1] * f.x + Wh[2] * f.y;
+      const double h1 = Wh[1] - 2.0 * hn * f.x, h2 = Wh[2] - 2.0 * hn * f.y;
+      Wh[1] = h1;
+      Wh[2] = h2;
+    } else {
+      W[1] = -W[1];
+      Wh[1] = -Wh[1];
+    }
+    hv = st.hvalid[i];
+  }
+  const double dti = st.dt[i];
+  const double E = exp(-(dti / tau));
+  for (int q = 0; q < NW; ++q) {
+    st.gW[b * NW + q] = W[q];
+    st.gWh[b * NW + q] = Wh[q];
+  }
+  st.gtau[b] = tau;
+  st.ghvalid[b] = hv;
+  int N = 0;
+  double mk = 0.0, depth = 0.0;
+  if (ty == kBcFarfield || ty == kBcOutflow) {
+    const Prim<DIM> s = prim<DIM>(W, p.NR);
+    const double Uin = -(DIM == 2 ? s.ux * f.x + s.uy * f.y : s.ux * f.x);
+    depth = dti * (Uin + 6.0 * sqrt(p.R * s.T));
+    if (depth > 0.0) {
+      const double Mslab = s.rho * E * depth * f.w;
+      if (Mslab > 0.0) {
+        const double Nd = ceil((Mslab / (s.rho * g.vol[i])) * static_cast<double>(p.n_ref));
+        if (Nd > 1048575.0) {
+          atomicOr(st.flags, kFlagOverflow);
+        } else {
+          N = static_cast<int>(Nd);
+          mk = Mslab / static_cast<double>(N);
+        }
+      }
+    }
+  }
+  st.ncount[g.nc + b] = N;
+  st.mnew[g.nc + b] = mk;
+  st.gdepth[b] = depth;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int counts into int64 offsets (three-phase: block sums,
+// one-block scan of the sums, add).  kScanBlock elements per block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t &total) {
+  // sh: blockDim.x entries; Hillis-Steele on wavefront sums
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  const int nwaves = blockDim.x >> 6;
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int k = 0; k < nwaves; ++k) {
+      const int64_t s = sh[k];
+      sh[k] = acc;
+      acc += s;
+    }
+    sh[nwaves] = acc;
+  }
+  __syncthreads();
+  total = sh[nwaves];
+  const int64_t r = sh[w] + x - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_scan_blocks(const int *__restrict__ in, int64_t n, int64_t *__restrict__ out,
+                              int64_t *__restrict__ bsum) {
+  __shared__ int64_t sh[kScanBlock / 64 + 1];
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
+  const int64_t v = i < n ? in[i] : 0;
+  int64_t total;
+  const int64_t r = block_excl_scan(v, sh, total);
+  if (i < n) out[i] = r;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total) {
+  __shared__ int64_t sh[kScanBlock / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanBlock) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    int64_t t;
+    const int64_t r = block_excl_scan(v, sh, t);
+    if (i < nb) bsum[i] = r + carry;
+    carry += t;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ bsum,
+                           const int64_t *__restrict__ total) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
+  if (i < n) out[i] += bsum[blockIdx.x];
+  if (i == n) out[n] = *total;
+}
+
+// ---------------------------------------------------------------------------
+// a3: resampling.  One wavefront per cell draws its N new particles:
+// position uniform in the cell, deviation z from the Maxwellian of W^h (with
+// Shakhov acceptance-rejection when Pr != 1), t_f = dt_i, pid = n<<44|i<<20|j.
+// For N >= 2 the set is shifted to zero mean and scaled so that it carries
+// exactly the momentum and thermal energy of W^hp (Eq. (25)).  The kernel
+// also writes W^{p,-} Omega = W^p Omega + the new particles' tally.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void sample_position(const Geo &g, int64_t cell, uint64_t seed, uint64_t pid,
+                                                int64_t step, double &x, double &y) {
+  double e0, e1, e2, e3;
+  rng2(seed, pid, step, kPos, 0, e0, e1);
+  const double2 *v = g.cverts + cell * g.NV;
+  if (DIM == 1) {
+    const double xl = v[0].x, xr = v[1].x;
+    x = xl + e0 * (xr - xl);
+    y = 0.0;
+    return;
+  }
+  rng2(seed, pid, step, kPos, 1, e2, e3);
+  const int nv = g.nv[cell];
+  const double x0 = v[0].x, y0 = v[0].y;
+  const double target = e0 * g.vol[cell];
+  double acc = 0.0;
+  int t = 0;
+  for (t = 0; t + 2 < nv; ++t) {
+    const double xa = v[t + 1].x, ya = v[t + 1].y, xb = v[t + 2].x, yb = v[t + 2].y;
+    acc += 0.5 * ((xa - x0) * (yb - y0) - (xb - x0) * (ya - y0));
+    if (target < acc) break;
+  }
+  if (t + 2 >= nv) t = nv - 3;
+  const double xa = v[t + 1].x, ya = v[t + 1].y, xb = v[t + 2].x, yb = v[t + 2].y;
+  double b1 = e1, b2 = e2;
+  if (b1 + b2 > 1.0) {
+    b1 = 1.0 - b1;
+    b2 = 1.0 - b2;
+  }
+  x = (x0 + b1 * (xa - x0)) + b2 * (xb - x0);
+  y = (y0 + b1 * (ya - y0)) + b2 * (yb - y0);
+}
+
+// Shakhov target by acceptance-rejection against the Maxwellian of W^h
+// (Eq. (4)); sh = {Ux, Uy, T, p, Qx, Qy} of the cell total.
+template <int DIM>
+__device__ __forceinline__ void sample_deviation(const Params &p, uint64_t pid, int64_t step, double Uhx,
+                                                 double Uhy, double Th, const double *sh, double z[3]) {
+  if (!sh) {
+    gauss3(p.seed, pid, step, kVel, 0, z);
+    return;
+  }
+  const double sig = sqrt(p.R * Th);
+  const double RT = p.R * sh[2];
+  const double cmax = 6.0 * sig;
+  const double du = sqrt((Uhx - sh[0]) * (Uhx - sh[0]) + (Uhy - sh[1]) * (Uhy - sh[1]));
+  const double cb = cmax + du;
+  const double qn = sqrt(sh[4] * sh[4] + sh[5] * sh[5]);
+  const double w = cb * cb / RT - 5.0;
+  const double Bnd = 1.0 + (fabs(1.0 - p.Pr) * qn * cb * (w > 5.0 ? w : 5.0)) / (5.0 * sh[3] * RT);
+  for (uint32_t att = 0; att < 64; ++att) {
+    gauss3(p.seed, pid, step, kVel, 2 * att, z);
+    const double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
+    double ea, eb;
+    rng2(p.seed, pid, step, kShakhov, att, ea, eb);
+    if (dz > cmax) continue;
+    const double cx = (Uhx + sig * z[0]) - sh[0], cy = (Uhy + sig * z[1]) - sh[1], cz = sig * z[2];
+    const double c2 = cx * cx + cy * cy + cz * cz;
+    const double cq = DIM == 2 ? cx * sh[4] + cy * sh[5] : cx * sh[4];
+    const double phi = ((1.0 - p.Pr) * cq) / (5.0 * sh[3] * RT) * (c2 / RT - 5.0);
+    if (ea * Bnd <= 1.0 + phi) return;
+  }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sample_cells(Geo g, Params p, State st, Store out, int64_t n_ret,
+                                                      int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  if (i >= g.nc) return;  // whole wavefront
+  const int lane = lane_id();
+  const int N = st.ncount[i];
+  double snew[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) snew[q] = 0.0;
+  if (N > 0) {
+    const int64_t base = n_ret + st.noff[i];
+    const double *Wh = st.Wh + i * NW;
+    const Prim<DIM> h = prim<DIM>(Wh, p.NR);
+    const double sig = sqrt(p.R * h.T);
+    const double mk = st.mnew[i];
+    double shv[6];
+    const double *sh = nullptr;
+    if (p.Pr != 1.0) {
+      const Prim<DIM> s = prim<DIM>(st.W + i * NW, p.NR);
+      shv[0] = s.ux;
+      shv[1] = s.uy;
+      shv[2] = s.T;
+      shv[3] = s.rho * p.R * s.T;
+      shv[4] = st.Q[2 * i] / g.vol[i];
+      shv[5] = st.Q[2 * i + 1] / g.vol[i];
+      sh = shv;
+    }
+    // pass 1: positions and raw deviations (z kept in the velocity slots)
+    double zs[3] = {0.0, 0.0, 0.0};
+    for (int j = lane; j < N; j += 64) {
+      const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(i) << 20) |
+                           static_cast<uint64_t>(j);
+      double x, y, z[3];
+      sample_position<DIM>(g, i, p.seed, pid, step, x, y);
+      sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, sh, z);
+      const int64_t k = base + j;
+      out.x[k] = x;
+      if (DIM == 2) out.y[k] = y;
+      out.ux[k] = z[0];
+      out.uy[k] = z[1];
+      out.uz[k] = z[2];
+      out.pid[k] = pid;
+      out.cell[k] = static_cast<int>(i);
+      out.m[k] = mk;
+      zs[0] += z[0];
+      zs[1] += z[1];
+      zs[2] += z[2];
+    }
+    double zm[3] = {0.0, 0.0, 0.0};
+    double alpha = 1.0;
+    if (N >= 2) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) zm[d] = wave_sum(zs[d]) / static_cast<double>(N);
+      double S = 0.0;
+      for (int j = lane; j < N; j += 64) {
+        const int64_t k = base + j;
+        const double a0 = out.ux[k] - zm[0], a1 = out.uy[k] - zm[1], a2 = out.uz[k] - zm[2];
+        S += a0 * a0 + a1 * a1 + a2 * a2;
+      }
+      S = wave_sum(S);
+      alpha = sqrt((3.0 * static_cast<double>(N)) / S);
+    }
+    // pass 2: final velocities and the tally of the new set
+    for (int j = lane; j < N; j += 64) {
+      const int64_t k = base + j;
+      const double w0 = (out.ux[k] - zm[0]) * alpha, w1 = (out.uy[k] - zm[1]) * alpha,
+                   w2 = (out.uz[k] - zm[2]) * alpha;
+      const double u0 = h.ux + sig * w0, u1 = h.uy + sig * w1, u2 = sig * w2;
+      out.ux[k] = u0;
+      out.uy[k] = u1;
+      out.uz[k] = u2;
+      const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+      snew[0] += mk;
+      snew[1] += mk * u0;
+      if (DIM == 2) snew[2] += mk * u1;
+      snew[NW - 1] += mk * en;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) snew[q] = wave_sum(snew[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) st.Sm[i * NW + q] = st.Sret[i * NW + q] + snew[q];
+  }
+}
+
+// Ghost injection: one wavefront per far-field/outflow face samples its slab;
+// particles whose straight flight reaches the face within dt_i enter cell i
+// at the crossing point (tangential position wrapped along the face) with the
+// remaining time.  Entering particles are compacted by ballot and appended.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st, Store out, int64_t gbase,
+                                                       int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t b = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  if (b >= g.nb) return;
+  const int N = st.ncount[g.nc + b];
+  if (N == 0) return;
+  const int lane = lane_id();
+  const int i = g.bcell[b];
+  const int kf = g.bk[b];
+  const double4 f = g.lfn[static_cast<int64_t>(i) * g.NV + kf];
+  const Prim<DIM> s = prim<DIM>(st.gW + b * NW, p.NR);
+  const double sg = sqrt(p.R * s.T);
+  const double depth = st.gdepth[b];
+  const double mk = st.mnew[g.nc + b];
+  const double dti = st.dt[i];
+  const double2 *v = g.cverts + static_cast<int64_t>(i) * g.NV;
+  const int nv = DIM == 2 ? g.nv[i] : 2;
+  const double xa = DIM == 2 ? v[kf].x : v[kf].x, ya = DIM == 2 ? v[kf].y : 0.0;
+  const double xb = DIM == 2 ? v[(kf + 1) % nv].x : 0.0, yb = DIM == 2 ? v[(kf + 1) % nv].y : 0.0;
+  for (int j0 = 0; j0 < N; j0 += 64) {
+    const int j = j0 + lane;
+    bool enter = false;
+    double px = 0, py = 0, u0 = 0, u1 = 0, u2 = 0, tr = 0;
+    uint64_t pid = 0;
+    if (j < N) {
+      pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(g.nc + b) << 20) | static_cast<uint64_t>(j);
+      double e0, e1, z[3];
+      rng2(p.seed, pid, step, kPos, 0, e0, e1);
+      sample_deviation<DIM>(p, pid, step, s.ux, s.uy, s.T, nullptr, z);
+      u0 = s.ux + sg * z[0];
+      u1 = s.uy + sg * z[1];
+      u2 = sg * z[2];
+      const double vin = -(DIM == 2 ? u0 * f.x + u1 * f.y : u0 * f.x);
+      if (vin > 0.0) {
+        const double tc = (e0 * depth) / vin;
+        if (tc < dti) {
+          enter = true;
+          tr = dti - tc;
+          if (DIM == 2) {
+            const double sface = f.w;
+            const double ut = u1 * f.x - u0 * f.y;
+            double a = e1 * sface + ut * tc;
+            a = a - sface * floor(a / sface);
+            const double w = a / sface;
+            px = xa + w * (xb - xa);
+            py = ya + w * (yb - ya);
+          } else {
+            px = xa;
+          }
+        }
+      }
+    }
+    const uint64_t mask = __ballot(enter);
+    int64_t pos = 0;
+    if (lane == 0 && mask) pos = atomicAdd(reinterpret_cast<unsigned long long *>(st.nghost),
+                                           static_cast<unsigned long long>(__popcll(mask)));
+    pos = __shfl(pos, 0, 64);
+    if (enter) {
+      const int64_t r = pos + popc_below(mask);
+      const int64_t k = gbase + r;
+      out.x[k] = px;
+      if (DIM == 2) out.y[k] = py;
+      out.ux[k] = u0;
+      out.uy[k] = u1;
+      out.uz[k] = u2;
+      out.m[k] = mk;
+      out.pid[k] = pid;
+      out.cell[k] = i;
+      st.tghost[r] = tr;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a6 + a7 (tally part): one thread per particle.
+// Free-transport time of retained particles (Eq. (51)); tracking with the
+// crossing scaling m <- m r, t <- (t - t_e) r, r = dt_R/dt_L (Eqs. (41), (52));
+// exit face = smallest t_e = (c_e - n_e.x)/(u.n_e) over u.n_e > 0 (clamped at
+// 0, ties to the lowest local index), crossing iff t_e < t; far field and
+// outflow remove, symmetry reflects specularly, diffuse walls re-emit
+// (normal speed sqrt(-2 R T_w ln e), WALL draws 2h, 2h+1 for the h-th hit).
+// Then W^{p,+} Omega over every particle ending inside (Eq. (30)), the next
+// step's W^p Omega and counts over the kept (non-collided) ones.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
+                                                   int64_t n_cellnew, int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t gbase = n_ret + n_cellnew;
+  const int64_t n_total = gbase + *st.nghost;
+  const bool active = k < n_total;
+  int cell = -1;
+  bool exited = false, collide = false;
+  double x = 0, y = 0, u0 = 0, u1 = 0, u2 = 0, m = 0;
+  if (active) {
+    cell = s.cell[k];
+    x = s.x[k];
+    y = DIM == 2 ? s.y[k] : 0.0;
+    u0 = s.ux[k];
+    u1 = s.uy[k];
+    u2 = s.uz[k];
+    m = s.m[k];
+    const uint64_t pid = s.pid[k];
+    double t;
+    if (k < n_ret) {
+      double e0, e1;
+      rng2(p.seed, pid, step, kFree, 0, e0, e1);
+      const double sfree = -st.tau[cell] * log(e0);
+      const double dtc = st.dt[cell];
+      collide = sfree < dtc;
+      t = collide ? sfree : dtc;
+    } else if (k < gbase) {
+      t = st.dt[cell];
+    } else {
+      t = st.tghost[k - gbase];
+    }
+    bool reflected = false;
+    int ncross = 0, hits = 0;
+    for (;;) {
+      const int64_t l0 = static_cast<int64_t>(cell) * g.NV;
+      double best = INFINITY;
+      int kb = -1;
+      for (int kk = 0; kk < g.NV; ++kk) {
+        const double4 f = g.lfn[l0 + kk];
+        const double un = DIM == 2 ? u0 * f.x + u1 * f.y : u0 * f.x;
+        if (!(un > 0.0)) continue;
+        const double xn = DIM == 2 ? f.x * x + f.y * y : f.x * x;
+        double te = (f.z - xn) / un;
+        if (te < 0.0) te = 0.0;
+        if (te < best) {
+          best = te;
+          kb = kk;
+        }
+      }
+      if (kb < 0 || !(best < t)) {
+        x = x + u0 * t;
+        if (DIM == 2) y = y + u1 * t;
+        break;
+      }
+      if (++ncross > kMaxCross) {
+        atomicOr(st.flags, kFlagRunaway);
+        break;
+      }
+      x = x + u0 * best;
+      if (DIM == 2) y = y + u1 * best;
+      const int64_t l = l0 + kb;
+      const int nb = g.lnb[l];
+      if (nb >= 0) {
+        const double r = g.ratio[l];
+        t = (t - best) * r;
+        m = m * r;
+        cell = nb;
+        continue;
+      }
+      const int bf = -nb - 1;
+      const int ty = g.btype[bf];
+      const double4 f = g.lfn[l];
+      t = t - best;
+      if (ty == kBcFarfield || ty == kBcOutflow) {
+        exited = true;
+        break;
+      }
+      reflected = true;
+      if (ty == kBcSymmetry) {
+        if (DIM == 2) {
+          const double un = u0 * f.x + u1 * f.y;
+          const double n0 = u0 - 2.0 * un * f.x, n1 = u1 - 2.0 * un * f.y;
+          u0 = n0;
+          u1 = n1;
+        } else {
+          u0 = -u0;
+        }
+        continue;
+      }
+      const double Tw = g.bdata[8 * bf];
+      const double sw = sqrt(p.R * Tw);
+      double e0, e1, e2, e3, z0, z1;
+      rng2(p.seed, pid, step, kWall, static_cast<uint32_t>(2 * hits), e0, e1);
+      rng2(p.seed, pid, step, kWall, static_cast<uint32_t>(2 * hits + 1), e2, e3);
+      ++hits;
+      const double vn = sqrt(-2.0 * p.R * Tw * log(e0));
+      box_muller(e1, e2, z0, z1);
+      const double b0 = u0, b1 = u1, b2 = u2;
+      if (DIM == 2) {
+        const double vt = sw * z0;
+        u0 = -vn * f.x - vt * f.y;
+        u1 = -vn * f.y + vt * f.x;
+        u2 = sw * z1;
+      } else {
+        u0 = -vn * f.x;
+        u1 = sw * z0;
+        u2 = sw * z1;
+      }
+      const double eb = 0.5 * (b0 * b0 + b1 * b1 + b2 * b2);
+      const double ea = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+      atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - u0));
+      atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - u1));
+      atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
+    }
+    s.x[k] = x;
+    if (DIM == 2) s.y[k] = y;
+    if (reflected) {
+      s.ux[k] = u0;
+      s.uy[k] = u1;
+      s.uz[k] = u2;
+    }
+    s.m[k] = m;
+    s.cell[k] = cell;
+  }
+  double v[NW];
+  const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  v[0] = m;
+  v[1] = m * u0;
+  if (DIM == 2) v[2] = m * u1;
+  v[NW - 1] = m * en;
+  const bool inside = active && !exited;
+  const bool keep = inside && !collide;
+  const int key = inside ? cell : -1;
+  const int rank = wave_tally<NW>(key, inside, keep, v, st.Sp, st.Sretn, st.count);
+  if (active) st.rank[k] = keep ? rank : -1;
+  // step statistics
+  const uint64_t me = __ballot(active && exited), mr = __ballot(inside && collide);
+  if (lane_id() == 0) {
+    if (me) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatExited]),
+                      static_cast<unsigned long long>(__popcll(me)));
+    if (mr) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatRemoved]),
+                      static_cast<unsigned long long>(__popcll(mr)));
+  }
+}
+
+// Re-sort: kept particle k goes to offset[cell] + rank in the other buffer.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__restrict__ rank,
+                                                 const int64_t *__restrict__ off, int64_t n_ret, int64_t n_cellnew,
+                                                 const int64_t *__restrict__ nghost) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t n_total = n_ret + n_cellnew + *nghost;
+  if (k >= n_total) return;
+  const int r = rank[k];
+  if (r < 0) return;
+  const int c = a.cell[k];
+  const int64_t d = off[c] + r;
+  b.x[d] = a.x[k];
+  if (DIM == 2) b.y[d] = a.y[k];
+  b.ux[d] = a.ux[k];
+  b.uy[d] = a.uy[k];
+  b.uz[d] = a.uz[k];
+  b.m[d] = a.m[k];
+  b.pid[d] = a.pid[k];
+  b.cell[d] = c;
+}
+
+// Heat flux Q_i = sum_k m_k c_k |c_k|^2 / 2, c = u - U_i, of the retained set
+// (Eq. (5); only needed for the Shakhov sampler, Pr != 1).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_heat_flux(Params p, Store s, const double *__restrict__ W, int64_t n,
+                                                   double *__restrict__ Q) {
+  constexpr int NW = DIM + 2;
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  int cell = -1;
+  double v[2] = {0.0, 0.0};
+  if (k < n) {
+    cell = s.cell[k];
+    const Prim<DIM> c = prim<DIM>(W + static_cast<int64_t>(cell) * NW, p.NR);
+    const double cx = s.ux[k] - c.ux, cy = s.uy[k] - c.uy, cz = s.uz[k];
+    const double h = 0.5 * (cx * cx + cy * cy + cz * cz);
+    const double m = s.m[k];
+    v[0] = m * cx * h;
+    v[1] = m * cy * h;
+  }
+  wave_tally<2>(cell, true, false, v, Q, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// a8: time-averaged wave fluxes, one thread per face (Eqs. (49)-(50)),
+// stored as F_j s_j along the face normal (outward of the face's L cell).
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
+  constexpr int NW = DIM + 2;
+  const int64_t fi = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (fi >= g.nf) return;
+  const int K = p.K;
+  const int L = g.fL[fi], R = g.fR[fi];
+  const double2 n = g.fn[fi];
+  const double4 xi = g.fxi[fi];  // LL, L, R, RR centroid coordinates along n
+  double F[4];
+  double wL[4], hL[4];
+  to_frame<DIM>(st.W + static_cast<int64_t>(L) * NW, n.x, n.y, wL);
+  to_frame<DIM>(st.Wh + static_cast<int64_t>(L) * NW, n.x, n.y, hL);
+  const bool hvL = st.hvalid[L] != 0;
+  if (R >= 0) {
+    const int LL = g.fLL[fi], RR = g.fRR[fi];
+    double wR[4], hR[4], wLL[4], hLL[4], wRR[4], hRR[4];
+    to_frame<DIM>(st.W + static_cast<int64_t>(R) * NW, n.x, n.y, wR);
+    to_frame<DIM>(st.Wh + static_cast<int64_t>(R) * NW, n.x, n.y, hR);
+    const bool hvR = st.hvalid[R] != 0;
+    if (LL >= 0) {
+      to_frame<DIM>(st.W + static_cast<int64_t>(LL) * NW, n.x, n.y, wLL);
+      to_frame<DIM>(st.Wh + static_cast<int64_t>(LL) * NW, n.x, n.y, hLL);
+    }
+    if (RR >= 0) {
+      to_frame<DIM>(st.W + static_cast<int64_t>(RR) * NW, n.x, n.y, wRR);
+      to_frame<DIM>(st.Wh + static_cast<int64_t>(RR) * NW, n.x, n.y, hRR);
+    }
+    double WLf[4], WRf[4], sl[4], sr[4], dW0[4];
+    reconstruct(LL >= 0 ? wLL : nullptr, xi.x, wL, xi.y, wR, xi.z, WLf, sl);
+    reconstruct(RR >= 0 ? wRR : nullptr, xi.w, wR, xi.z, wL, xi.y, WRf, sr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dW0[q] = (wR[q] - wL[q]) / (xi.z - xi.y);
+    double HLf[4], HRf[4], shl[4] = {0, 0, 0, 0}, shr[4] = {0, 0, 0, 0};
+    const double *pHL = nullptr, *pHR = nullptr;
+    if (hvL) {
+      const bool okf = LL >= 0 && st.hvalid[LL] != 0 && hvR;
+      reconstruct(okf ? hLL : nullptr, xi.x, hL, xi.y, hR, xi.z, HLf, shl);
+      pHL = HLf;
+    }
+    if (hvR) {
+      const bool okf = RR >= 0 && st.hvalid[RR] != 0 && hvL;
+      reconstruct(okf ? hRR : nullptr, xi.w, hR, xi.z, hL, xi.y, HRf, shr);
+      pHR = HRf;
+    }
+    flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr, F);
+  } else {
+    const int b = -R - 1;
+    if (g.btype[b] == kBcWall) {
+      flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, F);
+    } else {
+      double wG[4], hG[4], dW0[4];
+      const double z[4] = {0, 0, 0, 0};
+      to_frame<DIM>(st.gW + static_cast<int64_t>(b) * NW, n.x, n.y, wG);
+      to_frame<DIM>(st.gWh + static_cast<int64_t>(b) * NW, n.x, n.y, hG);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xi.y);
+      flux_interior(wL, wG, dW0, hvL ? hL : nullptr, st.ghvalid[b] ? hG : nullptr, z, z, st.dt[L], st.tau[L],
+                    st.dt[L], st.gtau[b], K, p.Pr, F);
+    }
+  }
+  double Fl[4];
+  from_frame<DIM>(F, n.x, n.y, Fl);
+  const double sj = g.fs[fi];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) st.Fs[fi * NW + q] = Fl[q] * sj;
+}
+
+// ---------------------------------------------------------------------------
+// a9: W^{n+1} = W^n - dt_i/Omega_i sum_j (+/-) F_j s_j + W^{fr,p}, Eq. (53),
+// with W^{fr,p} = W^{p,+} - W^{p,-} (Eq. (29)); faces in fixed local order.
+// Invalid results (a cell emptied into vacuum) take the content of the
+// particles that ended in the cell, or a vacuum floor state.
+// Also the residual sums and the running mean of the density.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0};
+  bool guarded = false;
+  if (i < g.nc) {
+    double acc[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) acc[q] = 0.0;
+    for (int k = 0; k < g.NV; ++k) {
+      const int64_t l = i * g.NV + k;
+      const int fs = g.lface[l];
+      if (fs == kNoFace) continue;
+      const int f = fs >= 0 ? fs : ~fs;
+      const double sg = fs >= 0 ? 1.0 : -1.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) acc[q] += sg * st.Fs[static_cast<int64_t>(f) * NW + q];
+    }
+    const double vol = g.vol[i];
+    const double coef = st.dt[i] / vol;
+    double Wn[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const double frp = st.Sp[i * NW + q] / vol - st.Sm[i * NW + q] / vol;
+      Wn[q] = (st.W[i * NW + q] - coef * acc[q]) + frp;
+    }
+    const Prim<DIM> s = prim<DIM>(Wn, p.NR);
+    if (!prim_ok(s)) {
+      guarded = true;
+      bool ok = false;
+      if (st.Sp[i * NW] > 0.0) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) Wn[q] = st.Sp[i * NW + q] / vol;
+        ok = prim_ok(prim<DIM>(Wn, p.NR));
+      }
+      if (!ok) {
+        const double rf = 1e-12 * p.rho_inf;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) Wn[q] = 0.0;
+        Wn[0] = rf;
+        Wn[NW - 1] = 0.5 * p.Nd * rf * p.R * p.T_inf;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NW; ++q) st.W[i * NW + q] = Wn[q];
+    const double rho = Wn[0];
+    const double d = rho - st.rho_prev[i];
+    r[0] = vol * d * d;
+    r[1] = vol;
+    const double sum = st.rho_sum[i] + rho;
+    st.rho_sum[i] = sum;
+    const double mean = sum / static_cast<double>(step + 1);
+    const double dm = step == 0 ? 0.0 : mean - st.rho_mean_prev[i];
+    r[2] = vol * dm * dm;
+    st.rho_mean_prev[i] = mean;
+    st.rho_prev[i] = rho;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[q] = wave_sum(r[q]);
+  const uint64_t gm = __ballot(guarded);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[q], r[q]);
+    if (gm) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatGuard]),
+                      static_cast<unsigned long long>(__popcll(gm)));
+  }
+}
+
+// a10: wall pressure, shear and heat flux (wave + particle impulses per unit
+// area and time), their running sum and EMA (2/1001), and the drag sum.
+template <int DIM>
+__global__ void k_surface(Geo g, Params p, State st, int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t w = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (w >= g.nwall) return;
+  const int b = g.wall_b[w];
+  const int i = g.bcell[b];
+  const int64_t l = static_cast<int64_t>(i) * g.NV + g.bk[b];
+  const double4 fl = g.lfn[l];
+  const int fs = g.lface[l];
+  const int f = fs >= 0 ? fs : ~fs;
+  const double s = fl.w;
+  double Fl[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) Fl[q] = st.Fs[static_cast<int64_t>(f) * NW + q] / s;
+  const double nx = fl.x, ny = DIM == 2 ? fl.y : 0.0;
+  const double mx = Fl[1], my = DIM == 2 ? Fl[2] : 0.0, eF = Fl[DIM + 1];
+  const double sdt = s * st.dt[i];
+  const double px = mx + st.wimp[3 * b] / sdt, py = my + (DIM == 2 ? st.wimp[3 * b + 1] / sdt : 0.0);
+  double v[3];
+  v[0] = px * nx + py * ny;
+  v[1] = py * nx - px * ny;
+  v[2] = eF + st.wimp[3 * b + 2] / sdt;
+  const double ex = p.u_inf_x / p.U_inf, ey = p.u_inf_y / p.U_inf;
+  atomicAdd(st.cdsum, (px * ex + py * ey) * s);
+  constexpr double a = 2.0 / 1001.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    st.wlast[3 * w + q] = v[q];
+    st.wsum[3 * w + q] += v[q];
+    st.wema[3 * w + q] = step == 0 ? v[q] : a * v[q] + (1.0 - a) * st.wema[3 * w + q];
+  }
+}
+
+// scalar bookkeeping after a step: residuals, C_d (last, sum, EMA)
+__global__ void k_finish(Params p, State st, int64_t step) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st.scal[kScalRinst] = sqrt(st.resid[0] / st.resid[1]) / p.rho_inf;
+  st.scal[kScalRavg] = sqrt(st.resid[2] / st.resid[1]) / p.rho_inf;
+  const double cd = *st.cdsum / (0.5 * p.rho_inf * p.U_inf * p.U_inf * p.L_ref);
+  constexpr double a = 2.0 / 1001.0;
+  st.scal[kScalCdLast] = cd;
+  st.scal[kScalCdSum] += cd;
+  st.scal[kScalCdEma] = step == 0 ? cd : a * cd + (1.0 - a) * st.scal[kScalCdEma];
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+#define UGK_INST(D)                                                                                       \
+  template __global__ void k_init_dt<D>(Geo, Params, const double *, double *, int *);                  \
+  template __global__ void k_cell_prep<D>(Geo, Params, State);                                           \
+  template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
+  template __global__ void k_sample_cells<D>(Geo, Params, State, Store, int64_t, int64_t);              \
+  template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t, int64_t);             \
+  template __global__ void k_transport<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);        \
+  template __global__ void k_scatter<D>(Store, Store, const int *, const int64_t *, int64_t, int64_t,   \
+                                        const int64_t *);                                                \
+  template __global__ void k_heat_flux<D>(Params, Store, const double *, int64_t, double *);            \
+  template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
+  template __global__ void k_update<D>(Geo, Params, State, int64_t);                                     \
+  template __global__ void k_surface<D>(Geo, Params, State, int64_t);
+UGK_INST(1)
+UGK_INST(2)
+
+}  // namespace ugk
