@@ -17,11 +17,11 @@ namespace {
 
 enum KernelId {
   kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKHeatFlux, kKSampleCells, kKSampleGhosts, kKTransport,
-  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCount
+  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKCount
 };
 const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "heat_flux",
                                      "sample_cells", "sample_ghosts", "transport", "face_flux", "update",
-                                     "surface",   "finish",    "scatter"};
+                                     "surface",   "finish",    "scatter",   "cell_tally"};
 
 struct ProfRec {
   int id;
@@ -520,19 +520,17 @@ int do_step(ugkwp_ctx *c) {
   State &S = c->S;
   const int64_t nc = c->nc, nb = c->nb;
   // zero per-step accumulators
-  HIPCHK(hipMemsetAsync(S.Sp, 0, nc * NW * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.Sretn, 0, nc * NW * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Scol, 0, nc * NW * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.wimp, 0, std::max<int64_t>(nb, 1) * 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.resid, 0, 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.cdsum, 0, sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
-  HIPCHK(hipMemsetAsync(S.stats, 0, kStatN * sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
   if (c->P.Pr != 1.0) {
-    HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
-    ProfScope ps(c, kKHeatFlux, 44.0 * c->n_ret);
-    hipLaunchKernelGGL(k_heat_flux<DIM>, dim3(nblk(c->n_ret, 256)), dim3(256), 0, c->stream, c->P, c->A, S.W,
-                       c->n_ret, S.Q);
+    ProfScope ps(c, kKHeatFlux, 32.0 * c->n_ret + 48.0 * nc);
+    hipLaunchKernelGGL(k_heat_flux<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, c->A, S.W,
+                       S.roff, S.Q);
   }
   {
     ProfScope ps(c, kKCellPrep, 160.0 * nc);
@@ -578,6 +576,20 @@ int do_step(ugkwp_ctx *c) {
     hipLaunchKernelGGL(k_transport<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
                        c->n_ret, n_cellnew, c->step);
   }
+  rc = scan(c, S.count, nc, S.coff);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(S.cursor, S.coff, nc * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+  {
+    ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->n_ret);
+    hipLaunchKernelGGL(k_scatter<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, c->A, c->B, S.rank,
+                       S.cursor, c->n_ret, n_cellnew, S.nghost);
+  }
+  {
+    const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
+    ProfScope ps(c, kKCellTally, rd * c->n_ret + (16.0 + 8.0 * NW) * nc);
+    hipLaunchKernelGGL(k_cell_tally<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->B, S.coff,
+                       S.Sretn);
+  }
   {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
     hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, 256)), dim3(256), 0, c->stream, g, c->P, S);
@@ -591,18 +603,12 @@ int do_step(ugkwp_ctx *c) {
     hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S, c->step);
   }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, c->stream, c->P, S, c->step);
-  rc = scan(c, S.count, nc, S.coff);
-  if (rc) return rc;
-  {
-    ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->n_ret);
-    hipLaunchKernelGGL(k_scatter<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, c->A, c->B, S.rank,
-                       S.coff, c->n_ret, n_cellnew, S.nghost);
-  }
   HIPCHK(hipGetLastError());
   std::swap(c->A, c->B);
   std::swap(S.Sret, S.Sretn);
+  std::swap(S.roff, S.coff);
   // the retained count is needed for the next launch sizes
-  HIPCHK(hipMemcpyAsync(&c->pinned[3], S.coff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&c->pinned[3], S.roff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(&c->pinned[4], S.nghost, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   const int64_t prev_ret = c->n_ret;
@@ -718,7 +724,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   const size_t ncw = nc * nw, nbw = std::max<int64_t>(nb, 1) * nw;
   if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.E, nc) ||
       dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) || dalloc(c, &S.Sm, ncw) ||
-      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.ncount, nc + nb) ||
+      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.ncount, nc + nb) ||
       dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
       dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, std::max<int64_t>(nb, 1)) ||
       dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
@@ -727,11 +733,13 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
       dalloc(c, &S.resid, 3) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
       dalloc(c, &S.wlast, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.wsum, std::max<int64_t>(c->nwall, 1) * 3) ||
       dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, 1) || dalloc(c, &S.scal, kScalN) ||
-      dalloc(c, &S.stats, kStatN) || dalloc(c, &S.flags, 1))
+      dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1))
     return set_err(c, UGKWP_ENOMEM, "device allocation failed");
   HIPCHK(hipMemsetAsync(S.Sret, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sm, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Scol, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.roff, 0, (nc + 1) * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_sum, 0, nc * sizeof(double), c->stream));
@@ -740,7 +748,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipMemsetAsync(S.wlast, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.wema, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.scal, 0, kScalN * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.stats, 0, kStatN * sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
   // rho_prev = initial density
@@ -859,12 +867,15 @@ int ugkwp_get_dt(ugkwp_ctx *c, double *dt) {
 int ugkwp_get_counts(ugkwp_ctx *c, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
                      int64_t *n_exited, int64_t *n_guard) {
   if (!c) return UGKWP_EINVAL;
-  int64_t st[kStatN];
-  HIPCHK(hipMemcpyAsync(st, c->S.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  std::vector<int64_t> slots(kStatSlots * kStatN);
+  HIPCHK(hipMemcpyAsync(slots.data(), c->S.stats, slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   if (count) HIPCHK(hipMemcpyAsync(count, c->S.count, c->nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (n_total) *n_total = c->last_total;
   if (n_new) *n_new = c->last_new;
+  int64_t st[kStatN] = {0, 0, 0, 0};
+  for (int k = 0; k < kStatSlots; ++k)
+    for (int q = 0; q < kStatN; ++q) st[q] += slots[k * kStatN + q];
   if (n_removed) *n_removed = st[kStatRemoved];
   if (n_exited) *n_exited = st[kStatExited];
   if (n_guard) *n_guard = st[kStatGuard];
@@ -962,6 +973,9 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
   }
   HIPCHK(hipMemcpy(c->S.Sret, Sr.data(), Sr.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->S.count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
+  std::vector<int64_t> ro(c->nc + 1, 0);
+  for (int64_t i = 0; i < c->nc; ++i) ro[i + 1] = ro[i] + cnt[i];
+  HIPCHK(hipMemcpy(c->S.roff, ro.data(), ro.size() * 8, hipMemcpyHostToDevice));
   c->n_ret = n;
   return UGKWP_OK;
 }

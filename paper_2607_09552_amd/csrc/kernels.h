@@ -15,6 +15,10 @@ constexpr int kMaxCross = 10000;
 enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4 };
 enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4 };
 enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
+// Step statistics are spread over kStatSlots copies (slot = block id mod
+// kStatSlots) so that the per-wave counter updates do not serialize on one
+// address; readers sum the slots.
+constexpr int kStatSlots = 256;
 enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalN };
 
 // Mesh tables (device pointers).  Local faces are padded to NV per cell:
@@ -54,7 +58,8 @@ struct Params {
 struct State {
   double *W, *Wh, *dt, *tau, *E;
   int *hvalid;
-  double *Sret, *Sretn, *Sm, *Sp, *Q;   // tallies sum_k m_k Psi_k [nc*NW], heat flux [nc*2]
+  double *Sret, *Sretn, *Sm, *Sp, *Scol, *Q; // tallies sum_k m_k Psi_k [nc*NW], heat flux [nc*2]
+  int64_t *roff;                        // [nc + 1] offsets of the retained (sorted) store
   int *ncount;                          // [nc + nb] new particles per cell / boundary face
   int64_t *noff;                        // [nc + nb + 1] exclusive scan of ncount
   double *mnew;                         // [nc + nb] mass of each new particle
@@ -64,7 +69,8 @@ struct State {
   double *tghost;                       // remaining time of entered ghost particles
   int *count;                           // [nc] kept particles per cell
   int64_t *coff;                        // [nc + 1] exclusive scan of count
-  int *rank;                            // [cap] rank of a kept particle in its cell, -1 removed
+  int *rank;                            // [cap] 0 kept, -1 removed or left
+  int64_t *cursor;                      // [nc] slot cursor of the scatter
   double *Fs;                           // [nf*NW] time-averaged face flux times s_j
   double *rho_prev, *rho_sum, *rho_mean_prev;
   double *resid;                        // [3] residual sums
@@ -72,7 +78,7 @@ struct State {
   double *wlast, *wsum, *wema;          // [nwall*3] p, tau, q
   double *cdsum;                        // drag of the step
   double *scal;                         // [kScalN]
-  int64_t *stats;                       // [kStatN]
+  int64_t *stats;                       // [kStatSlots * kStatN]
   int *flags;
 };
 
@@ -93,8 +99,9 @@ template <int DIM> __global__ void k_sample_cells(Geo, Params, State, Store, int
 template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t, int64_t);
 template <int DIM> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
 template <int DIM>
-__global__ void k_scatter(Store, Store, const int *, const int64_t *, int64_t, int64_t, const int64_t *);
-template <int DIM> __global__ void k_heat_flux(Params, Store, const double *, int64_t, double *);
+__global__ void k_scatter(Store, Store, const int *, int64_t *, int64_t, int64_t, const int64_t *);
+template <int DIM> __global__ void k_heat_flux(Geo, Params, Store, const double *, const int64_t *, double *);
+template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State, int64_t);
 template <int DIM> __global__ void k_surface(Geo, Params, State, int64_t);

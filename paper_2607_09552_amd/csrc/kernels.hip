@@ -66,38 +66,23 @@ __device__ __forceinline__ void from_frame(const double F[4], double nx, double 
   }
 }
 
-// Wavefront-aggregated tally: lanes with equal key (cell id >= 0) are reduced
-// in registers and one lane per key adds to global memory.  Lanes pass a
-// value vector and two membership flags: `all` adds v to A[key], `keep` adds
-// v to B[key] and counts into cnt[key], returning each kept lane's rank among
-// the kept particles of its cell.  Every lane of the wave must call this.
-template <int NW>
-__device__ __forceinline__ int wave_tally(int key, bool all, bool keep, const double v[NW], double *A, double *B,
-                                          int *cnt) {
-  int rank = -1;
-  uint64_t todo = __ballot(key >= 0 && (all || keep));
+// Groups the lanes of a wavefront by key (destination cell >= 0; -1 = none):
+// returns the lane mask of the caller's group and sets `leader` to its lowest
+// lane.  Integer work only (ballot and readlane).
+__device__ __forceinline__ uint64_t wave_group(int key, int &leader) {
+  uint64_t todo = __ballot(key >= 0), mine = 0;
+  leader = -1;
   while (todo) {
-    const int leader = __ffsll(static_cast<long long>(todo)) - 1;
-    const int k = __shfl(key, leader, 64);
-    const bool mine = key == k && (all || keep);
-    const uint64_t same = __ballot(mine);
-    const uint64_t kmask = __ballot(mine && keep);
-#pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      const double sa = wave_sum(mine && all ? v[q] : 0.0);
-      const double sb = wave_sum(mine && keep ? v[q] : 0.0);
-      if (lane_id() == leader) {
-        if (A && sa != 0.0) atomicAdd(&A[static_cast<int64_t>(k) * NW + q], sa);
-        if (B && sb != 0.0) atomicAdd(&B[static_cast<int64_t>(k) * NW + q], sb);
-      }
+    const int l = __ffsll(static_cast<long long>(todo)) - 1;
+    const int k = __builtin_amdgcn_readlane(key, l);
+    const uint64_t same = __ballot(key == k);
+    if (key == k) {
+      mine = same;
+      leader = l;
     }
-    int base = 0;
-    if (lane_id() == leader && kmask) base = atomicAdd(&cnt[k], __popcll(kmask));
-    base = __shfl(base, leader, 64);
-    if (mine && keep) rank = base + popc_below(kmask);
     todo &= ~same;
   }
-  return rank;
+  return mine;
 }
 
 // ---------------------------------------------------------------------------
@@ -583,7 +568,7 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
 // step's W^p Omega and counts over the kept (non-collided) ones.
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void __launch_bounds__(256) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
+__global__ void __launch_bounds__(256, 5) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
                                                    int64_t n_cellnew, int64_t step) {
   constexpr int NW = DIM + 2;
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -708,39 +693,58 @@ __global__ void __launch_bounds__(256) k_transport(Geo g, Params p, State st, St
     s.m[k] = m;
     s.cell[k] = cell;
   }
-  double v[NW];
-  const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-  v[0] = m;
-  v[1] = m * u0;
-  if (DIM == 2) v[2] = m * u1;
-  v[NW - 1] = m * en;
   const bool inside = active && !exited;
   const bool keep = inside && !collide;
-  const int key = inside ? cell : -1;
-  const int rank = wave_tally<NW>(key, inside, keep, v, st.Sp, st.Sretn, st.count);
-  if (active) st.rank[k] = keep ? rank : -1;
+  // collided particles end their flight here (Eq. (51)) and are dropped after
+  // the tally; their share of W^{p,+} (Eq. (30)) is added directly
+  if (inside && collide) {
+    const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    double *S = st.Scol + static_cast<int64_t>(cell) * NW;
+    atomicAdd(&S[0], m);
+    atomicAdd(&S[1], m * u0);
+    if (DIM == 2) atomicAdd(&S[2], m * u1);
+    atomicAdd(&S[NW - 1], m * en);
+  }
+  // histogram of the kept particles per destination cell (one atomic per
+  // group, no return value needed)
+  {
+    const int key = keep ? cell : -1;
+    int leader;
+    const uint64_t grp = wave_group(key, leader);
+    if (key >= 0 && lane_id() == leader) atomicAdd(&st.count[key], __popcll(grp));
+  }
+  if (active) st.rank[k] = keep ? 0 : -1;
   // step statistics
   const uint64_t me = __ballot(active && exited), mr = __ballot(inside && collide);
   if (lane_id() == 0) {
-    if (me) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatExited]),
+    int64_t *slot = st.stats + (blockIdx.x % kStatSlots) * kStatN;
+    if (me) atomicAdd(reinterpret_cast<unsigned long long *>(&slot[kStatExited]),
                       static_cast<unsigned long long>(__popcll(me)));
-    if (mr) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatRemoved]),
+    if (mr) atomicAdd(reinterpret_cast<unsigned long long *>(&slot[kStatRemoved]),
                       static_cast<unsigned long long>(__popcll(mr)));
   }
 }
 
-// Re-sort: kept particle k goes to offset[cell] + rank in the other buffer.
+// Re-sort (counting sort, scatter pass): cursor[c] starts at the exclusive
+// scan of the kept counts; each wavefront claims contiguous slots for its
+// lanes of equal destination with one atomic per group, all groups of the
+// wave in the same instruction.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__restrict__ rank,
-                                                 const int64_t *__restrict__ off, int64_t n_ret, int64_t n_cellnew,
+__global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__restrict__ keep,
+                                                 int64_t *__restrict__ cursor, int64_t n_ret, int64_t n_cellnew,
                                                  const int64_t *__restrict__ nghost) {
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t n_total = n_ret + n_cellnew + *nghost;
-  if (k >= n_total) return;
-  const int r = rank[k];
-  if (r < 0) return;
-  const int c = a.cell[k];
-  const int64_t d = off[c] + r;
+  const bool live = k < n_total && keep[k] >= 0;
+  const int c = live ? a.cell[k] : -1;
+  int leader;
+  const uint64_t grp = wave_group(c, leader);
+  unsigned long long base = 0;
+  if (live && lane_id() == leader)
+    base = atomicAdd(reinterpret_cast<unsigned long long *>(&cursor[c]), static_cast<unsigned long long>(__popcll(grp)));
+  base = __shfl(base, leader >= 0 ? leader : lane_id(), 64);
+  if (!live) return;
+  const int64_t d = static_cast<int64_t>(base) + popc_below(grp);
   b.x[d] = a.x[k];
   if (DIM == 2) b.y[d] = a.y[k];
   b.ux[d] = a.ux[k];
@@ -751,25 +755,62 @@ __global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__
   b.cell[d] = c;
 }
 
-// Heat flux Q_i = sum_k m_k c_k |c_k|^2 / 2, c = u - U_i, of the retained set
-// (Eq. (5); only needed for the Shakhov sampler, Pr != 1).
+// Per-cell tally of the retained (kept) particles after the re-sort, one
+// wavefront per cell over its contiguous range [off[c], off[c+1]):
+// S[c] = sum_k m_k Psi_k (the next step's W^p Omega, Eq. (24), and the kept
+// part of W^{p,+} Omega, Eq. (30)).  Lane-strided partial sums in a fixed
+// order, then one butterfly per component: no atomics.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_heat_flux(Params p, Store s, const double *__restrict__ W, int64_t n,
-                                                   double *__restrict__ Q) {
+__global__ void __launch_bounds__(256) k_cell_tally(Geo g, Store s, const int64_t *__restrict__ off,
+                                                    double *__restrict__ S) {
   constexpr int NW = DIM + 2;
-  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  int cell = -1;
-  double v[2] = {0.0, 0.0};
-  if (k < n) {
-    cell = s.cell[k];
-    const Prim<DIM> c = prim<DIM>(W + static_cast<int64_t>(cell) * NW, p.NR);
-    const double cx = s.ux[k] - c.ux, cy = s.uy[k] - c.uy, cz = s.uz[k];
+  const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  if (c >= g.nc) return;
+  const int64_t a = off[c], b = off[c + 1];
+  double v[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) v[q] = 0.0;
+  for (int64_t k = a + lane_id(); k < b; k += 64) {
+    const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
+    const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    v[0] += m;
+    v[1] += m * u0;
+    if (DIM == 2) v[2] += m * u1;
+    v[NW - 1] += m * en;
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) S[c * NW + q] = v[q];
+  }
+}
+
+// Heat flux Q_i = sum_k m_k c_k |c_k|^2 / 2, c = u - U_i, of the retained set
+// (Eq. (5); only needed for the Shakhov sampler, Pr != 1); one wavefront per
+// cell over the sorted store.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_heat_flux(Geo g, Params p, Store s, const double *__restrict__ W,
+                                                   const int64_t *__restrict__ off, double *__restrict__ Q) {
+  constexpr int NW = DIM + 2;
+  const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  if (c >= g.nc) return;
+  const int64_t a = off[c], b = off[c + 1];
+  const Prim<DIM> U = prim<DIM>(W + c * NW, p.NR);
+  double v0 = 0.0, v1 = 0.0;
+  for (int64_t k = a + lane_id(); k < b; k += 64) {
+    const double cx = s.ux[k] - U.ux, cy = s.uy[k] - U.uy, cz = s.uz[k];
     const double h = 0.5 * (cx * cx + cy * cy + cz * cz);
     const double m = s.m[k];
-    v[0] = m * cx * h;
-    v[1] = m * cy * h;
+    v0 += m * cx * h;
+    v1 += m * cy * h;
   }
-  wave_tally<2>(cell, true, false, v, Q, nullptr, nullptr);
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  if (lane_id() == 0) {
+    Q[2 * c] = v0;
+    Q[2 * c + 1] = v1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -875,7 +916,9 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64
     double Wn[NW];
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
-      const double frp = st.Sp[i * NW + q] / vol - st.Sm[i * NW + q] / vol;
+      const double sp = st.Sretn[i * NW + q] + st.Scol[i * NW + q];
+      st.Sp[i * NW + q] = sp;
+      const double frp = sp / vol - st.Sm[i * NW + q] / vol;
       Wn[q] = (st.W[i * NW + q] - coef * acc[q]) + frp;
     }
     const Prim<DIM> s = prim<DIM>(Wn, p.NR);
@@ -915,7 +958,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64
   if (lane_id() == 0) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[q], r[q]);
-    if (gm) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[kStatGuard]),
+    if (gm) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[(blockIdx.x % kStatSlots) * kStatN + kStatGuard]),
                       static_cast<unsigned long long>(__popcll(gm)));
   }
 }
@@ -978,9 +1021,10 @@ __global__ void k_finish(Params p, State st, int64_t step) {
   template __global__ void k_sample_cells<D>(Geo, Params, State, Store, int64_t, int64_t);              \
   template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t, int64_t);             \
   template __global__ void k_transport<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);        \
-  template __global__ void k_scatter<D>(Store, Store, const int *, const int64_t *, int64_t, int64_t,   \
+  template __global__ void k_scatter<D>(Store, Store, const int *, int64_t *, int64_t, int64_t,         \
                                         const int64_t *);                                                \
-  template __global__ void k_heat_flux<D>(Params, Store, const double *, int64_t, double *);            \
+  template __global__ void k_heat_flux<D>(Geo, Params, Store, const double *, const int64_t *, double *); \
+  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *);                       \
   template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
   template __global__ void k_update<D>(Geo, Params, State, int64_t);                                     \
   template __global__ void k_surface<D>(Geo, Params, State, int64_t);
