@@ -17,11 +17,11 @@ namespace {
 
 enum KernelId {
   kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKHeatFlux, kKSampleCells, kKSampleGhosts, kKTransport,
-  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKCount
+  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKSampleMatch, kKCount
 };
 const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "heat_flux",
-                                     "sample_cells", "sample_ghosts", "transport", "face_flux", "update",
-                                     "surface",   "finish",    "scatter",   "cell_tally"};
+                                     "sample_draw", "sample_ghosts", "transport", "face_flux", "update",
+                                     "surface",   "finish",    "scatter",   "cell_tally", "sample_match"};
 
 struct ProfRec {
   int id;
@@ -561,8 +561,14 @@ int do_step(ugkwp_ctx *c) {
   const double rec = DIM == 2 ? 60.0 : 52.0;  // bytes of one particle record
   {
     ProfScope ps(c, kKSampleCells, rec * n_cellnew);
-    hipLaunchKernelGGL(k_sample_cells<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
-                       c->n_ret, c->step);
+    if (n_cellnew > 0)
+      hipLaunchKernelGGL(k_sample_draw<DIM>, dim3(nblk(n_cellnew, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+                         c->n_ret, n_cellnew, c->step);
+  }
+  {
+    ProfScope ps(c, kKSampleMatch, 48.0 * n_cellnew + (8.0 * 2 * NW + 24.0) * nc);
+    hipLaunchKernelGGL(k_sample_match<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+                       c->n_ret);
   }
   if (nb > 0) {
     ProfScope ps(c, kKSampleGhosts, rec * (n_newall - n_cellnew));

@@ -95,7 +95,8 @@ template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
 __global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *);
 __global__ void k_scan_sums(int64_t *, int64_t, int64_t *);
 __global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *);
-template <int DIM> __global__ void k_sample_cells(Geo, Params, State, Store, int64_t, int64_t);
+template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+template <int DIM> __global__ void k_sample_match(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t, int64_t);
 template <int DIM> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
 template <int DIM>

@@ -389,9 +389,60 @@ __device__ __forceinline__ void sample_deviation(const Params &p, uint64_t pid, 
   }
 }
 
+// Draw pass: one thread per new particle of the interior cells.  The birth
+// cell i is the last cell with noff[i] <= k (binary search over the exclusive
+// scan of the counts), j = k - noff[i].  Writes the position, the raw
+// deviation z (in the velocity slots), pid, cell and mass.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_cells(Geo g, Params p, State st, Store out, int64_t n_ret,
-                                                      int64_t step) {
+__global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, Store out, int64_t n_ret,
+                                                     int64_t n_cellnew, int64_t step) {
+  constexpr int NW = DIM + 2;
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (k >= n_cellnew) return;
+  int64_t lo = 0, hi = g.nc;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (st.noff[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  const int64_t i = lo;
+  const int64_t j = k - st.noff[i];
+  const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(i) << 20) |
+                       static_cast<uint64_t>(j);
+  const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
+  double x, y, z[3];
+  sample_position<DIM>(g, i, p.seed, pid, step, x, y);
+  if (p.Pr != 1.0) {
+    const Prim<DIM> s = prim<DIM>(st.W + i * NW, p.NR);
+    double shv[6];
+    shv[0] = s.ux;
+    shv[1] = s.uy;
+    shv[2] = s.T;
+    shv[3] = s.rho * p.R * s.T;
+    shv[4] = st.Q[2 * i] / g.vol[i];
+    shv[5] = st.Q[2 * i + 1] / g.vol[i];
+    sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, shv, z);
+  } else {
+    sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, nullptr, z);
+  }
+  const int64_t o = n_ret + k;
+  out.x[o] = x;
+  if (DIM == 2) out.y[o] = y;
+  out.ux[o] = z[0];
+  out.uy[o] = z[1];
+  out.uz[o] = z[2];
+  out.pid[o] = pid;
+  out.cell[o] = static_cast<int>(i);
+  out.m[o] = st.mnew[i];
+}
+
+// Moment-matching pass: one wavefront per cell over its new particles.  For
+// N >= 2 the deviations are shifted to zero mean and scaled so that the set
+// carries exactly the momentum and thermal energy of W^hp (Eq. (25)):
+// u = U^h + sqrt(R T^h) ((z - zbar) alpha), alpha = sqrt(3 N / sum |z - zbar|^2).
+// Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, Store out, int64_t n_ret) {
   constexpr int NW = DIM + 2;
   const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (i >= g.nc) return;  // whole wavefront
@@ -402,58 +453,28 @@ __global__ void __launch_bounds__(256) k_sample_cells(Geo g, Params p, State st,
   for (int q = 0; q < NW; ++q) snew[q] = 0.0;
   if (N > 0) {
     const int64_t base = n_ret + st.noff[i];
-    const double *Wh = st.Wh + i * NW;
-    const Prim<DIM> h = prim<DIM>(Wh, p.NR);
+    const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
     const double sig = sqrt(p.R * h.T);
     const double mk = st.mnew[i];
-    double shv[6];
-    const double *sh = nullptr;
-    if (p.Pr != 1.0) {
-      const Prim<DIM> s = prim<DIM>(st.W + i * NW, p.NR);
-      shv[0] = s.ux;
-      shv[1] = s.uy;
-      shv[2] = s.T;
-      shv[3] = s.rho * p.R * s.T;
-      shv[4] = st.Q[2 * i] / g.vol[i];
-      shv[5] = st.Q[2 * i + 1] / g.vol[i];
-      sh = shv;
-    }
-    // pass 1: positions and raw deviations (z kept in the velocity slots)
-    double zs[3] = {0.0, 0.0, 0.0};
-    for (int j = lane; j < N; j += 64) {
-      const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(i) << 20) |
-                           static_cast<uint64_t>(j);
-      double x, y, z[3];
-      sample_position<DIM>(g, i, p.seed, pid, step, x, y);
-      sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, sh, z);
-      const int64_t k = base + j;
-      out.x[k] = x;
-      if (DIM == 2) out.y[k] = y;
-      out.ux[k] = z[0];
-      out.uy[k] = z[1];
-      out.uz[k] = z[2];
-      out.pid[k] = pid;
-      out.cell[k] = static_cast<int>(i);
-      out.m[k] = mk;
-      zs[0] += z[0];
-      zs[1] += z[1];
-      zs[2] += z[2];
-    }
     double zm[3] = {0.0, 0.0, 0.0};
     double alpha = 1.0;
     if (N >= 2) {
+      double zs[3] = {0.0, 0.0, 0.0};
+      for (int j = lane; j < N; j += 64) {
+        zs[0] += out.ux[base + j];
+        zs[1] += out.uy[base + j];
+        zs[2] += out.uz[base + j];
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) zm[d] = wave_sum(zs[d]) / static_cast<double>(N);
       double S = 0.0;
       for (int j = lane; j < N; j += 64) {
-        const int64_t k = base + j;
-        const double a0 = out.ux[k] - zm[0], a1 = out.uy[k] - zm[1], a2 = out.uz[k] - zm[2];
+        const double a0 = out.ux[base + j] - zm[0], a1 = out.uy[base + j] - zm[1], a2 = out.uz[base + j] - zm[2];
         S += a0 * a0 + a1 * a1 + a2 * a2;
       }
       S = wave_sum(S);
       alpha = sqrt((3.0 * static_cast<double>(N)) / S);
     }
-    // pass 2: final velocities and the tally of the new set
     for (int j = lane; j < N; j += 64) {
       const int64_t k = base + j;
       const double w0 = (out.ux[k] - zm[0]) * alpha, w1 = (out.uy[k] - zm[1]) * alpha,
@@ -1018,7 +1039,8 @@ __global__ void k_finish(Params p, State st, int64_t step) {
   template __global__ void k_init_dt<D>(Geo, Params, const double *, double *, int *);                  \
   template __global__ void k_cell_prep<D>(Geo, Params, State);                                           \
   template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
-  template __global__ void k_sample_cells<D>(Geo, Params, State, Store, int64_t, int64_t);              \
+  template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);      \
+  template __global__ void k_sample_match<D>(Geo, Params, State, Store, int64_t);                        \
   template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t, int64_t);             \
   template __global__ void k_transport<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);        \
   template __global__ void k_scatter<D>(Store, Store, const int *, int64_t *, int64_t, int64_t,         \
