@@ -16,10 +16,10 @@ using namespace ugk;
 namespace {
 
 enum KernelId {
-  kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKHeatFlux, kKSampleCells, kKSampleGhosts, kKTransport,
+  kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKUnused, kKSampleCells, kKSampleGhosts, kKTransport,
   kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKSampleMatch, kKCount
 };
-const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "heat_flux",
+const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "unused",
                                      "sample_draw", "sample_ghosts", "transport", "face_flux", "update",
                                      "surface",   "finish",    "scatter",   "cell_tally", "sample_match"};
 
@@ -52,7 +52,7 @@ struct ugkwp_ctx {
   // device geometry
   double4 *lfn = nullptr;
   int *lnb = nullptr, *lface = nullptr, *nv = nullptr;
-  double *ratio = nullptr, *vol = nullptr;
+  double *lfs = nullptr, *vol = nullptr;
   double2 *cverts = nullptr;
   int *fL = nullptr, *fR = nullptr, *fLL = nullptr, *fRR = nullptr;
   double2 *fn = nullptr;
@@ -85,7 +85,7 @@ struct ugkwp_ctx {
     g.nwall = nwall;
     g.lfn = lfn;
     g.lnb = lnb;
-    g.ratio = ratio;
+    g.lfs = lfs;
     g.lface = lface;
     g.vol = vol;
     g.cverts = cverts;
@@ -527,11 +527,6 @@ int do_step(ugkwp_ctx *c) {
   HIPCHK(hipMemsetAsync(S.cdsum, 0, sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
-  if (c->P.Pr != 1.0) {
-    ProfScope ps(c, kKHeatFlux, 32.0 * c->n_ret + 48.0 * nc);
-    hipLaunchKernelGGL(k_heat_flux<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, c->A, S.W,
-                       S.roff, S.Q);
-  }
   {
     ProfScope ps(c, kKCellPrep, 160.0 * nc);
     hipLaunchKernelGGL(k_cell_prep<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
@@ -579,8 +574,19 @@ int do_step(ugkwp_ctx *c) {
     // transport reads a record and writes x, (y), m, cell and the rank
     const double wr = DIM == 2 ? 32.0 : 24.0;
     ProfScope ps(c, kKTransport, (rec + wr) * (c->n_ret + n_cellnew));
-    hipLaunchKernelGGL(k_transport<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
-                       c->n_ret, n_cellnew, c->step);
+    const dim3 gr(nblk(n_max, 256)), bl(256);
+    if (DIM == 1) {
+      hipLaunchKernelGGL((k_transport<DIM, 2>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step);
+    } else {
+      switch (c->NV) {
+        case 3: hipLaunchKernelGGL((k_transport<2, 3>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        case 4: hipLaunchKernelGGL((k_transport<2, 4>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        case 5: hipLaunchKernelGGL((k_transport<2, 5>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        case 6: hipLaunchKernelGGL((k_transport<2, 6>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        case 7: hipLaunchKernelGGL((k_transport<2, 7>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        default: hipLaunchKernelGGL((k_transport<2, 8>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+      }
+    }
   }
   rc = scan(c, S.count, nc, S.coff);
   if (rc) return rc;
@@ -594,7 +600,7 @@ int do_step(ugkwp_ctx *c) {
     const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
     ProfScope ps(c, kKCellTally, rd * c->n_ret + (16.0 + 8.0 * NW) * nc);
     hipLaunchKernelGGL(k_cell_tally<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->B, S.coff,
-                       S.Sretn);
+                       S.Sretn, S.Mrawn, c->P.Pr != 1.0 ? 1 : 0);
   }
   {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
@@ -613,6 +619,7 @@ int do_step(ugkwp_ctx *c) {
   std::swap(c->A, c->B);
   std::swap(S.Sret, S.Sretn);
   std::swap(S.roff, S.coff);
+  std::swap(S.Mraw, S.Mrawn);
   // the retained count is needed for the next launch sizes
   HIPCHK(hipMemcpyAsync(&c->pinned[3], S.roff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(&c->pinned[4], S.nghost, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
@@ -707,30 +714,35 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   c->h_wall_b = wall_b;
   c->nwall = static_cast<int64_t>(wall_b.size());
   // device geometry
+  // face record: normal, offset and (set on the device from the time steps)
+  // the crossing ratio; lengths separately
   std::vector<double4> lfn4(nc * c->NV);
-  for (int64_t l = 0; l < nc * c->NV; ++l) lfn4[l] = make_double4(h.lfn[4 * l], h.lfn[4 * l + 1], h.lfn[4 * l + 2], h.lfn[4 * l + 3]);
+  std::vector<double> lfs(nc * c->NV);
+  for (int64_t l = 0; l < nc * c->NV; ++l) {
+    lfn4[l] = make_double4(h.lfn[4 * l], h.lfn[4 * l + 1], h.lfn[4 * l + 2], 1.0);
+    lfs[l] = h.lfn[4 * l + 3];
+  }
   std::vector<double2> cv2(nc * c->NV), fn2(c->nf);
   for (int64_t l = 0; l < nc * c->NV; ++l) cv2[l] = make_double2(h.cverts[2 * l], h.cverts[2 * l + 1]);
   for (int64_t f = 0; f < c->nf; ++f) fn2[f] = make_double2(h.fn[2 * f], h.fn[2 * f + 1]);
   std::vector<double4> fxi4(c->nf);
   for (int64_t f = 0; f < c->nf; ++f) fxi4[f] = make_double4(h.fxi[4 * f], h.fxi[4 * f + 1], h.fxi[4 * f + 2], h.fxi[4 * f + 3]);
   std::vector<double> bdata(mesh->bface_data, mesh->bface_data + nb * 8);
-  if ((rc = upload(c, &c->lfn, lfn4)) || (rc = upload(c, &c->lnb, h.lnb)) || (rc = upload(c, &c->lface, h.lface)) ||
+  if ((rc = upload(c, &c->lfn, lfn4)) || (rc = upload(c, &c->lfs, lfs)) || (rc = upload(c, &c->lnb, h.lnb)) || (rc = upload(c, &c->lface, h.lface)) ||
       (rc = upload(c, &c->nv, h.nv)) || (rc = upload(c, &c->vol, h.vol)) || (rc = upload(c, &c->cverts, cv2)) ||
       (rc = upload(c, &c->fL, h.fL)) || (rc = upload(c, &c->fR, h.fR)) || (rc = upload(c, &c->fLL, h.fLL)) ||
       (rc = upload(c, &c->fRR, h.fRR)) || (rc = upload(c, &c->fn, fn2)) || (rc = upload(c, &c->fs, h.fs)) ||
       (rc = upload(c, &c->fxi, fxi4)) || (rc = upload(c, &c->bcell, h.bcell)) || (rc = upload(c, &c->bk, h.bk)) ||
       (rc = upload(c, &c->btype, btype)) || (rc = upload(c, &c->bdata, bdata)) || (rc = upload(c, &c->wall_b, wall_b)))
     return rc;
-  if ((rc = dalloc(c, &c->ratio, nc * c->NV))) return rc;
   // state
   State &S = c->S;
   std::vector<double> W(W0, W0 + nc * nw);
   if ((rc = upload(c, &S.W, W))) return rc;
   const size_t ncw = nc * nw, nbw = std::max<int64_t>(nb, 1) * nw;
-  if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.E, nc) ||
+  if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.tdt, nc) || dalloc(c, &S.E, nc) ||
       dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) || dalloc(c, &S.Sm, ncw) ||
-      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.ncount, nc + nb) ||
+      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.Mraw, nc * 5) || dalloc(c, &S.Mrawn, nc * 5) || dalloc(c, &S.ncount, nc + nb) ||
       dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
       dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, std::max<int64_t>(nb, 1)) ||
       dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
@@ -747,6 +759,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipMemsetAsync(S.Scol, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.roff, 0, (nc + 1) * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Mraw, 0, nc * 5 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_sum, 0, nc * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_mean_prev, 0, nc * sizeof(double), c->stream));
@@ -786,7 +799,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
     HIPCHK(hipMemcpy(S.dt, dt.data(), nc * sizeof(double), hipMemcpyHostToDevice));
   }
   Geo g2 = c->geo();
-  hipLaunchKernelGGL(k_init_ratio, dim3(nblk(nc * c->NV, 256)), dim3(256), 0, c->stream, g2, S.dt, c->ratio);
+  hipLaunchKernelGGL(k_init_ratio, dim3(nblk(nc * c->NV, 256)), dim3(256), 0, c->stream, g2, S.dt, c->lfn);
   HIPCHK(hipGetLastError());
   const int64_t cap0 = par->particle_capacity > 0 ? par->particle_capacity
                                                   : std::max<int64_t>(4096, 2 * static_cast<int64_t>(par->n_ref) * nc);
@@ -946,7 +959,7 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
   std::vector<uint64_t> P(n);
   std::vector<int> C(n);
   std::vector<double> X(n), Y(n), U0(n), U1(n), U2(n), M(n);
-  std::vector<double> Sr(c->nc * c->nw, 0.0);
+  std::vector<double> Sr(c->nc * c->nw, 0.0), Mr(c->nc * 5, 0.0);
   std::vector<int> cnt(c->nc, 0);
   for (int64_t j = 0; j < n; ++j) {
     const int64_t k = order[j];
@@ -959,6 +972,13 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     U1[j] = u[3 * k + 1];
     U2[j] = u[3 * k + 2];
     const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]);
+    const double q2 = U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j];
+    double *mr = &Mr[C[j] * 5];
+    mr[0] += M[j] * U0[j] * q2;
+    mr[1] += M[j] * U1[j] * q2;
+    mr[2] += M[j] * U0[j] * U0[j];
+    mr[3] += M[j] * U0[j] * U1[j];
+    mr[4] += M[j] * U1[j] * U1[j];
     double *sr = &Sr[C[j] * c->nw];
     sr[0] += M[j];
     sr[1] += M[j] * U0[j];
@@ -978,6 +998,7 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     HIPCHK(hipMemcpy(s.m, M.data(), n * 8, hipMemcpyHostToDevice));
   }
   HIPCHK(hipMemcpy(c->S.Sret, Sr.data(), Sr.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->S.Mraw, Mr.data(), Mr.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->S.count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
   std::vector<int64_t> ro(c->nc + 1, 0);
   for (int64_t i = 0; i < c->nc; ++i) ro[i + 1] = ro[i] + cnt[i];

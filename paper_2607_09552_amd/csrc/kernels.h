@@ -26,9 +26,10 @@ enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kSc
 struct Geo {
   int NV;
   int64_t nc, nf, nb, nwall;
-  const double4 *lfn;    // [nc*NV] outward unit normal (x, y), offset c = n . v_k (z), length s (w)
+  const double4 *lfn;    // [nc*NV] outward unit normal (x, y), offset c = n . v_k (z),
+                         //   crossing ratio dt_neighbour / dt_cell (w; 1 at boundaries)
+  const double *lfs;     // [nc*NV] face length s
   const int *lnb;        // [nc*NV] neighbour cell, -(b+1) for boundary face b, kPad for padding
-  const double *ratio;   // [nc*NV] dt_neighbour / dt_cell (1 at boundaries)
   const int *lface;      // [nc*NV] global face id f (cell is L) or ~f (cell is R); kNoFace for padding
   const double *vol;     // [nc]
   const double2 *cverts; // [nc*NV] vertex coordinates (1D: x of left/right node)
@@ -57,8 +58,10 @@ struct Params {
 // Per-step and persistent state (device pointers).
 struct State {
   double *W, *Wh, *dt, *tau, *E;
+  double2 *tdt;                         // [nc] (tau, dt) for the transport
   int *hvalid;
   double *Sret, *Sretn, *Sm, *Sp, *Scol, *Q; // tallies sum_k m_k Psi_k [nc*NW], heat flux [nc*2]
+  double *Mraw, *Mrawn;                 // [nc*5] sum m u_a |u|^2 (a = x, y), sum m u_x u_x, u_x u_y, u_y u_y
   int64_t *roff;                        // [nc + 1] offsets of the retained (sorted) store
   int *ncount;                          // [nc + nb] new particles per cell / boundary face
   int64_t *noff;                        // [nc + nb + 1] exclusive scan of ncount
@@ -89,7 +92,7 @@ struct Store {
 };
 
 template <int DIM> __global__ void k_init_dt(Geo, Params, const double *, double *, int *);
-__global__ void k_init_ratio(Geo, const double *, double *);
+__global__ void k_init_ratio(Geo, const double *, double4 *);
 template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
 template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
 __global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *);
@@ -98,11 +101,10 @@ __global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *)
 template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t, int64_t, int64_t);
 template <int DIM> __global__ void k_sample_match(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t, int64_t);
-template <int DIM> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+template <int DIM, int NV> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
 template <int DIM>
 __global__ void k_scatter(Store, Store, const int *, int64_t *, int64_t, int64_t, const int64_t *);
-template <int DIM> __global__ void k_heat_flux(Geo, Params, Store, const double *, const int64_t *, double *);
-template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *);
+template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *, double *, int);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State, int64_t);
 template <int DIM> __global__ void k_surface(Geo, Params, State, int64_t);

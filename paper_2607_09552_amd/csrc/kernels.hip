@@ -105,18 +105,18 @@ __global__ void k_init_dt(Geo g, Params p, const double *__restrict__ W, double 
   for (int k = 0; k < g.NV; ++k) {
     const int64_t l = i * g.NV + k;
     if (g.lnb[l] == kPad) continue;
-    S += g.lfn[l].w;
+    S += g.lfs[l];
   }
   dt[i] = (p.cfl * g.vol[i]) / (a * S);
 }
 
 // dt_i <- min_j dt_j under GTS; directed crossing ratios dt_R / dt_L (Eq. (41)).
-__global__ void k_init_ratio(Geo g, const double *__restrict__ dt, double *__restrict__ ratio) {
+__global__ void k_init_ratio(Geo g, const double *__restrict__ dt, double4 *__restrict__ lfn) {
   const int64_t l = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (l >= g.nc * g.NV) return;
   const int64_t i = l / g.NV;
   const int nb = g.lnb[l];
-  ratio[l] = nb >= 0 ? dt[nb] / dt[i] : 1.0;
+  lfn[l].w = nb >= 0 ? dt[nb] / dt[i] : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -143,6 +143,7 @@ __global__ void k_cell_prep(Geo g, Params p, State st) {
     const double E = exp(-(st.dt[i] / tau));
     st.tau[i] = tau;
     st.E[i] = E;
+    st.tdt[i] = make_double2(tau, st.dt[i]);
     double Wh[NW];
     const double vol = g.vol[i];
 #pragma unroll
@@ -153,6 +154,19 @@ __global__ void k_cell_prep(Geo g, Params p, State st) {
     const Prim<DIM> h = prim<DIM>(Wh, p.NR);
     const bool hv = prim_ok(h);
     st.hvalid[i] = hv ? 1 : 0;
+    if (p.Pr != 1.0) {
+      // heat flux of the retained particles relative to U_i (Eq. (5)):
+      // Q_a = 1/2 sum m (u - U)_a |u - U|^2 expanded in raw moments
+      const double *Sr = st.Sret + i * NW;
+      const double *Mr = st.Mraw + i * 5;
+      const double Ux = s.ux, Uy = s.uy;
+      const double m0 = Sr[0], mx = Sr[1], my = DIM == 2 ? Sr[2] : 0.0, mq = 2.0 * Sr[NW - 1];
+      const double UU = Ux * Ux + Uy * Uy;
+      const double PxU = Mr[2] * Ux + Mr[3] * Uy, PyU = Mr[3] * Ux + Mr[4] * Uy;
+      const double mU = mx * Ux + my * Uy;
+      st.Q[2 * i] = 0.5 * ((((Mr[0] - 2.0 * PxU) + UU * mx) - Ux * mq) + (2.0 * Ux * mU - Ux * UU * m0));
+      st.Q[2 * i + 1] = 0.5 * ((((Mr[1] - 2.0 * PyU) + UU * my) - Uy * mq) + (2.0 * Uy * mU - Uy * UU * m0));
+    }
     if (hv) {
       const double rho_hp = Wh[0] * E;
       if (rho_hp > 0.0) {
@@ -234,7 +248,7 @@ __global__ void k_ghost_prep(Geo g, Params p, State st) {
     const double Uin = -(DIM == 2 ? s.ux * f.x + s.uy * f.y : s.ux * f.x);
     depth = dti * (Uin + 6.0 * sqrt(p.R * s.T));
     if (depth > 0.0) {
-      const double Mslab = s.rho * E * depth * f.w;
+      const double Mslab = s.rho * E * depth * g.lfs[static_cast<int64_t>(i) * g.NV + g.bk[b]];
       if (Mslab > 0.0) {
         const double Nd = ceil((Mslab / (s.rho * g.vol[i])) * static_cast<double>(p.n_ref));
         if (Nd > 1048575.0) {
@@ -543,7 +557,7 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
           enter = true;
           tr = dti - tc;
           if (DIM == 2) {
-            const double sface = f.w;
+            const double sface = g.lfs[static_cast<int64_t>(i) * g.NV + kf];
             const double ut = u1 * f.x - u0 * f.y;
             double a = e1 * sface + ut * tc;
             a = a - sface * floor(a / sface);
@@ -588,9 +602,9 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
 // Then W^{p,+} Omega over every particle ending inside (Eq. (30)), the next
 // step's W^p Omega and counts over the kept (non-collided) ones.
 // ---------------------------------------------------------------------------
-template <int DIM>
-__global__ void __launch_bounds__(256, 5) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
-                                                   int64_t n_cellnew, int64_t step) {
+template <int DIM, int NV>
+__global__ void __launch_bounds__(256, 4) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
+                                                      int64_t n_cellnew, int64_t step) {
   constexpr int NW = DIM + 2;
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t gbase = n_ret + n_cellnew;
@@ -608,35 +622,43 @@ __global__ void __launch_bounds__(256, 5) k_transport(Geo g, Params p, State st,
     u2 = s.uz[k];
     m = s.m[k];
     const uint64_t pid = s.pid[k];
+    // the cell's faces and neighbours, loaded together on entering a cell
+    double4 F[NV];
+    int nbr[NV];
+    const double2 td = st.tdt[cell];
+#pragma unroll
+    for (int kk = 0; kk < NV; ++kk) {
+      F[kk] = g.lfn[static_cast<int64_t>(cell) * NV + kk];
+      nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
+    }
     double t;
     if (k < n_ret) {
       double e0, e1;
       rng2(p.seed, pid, step, kFree, 0, e0, e1);
-      const double sfree = -st.tau[cell] * log(e0);
-      const double dtc = st.dt[cell];
-      collide = sfree < dtc;
-      t = collide ? sfree : dtc;
+      const double sfree = -td.x * log(e0);
+      collide = sfree < td.y;
+      t = collide ? sfree : td.y;
     } else if (k < gbase) {
-      t = st.dt[cell];
+      t = td.y;
     } else {
       t = st.tghost[k - gbase];
     }
     bool reflected = false;
     int ncross = 0, hits = 0;
     for (;;) {
-      const int64_t l0 = static_cast<int64_t>(cell) * g.NV;
       double best = INFINITY;
       int kb = -1;
-      for (int kk = 0; kk < g.NV; ++kk) {
-        const double4 f = g.lfn[l0 + kk];
-        const double un = DIM == 2 ? u0 * f.x + u1 * f.y : u0 * f.x;
-        if (!(un > 0.0)) continue;
-        const double xn = DIM == 2 ? f.x * x + f.y * y : f.x * x;
-        double te = (f.z - xn) / un;
-        if (te < 0.0) te = 0.0;
-        if (te < best) {
-          best = te;
-          kb = kk;
+#pragma unroll
+      for (int kk = 0; kk < NV; ++kk) {
+        const double un = DIM == 2 ? u0 * F[kk].x + u1 * F[kk].y : u0 * F[kk].x;
+        if (un > 0.0) {
+          const double xn = DIM == 2 ? F[kk].x * x + F[kk].y * y : F[kk].x * x;
+          double te = (F[kk].z - xn) / un;
+          if (te < 0.0) te = 0.0;
+          if (te < best) {
+            best = te;
+            kb = kk;
+          }
         }
       }
       if (kb < 0 || !(best < t)) {
@@ -650,18 +672,28 @@ __global__ void __launch_bounds__(256, 5) k_transport(Geo g, Params p, State st,
       }
       x = x + u0 * best;
       if (DIM == 2) y = y + u1 * best;
-      const int64_t l = l0 + kb;
-      const int nb = g.lnb[l];
+      double4 f = F[0];
+      int nb = nbr[0];
+#pragma unroll
+      for (int kk = 1; kk < NV; ++kk)
+        if (kb == kk) {
+          f = F[kk];
+          nb = nbr[kk];
+        }
       if (nb >= 0) {
-        const double r = g.ratio[l];
+        const double r = f.w;
         t = (t - best) * r;
         m = m * r;
         cell = nb;
+#pragma unroll
+        for (int kk = 0; kk < NV; ++kk) {
+          F[kk] = g.lfn[static_cast<int64_t>(cell) * NV + kk];
+          nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
+        }
         continue;
       }
       const int bf = -nb - 1;
       const int ty = g.btype[bf];
-      const double4 f = g.lfn[l];
       t = t - best;
       if (ty == kBcFarfield || ty == kBcOutflow) {
         exited = true;
@@ -779,58 +811,49 @@ __global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__
 // Per-cell tally of the retained (kept) particles after the re-sort, one
 // wavefront per cell over its contiguous range [off[c], off[c+1]):
 // S[c] = sum_k m_k Psi_k (the next step's W^p Omega, Eq. (24), and the kept
-// part of W^{p,+} Omega, Eq. (30)).  Lane-strided partial sums in a fixed
-// order, then one butterfly per component: no atomics.
+// part of W^{p,+} Omega, Eq. (30)).  With Pr != 1 also the raw moments
+// sum m u_a |u|^2 and sum m u_a u_b that give the heat flux of Eq. (5) once
+// the next step's U is known.  Lane-strided partial sums in a fixed order,
+// then one butterfly per value: no atomics.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_cell_tally(Geo g, Store s, const int64_t *__restrict__ off,
-                                                    double *__restrict__ S) {
+                                                    double *__restrict__ S, double *__restrict__ M, int raw) {
   constexpr int NW = DIM + 2;
   const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (c >= g.nc) return;
   const int64_t a = off[c], b = off[c + 1];
-  double v[NW];
+  double v[NW], r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < NW; ++q) v[q] = 0.0;
+#pragma unroll 4
   for (int64_t k = a + lane_id(); k < b; k += 64) {
     const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
-    const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
     v[0] += m;
     v[1] += m * u0;
     if (DIM == 2) v[2] += m * u1;
-    v[NW - 1] += m * en;
+    v[NW - 1] += m * (0.5 * q2);
+    if (raw) {
+      r[0] += m * u0 * q2;
+      r[1] += m * u1 * q2;
+      r[2] += m * u0 * u0;
+      r[3] += m * u0 * u1;
+      r[4] += m * u1 * u1;
+    }
   }
 #pragma unroll
   for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
+  if (raw) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = wave_sum(r[q]);
+  }
   if (lane_id() == 0) {
 #pragma unroll
     for (int q = 0; q < NW; ++q) S[c * NW + q] = v[q];
-  }
-}
-
-// Heat flux Q_i = sum_k m_k c_k |c_k|^2 / 2, c = u - U_i, of the retained set
-// (Eq. (5); only needed for the Shakhov sampler, Pr != 1); one wavefront per
-// cell over the sorted store.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_heat_flux(Geo g, Params p, Store s, const double *__restrict__ W,
-                                                   const int64_t *__restrict__ off, double *__restrict__ Q) {
-  constexpr int NW = DIM + 2;
-  const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (c >= g.nc) return;
-  const int64_t a = off[c], b = off[c + 1];
-  const Prim<DIM> U = prim<DIM>(W + c * NW, p.NR);
-  double v0 = 0.0, v1 = 0.0;
-  for (int64_t k = a + lane_id(); k < b; k += 64) {
-    const double cx = s.ux[k] - U.ux, cy = s.uy[k] - U.uy, cz = s.uz[k];
-    const double h = 0.5 * (cx * cx + cy * cy + cz * cz);
-    const double m = s.m[k];
-    v0 += m * cx * h;
-    v1 += m * cy * h;
-  }
-  v0 = wave_sum(v0);
-  v1 = wave_sum(v1);
-  if (lane_id() == 0) {
-    Q[2 * c] = v0;
-    Q[2 * c + 1] = v1;
+    if (raw) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) M[c * 5 + q] = r[q];
+    }
   }
 }
 
@@ -997,7 +1020,7 @@ __global__ void k_surface(Geo g, Params p, State st, int64_t step) {
   const double4 fl = g.lfn[l];
   const int fs = g.lface[l];
   const int f = fs >= 0 ? fs : ~fs;
-  const double s = fl.w;
+  const double s = g.lfs[l];
   double Fl[NW];
 #pragma unroll
   for (int q = 0; q < NW; ++q) Fl[q] = st.Fs[static_cast<int64_t>(f) * NW + q] / s;
@@ -1042,15 +1065,20 @@ __global__ void k_finish(Params p, State st, int64_t step) {
   template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);      \
   template __global__ void k_sample_match<D>(Geo, Params, State, Store, int64_t);                        \
   template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t, int64_t);             \
-  template __global__ void k_transport<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);        \
+  template __global__ void k_transport<D, 2 * D>(Geo, Params, State, Store, int64_t, int64_t, int64_t); \
   template __global__ void k_scatter<D>(Store, Store, const int *, int64_t *, int64_t, int64_t,         \
                                         const int64_t *);                                                \
-  template __global__ void k_heat_flux<D>(Geo, Params, Store, const double *, const int64_t *, double *); \
-  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *);                       \
+  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *, double *, int);       \
   template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
   template __global__ void k_update<D>(Geo, Params, State, int64_t);                                     \
   template __global__ void k_surface<D>(Geo, Params, State, int64_t);
 UGK_INST(1)
 UGK_INST(2)
+#define UGK_INST_NV(N) template __global__ void k_transport<2, N>(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+UGK_INST_NV(3)
+UGK_INST_NV(5)
+UGK_INST_NV(6)
+UGK_INST_NV(7)
+UGK_INST_NV(8)
 
 }  // namespace ugk
