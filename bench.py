@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# 2D transport: reads a particle record (x, y, u_x, u_y, u_z, m, pid, cell:
+# 60 B) and writes x, y, m (24 B), the cell (4 B) and the keep flag (4 B)
+TRANSPORT_BYTES_PER_PARTICLE = 92.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transport_cylinder_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2607_09552_amd", "csrc", "kernels.hip")
 
@@ -113,20 +116,21 @@ def main():
     s.step(a.warmup)
     torch.cuda.synchronize()
     s.profile(True)
-    n_upd = 0
+    work0 = s.work()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(a.steps):
-        s.step(1)
-        n_upd += s.counts()[1]["total"]
+    s.step(a.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    n_upd = s.work() - work0
     prof = s.profile_read()
     s.profile(False)
     print(f"# timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
     tr = prof["transport"]
     avg_ms = tr["ms"] / max(tr["launches"], 1)
-    bytes_per_launch = tr["bytes"] / max(tr["launches"], 1)
+    # algorithmic bytes of one launch: the byte model per particle times the
+    # particles one launch transports on average over the timed steps
+    bytes_per_launch = TRANSPORT_BYTES_PER_PARTICLE * n_upd / max(tr["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = traffic_per_launch()
     kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),

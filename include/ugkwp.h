@@ -121,6 +121,10 @@ int ugkwp_get_dt(ugkwp_ctx *ctx, double *dt);
  * be NULL. */
 int ugkwp_get_counts(ugkwp_ctx *ctx, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
                      int64_t *n_exited, int64_t *n_guard);
+/* Running sum over every committed step of the particles transported in it
+ * (the n_total of ugkwp_get_counts, summed): the work counter behind the
+ * particle-update rate.  Starts at 0 at init. */
+int ugkwp_get_work(ugkwp_ctx *ctx, int64_t *n_transported);
 /* Retained particles sorted by pid: pid = step << 44 | birth cell << 20 | j
  * (birth cell >= n_cells marks a boundary face), cell, mass, position
  * [n*dim], velocity [n*3].  Pointers may be NULL; *n is set even when

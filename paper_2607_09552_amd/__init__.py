@@ -21,7 +21,7 @@ BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
 # Every entry point declared in include/ugkwp.h.
 ABI_SYMBOLS = (
     "ugkwp_init", "ugkwp_step", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
-    "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_particles",
+    "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_last_error", "ugkwp_free",
 )
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_get_fields_device.argtypes = [vp, vp]
     L.ugkwp_get_dt.argtypes = [vp, dp]
     L.ugkwp_get_counts.argtypes = [vp, i32p, i64p, i64p, i64p, i64p, i64p]
+    L.ugkwp_get_work.argtypes = [vp, i64p]
     L.ugkwp_get_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp, i64p]
     L.ugkwp_set_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp]
     L.ugkwp_get_tally.argtypes = [vp, dp, dp]
@@ -170,6 +171,12 @@ class Solver:
         v = [C.c_int64() for _ in range(5)]
         self._check(load_library().ugkwp_get_counts(self.h, _ptr(cnt, C.c_int32), *[C.byref(x) for x in v]))
         return cnt, dict(total=v[0].value, new=v[1].value, removed=v[2].value, exited=v[3].value, guard=v[4].value)
+
+    def work(self):
+        """Particles transported, summed over every step done."""
+        n = C.c_int64()
+        self._check(load_library().ugkwp_get_work(self.h, C.byref(n)))
+        return n.value
 
     def particles(self):
         L = load_library()

@@ -13,6 +13,9 @@
 
 using namespace ugk;
 
+// steps enqueued between two host synchronizations
+constexpr int32_t kBatchSteps = 32;
+
 namespace {
 
 enum KernelId {
@@ -64,7 +67,9 @@ struct ugkwp_ctx {
   State S{};
   Store A{}, B{};
   int64_t cap = 0, n_ret = 0, step = 0;
-  int64_t last_total = 0, last_new = 0;
+  int64_t last_total = 0, last_new = 0, last_need = 0, last_need_new = 0;
+  int64_t est_total = 0, est_new = 0, est_kept = 0;  // byte-model estimates for the profiler
+  int64_t cover = 0, cover_new = 0;  // particles covered by the particle-parallel launches
   int64_t *scan_tmp = nullptr;   // block sums
   int64_t scan_tmp_n = 0;
   int64_t *pinned = nullptr;     // host pinned mailbox
@@ -440,11 +445,12 @@ int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
     c->scan_tmp_n = nblocks + 1;
   }
   ProfScope ps(c, kKScan, 12.0 * static_cast<double>(n));
-  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanBlock), 0, c->stream, in, n, out, c->scan_tmp);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanBlock), 0, c->stream, in, n, out, c->scan_tmp,
+                     c->S.halt);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, c->stream, c->scan_tmp, nblocks,
-                     c->scan_tmp + nblocks);
+                     c->scan_tmp + nblocks, c->S.halt);
   hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, c->stream, out, n, c->scan_tmp,
-                     c->scan_tmp + nblocks);
+                     c->scan_tmp + nblocks, c->S.halt);
   HIPCHK(hipGetLastError());
   return UGKWP_OK;
 }
@@ -492,6 +498,8 @@ int copy_store(ugkwp_ctx *c, const Store &from, const Store &to, int64_t n) {
 int ensure_capacity(ugkwp_ctx *c, int64_t need) {
   if (need <= c->cap) return UGKWP_OK;
   const int64_t ncap = std::max<int64_t>(need + need / 4 + 1024, c->cap + c->cap / 2);
+  if (ncap > (int64_t{1} << 31) - 256)
+    return set_err(c, UGKWP_EOVERFLOW, "particle store of %lld exceeds 2^31", (long long)ncap);
   Store A2{}, B2{};
   int rc = alloc_store(c, A2, ncap);
   if (!rc) rc = alloc_store(c, B2, ncap);
@@ -513,20 +521,36 @@ int ensure_capacity(ugkwp_ctx *c, int64_t need) {
   return UGKWP_OK;
 }
 
+void swap_buffers(ugkwp_ctx *c) {
+  std::swap(c->A, c->B);
+  std::swap(c->S.Sret, c->S.Sretn);
+  std::swap(c->S.roff, c->S.coff);
+  std::swap(c->S.Mraw, c->S.Mrawn);
+}
+
+// zero n 32-bit words with a kernel (graph-safe, unlike memset nodes)
+void zero32(ugkwp_ctx *c, void *p, int64_t words) {
+  hipLaunchKernelGGL(k_zero32, dim3(nblk(words, 256) > 1024 ? 1024 : nblk(words, 256)), dim3(256), 0, c->stream,
+                     static_cast<uint32_t *>(p), words);
+}
+
+// Enqueues one step on the stream; no host synchronization.  Every launch
+// size depends only on host-known constants (mesh sizes, capacity, grid
+// estimates); the particle counts live on the device.  The host swaps the
+// double-buffered pointers; after a halted batch it restores their parity.
 template <int DIM>
-int do_step(ugkwp_ctx *c) {
+int enqueue_step(ugkwp_ctx *c) {
   const int NW = DIM + 2;
   const Geo g = c->geo();
   State &S = c->S;
   const int64_t nc = c->nc, nb = c->nb;
-  // zero per-step accumulators
-  HIPCHK(hipMemsetAsync(S.Scol, 0, nc * NW * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
-  HIPCHK(hipMemsetAsync(S.wimp, 0, std::max<int64_t>(nb, 1) * 3 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.resid, 0, 3 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.cdsum, 0, sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
-  HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
+  zero32(c, S.Scol, nc * NW * 2);
+  zero32(c, S.count, nc);
+  zero32(c, S.wimp, std::max<int64_t>(nb, 1) * 3 * 2);
+  zero32(c, S.resid, 3 * 2);
+  zero32(c, S.cdsum, 2);
+  zero32(c, S.nghost, 2);
+  zero32(c, S.stats, kStatSlots * kStatN * 2);
   {
     ProfScope ps(c, kKCellPrep, 160.0 * nc);
     hipLaunchKernelGGL(k_cell_prep<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
@@ -537,70 +561,58 @@ int do_step(ugkwp_ctx *c) {
   }
   int rc = scan(c, S.ncount, nc + nb, S.noff);
   if (rc) return rc;
-  HIPCHK(hipGetLastError());
-  // one host sync per step: totals of the new sets and error flags
-  HIPCHK(hipMemcpyAsync(&c->pinned[0], S.noff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(&c->pinned[1], S.noff + nc + nb, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(&c->pinned[2], S.flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  if (c->prof) prof_harvest(c);
-  const int flags = static_cast<int>(c->pinned[2] & 0xffffffff);
-  if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state at step %lld", (long long)c->step);
-  if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking before step %lld", (long long)c->step);
-  if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
-  const int64_t n_cellnew = c->pinned[0];
-  const int64_t n_newall = c->pinned[1];
-  rc = ensure_capacity(c, c->n_ret + n_newall);
-  if (rc) return rc;
-  const int64_t n_max = c->n_ret + n_newall;
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, c->stream, g, S, c->cap, c->cover, c->cover_new);
   const double rec = DIM == 2 ? 60.0 : 52.0;  // bytes of one particle record
+  // particle-parallel grids cover c->cover particles (c->cover_new new ones);
+  // a step whose counts exceed them halts in k_check and is redone with
+  // larger grids.  Blocks past the step's count return at once.
+  const unsigned gcap = static_cast<unsigned>(nblk(c->cover, 256));
+  const unsigned gnew = static_cast<unsigned>(nblk(c->cover_new, 256));
   {
-    ProfScope ps(c, kKSampleCells, rec * n_cellnew);
-    if (n_cellnew > 0)
-      hipLaunchKernelGGL(k_sample_draw<DIM>, dim3(nblk(n_cellnew, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
-                         c->n_ret, n_cellnew, c->step);
+    ProfScope ps(c, kKSampleCells, rec * c->est_new);
+    hipLaunchKernelGGL(k_sample_draw<DIM>, dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, c->A, c->cap);
   }
   {
-    ProfScope ps(c, kKSampleMatch, 48.0 * n_cellnew + (8.0 * 2 * NW + 24.0) * nc);
+    ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
     hipLaunchKernelGGL(k_sample_match<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
-                       c->n_ret);
+                       c->cap);
   }
   if (nb > 0) {
-    ProfScope ps(c, kKSampleGhosts, rec * (n_newall - n_cellnew));
-    hipLaunchKernelGGL(k_sample_ghosts<DIM>, dim3(nblk(nb * 64, 256)), dim3(256), 0, c->stream, g, c->P, S,
-                       c->A, c->n_ret + n_cellnew, c->step);
+    ProfScope ps(c, kKSampleGhosts, 0.0);
+    hipLaunchKernelGGL(k_sample_ghosts<DIM>, dim3(nblk(nb * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+                       c->cap);
   }
   {
-    // transport reads a record and writes x, (y), m, cell and the rank
+    // transport reads a record and writes x, (y), m, cell and the keep flag
     const double wr = DIM == 2 ? 32.0 : 24.0;
-    ProfScope ps(c, kKTransport, (rec + wr) * (c->n_ret + n_cellnew));
-    const dim3 gr(nblk(n_max, 256)), bl(256);
+    ProfScope ps(c, kKTransport, (rec + wr) * c->est_total);
+    const dim3 gr(gcap), bl(256);
     if (DIM == 1) {
-      hipLaunchKernelGGL((k_transport<DIM, 2>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step);
+      hipLaunchKernelGGL((k_transport<DIM, 2>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap);
     } else {
       switch (c->NV) {
-        case 3: hipLaunchKernelGGL((k_transport<2, 3>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
-        case 4: hipLaunchKernelGGL((k_transport<2, 4>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
-        case 5: hipLaunchKernelGGL((k_transport<2, 5>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
-        case 6: hipLaunchKernelGGL((k_transport<2, 6>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
-        case 7: hipLaunchKernelGGL((k_transport<2, 7>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
-        default: hipLaunchKernelGGL((k_transport<2, 8>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->n_ret, n_cellnew, c->step); break;
+        case 3: hipLaunchKernelGGL((k_transport<2, 3>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        case 4: hipLaunchKernelGGL((k_transport<2, 4>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        case 5: hipLaunchKernelGGL((k_transport<2, 5>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        case 6: hipLaunchKernelGGL((k_transport<2, 6>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        case 7: hipLaunchKernelGGL((k_transport<2, 7>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        default: hipLaunchKernelGGL((k_transport<2, 8>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
       }
     }
   }
   rc = scan(c, S.count, nc, S.coff);
   if (rc) return rc;
-  HIPCHK(hipMemcpyAsync(S.cursor, S.coff, nc * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_copy64, dim3(nblk(nc, 256) > 1024 ? 1024 : nblk(nc, 256)), dim3(256), 0, c->stream, S.cursor,
+                     S.coff, nc);
   {
-    ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->n_ret);
-    hipLaunchKernelGGL(k_scatter<DIM>, dim3(nblk(n_max, 256)), dim3(256), 0, c->stream, c->A, c->B, S.rank,
-                       S.cursor, c->n_ret, n_cellnew, S.nghost);
+    ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->est_kept);
+    hipLaunchKernelGGL(k_scatter<DIM>, dim3(gcap), dim3(256), 0, c->stream, S, c->A, c->B, c->cap);
   }
   {
     const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
-    ProfScope ps(c, kKCellTally, rd * c->n_ret + (16.0 + 8.0 * NW) * nc);
+    ProfScope ps(c, kKCellTally, rd * c->est_kept + (16.0 + 8.0 * NW) * nc);
     hipLaunchKernelGGL(k_cell_tally<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->B, S.coff,
-                       S.Sretn, S.Mrawn, c->P.Pr != 1.0 ? 1 : 0);
+                       S.Sretn, S.Mrawn, c->P.Pr != 1.0 ? 1 : 0, S.halt);
   }
   {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
@@ -608,27 +620,15 @@ int do_step(ugkwp_ctx *c) {
   }
   {
     ProfScope ps(c, kKUpdate, 350.0 * nc);
-    hipLaunchKernelGGL(k_update<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S, c->step);
+    hipLaunchKernelGGL(k_update<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
   }
   if (c->nwall > 0) {
     ProfScope ps(c, kKSurface, 150.0 * c->nwall);
-    hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S, c->step);
+    hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S);
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, c->stream, c->P, S, c->step);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, c->stream, c->P, S, nc);
   HIPCHK(hipGetLastError());
-  std::swap(c->A, c->B);
-  std::swap(S.Sret, S.Sretn);
-  std::swap(S.roff, S.coff);
-  std::swap(S.Mraw, S.Mrawn);
-  // the retained count is needed for the next launch sizes
-  HIPCHK(hipMemcpyAsync(&c->pinned[3], S.roff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(&c->pinned[4], S.nghost, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  const int64_t prev_ret = c->n_ret;
-  c->n_ret = c->pinned[3];
-  c->last_new = n_cellnew + c->pinned[4];
-  c->last_total = prev_ret + c->last_new;
-  c->step += 1;
+  swap_buffers(c);
   return UGKWP_OK;
 }
 
@@ -639,6 +639,20 @@ int check_flags(ugkwp_ctx *c) {
   if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state");
   if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking");
   if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+  return UGKWP_OK;
+}
+
+// Reads the retained count and the last step's counts (host sync).
+int sync_counts(ugkwp_ctx *c) {
+  int64_t info[kInfoN];
+  HIPCHK(hipMemcpyAsync(&c->pinned[4], c->S.roff + c->nc, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(info, c->S.info, sizeof info, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->n_ret = c->pinned[4];
+  c->last_total = info[kInfoTotal];
+  c->last_new = info[kInfoNew];
+  c->last_need = info[kInfoNeed];
+  c->last_need_new = info[kInfoNeedNew];
   return UGKWP_OK;
 }
 
@@ -751,8 +765,10 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
       dalloc(c, &S.resid, 3) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
       dalloc(c, &S.wlast, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.wsum, std::max<int64_t>(c->nwall, 1) * 3) ||
       dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, 1) || dalloc(c, &S.scal, kScalN) ||
-      dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1))
+      dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1) || dalloc(c, &S.halt, 1) ||
+      dalloc(c, &S.dstep, 1) || dalloc(c, &S.info, kInfoN))
     return set_err(c, UGKWP_ENOMEM, "device allocation failed");
+  S.nc_scatter = nc;
   HIPCHK(hipMemsetAsync(S.Sret, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sm, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
@@ -769,6 +785,9 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipMemsetAsync(S.scal, 0, kScalN * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.halt, 0, sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.dstep, 0, sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.info, 0, kInfoN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
   // rho_prev = initial density
   {
@@ -808,15 +827,72 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   return UGKWP_OK;
 }
 
+// Sizes the store and the particle-parallel grids for steps whose
+// pre-transport set is about `need` particles, `need_new` of them new.
+int plan_launches(ugkwp_ctx *c, int64_t need, int64_t need_new) {
+  int rc = ensure_capacity(c, need);
+  if (rc) return rc;
+  c->cover = std::min<int64_t>(c->cap, need + need / 8 + 65536);
+  c->cover_new = need_new + need_new / 8 + 16384;
+  c->est_total = std::max<int64_t>(c->last_total, 1);
+  c->est_new = std::max<int64_t>(c->last_new, 1);
+  c->est_kept = std::max<int64_t>(c->n_ret, 1);
+  return UGKWP_OK;
+}
+
 int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
   if (!c || n_steps < 0) return UGKWP_EINVAL;
   if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
-  for (int32_t k = 0; k < n_steps; ++k) {
-    if (c->step >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
-    const int rc = c->dim == 1 ? do_step<1>(c) : do_step<2>(c);
+  if (c->step + n_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+  int rc = sync_counts(c);
+  if (rc) return rc;
+  // the last pre-transport set with margin for growth over a batch
+  rc = plan_launches(c, std::max(c->last_need, c->n_ret + std::max<int64_t>(2 * c->last_new, 4096) + c->last_new / 2),
+                     std::max<int64_t>(c->last_need_new, 2 * c->last_new));
+  if (rc) return rc;
+  int32_t done = 0;
+  while (done < n_steps) {
+    const int32_t batch = std::min<int32_t>(n_steps - done, kBatchSteps);
+    const int64_t step0 = c->step;
+    for (int32_t k = 0; k < batch; ++k) {
+      rc = c->dim == 1 ? enqueue_step<1>(c) : enqueue_step<2>(c);
+      if (rc) return rc;
+    }
+    // one host synchronization per batch
+    HIPCHK(hipMemcpyAsync(&c->pinned[0], c->S.dstep, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->pinned[1], c->S.halt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->pinned[2], c->S.flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->prof) prof_harvest(c);
+    const int64_t committed = c->pinned[0] - step0;
+    if ((batch - committed) % 2 != 0) swap_buffers(c);  // halted steps did not advance the buffers
+    c->step = c->pinned[0];
+    done += static_cast<int32_t>(committed);
+    const int halt = static_cast<int>(c->pinned[1] & 0xffffffff), flags = static_cast<int>(c->pinned[2] & 0xffffffff);
+    rc = sync_counts(c);
+    if (rc) return rc;
+    if (halt && (flags & ~(kFlagCapacity | kFlagGrid)) == 0) {
+      // the step was not committed: grow the store or the grids to its
+      // recorded bounds and resume from it
+      rc = plan_launches(c, c->last_need + c->last_need / 4 + 4096, c->last_need_new + c->last_need_new / 4);
+      if (rc) return rc;
+      HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+      HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+      continue;
+    }
+    if (halt) {
+      if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state at step %lld", (long long)c->step);
+      if (flags & kFlagRunaway)
+        return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking at step %lld", (long long)(c->step - 1));
+      if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+      return set_err(c, UGKWP_EDEVICE, "step halted (flags %d)", flags);
+    }
+    // room for the next batch
+    rc = plan_launches(c, std::max(c->last_need, c->n_ret + std::max<int64_t>(2 * c->last_new, 4096) + c->last_new / 2),
+                       std::max<int64_t>(c->last_need_new, 2 * c->last_new));
     if (rc) return rc;
   }
-  return check_flags(c);
+  return UGKWP_OK;
 }
 
 int ugkwp_residual(ugkwp_ctx *c, double *r_inst, double *r_avg, int64_t *step) {
@@ -898,6 +974,15 @@ int ugkwp_get_counts(ugkwp_ctx *c, int32_t *count, int64_t *n_total, int64_t *n_
   if (n_removed) *n_removed = st[kStatRemoved];
   if (n_exited) *n_exited = st[kStatExited];
   if (n_guard) *n_guard = st[kStatGuard];
+  return UGKWP_OK;
+}
+
+int ugkwp_get_work(ugkwp_ctx *c, int64_t *n_transported) {
+  if (!c || !n_transported) return UGKWP_EINVAL;
+  int64_t info[kInfoN];
+  HIPCHK(hipMemcpyAsync(info, c->S.info, sizeof info, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *n_transported = info[kInfoSumTotal];
   return UGKWP_OK;
 }
 
@@ -1018,6 +1103,7 @@ int ugkwp_set_fields(ugkwp_ctx *c, const double *W) {
 
 int ugkwp_set_step(ugkwp_ctx *c, int64_t step) {
   if (!c || step < 0 || step >= (1 << 20)) return UGKWP_EINVAL;
+  HIPCHK(hipMemcpy(c->S.dstep, &step, sizeof(int64_t), hipMemcpyHostToDevice));
   c->step = step;
   return UGKWP_OK;
 }

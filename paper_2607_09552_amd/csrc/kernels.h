@@ -13,7 +13,7 @@ constexpr int kScanBlock = 1024;
 constexpr int kMaxCross = 10000;
 
 enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4 };
-enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4 };
+enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16 };
 enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
 // Step statistics are spread over kStatSlots copies (slot = block id mod
 // kStatSlots) so that the per-wave counter updates do not serialize on one
@@ -74,6 +74,7 @@ struct State {
   int64_t *coff;                        // [nc + 1] exclusive scan of count
   int *rank;                            // [cap] 0 kept, -1 removed or left
   int64_t *cursor;                      // [nc] slot cursor of the scatter
+  int64_t nc_scatter;                   // number of cells (for kernels without Geo)
   double *Fs;                           // [nf*NW] time-averaged face flux times s_j
   double *rho_prev, *rho_sum, *rho_mean_prev;
   double *resid;                        // [3] residual sums
@@ -83,7 +84,11 @@ struct State {
   double *scal;                         // [kScalN]
   int64_t *stats;                       // [kStatSlots * kStatN]
   int *flags;
+  int *halt;                            // nonzero: every kernel of later steps returns at once
+  int64_t *dstep;                       // step counter (keys the random numbers)
+  int64_t *info;                        // [kInfoN] counts of the last committed step and running sums
 };
+enum : int { kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, kInfoN };
 
 struct Store {
   double *x, *y, *ux, *uy, *uz, *m;
@@ -95,19 +100,21 @@ template <int DIM> __global__ void k_init_dt(Geo, Params, const double *, double
 __global__ void k_init_ratio(Geo, const double *, double4 *);
 template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
 template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
-__global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *);
-__global__ void k_scan_sums(int64_t *, int64_t, int64_t *);
-__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *);
-template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+__global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *, const int *);
+__global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
+__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *);
+template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_sample_match(Geo, Params, State, Store, int64_t);
-template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t, int64_t);
-template <int DIM, int NV> __global__ void k_transport(Geo, Params, State, Store, int64_t, int64_t, int64_t);
-template <int DIM>
-__global__ void k_scatter(Store, Store, const int *, int64_t *, int64_t, int64_t, const int64_t *);
-template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *, double *, int);
+template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t);
+template <int DIM, int NV> __global__ void k_transport(Geo, Params, State, Store, int64_t);
+template <int DIM> __global__ void k_scatter(State, Store, Store, int64_t);
+template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *, double *, int, const int *);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
-template <int DIM> __global__ void k_update(Geo, Params, State, int64_t);
-template <int DIM> __global__ void k_surface(Geo, Params, State, int64_t);
+template <int DIM> __global__ void k_update(Geo, Params, State);
+template <int DIM> __global__ void k_surface(Geo, Params, State);
 __global__ void k_finish(Params, State, int64_t);
+__global__ void k_check(Geo, State, int64_t, int64_t, int64_t);
+__global__ void k_zero32(uint32_t *, int64_t);
+__global__ void k_copy64(int64_t *, const int64_t *, int64_t);
 
 }  // namespace ugk

@@ -128,7 +128,7 @@ template <int DIM>
 __global__ void k_cell_prep(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= g.nc) return;
+  if (i >= g.nc || *st.halt) return;
   const double *W = st.W + i * NW;
   const Prim<DIM> s = prim<DIM>(W, p.NR);
   int N = 0;
@@ -193,7 +193,7 @@ template <int DIM>
 __global__ void k_ghost_prep(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   const int64_t b = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (b >= g.nb) return;
+  if (b >= g.nb || *st.halt) return;
   const int i = g.bcell[b];
   const int ty = g.btype[b];
   const double4 f = g.lfn[static_cast<int64_t>(i) * g.NV + g.bk[b]];
@@ -299,8 +299,9 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64
 }
 
 __global__ void k_scan_blocks(const int *__restrict__ in, int64_t n, int64_t *__restrict__ out,
-                              int64_t *__restrict__ bsum) {
+                              int64_t *__restrict__ bsum, const int *__restrict__ halt) {
   __shared__ int64_t sh[kScanBlock / 64 + 1];
+  if (*halt) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
   const int64_t v = i < n ? in[i] : 0;
   int64_t total;
@@ -309,8 +310,10 @@ __global__ void k_scan_blocks(const int *__restrict__ in, int64_t n, int64_t *__
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total) {
+__global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total,
+                            const int *__restrict__ halt) {
   __shared__ int64_t sh[kScanBlock / 64 + 1];
+  if (*halt) return;
   int64_t carry = 0;
   for (int64_t base = 0; base < nb; base += kScanBlock) {
     const int64_t i = base + threadIdx.x;
@@ -324,7 +327,8 @@ __global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__r
 }
 
 __global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ bsum,
-                           const int64_t *__restrict__ total) {
+                           const int64_t *__restrict__ total, const int *__restrict__ halt) {
+  if (*halt) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
   if (i < n) out[i] += bsum[blockIdx.x];
   if (i == n) out[n] = *total;
@@ -408,11 +412,9 @@ __device__ __forceinline__ void sample_deviation(const Params &p, uint64_t pid, 
 // scan of the counts), j = k - noff[i].  Writes the position, the raw
 // deviation z (in the velocity slots), pid, cell and mass.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, Store out, int64_t n_ret,
-                                                     int64_t n_cellnew, int64_t step) {
+__device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, const State &st, const Store &out,
+                                                int64_t n_ret, int64_t step, int64_t k) {
   constexpr int NW = DIM + 2;
-  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (k >= n_cellnew) return;
   int64_t lo = 0, hi = g.nc;
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) >> 1;
@@ -450,18 +452,27 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
   out.m[o] = st.mnew[i];
 }
 
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, Store out, int64_t cap) {
+  if (*st.halt) return;
+  const int64_t n_ret = st.roff[g.nc], n_cellnew = st.noff[g.nc], step = *st.dstep;
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (k < n_cellnew && n_ret + k < cap) sample_draw_one<DIM>(g, p, st, out, n_ret, step, k);
+}
+
 // Moment-matching pass: one wavefront per cell over its new particles.  For
 // N >= 2 the deviations are shifted to zero mean and scaled so that the set
 // carries exactly the momentum and thermal energy of W^hp (Eq. (25)):
 // u = U^h + sqrt(R T^h) ((z - zbar) alpha), alpha = sqrt(3 N / sum |z - zbar|^2).
 // Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, Store out, int64_t n_ret) {
+__global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, Store out, int64_t cap) {
   constexpr int NW = DIM + 2;
   const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (i >= g.nc) return;  // whole wavefront
+  if (i >= g.nc || *st.halt) return;  // whole wavefront
+  const int64_t n_ret = st.roff[g.nc];
   const int lane = lane_id();
-  const int N = st.ncount[i];
+  const int N = n_ret + st.noff[i] + st.ncount[i] <= cap ? st.ncount[i] : 0;
   double snew[NW];
 #pragma unroll
   for (int q = 0; q < NW; ++q) snew[q] = 0.0;
@@ -517,11 +528,11 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
 // at the crossing point (tangential position wrapped along the face) with the
 // remaining time.  Entering particles are compacted by ballot and appended.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st, Store out, int64_t gbase,
-                                                       int64_t step) {
+__global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st, Store out, int64_t cap) {
   constexpr int NW = DIM + 2;
   const int64_t b = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (b >= g.nb) return;
+  if (b >= g.nb || *st.halt) return;
+  const int64_t gbase = st.roff[g.nc] + st.noff[g.nc], step = *st.dstep;
   const int N = st.ncount[g.nc + b];
   if (N == 0) return;
   const int lane = lane_id();
@@ -575,7 +586,7 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
     if (lane == 0 && mask) pos = atomicAdd(reinterpret_cast<unsigned long long *>(st.nghost),
                                            static_cast<unsigned long long>(__popcll(mask)));
     pos = __shfl(pos, 0, 64);
-    if (enter) {
+    if (enter && gbase + pos + popc_below(mask) < cap) {
       const int64_t r = pos + popc_below(mask);
       const int64_t k = gbase + r;
       out.x[k] = px;
@@ -603,12 +614,10 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
 // step's W^p Omega and counts over the kept (non-collided) ones.
 // ---------------------------------------------------------------------------
 template <int DIM, int NV>
-__global__ void __launch_bounds__(256, 4) k_transport(Geo g, Params p, State st, Store s, int64_t n_ret,
-                                                      int64_t n_cellnew, int64_t step) {
+__device__ __forceinline__ void transport_one(const Geo &g, const Params &p, const State &st, const Store &s,
+                                              int64_t n_ret, int64_t gbase, int64_t n_total, int64_t step,
+                                              int64_t k) {
   constexpr int NW = DIM + 2;
-  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t gbase = n_ret + n_cellnew;
-  const int64_t n_total = gbase + *st.nghost;
   const bool active = k < n_total;
   int cell = -1;
   bool exited = false, collide = false;
@@ -778,26 +787,42 @@ __global__ void __launch_bounds__(256, 4) k_transport(Geo g, Params p, State st,
   }
 }
 
+template <int DIM, int NV>
+__global__ void __launch_bounds__(256, 4) k_transport(Geo g, Params p, State st, Store s, int64_t cap) {
+  if (*st.halt) return;
+  const int64_t n_ret = st.roff[g.nc];
+  const int64_t gbase = n_ret + st.noff[g.nc];
+  const int64_t nt = gbase + *st.nghost;
+  const int64_t n_total = nt < cap ? nt : cap;
+  const int64_t step = *st.dstep;
+  // the grid covers the store capacity, which bounds every step's set
+  const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
+  if (base >= n_total) return;  // block-uniform: whole wavefronts take part in the grouping
+  transport_one<DIM, NV>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
+}
+
 // Re-sort (counting sort, scatter pass): cursor[c] starts at the exclusive
 // scan of the kept counts; each wavefront claims contiguous slots for its
 // lanes of equal destination with one atomic per group, all groups of the
 // wave in the same instruction.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__restrict__ keep,
-                                                 int64_t *__restrict__ cursor, int64_t n_ret, int64_t n_cellnew,
-                                                 const int64_t *__restrict__ nghost) {
-  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t n_total = n_ret + n_cellnew + *nghost;
-  const bool live = k < n_total && keep[k] >= 0;
+__global__ void __launch_bounds__(256) k_scatter(State st, Store a, Store b, int64_t cap) {
+  if (*st.halt) return;
+  const int64_t nt = st.roff[st.nc_scatter] + st.noff[st.nc_scatter] + *st.nghost;
+  const int64_t n_total = nt < cap ? nt : cap;
+  const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
+  if (base >= n_total) return;  // block-uniform
+  const int64_t k = base + threadIdx.x;
+  const bool live = k < n_total && st.rank[k] >= 0;
   const int c = live ? a.cell[k] : -1;
   int leader;
   const uint64_t grp = wave_group(c, leader);
-  unsigned long long base = 0;
+  unsigned long long bs = 0;
   if (live && lane_id() == leader)
-    base = atomicAdd(reinterpret_cast<unsigned long long *>(&cursor[c]), static_cast<unsigned long long>(__popcll(grp)));
-  base = __shfl(base, leader >= 0 ? leader : lane_id(), 64);
+    bs = atomicAdd(reinterpret_cast<unsigned long long *>(&st.cursor[c]), static_cast<unsigned long long>(__popcll(grp)));
+  bs = __shfl(bs, leader >= 0 ? leader : lane_id(), 64);
   if (!live) return;
-  const int64_t d = static_cast<int64_t>(base) + popc_below(grp);
+  const int64_t d = static_cast<int64_t>(bs) + popc_below(grp);
   b.x[d] = a.x[k];
   if (DIM == 2) b.y[d] = a.y[k];
   b.ux[d] = a.ux[k];
@@ -817,10 +842,11 @@ __global__ void __launch_bounds__(256) k_scatter(Store a, Store b, const int *__
 // then one butterfly per value: no atomics.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_cell_tally(Geo g, Store s, const int64_t *__restrict__ off,
-                                                    double *__restrict__ S, double *__restrict__ M, int raw) {
+                                                    double *__restrict__ S, double *__restrict__ M, int raw,
+                                                    const int *__restrict__ halt) {
   constexpr int NW = DIM + 2;
   const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (c >= g.nc) return;
+  if (c >= g.nc || *halt) return;
   const int64_t a = off[c], b = off[c + 1];
   double v[NW], r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -865,7 +891,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   const int64_t fi = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (fi >= g.nf) return;
+  if (fi >= g.nf || *st.halt) return;
   const int K = p.K;
   const int L = g.fL[fi], R = g.fR[fi];
   const double2 n = g.fn[fi];
@@ -937,8 +963,10 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
 // Also the residual sums and the running mean of the density.
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64_t step) {
+__global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
+  if (*st.halt) return;
+  const int64_t step = *st.dstep;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   double r[3] = {0.0, 0.0, 0.0};
   bool guarded = false;
@@ -1010,10 +1038,11 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64
 // a10: wall pressure, shear and heat flux (wave + particle impulses per unit
 // area and time), their running sum and EMA (2/1001), and the drag sum.
 template <int DIM>
-__global__ void k_surface(Geo g, Params p, State st, int64_t step) {
+__global__ void k_surface(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   const int64_t w = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (w >= g.nwall) return;
+  if (w >= g.nwall || *st.halt) return;
+  const int64_t step = *st.dstep;
   const int b = g.wall_b[w];
   const int i = g.bcell[b];
   const int64_t l = static_cast<int64_t>(i) * g.NV + g.bk[b];
@@ -1043,9 +1072,12 @@ __global__ void k_surface(Geo g, Params p, State st, int64_t step) {
   }
 }
 
-// scalar bookkeeping after a step: residuals, C_d (last, sum, EMA)
-__global__ void k_finish(Params p, State st, int64_t step) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// scalar bookkeeping after a step: residuals, C_d (last, sum, EMA), the
+// step's particle counts, then the step counter advances (the step is
+// committed).  A runaway track halts later steps.
+__global__ void k_finish(Params p, State st, int64_t nc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *st.halt) return;
+  const int64_t step = *st.dstep;
   st.scal[kScalRinst] = sqrt(st.resid[0] / st.resid[1]) / p.rho_inf;
   st.scal[kScalRavg] = sqrt(st.resid[2] / st.resid[1]) / p.rho_inf;
   const double cd = *st.cdsum / (0.5 * p.rho_inf * p.U_inf * p.U_inf * p.L_ref);
@@ -1053,6 +1085,39 @@ __global__ void k_finish(Params p, State st, int64_t step) {
   st.scal[kScalCdLast] = cd;
   st.scal[kScalCdSum] += cd;
   st.scal[kScalCdEma] = step == 0 ? cd : a * cd + (1.0 - a) * st.scal[kScalCdEma];
+  const int64_t nnew = st.noff[nc] + *st.nghost;
+  const int64_t ntot = st.roff[nc] + nnew;
+  st.info[kInfoTotal] = ntot;
+  st.info[kInfoNew] = nnew;
+  st.info[kInfoSumTotal] += ntot;
+  *st.dstep = step + 1;
+  if (*st.flags & kFlagRunaway) *st.halt = 1;
+}
+
+// After the count scan, before anything of the step is modified: halt if a
+// cell state was invalid, a cell asked for more than 2^20 particles, the
+// pre-transport set would not fit the store, or the particle-parallel launches
+// (sized on the host from earlier counts) would not cover it.  The bounds are
+// recorded so the host can grow the store or the grids and redo this step.
+__global__ void k_check(Geo g, State st, int64_t cap, int64_t cover, int64_t cover_new) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *st.halt) return;
+  const int64_t need = st.roff[g.nc] + st.noff[g.nc + g.nb];
+  const int64_t nnew = st.noff[g.nc];
+  st.info[kInfoNeed] = need;
+  st.info[kInfoNeedNew] = nnew;
+  if (need > cap) *st.flags |= kFlagCapacity;
+  if (need > cover || nnew > cover_new) *st.flags |= kFlagGrid;
+  if (*st.flags) *st.halt = 1;
+}
+
+__global__ void k_zero32(uint32_t *__restrict__ p, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+__global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ src, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,19 +1127,19 @@ __global__ void k_finish(Params p, State st, int64_t step) {
   template __global__ void k_init_dt<D>(Geo, Params, const double *, double *, int *);                  \
   template __global__ void k_cell_prep<D>(Geo, Params, State);                                           \
   template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
-  template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t, int64_t, int64_t);      \
+  template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t);                          \
   template __global__ void k_sample_match<D>(Geo, Params, State, Store, int64_t);                        \
-  template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t, int64_t);             \
-  template __global__ void k_transport<D, 2 * D>(Geo, Params, State, Store, int64_t, int64_t, int64_t); \
-  template __global__ void k_scatter<D>(Store, Store, const int *, int64_t *, int64_t, int64_t,         \
-                                        const int64_t *);                                                \
-  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *, double *, int);       \
+  template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t);                      \
+  template __global__ void k_transport<D, 2 * D>(Geo, Params, State, Store, int64_t);                   \
+  template __global__ void k_scatter<D>(State, Store, Store, int64_t);                                    \
+  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *, double *, int,         \
+                                           const int *);                                                 \
   template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
-  template __global__ void k_update<D>(Geo, Params, State, int64_t);                                     \
-  template __global__ void k_surface<D>(Geo, Params, State, int64_t);
+  template __global__ void k_update<D>(Geo, Params, State);                                              \
+  template __global__ void k_surface<D>(Geo, Params, State);
 UGK_INST(1)
 UGK_INST(2)
-#define UGK_INST_NV(N) template __global__ void k_transport<2, N>(Geo, Params, State, Store, int64_t, int64_t, int64_t);
+#define UGK_INST_NV(N) template __global__ void k_transport<2, N>(Geo, Params, State, Store, int64_t);
 UGK_INST_NV(3)
 UGK_INST_NV(5)
 UGK_INST_NV(6)

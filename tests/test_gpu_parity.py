@@ -208,3 +208,37 @@ def test_cylinder_full_size_sampled_steps():
     w = bench.workload()
     run_pair(w, [1, 2])
     common_state_steps(w, [2])
+
+
+def test_capacity_growth_resumes_mid_batch():
+    """A store far too small for the particle count: a step that does not fit
+    is halted before it modifies anything, the store grows and the step is
+    redone; results match the oracle as if nothing happened."""
+    w = wl.shock1d()
+    g = _solver(w, particle_capacity=64)
+    r = oracle.Oracle(w)
+    r.vol = cell_volumes(w)
+    g.step(40)
+    r.step(40)
+    compare(g, r, "after growth", TOL)
+    assert g.residual()[2] == 40
+
+
+def test_work_counter_sums_step_totals():
+    """The running transported-particle count equals the sum of the per-step
+    totals, whether steps are taken one at a time or in one batched call."""
+    w = wl.shock1d()
+    g1, g2 = _solver(w), _solver(w)
+    s = 0
+    for _ in range(12):
+        g1.step(1)
+        s += g1.counts()[1]["total"]
+    g2.step(12)
+    assert g1.work() == s
+    assert g2.work() == s
+    r = oracle.Oracle(w)
+    t = 0
+    for _ in range(12):
+        r.step(1)
+        t += r.counts()[1]["total"]
+    assert t == s
