@@ -20,11 +20,12 @@ namespace {
 
 enum KernelId {
   kKInitDt, kKCellPrep, kKGhostPrep, kKScan, kKUnused, kKSampleCells, kKSampleGhosts, kKTransport,
-  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKSampleMatch, kKCount
+  kKFaceFlux, kKUpdate, kKSurface, kKFinish, kKScatter, kKCellTally, kKSampleMatch, kKSampleShakhov, kKCount
 };
 const char *kKernelNames[kKCount] = {"init_dt",   "cell_prep", "ghost_prep", "scan",      "unused",
                                      "sample_draw", "sample_ghosts", "transport", "face_flux", "update",
-                                     "surface",   "finish",    "scatter",   "cell_tally", "sample_match"};
+                                     "surface",   "finish",    "scatter",   "cell_tally", "sample_match",
+                                     "sample_shakhov"};
 
 struct ProfRec {
   int id;
@@ -528,11 +529,21 @@ void swap_buffers(ugkwp_ctx *c) {
   std::swap(c->S.Mraw, c->S.Mrawn);
 }
 
-// zero n 32-bit words with a kernel (graph-safe, unlike memset nodes)
-void zero32(ugkwp_ctx *c, void *p, int64_t words) {
-  hipLaunchKernelGGL(k_zero32, dim3(nblk(words, 256) > 1024 ? 1024 : nblk(words, 256)), dim3(256), 0, c->stream,
-                     static_cast<uint32_t *>(p), words);
-}
+// Collects buffers to clear with one k_zero_many launch.
+struct Zeroer {
+  ZeroList L{};
+  int64_t total = 0;
+  void add(void *p, int64_t words) {
+    L.p[L.count] = static_cast<uint32_t *>(p);
+    L.n[L.count] = words;
+    ++L.count;
+    total = std::max(total, words);
+  }
+  void launch(ugkwp_ctx *c) {
+    hipLaunchKernelGGL(k_zero_many, dim3(std::min<unsigned>(nblk(total, 256), 1024u)), dim3(256), 0, c->stream, L,
+                       c->S.halt);
+  }
+};
 
 // Enqueues one step on the stream; no host synchronization.  Every launch
 // size depends only on host-known constants (mesh sizes, capacity, grid
@@ -544,13 +555,17 @@ int enqueue_step(ugkwp_ctx *c) {
   const Geo g = c->geo();
   State &S = c->S;
   const int64_t nc = c->nc, nb = c->nb;
-  zero32(c, S.Scol, nc * NW * 2);
-  zero32(c, S.count, nc);
-  zero32(c, S.wimp, std::max<int64_t>(nb, 1) * 3 * 2);
-  zero32(c, S.resid, 3 * 2);
-  zero32(c, S.cdsum, 2);
-  zero32(c, S.nghost, 2);
-  zero32(c, S.stats, kStatSlots * kStatN * 2);
+  {
+    Zeroer z;
+    z.add(S.Scol, nc * NW * 2);
+    z.add(S.count, nc);
+    z.add(S.wimp, std::max<int64_t>(nb, 1) * 3 * 2);
+    z.add(S.resid, 3 * 2);
+    z.add(S.cdsum, 2);
+    z.add(S.nghost, 2);
+    z.add(S.stats, kStatSlots * kStatN * 2);
+    z.launch(c);
+  }
   {
     ProfScope ps(c, kKCellPrep, 160.0 * nc);
     hipLaunchKernelGGL(k_cell_prep<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
@@ -571,6 +586,10 @@ int enqueue_step(ugkwp_ctx *c) {
   {
     ProfScope ps(c, kKSampleCells, rec * c->est_new);
     hipLaunchKernelGGL(k_sample_draw<DIM>, dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, c->A, c->cap);
+  }
+  if (c->P.Pr != 1.0) {
+    ProfScope ps(c, kKSampleShakhov, 40.0 * c->est_new);
+    hipLaunchKernelGGL(k_sample_shakhov<DIM>, dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, c->A, c->cap);
   }
   {
     ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
@@ -756,7 +775,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   const size_t ncw = nc * nw, nbw = std::max<int64_t>(nb, 1) * nw;
   if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.tdt, nc) || dalloc(c, &S.E, nc) ||
       dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) || dalloc(c, &S.Sm, ncw) ||
-      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.Q, nc * 2) || dalloc(c, &S.Mraw, nc * 5) || dalloc(c, &S.Mrawn, nc * 5) || dalloc(c, &S.ncount, nc + nb) ||
+      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.ar, nc * kArN) || dalloc(c, &S.Mraw, nc * 5) || dalloc(c, &S.Mrawn, nc * 5) || dalloc(c, &S.ncount, nc + nb) ||
       dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
       dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, std::max<int64_t>(nb, 1)) ||
       dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
@@ -774,7 +793,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Scol, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.roff, 0, (nc + 1) * sizeof(int64_t), c->stream));
-  HIPCHK(hipMemsetAsync(S.Q, 0, nc * 2 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.ar, 0, nc * kArN * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Mraw, 0, nc * 5 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_sum, 0, nc * sizeof(double), c->stream));
@@ -1072,22 +1091,24 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     cnt[C[j]]++;
   }
   const Store &s = c->A;
+  const hipMemcpyKind h2d = hipMemcpyHostToDevice;
   if (n > 0) {
-    HIPCHK(hipMemcpy(s.pid, P.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.cell, C.data(), n * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.x, X.data(), n * 8, hipMemcpyHostToDevice));
-    if (c->dim == 2) HIPCHK(hipMemcpy(s.y, Y.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.ux, U0.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.uy, U1.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.uz, U2.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s.m, M.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(s.pid, P.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.cell, C.data(), n * 4, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.x, X.data(), n * 8, h2d, c->stream));
+    if (c->dim == 2) HIPCHK(hipMemcpyAsync(s.y, Y.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.ux, U0.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.uy, U1.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.uz, U2.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.m, M.data(), n * 8, h2d, c->stream));
   }
-  HIPCHK(hipMemcpy(c->S.Sret, Sr.data(), Sr.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->S.Mraw, Mr.data(), Mr.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->S.count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(c->S.Sret, Sr.data(), Sr.size() * 8, h2d, c->stream));
+  HIPCHK(hipMemcpyAsync(c->S.Mraw, Mr.data(), Mr.size() * 8, h2d, c->stream));
+  HIPCHK(hipMemcpyAsync(c->S.count, cnt.data(), cnt.size() * 4, h2d, c->stream));
   std::vector<int64_t> ro(c->nc + 1, 0);
   for (int64_t i = 0; i < c->nc; ++i) ro[i + 1] = ro[i] + cnt[i];
-  HIPCHK(hipMemcpy(c->S.roff, ro.data(), ro.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(c->S.roff, ro.data(), ro.size() * 8, h2d, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   c->n_ret = n;
   return UGKWP_OK;
 }

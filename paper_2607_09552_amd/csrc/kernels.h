@@ -19,6 +19,10 @@ enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
 // kStatSlots) so that the per-wave counter updates do not serialize on one
 // address; readers sum the slots.
 constexpr int kStatSlots = 256;
+// Shakhov acceptance-rejection table of a cell: the proposal Maxwellian of
+// W^h (U^h, sigma = sqrt(R T^h)), the 6 sigma cutoff, R T, the bound B and
+// the target's U, p and heat flux q.
+enum : int { kArUhx = 0, kArUhy, kArSig, kArCmax, kArRT, kArBnd, kArUx, kArUy, kArP, kArQx, kArQy, kArN };
 enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalN };
 
 // Mesh tables (device pointers).  Local faces are padded to NV per cell:
@@ -60,7 +64,8 @@ struct State {
   double *W, *Wh, *dt, *tau, *E;
   double2 *tdt;                         // [nc] (tau, dt) for the transport
   int *hvalid;
-  double *Sret, *Sretn, *Sm, *Sp, *Scol, *Q; // tallies sum_k m_k Psi_k [nc*NW], heat flux [nc*2]
+  double *Sret, *Sretn, *Sm, *Sp, *Scol;  // tallies sum_k m_k Psi_k [nc*NW]
+  double *ar;                           // [nc*kArN] Shakhov acceptance-rejection table (Pr != 1)
   double *Mraw, *Mrawn;                 // [nc*5] sum m u_a |u|^2 (a = x, y), sum m u_x u_x, u_x u_y, u_y u_y
   int64_t *roff;                        // [nc + 1] offsets of the retained (sorted) store
   int *ncount;                          // [nc + nb] new particles per cell / boundary face
@@ -105,6 +110,7 @@ __global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
 __global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *);
 template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_sample_match(Geo, Params, State, Store, int64_t);
+template <int DIM> __global__ void k_sample_shakhov(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t);
 template <int DIM, int NV> __global__ void k_transport(Geo, Params, State, Store, int64_t);
 template <int DIM> __global__ void k_scatter(State, Store, Store, int64_t);
@@ -114,7 +120,14 @@ template <int DIM> __global__ void k_update(Geo, Params, State);
 template <int DIM> __global__ void k_surface(Geo, Params, State);
 __global__ void k_finish(Params, State, int64_t);
 __global__ void k_check(Geo, State, int64_t, int64_t, int64_t);
-__global__ void k_zero32(uint32_t *, int64_t);
+// Up to kZeroMax buffers cleared by one launch (32-bit words each).
+constexpr int kZeroMax = 12;
+struct ZeroList {
+  uint32_t *p[kZeroMax];
+  int64_t n[kZeroMax];
+  int count;
+};
+__global__ void k_zero_many(ZeroList, const int *);
 __global__ void k_copy64(int64_t *, const int64_t *, int64_t);
 
 }  // namespace ugk

@@ -164,8 +164,33 @@ __global__ void k_cell_prep(Geo g, Params p, State st) {
       const double UU = Ux * Ux + Uy * Uy;
       const double PxU = Mr[2] * Ux + Mr[3] * Uy, PyU = Mr[3] * Ux + Mr[4] * Uy;
       const double mU = mx * Ux + my * Uy;
-      st.Q[2 * i] = 0.5 * ((((Mr[0] - 2.0 * PxU) + UU * mx) - Ux * mq) + (2.0 * Ux * mU - Ux * UU * m0));
-      st.Q[2 * i + 1] = 0.5 * ((((Mr[1] - 2.0 * PyU) + UU * my) - Uy * mq) + (2.0 * Uy * mU - Uy * UU * m0));
+      const double Qx = 0.5 * ((((Mr[0] - 2.0 * PxU) + UU * mx) - Ux * mq) + (2.0 * Ux * mU - Ux * UU * m0));
+      const double Qy = 0.5 * ((((Mr[1] - 2.0 * PyU) + UU * my) - Uy * mq) + (2.0 * Uy * mU - Uy * UU * m0));
+      if (hv) {
+        // acceptance-rejection constants of the Shakhov target for the
+        // cell's new particles: proposal = Maxwellian of W^h, target
+        // parameters = U, T, p and heat flux of the cell total
+        double *a = st.ar + i * kArN;
+        const double sh3 = s.rho * p.R * s.T, sh4 = Qx / vol, sh5 = Qy / vol;
+        const double sig = sqrt(p.R * h.T);
+        const double RT = p.R * s.T;
+        const double cmax = 6.0 * sig;
+        const double du = sqrt((h.ux - s.ux) * (h.ux - s.ux) + (h.uy - s.uy) * (h.uy - s.uy));
+        const double cb = cmax + du;
+        const double qn = sqrt(sh4 * sh4 + sh5 * sh5);
+        const double w = cb * cb / RT - 5.0;
+        a[kArUhx] = h.ux;
+        a[kArUhy] = h.uy;
+        a[kArSig] = sig;
+        a[kArCmax] = cmax;
+        a[kArRT] = RT;
+        a[kArBnd] = 1.0 + (fabs(1.0 - p.Pr) * qn * cb * (w > 5.0 ? w : 5.0)) / (5.0 * sh3 * RT);
+        a[kArUx] = s.ux;
+        a[kArUy] = s.uy;
+        a[kArP] = sh3;
+        a[kArQx] = sh4;
+        a[kArQy] = sh5;
+      }
     }
     if (hv) {
       const double rho_hp = Wh[0] * E;
@@ -376,35 +401,26 @@ __device__ __forceinline__ void sample_position(const Geo &g, int64_t cell, uint
   y = (y0 + b1 * (ya - y0)) + b2 * (yb - y0);
 }
 
-// Shakhov target by acceptance-rejection against the Maxwellian of W^h
-// (Eq. (4)); sh = {Ux, Uy, T, p, Qx, Qy} of the cell total.
+// One acceptance-rejection attempt `att` for the Shakhov target (Eq. (4))
+// against the Maxwellian of W^h (table a of the cell, from cell_prep):
+// draws z (calls 2 att, 2 att + 1), rejects beyond 6 sigma, else accepts
+// with probability (1 + phi) / B.  z is set even when rejected.
 template <int DIM>
-__device__ __forceinline__ void sample_deviation(const Params &p, uint64_t pid, int64_t step, double Uhx,
-                                                 double Uhy, double Th, const double *sh, double z[3]) {
-  if (!sh) {
-    gauss3(p.seed, pid, step, kVel, 0, z);
-    return;
-  }
-  const double sig = sqrt(p.R * Th);
-  const double RT = p.R * sh[2];
-  const double cmax = 6.0 * sig;
-  const double du = sqrt((Uhx - sh[0]) * (Uhx - sh[0]) + (Uhy - sh[1]) * (Uhy - sh[1]));
-  const double cb = cmax + du;
-  const double qn = sqrt(sh[4] * sh[4] + sh[5] * sh[5]);
-  const double w = cb * cb / RT - 5.0;
-  const double Bnd = 1.0 + (fabs(1.0 - p.Pr) * qn * cb * (w > 5.0 ? w : 5.0)) / (5.0 * sh[3] * RT);
-  for (uint32_t att = 0; att < 64; ++att) {
-    gauss3(p.seed, pid, step, kVel, 2 * att, z);
-    const double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
-    double ea, eb;
-    rng2(p.seed, pid, step, kShakhov, att, ea, eb);
-    if (dz > cmax) continue;
-    const double cx = (Uhx + sig * z[0]) - sh[0], cy = (Uhy + sig * z[1]) - sh[1], cz = sig * z[2];
-    const double c2 = cx * cx + cy * cy + cz * cz;
-    const double cq = DIM == 2 ? cx * sh[4] + cy * sh[5] : cx * sh[4];
-    const double phi = ((1.0 - p.Pr) * cq) / (5.0 * sh[3] * RT) * (c2 / RT - 5.0);
-    if (ea * Bnd <= 1.0 + phi) return;
-  }
+__device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a, uint64_t pid, int64_t step,
+                                                uint32_t att, double z[3]) {
+  gauss3(p.seed, pid, step, kVel, 2 * att, z);
+  const double sig = a[kArSig];
+  const double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
+  if (dz > a[kArCmax]) return false;
+  double ea, eb;
+  rng2(p.seed, pid, step, kShakhov, att, ea, eb);
+  const double RT = a[kArRT];
+  const double cx = (a[kArUhx] + sig * z[0]) - a[kArUx], cy = (a[kArUhy] + sig * z[1]) - a[kArUy];
+  const double cz = sig * z[2];
+  const double c2 = cx * cx + cy * cy + cz * cz;
+  const double cq = DIM == 2 ? cx * a[kArQx] + cy * a[kArQy] : cx * a[kArQx];
+  const double phi = ((1.0 - p.Pr) * cq) / (5.0 * a[kArP] * RT) * (c2 / RT - 5.0);
+  return ea * a[kArBnd] <= 1.0 + phi;
 }
 
 // Draw pass: one thread per new particle of the interior cells.  The birth
@@ -425,28 +441,19 @@ __device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, c
   const int64_t j = k - st.noff[i];
   const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(i) << 20) |
                        static_cast<uint64_t>(j);
-  const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
-  double x, y, z[3];
+  double x, y;
   sample_position<DIM>(g, i, p.seed, pid, step, x, y);
-  if (p.Pr != 1.0) {
-    const Prim<DIM> s = prim<DIM>(st.W + i * NW, p.NR);
-    double shv[6];
-    shv[0] = s.ux;
-    shv[1] = s.uy;
-    shv[2] = s.T;
-    shv[3] = s.rho * p.R * s.T;
-    shv[4] = st.Q[2 * i] / g.vol[i];
-    shv[5] = st.Q[2 * i + 1] / g.vol[i];
-    sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, shv, z);
-  } else {
-    sample_deviation<DIM>(p, pid, step, h.ux, h.uy, h.T, nullptr, z);
-  }
   const int64_t o = n_ret + k;
   out.x[o] = x;
   if (DIM == 2) out.y[o] = y;
-  out.ux[o] = z[0];
-  out.uy[o] = z[1];
-  out.uz[o] = z[2];
+  if (p.Pr == 1.0) {
+    // Maxwellian of W^h; with Pr != 1 k_sample_shakhov draws z
+    double z[3];
+    gauss3(p.seed, pid, step, kVel, 0, z);
+    out.ux[o] = z[0];
+    out.uy[o] = z[1];
+    out.uz[o] = z[2];
+  }
   out.pid[o] = pid;
   out.cell[o] = static_cast<int>(i);
   out.m[o] = st.mnew[i];
@@ -458,6 +465,83 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
   const int64_t n_ret = st.roff[g.nc], n_cellnew = st.noff[g.nc], step = *st.dstep;
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (k < n_cellnew && n_ret + k < cap) sample_draw_one<DIM>(g, p, st, out, n_ret, step, k);
+}
+
+// Shakhov deviations of the new particles (Pr != 1), one wavefront per 64
+// consecutive new particles.  The result is that of the sequential rule: the
+// lowest accepted attempt of 0..63, else attempt 63.  The number of attempts
+// varies widely (about B, the acceptance bound, and all 64 in near-vacuum
+// cells where B is huge), so a lane-per-particle loop would hold the whole
+// wavefront for its slowest particle.  Instead:
+//  1. every lane tries attempts 0..kShR-1 of its own particle;
+//  2. the particles not yet accepted are finished four at a time, 16 lanes
+//     each, which evaluate 16 consecutive attempts of their particle at once
+//     and keep the lowest accepted one.
+constexpr uint32_t kShR = 4;
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, Store out, int64_t cap) {
+  if (*st.halt) return;
+  const int64_t n_ret = st.roff[g.nc], step = *st.dstep;
+  int64_t end = st.noff[g.nc];
+  if (end > cap - n_ret) end = cap - n_ret;
+  const int64_t base = ((blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6) << 6;
+  if (base >= end) return;  // whole wavefront
+  const int lane = lane_id();
+  const int64_t o = n_ret + base + lane;
+  const bool act = base + lane < end;
+  uint64_t pid = 0;
+  int cell = 0;
+  if (act) {
+    pid = out.pid[o];
+    cell = out.cell[o];
+  }
+  bool done = !act;
+  for (uint32_t att = 0; att < kShR; ++att) {
+    if (!done) {
+      double z[3];
+      if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, pid, step, att, z)) {
+        out.ux[o] = z[0];
+        out.uy[o] = z[1];
+        out.uz[o] = z[2];
+        done = true;
+      }
+    }
+  }
+  uint64_t hard = __ballot(!done);
+  const int grp = lane >> 4, sl = lane & 15;
+  while (hard) {
+    // this group's particle: the grp-th remaining lane, if any
+    uint64_t h = hard;
+    for (int q = 0; q < grp && h; ++q) h &= h - 1;
+    const int src = h ? __ffsll(static_cast<long long>(h)) - 1 : -1;
+    for (int q = 0; q < 4 && hard; ++q) hard &= hard - 1;  // the chunk taken
+    const uint64_t gpid = __shfl(pid, src < 0 ? 0 : src, 64);
+    const int gcell = __shfl(cell, src < 0 ? 0 : src, 64);
+    const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
+    bool gdone = src < 0;
+    uint32_t a = kShR;
+    while (__ballot(!gdone)) {
+      const uint32_t att = a + static_cast<uint32_t>(sl);
+      double z[3] = {0.0, 0.0, 0.0};
+      bool acc = false;
+      if (!gdone && att < 64) acc = shakhov_attempt<DIM>(p, tab, gpid, step, att, z);
+      const uint64_t seg = (__ballot(acc) >> (grp * 16)) & 0xffffull;
+      if (!gdone) {
+        if (seg != 0 || a + 16 >= 64) {
+          const int wr = seg != 0 ? __ffsll(static_cast<long long>(seg)) - 1 : static_cast<int>(63 - a);
+          if (sl == wr) {
+            const int64_t d = n_ret + base + src;
+            out.ux[d] = z[0];
+            out.uy[d] = z[1];
+            out.uz[d] = z[2];
+          }
+          gdone = true;
+        } else {
+          a += 16;
+        }
+      }
+    }
+  }
 }
 
 // Moment-matching pass: one wavefront per cell over its new particles.  For
@@ -557,7 +641,7 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
       pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(g.nc + b) << 20) | static_cast<uint64_t>(j);
       double e0, e1, z[3];
       rng2(p.seed, pid, step, kPos, 0, e0, e1);
-      sample_deviation<DIM>(p, pid, step, s.ux, s.uy, s.T, nullptr, z);
+      gauss3(p.seed, pid, step, kVel, 0, z);
       u0 = s.ux + sg * z[0];
       u1 = s.uy + sg * z[1];
       u2 = sg * z[2];
@@ -787,8 +871,11 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   }
 }
 
+// Four wavefronts per SIMD keep the triangle and quad kernels within 128
+// VGPRs without spills; polygons with more faces hold more face data per
+// lane and get up to 256.
 template <int DIM, int NV>
-__global__ void __launch_bounds__(256, 4) k_transport(Geo g, Params p, State st, Store s, int64_t cap) {
+__global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Params p, State st, Store s, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];
   const int64_t gbase = n_ret + st.noff[g.nc];
@@ -1110,9 +1197,18 @@ __global__ void k_check(Geo g, State st, int64_t cap, int64_t cover, int64_t cov
   if (*st.flags) *st.halt = 1;
 }
 
-__global__ void k_zero32(uint32_t *__restrict__ p, int64_t n) {
+// Clears the per-step accumulators of a step (a kernel, not a memset, so
+// that the sequence can be captured in a graph).  Does nothing after a halt:
+// the steps skipped after a halt must leave the last committed step's
+// results as they are.
+__global__ void k_zero_many(ZeroList L, const int *__restrict__ halt) {
+  if (*halt) return;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) p[i] = 0u;
+  const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (int b = 0; b < L.count; ++b) {
+    uint32_t *p = L.p[b];
+    for (int64_t i = i0; i < L.n[b]; i += stride) p[i] = 0u;
+  }
 }
 
 __global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ src, int64_t n) {
@@ -1129,6 +1225,7 @@ __global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ 
   template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
   template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t);                          \
   template __global__ void k_sample_match<D>(Geo, Params, State, Store, int64_t);                        \
+  template __global__ void k_sample_shakhov<D>(Geo, Params, State, Store, int64_t);                        \
   template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t);                      \
   template __global__ void k_transport<D, 2 * D>(Geo, Params, State, Store, int64_t);                   \
   template __global__ void k_scatter<D>(State, Store, Store, int64_t);                                    \
