@@ -43,9 +43,10 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per transport launch from committed rocprofv3 counters, if
-    they were taken on the current kernel source; else None."""
+def traffic_per_particle():
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading)
+    per particle of a transport launch, from the committed rocprofv3 counter
+    summary if it was taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -53,15 +54,19 @@ def traffic_per_launch():
         return None
     if t.get("kernel_sha") != kernel_sha():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_particle")
 
 
-def cpu_baseline(kn, steps):
-    """The CPU oracle, as it stands, on the first `steps` steps of the same
-    workload (single thread)."""
+def cpu_baseline(w, state, steps):
+    """The CPU oracle, as it stands (serial, one thread), on `steps` steps of
+    the same workload from the state the GPU run reached (fields, particles
+    and step counter loaded into the oracle)."""
     import oracle
-    w = workload(kn)
+    W, p, step0 = state
     o = oracle.Oracle(w)
+    o.set_fields(W)
+    o.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"])
+    o.set_step(step0)
     n_upd = 0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -70,8 +75,8 @@ def cpu_baseline(kn, steps):
     dt = time.perf_counter() - t0
     o.close()
     return dict(value=n_upd / dt, unit="particle updates/s", cores=1, kind="oracle",
-                sample=f"first {steps} steps of the same cylinder workload from the freestream start, "
-                       f"{n_upd} particle updates in {dt:.1f} s, 1 thread")
+                sample=f"{steps} steps of the same cylinder workload from the GPU state after step {step0} "
+                       f"({len(p['pid'])} retained particles), {n_upd} particle updates in {dt:.1f} s, 1 thread")
 
 
 def copy_probe(gib=1.0, reps=5):
@@ -89,8 +94,10 @@ def copy_probe(gib=1.0, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=50)
+    # the throughput settles once the bow shock has formed (about 3000 steps
+    # from the freestream start); the default times the developed flow
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=3000)
     ap.add_argument("--kn", type=float, default=0.01)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -115,7 +122,9 @@ def main():
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
     s.step(a.warmup)
     torch.cuda.synchronize()
-    s.profile(True)
+    # timed region: HIP events around the transport launches only (events
+    # around every kernel would slow the step measurably)
+    s.profile(True, transport_only=True)
     work0 = s.work()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -126,17 +135,31 @@ def main():
     prof = s.profile_read()
     s.profile(False)
     print(f"# timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # per-kernel breakdown from a separate, untimed segment with events
+    # around every kernel
+    nb = min(a.steps, 50)
+    s.profile(True)
+    s.step(nb)
+    breakdown = s.profile_read()
+    s.profile(False)
+    state = None
+    if not a.no_cpu:
+        state = (s.fields(), s.particles(), a.warmup + a.steps + nb)
     tr = prof["transport"]
     avg_ms = tr["ms"] / max(tr["launches"], 1)
     # algorithmic bytes of one launch: the byte model per particle times the
     # particles one launch transports on average over the timed steps
     bytes_per_launch = TRANSPORT_BYTES_PER_PARTICLE * n_upd / max(tr["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_per_launch()
+    tpp = traffic_per_particle()
+    traffic = None if tpp is None else tpp * n_upd / max(tr["launches"], 1)
     kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),
                     GBs=round(v["bytes"] / max(v["ms"], 1e-12) * 1e-6, 1) if v["ms"] > 0 else None)
-            for k, v in prof.items() if v["launches"] > 0}
+            for k, v in breakdown.items() if v["launches"] > 0}
     value = n_upd / elapsed
+    # whole-step algorithmic bytes: every transported particle read and
+    # written once, plus the cell and face data of a step
+    step_bytes = 120.0 * n_upd / a.steps + 400.0 * w["n_cells"]
     out = {
         "metric": "particle updates/s",
         "value": value,
@@ -158,10 +181,16 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "transport", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms},
+        "step_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                          "achieved": step_bytes / (elapsed / a.steps) / 1e9,
+                          "frac": step_bytes / (elapsed / a.steps) / 1e9 / HBM_PEAK_GBS,
+                          "bytes_per_step": step_bytes,
+                          "model": "120 B per particle update (read + write one 60 B record) + 400 B per cell"},
         "kernels": kern,
+        "kernels_note": f"per-kernel breakdown from {nb} further steps with events around every kernel",
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(a.kn, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, state, a.cpu_steps)
     print(json.dumps(out))
 
 

@@ -145,7 +145,8 @@ int ugkwp_set_step(ugkwp_ctx *ctx, int64_t step);
 int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
 
 /* Per-kernel timing with HIP events on the library's stream.  enable = 1
- * starts accumulating (and resets), 0 stops.  ugkwp_profile_read returns up
+ * starts accumulating for every kernel (and resets), 2 for the particle
+ * transport kernel only (two events per step, for timing runs), 0 stops.  ugkwp_profile_read returns up
  * to cap entries: name, total milliseconds, launches and the algorithmic
  * bytes moved (the byte model of each kernel). */
 int ugkwp_profile(ugkwp_ctx *ctx, int32_t enable);

@@ -225,8 +225,9 @@ class Solver:
         self._check(load_library().ugkwp_get_tally(self.h, _ptr(Sm), _ptr(Sp)))
         return Sm, Sp
 
-    def profile(self, enable=True):
-        self._check(load_library().ugkwp_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, transport_only=False):
+        mode = 0 if not enable else (2 if transport_only else 1)
+        self._check(load_library().ugkwp_profile(self.h, mode))
 
     def profile_read(self):
         L = load_library()

@@ -76,7 +76,7 @@ struct ugkwp_ctx {
   int64_t *pinned = nullptr;     // host pinned mailbox
   std::vector<void *> allocs;
   // profiling
-  bool prof = false;
+  bool prof = false, prof_all = false;  // events around every kernel, or the transport only
   std::vector<hipEvent_t> ev_pool;
   std::vector<ProfRec> prof_pending;
   double prof_ms[kKCount] = {0};
@@ -169,8 +169,11 @@ hipEvent_t ev_get(ugkwp_ctx *c) {
     c->ev_pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (that would write back L2 after
+  // every timed kernel and slow the step it measures); the times are read
+  // after the batch's stream synchronization
   hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -180,7 +183,7 @@ struct ProfScope {
   double bytes;
   hipEvent_t a = nullptr;
   ProfScope(ugkwp_ctx *c_, int id_, double bytes_) : c(c_), id(id_), bytes(bytes_) {
-    if (c->prof) {
+    if (c->prof && (c->prof_all || id == kKTransport)) {
       a = ev_get(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -1150,6 +1153,7 @@ int ugkwp_profile(ugkwp_ctx *c, int32_t enable) {
     }
   }
   c->prof = enable != 0;
+  c->prof_all = enable == 1;
   return UGKWP_OK;
 }
 

@@ -202,12 +202,13 @@ def test_shakhov_parity():
 
 def test_cylinder_full_size_sampled_steps():
     """The benchmark workload at full size (200 x 150 O-grid, N_ref 400,
-    Kn 0.01, Pr 2/3): two steps in the benchmark's launch configuration; every
+    Kn 0.01, Pr 2/3): two steps in the benchmark's launch configuration, and
+    one step from the state after 400 steps (bow shock forming); every
     particle and every cell is compared."""
     import bench
     w = bench.workload()
     run_pair(w, [1, 2])
-    common_state_steps(w, [2])
+    common_state_steps(w, [2, 400])
 
 
 def test_capacity_growth_resumes_mid_batch():
