@@ -91,6 +91,40 @@ def copy_probe(gib=1.0, reps=5):
     print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps}))
 
 
+def time_to_residual(a):
+    """Wall clock from the first step (init excluded) to the first step
+    n >= 100 with r_avg < target (the residual of the running mean density),
+    plain FP64 path from the uniform freestream start.  Prints progress and
+    one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2607_09552_amd import Solver
+    w = workload(a.kn)
+    s = Solver(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv, n = False, 0
+    chunk = 20000
+    while not conv and n < a.ttr_max_steps:
+        conv, n = s.step_until(a.ttr_target, min(chunk, a.ttr_max_steps - n))
+        ri, ra, _ = s.residual()
+        print(f"# step {n} r_inst {ri:.3e} r_avg {ra:.3e} {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ri, ra, _ = s.residual()
+    surf, cd = s.surface(1)
+    out = {"metric": f"time-to-residual {a.ttr_target:g}", "value": elapsed if conv else None, "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "steps": int(n), "converged": bool(conv),
+           "elapsed_s": elapsed, "ms_per_step": elapsed / max(n, 1) * 1e3, "r_avg": ra, "r_inst": ri,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
+                                  f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, FP64, Philox seed 1",
+                      "start": "uniform freestream", "rule": "first n >= 100 with r_avg < target"},
+           "wall": {"Cd_mean": cd, "Cp_max": float(np.max(surf[:, 3])), "CF_absmax": float(np.max(np.abs(surf[:, 4]))),
+                    "CQ_max": float(np.max(surf[:, 5]))}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +136,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--ttr", action="store_true",
+                    help="time to residual: run from the freestream start until r_avg < --ttr-target")
+    ap.add_argument("--ttr-target", type=float, default=1e-6)
+    ap.add_argument("--ttr-max-steps", type=int, default=600000)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is a "
@@ -117,6 +155,9 @@ def main():
         return
     from paper_2607_09552_amd import Solver
 
+    if a.ttr:
+        time_to_residual(a)
+        return
     w = workload(a.kn)
     s = Solver(w)
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)

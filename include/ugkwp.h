@@ -96,6 +96,14 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double 
  * (more than 2^20 particles born in one cell), ENOMEM, EDEVICE. */
 int ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps);
 
+/* Advances until the residual target is met: stops after the first step
+ * n >= 100 whose r_avg (see ugkwp_residual) is below r_avg_target (the
+ * convergence rule used for time-to-residual), or after max_steps steps.
+ * *converged = 1 if the target was met; the step count is that of
+ * ugkwp_residual.  The test runs on the device after every step.  Errors as
+ * ugkwp_step; EINVAL if r_avg_target <= 0. */
+int ugkwp_step_until(ugkwp_ctx *ctx, double r_avg_target, int32_t max_steps, int32_t *converged);
+
 /* Residuals after the last step (the paper defines none; reading): r_inst is
  * the area-weighted RMS of the last density change over rho_inf, r_avg the
  * same for the running mean of the density over all steps.  step = steps done. */

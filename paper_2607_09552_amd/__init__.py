@@ -20,7 +20,7 @@ BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
 
 # Every entry point declared in include/ugkwp.h.
 ABI_SYMBOLS = (
-    "ugkwp_init", "ugkwp_step", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
+    "ugkwp_init", "ugkwp_step", "ugkwp_step_until", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
     "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_last_error", "ugkwp_free",
@@ -64,6 +64,7 @@ def load_library(path: str = LIB_PATH):
     vp, dp, i64p, i32p, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)
     L.ugkwp_init.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.POINTER(vp)]
     L.ugkwp_step.argtypes = [vp, C.c_int32]
+    L.ugkwp_step_until.argtypes = [vp, C.c_double, C.c_int32, i32p]
     L.ugkwp_residual.argtypes = [vp, dp, dp, i64p]
     L.ugkwp_surface.argtypes = [vp, C.c_int32, dp, C.c_int64, i64p, dp]
     L.ugkwp_get_fields.argtypes = [vp, dp]
@@ -148,6 +149,13 @@ class Solver:
 
     def step(self, n=1):
         self._check(load_library().ugkwp_step(self.h, n))
+
+    def step_until(self, r_avg_target, max_steps):
+        """Steps until the first step n >= 100 with r_avg < r_avg_target or
+        max_steps steps; returns (converged, steps done in total)."""
+        conv = C.c_int32()
+        self._check(load_library().ugkwp_step_until(self.h, r_avg_target, max_steps, C.byref(conv)))
+        return bool(conv.value), self.residual()[2]
 
     def fields(self):
         W = np.zeros((self.nc, self.nw))

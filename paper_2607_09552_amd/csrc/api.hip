@@ -849,6 +849,10 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   return UGKWP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Sizes the store and the particle-parallel grids for steps whose
 // pre-transport set is about `need` particles, `need_new` of them new.
 int plan_launches(ugkwp_ctx *c, int64_t need, int64_t need_new) {
@@ -862,10 +866,10 @@ int plan_launches(ugkwp_ctx *c, int64_t need, int64_t need_new) {
   return UGKWP_OK;
 }
 
-int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
-  if (!c || n_steps < 0) return UGKWP_EINVAL;
-  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
-  if (c->step + n_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+// Runs up to n_steps steps in batches; with `until`, stops after the step at
+// which k_finish found the residual target met (*converged = 1).
+int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
+  if (converged) *converged = 0;
   int rc = sync_counts(c);
   if (rc) return rc;
   // the last pre-transport set with margin for growth over a batch
@@ -893,6 +897,14 @@ int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
     const int halt = static_cast<int>(c->pinned[1] & 0xffffffff), flags = static_cast<int>(c->pinned[2] & 0xffffffff);
     rc = sync_counts(c);
     if (rc) return rc;
+    if (halt && until && flags == kFlagConverged) {
+      // the step that met the target is done; the rest of the batch was skipped
+      HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+      HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (converged) *converged = 1;
+      return UGKWP_OK;
+    }
     if (halt && (flags & ~(kFlagCapacity | kFlagGrid)) == 0) {
       // the step was not committed: grow the store or the grids to its
       // recorded bounds and resume from it
@@ -915,6 +927,29 @@ int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
     if (rc) return rc;
   }
   return UGKWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
+  if (!c || n_steps < 0) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  if (c->step + n_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+  return run_steps(c, n_steps, false, nullptr);
+}
+
+int ugkwp_step_until(ugkwp_ctx *c, double r_avg_target, int32_t max_steps, int32_t *converged) {
+  if (!c || max_steps < 0 || !(r_avg_target > 0.0) || !converged) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  if (c->step + max_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+  HIPCHK(hipMemcpyAsync(c->S.scal + kScalTarget, &r_avg_target, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const int rc = run_steps(c, max_steps, true, converged);
+  const double off = 0.0;
+  HIPCHK(hipMemcpyAsync(c->S.scal + kScalTarget, &off, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return rc;
 }
 
 int ugkwp_residual(ugkwp_ctx *c, double *r_inst, double *r_avg, int64_t *step) {

@@ -13,7 +13,9 @@ constexpr int kScanBlock = 1024;
 constexpr int kMaxCross = 10000;
 
 enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4 };
-enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16 };
+// kFlagConverged is not an error: the step that reached the residual target
+// (scal[kScalTarget] > 0) is done and later steps are skipped
+enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16, kFlagConverged = 32 };
 enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
 // Step statistics are spread over kStatSlots copies (slot = block id mod
 // kStatSlots) so that the per-wave counter updates do not serialize on one
@@ -23,7 +25,7 @@ constexpr int kStatSlots = 256;
 // W^h (U^h, sigma = sqrt(R T^h)), the 6 sigma cutoff, R T, the bound B and
 // the target's U, p and heat flux q.
 enum : int { kArUhx = 0, kArUhy, kArSig, kArCmax, kArRT, kArBnd, kArUx, kArUy, kArP, kArQx, kArQy, kArN };
-enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalN };
+enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalTarget, kScalN };
 
 // Mesh tables (device pointers).  Local faces are padded to NV per cell:
 // local face l = cell * NV + k.

@@ -1179,6 +1179,12 @@ __global__ void k_finish(Params p, State st, int64_t nc) {
   st.info[kInfoSumTotal] += ntot;
   *st.dstep = step + 1;
   if (*st.flags & kFlagRunaway) *st.halt = 1;
+  // convergence test: the first step n >= 100 with r_avg below the target
+  const double tgt = st.scal[kScalTarget];
+  if (tgt > 0.0 && step + 1 >= 100 && st.scal[kScalRavg] < tgt) {
+    *st.flags |= kFlagConverged;
+    *st.halt = 1;
+  }
 }
 
 // After the count scan, before anything of the step is modified: halt if a

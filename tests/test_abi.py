@@ -38,3 +38,17 @@ def test_solver_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         pkg.load_library(str(tmp_path / "nope.so"))
+
+
+def test_library_exports_no_other_c_symbols():
+    """Only the declared entry points are exported with C linkage."""
+    import shutil
+    import subprocess
+    import paper_2607_09552_amd as pkg
+    if shutil.which("nm") is None or not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("nm or the library is not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    syms = {ln.split()[-1] for ln in out.splitlines() if ln.split() and ln.split()[1] in "TW"}
+    c_syms = {x for x in syms if not x.startswith("_")}
+    assert c_syms == set(declared_functions()), sorted(c_syms ^ set(declared_functions()))

@@ -243,3 +243,41 @@ def test_work_counter_sums_step_totals():
         r.step(1)
         t += r.counts()[1]["total"]
     assert t == s
+
+
+def test_step_until_stops_at_the_first_converged_step():
+    """ugkwp_step_until stops after the first step n >= 100 whose r_avg is
+    below the target (the time-to-residual rule); the target is placed between
+    the oracle's r_avg at the chosen step and every earlier value from step
+    100 on, far from both, so the GPU's last-bit differences cannot move n."""
+    w = wl.shock1d()
+    r = oracle.Oracle(w)
+    ravg = []
+    for _ in range(320):
+        r.step(1)
+        ravg.append(r.residual()[1])
+    ravg = np.array(ravg)
+    best = None
+    for n in range(150, 321):
+        prev = ravg[99:n - 1].min()
+        if ravg[n - 1] < prev:
+            margin = prev / ravg[n - 1]
+            if best is None or margin > best[1]:
+                best = (n, margin)
+    n_star, margin = best
+    assert margin > 1.0 + 1e-6
+    target = np.sqrt(ravg[n_star - 1] * ravg[99:n_star - 1].min())
+    g = _solver(w)
+    conv, steps = g.step_until(target, 1000)
+    assert conv and steps == n_star
+    compare(g, r_at(w, n_star), f"converged at {n_star}", TOL)
+    # an unreachable target runs max_steps more steps
+    conv, steps = g.step_until(1e-300, 25)
+    assert not conv and steps == n_star + 25
+
+
+def r_at(w, n):
+    r = oracle.Oracle(w)
+    r.vol = cell_volumes(w)
+    r.step(n)
+    return r
