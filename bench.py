@@ -27,9 +27,12 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # 2D transport: reads a particle record (x, y, u_x, u_y, u_z, m, pid, cell:
-# 60 B) and writes x, y, m (24 B), the cell (4 B) and the keep flag (4 B)
-TRANSPORT_BYTES_PER_PARTICLE = 92.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transport_cylinder_traffic.json")
+# 60 B in FP64, 40 B with FP32 positions and velocities) and writes x, y, m,
+# the cell and the keep flag (32 B, 24 B)
+TRANSPORT_BYTES = {"f64": 92.0, "mixed": 64.0}
+TRANSPORT_BYTES_PER_PARTICLE = TRANSPORT_BYTES["f64"]
+TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "transport_cylinder_traffic.json"),
+                 "mixed": os.path.join(ROOT, "profiles", "transport_cylinder_mixed_traffic.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2607_09552_amd", "csrc", "kernels.hip")
 
 
@@ -43,12 +46,12 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_particle():
+def traffic_per_particle(precision="f64"):
     """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading)
     per particle of a transport launch, from the committed rocprofv3 counter
     summary if it was taken on the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[precision]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -136,6 +139,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--precision", choices=("f64", "mixed"), default="f64",
+                    help="mixed: FP32 particle positions (cell-relative) and velocities, FP64 elsewhere")
     ap.add_argument("--ttr", action="store_true",
                     help="time to residual: run from the freestream start until r_avg < --ttr-target")
     ap.add_argument("--ttr-target", type=float, default=1e-6)
@@ -159,7 +164,7 @@ def main():
         time_to_residual(a)
         return
     w = workload(a.kn)
-    s = Solver(w)
+    s = Solver(w, precision=a.precision)
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
     s.step(a.warmup)
     torch.cuda.synchronize()
@@ -184,15 +189,15 @@ def main():
     breakdown = s.profile_read()
     s.profile(False)
     state = None
-    if not a.no_cpu:
+    if not a.no_cpu and a.precision == "f64":
         state = (s.fields(), s.particles(), a.warmup + a.steps + nb)
     tr = prof["transport"]
     avg_ms = tr["ms"] / max(tr["launches"], 1)
     # algorithmic bytes of one launch: the byte model per particle times the
     # particles one launch transports on average over the timed steps
-    bytes_per_launch = TRANSPORT_BYTES_PER_PARTICLE * n_upd / max(tr["launches"], 1)
+    bytes_per_launch = TRANSPORT_BYTES[a.precision] * n_upd / max(tr["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tpp = traffic_per_particle()
+    tpp = traffic_per_particle(a.precision)
     traffic = None if tpp is None else tpp * n_upd / max(tr["launches"], 1)
     kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),
                     GBs=round(v["bytes"] / max(v["ms"], 1e-12) * 1e-6, 1) if v["ms"] > 0 else None)
@@ -200,7 +205,8 @@ def main():
     value = n_upd / elapsed
     # whole-step algorithmic bytes: every transported particle read and
     # written once, plus the cell and face data of a step
-    step_bytes = 120.0 * n_upd / a.steps + 400.0 * w["n_cells"]
+    rec2 = 120.0 if a.precision == "f64" else 80.0  # one record read and written
+    step_bytes = rec2 * n_upd / a.steps + 400.0 * w["n_cells"]
     out = {
         "metric": "particle updates/s",
         "value": value,
@@ -212,10 +218,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.precision == "f64" else "f32 particles, f64 cells",
         "data": "synthetic",
         "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
-                               f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, FP64, Philox seed 1",
+                               f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, "
+                               f"{'FP64' if a.precision == 'f64' else 'FP32 particle push'}, Philox seed 1",
                    "cells": int(w["n_cells"]),
                    "particles_per_step": n_upd / a.steps,
                    "cell_steps_per_s": w["n_cells"] * a.steps / elapsed},
@@ -226,11 +233,11 @@ def main():
                           "achieved": step_bytes / (elapsed / a.steps) / 1e9,
                           "frac": step_bytes / (elapsed / a.steps) / 1e9 / HBM_PEAK_GBS,
                           "bytes_per_step": step_bytes,
-                          "model": "120 B per particle update (read + write one 60 B record) + 400 B per cell"},
+                          "model": f"{rec2:.0f} B per particle update (read + write one record) + 400 B per cell"},
         "kernels": kern,
         "kernels_note": f"per-kernel breakdown from {nb} further steps with events around every kernel",
     }
-    if not a.no_cpu:
+    if not a.no_cpu and a.precision == "f64":
         out["cpu_baseline"] = cpu_baseline(w, state, a.cpu_steps)
     print(json.dumps(out))
 

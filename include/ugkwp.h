@@ -82,6 +82,10 @@ typedef struct {
   double rho_inf, u_inf_x, u_inf_y, T_inf, L_ref;
   int64_t particle_capacity;  /* 0 = automatic; grows on demand */
   void *stream;               /* hipStream_t or NULL */
+  int32_t precision;          /* 0: FP64 particles (the parity path); 1: mixed,
+                                 particle positions (relative to the cell's
+                                 centroid) and velocities in FP32, masses,
+                                 tallies, cells and fluxes in FP64 */
 } ugkwp_params;
 
 /* Builds faces and geometry, uploads the state and computes the local time

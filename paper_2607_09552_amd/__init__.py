@@ -47,6 +47,7 @@ class _Params(C.Structure):
         ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32), ("lts", C.c_int32),
         ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double), ("u_inf_y", C.c_double),
         ("T_inf", C.c_double), ("L_ref", C.c_double), ("particle_capacity", C.c_int64), ("stream", C.c_void_p),
+        ("precision", C.c_int32),
     ]
 
 
@@ -103,7 +104,7 @@ class Solver:
     or None for the library's own stream.
     """
 
-    def __init__(self, wl, W0=None, stream=None, particle_capacity=0):
+    def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64"):
         L = load_library()
         self.dim = int(wl["dim"])
         self.nw = self.dim + 2
@@ -133,7 +134,8 @@ class Solver:
         p = _Params(R=g["R"], omega=g["omega"], mu_ref=g["mu_ref"], T_ref=g["T_ref"], Pr=g["Pr"], D=g["D"],
                     cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
                     u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
-                    particle_capacity=particle_capacity, stream=stream)
+                    particle_capacity=particle_capacity, stream=stream,
+                    precision={"f64": 0, "mixed": 1}[precision])
         W = arr(wl["W0"] if W0 is None else W0, np.float64).ravel()
         h = C.c_void_p()
         rc = L.ugkwp_init(C.byref(m), C.byref(p), _ptr(W), C.byref(h))

@@ -66,7 +66,13 @@ struct ugkwp_ctx {
   double *bdata = nullptr;
   // state
   State S{};
-  Store A{}, B{};
+  int precision = 0;        // 0: FP64 store, 1: mixed (FP32 positions/velocities)
+  Store A{}, B{};           // FP64 store (precision 0)
+  Store32 A32{}, B32{};     // FP32 store (precision 1)
+  double2 *anchor = nullptr;
+  float4 *lfn32 = nullptr;
+  float2 *lda = nullptr;
+  std::vector<double> h_anchor;  // [nc*2]
   int64_t cap = 0, n_ret = 0, step = 0;
   int64_t last_total = 0, last_new = 0, last_need = 0, last_need_new = 0;
   int64_t est_total = 0, est_new = 0, est_kept = 0;  // byte-model estimates for the profiler
@@ -108,6 +114,9 @@ struct ugkwp_ctx {
     g.btype = btype;
     g.bdata = bdata;
     g.wall_b = wall_b;
+    g.anchor = anchor;
+    g.lfn32 = lfn32;
+    g.lda = lda;
     return g;
   }
 };
@@ -459,7 +468,8 @@ int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
   return UGKWP_OK;
 }
 
-int alloc_store(ugkwp_ctx *c, Store &s, int64_t n) {
+template <class R>
+int alloc_store(ugkwp_ctx *c, StoreT<R> &s, int64_t n) {
   int rc = 0;
   rc |= dalloc(c, &s.x, n);
   if (c->dim == 2) rc |= dalloc(c, &s.y, n);
@@ -472,7 +482,8 @@ int alloc_store(ugkwp_ctx *c, Store &s, int64_t n) {
   return rc ? UGKWP_ENOMEM : UGKWP_OK;
 }
 
-void free_store(ugkwp_ctx *c, Store &s) {
+template <class R>
+void free_store(ugkwp_ctx *c, StoreT<R> &s) {
   dfree(c, s.x);
   dfree(c, s.y);
   dfree(c, s.ux);
@@ -481,17 +492,18 @@ void free_store(ugkwp_ctx *c, Store &s) {
   dfree(c, s.m);
   dfree(c, s.pid);
   dfree(c, s.cell);
-  s = Store{};
+  s = StoreT<R>{};
 }
 
-int copy_store(ugkwp_ctx *c, const Store &from, const Store &to, int64_t n) {
+template <class R>
+int copy_store(ugkwp_ctx *c, const StoreT<R> &from, const StoreT<R> &to, int64_t n) {
   if (n <= 0) return UGKWP_OK;
-  const size_t d8 = n * sizeof(double);
-  HIPCHK(hipMemcpyAsync(to.x, from.x, d8, hipMemcpyDeviceToDevice, c->stream));
-  if (c->dim == 2) HIPCHK(hipMemcpyAsync(to.y, from.y, d8, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(to.ux, from.ux, d8, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(to.uy, from.uy, d8, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(to.uz, from.uz, d8, hipMemcpyDeviceToDevice, c->stream));
+  const size_t d8 = n * sizeof(double), dr = n * sizeof(R);
+  HIPCHK(hipMemcpyAsync(to.x, from.x, dr, hipMemcpyDeviceToDevice, c->stream));
+  if (c->dim == 2) HIPCHK(hipMemcpyAsync(to.y, from.y, dr, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.ux, from.ux, dr, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.uy, from.uy, dr, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(to.uz, from.uz, dr, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.m, from.m, d8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.pid, from.pid, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.cell, from.cell, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -499,34 +511,42 @@ int copy_store(ugkwp_ctx *c, const Store &from, const Store &to, int64_t n) {
 }
 
 // Grow the particle buffers to hold at least `need` particles (retained kept).
+template <class R>
+int grow_stores(ugkwp_ctx *c, StoreT<R> &A, StoreT<R> &B, int64_t ncap) {
+  StoreT<R> A2{}, B2{};
+  int rc = alloc_store(c, A2, ncap);
+  if (!rc) rc = alloc_store(c, B2, ncap);
+  if (rc) return set_err(c, UGKWP_ENOMEM, "cannot grow particle store to %lld", (long long)ncap);
+  rc = copy_store(c, A, A2, c->n_ret);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  free_store(c, A);
+  free_store(c, B);
+  A = A2;
+  B = B2;
+  return UGKWP_OK;
+}
+
 int ensure_capacity(ugkwp_ctx *c, int64_t need) {
   if (need <= c->cap) return UGKWP_OK;
   const int64_t ncap = std::max<int64_t>(need + need / 4 + 1024, c->cap + c->cap / 2);
   if (ncap > (int64_t{1} << 31) - 256)
     return set_err(c, UGKWP_EOVERFLOW, "particle store of %lld exceeds 2^31", (long long)ncap);
-  Store A2{}, B2{};
-  int rc = alloc_store(c, A2, ncap);
-  if (!rc) rc = alloc_store(c, B2, ncap);
-  if (rc) return set_err(c, UGKWP_ENOMEM, "cannot grow particle store to %lld", (long long)ncap);
-  rc = copy_store(c, c->A, A2, c->n_ret);
+  const int rc = c->precision ? grow_stores(c, c->A32, c->B32, ncap) : grow_stores(c, c->A, c->B, ncap);
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(c->stream));
-  free_store(c, c->A);
-  free_store(c, c->B);
   dfree(c, c->S.rank);
   dfree(c, c->S.tghost);
   c->S.rank = nullptr;
   c->S.tghost = nullptr;
   if (dalloc(c, &c->S.rank, ncap) || dalloc(c, &c->S.tghost, ncap))
     return set_err(c, UGKWP_ENOMEM, "cannot grow particle work arrays");
-  c->A = A2;
-  c->B = B2;
   c->cap = ncap;
   return UGKWP_OK;
 }
 
 void swap_buffers(ugkwp_ctx *c) {
   std::swap(c->A, c->B);
+  std::swap(c->A32, c->B32);
   std::swap(c->S.Sret, c->S.Sretn);
   std::swap(c->S.roff, c->S.coff);
   std::swap(c->S.Mraw, c->S.Mrawn);
@@ -552,8 +572,8 @@ struct Zeroer {
 // size depends only on host-known constants (mesh sizes, capacity, grid
 // estimates); the particle counts live on the device.  The host swaps the
 // double-buffered pointers; after a halted batch it restores their parity.
-template <int DIM>
-int enqueue_step(ugkwp_ctx *c) {
+template <int DIM, class R>
+int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
   const int NW = DIM + 2;
   const Geo g = c->geo();
   State &S = c->S;
@@ -580,7 +600,8 @@ int enqueue_step(ugkwp_ctx *c) {
   int rc = scan(c, S.ncount, nc + nb, S.noff);
   if (rc) return rc;
   hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, c->stream, g, S, c->cap, c->cover, c->cover_new);
-  const double rec = DIM == 2 ? 60.0 : 52.0;  // bytes of one particle record
+  // bytes of one particle record: positions and velocities, mass, pid, cell
+  const double rec = (DIM + 3) * static_cast<double>(sizeof(R)) + 20.0;
   // particle-parallel grids cover c->cover particles (c->cover_new new ones);
   // a step whose counts exceed them halts in k_check and is redone with
   // larger grids.  Blocks past the step's count return at once.
@@ -588,37 +609,37 @@ int enqueue_step(ugkwp_ctx *c) {
   const unsigned gnew = static_cast<unsigned>(nblk(c->cover_new, 256));
   {
     ProfScope ps(c, kKSampleCells, rec * c->est_new);
-    hipLaunchKernelGGL(k_sample_draw<DIM>, dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, c->A, c->cap);
+    hipLaunchKernelGGL((k_sample_draw<DIM, R>), dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, A, c->cap);
   }
   if (c->P.Pr != 1.0) {
     ProfScope ps(c, kKSampleShakhov, 40.0 * c->est_new);
-    hipLaunchKernelGGL(k_sample_shakhov<DIM>, dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, c->A, c->cap);
+    hipLaunchKernelGGL((k_sample_shakhov<DIM, R>), dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, A, c->cap);
   }
   {
     ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
-    hipLaunchKernelGGL(k_sample_match<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+    hipLaunchKernelGGL((k_sample_match<DIM, R>), dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, A,
                        c->cap);
   }
   if (nb > 0) {
     ProfScope ps(c, kKSampleGhosts, 0.0);
-    hipLaunchKernelGGL(k_sample_ghosts<DIM>, dim3(nblk(nb * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, c->A,
+    hipLaunchKernelGGL((k_sample_ghosts<DIM, R>), dim3(nblk(nb * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, A,
                        c->cap);
   }
   {
     // transport reads a record and writes x, (y), m, cell and the keep flag
-    const double wr = DIM == 2 ? 32.0 : 24.0;
+    const double wr = DIM * static_cast<double>(sizeof(R)) + 16.0;
     ProfScope ps(c, kKTransport, (rec + wr) * c->est_total);
     const dim3 gr(gcap), bl(256);
     if (DIM == 1) {
-      hipLaunchKernelGGL((k_transport<DIM, 2>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap);
+      hipLaunchKernelGGL((k_transport<DIM, 2, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap);
     } else {
       switch (c->NV) {
-        case 3: hipLaunchKernelGGL((k_transport<2, 3>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
-        case 4: hipLaunchKernelGGL((k_transport<2, 4>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
-        case 5: hipLaunchKernelGGL((k_transport<2, 5>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
-        case 6: hipLaunchKernelGGL((k_transport<2, 6>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
-        case 7: hipLaunchKernelGGL((k_transport<2, 7>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
-        default: hipLaunchKernelGGL((k_transport<2, 8>), gr, bl, 0, c->stream, g, c->P, S, c->A, c->cap); break;
+        case 3: hipLaunchKernelGGL((k_transport<2, 3, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        case 4: hipLaunchKernelGGL((k_transport<2, 4, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        case 5: hipLaunchKernelGGL((k_transport<2, 5, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        case 6: hipLaunchKernelGGL((k_transport<2, 6, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        case 7: hipLaunchKernelGGL((k_transport<2, 7, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        default: hipLaunchKernelGGL((k_transport<2, 8, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
       }
     }
   }
@@ -628,12 +649,12 @@ int enqueue_step(ugkwp_ctx *c) {
                      S.coff, nc);
   {
     ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->est_kept);
-    hipLaunchKernelGGL(k_scatter<DIM>, dim3(gcap), dim3(256), 0, c->stream, S, c->A, c->B, c->cap);
+    hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(256), 0, c->stream, S, A, B, c->cap);
   }
   {
     const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
     ProfScope ps(c, kKCellTally, rd * c->est_kept + (16.0 + 8.0 * NW) * nc);
-    hipLaunchKernelGGL(k_cell_tally<DIM>, dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->B, S.coff,
+    hipLaunchKernelGGL((k_cell_tally<DIM, R>), dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, B, S.coff,
                        S.Sretn, S.Mrawn, c->P.Pr != 1.0 ? 1 : 0, S.halt);
   }
   {
@@ -652,6 +673,12 @@ int enqueue_step(ugkwp_ctx *c) {
   HIPCHK(hipGetLastError());
   swap_buffers(c);
   return UGKWP_OK;
+}
+
+int enqueue(ugkwp_ctx *c) {
+  if (c->precision)
+    return c->dim == 1 ? enqueue_step<1, float>(c, c->A32, c->B32) : enqueue_step<2, float>(c, c->A32, c->B32);
+  return c->dim == 1 ? enqueue_step<1, double>(c, c->A, c->B) : enqueue_step<2, double>(c, c->A, c->B);
 }
 
 int check_flags(ugkwp_ctx *c) {
@@ -703,6 +730,8 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   c->dim = mesh->dim;
   c->nw = mesh->dim + 2;
   c->lts = par->lts;
+  if (par->precision != 0 && par->precision != 1) return set_err(c, UGKWP_EINVAL, "precision must be 0 or 1");
+  c->precision = par->precision;
   Params &P = c->P;
   P.R = par->R;
   P.omega = par->omega;
@@ -743,6 +772,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   c->h_bcell = h.bcell;
   c->h_bk = h.bk;
   c->h_lfn = h.lfn;
+  c->h_anchor = h.cen;
   c->h_lface = h.lface;
   std::vector<int> wall_b, btype(mesh->bface_type, mesh->bface_type + nb);
   for (int64_t b = 0; b < nb; ++b)
@@ -842,6 +872,17 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   Geo g2 = c->geo();
   hipLaunchKernelGGL(k_init_ratio, dim3(nblk(nc * c->NV, 256)), dim3(256), 0, c->stream, g2, S.dt, c->lfn);
   HIPCHK(hipGetLastError());
+  if (c->precision) {
+    // cell anchors (centroids) and the FP32 tracking tables
+    std::vector<double2> anc(nc);
+    for (int64_t i = 0; i < nc; ++i) anc[i] = make_double2(c->h_anchor[2 * i], c->h_anchor[2 * i + 1]);
+    if ((rc = upload(c, &c->anchor, anc))) return rc;
+    if (dalloc(c, &c->lfn32, nc * c->NV) || dalloc(c, &c->lda, nc * c->NV))
+      return set_err(c, UGKWP_ENOMEM, "device allocation failed");
+    Geo g3 = c->geo();
+    hipLaunchKernelGGL(k_init_mixed, dim3(nblk(nc * c->NV, 256)), dim3(256), 0, c->stream, g3, c->lfn32, c->lda);
+    HIPCHK(hipGetLastError());
+  }
   const int64_t cap0 = par->particle_capacity > 0 ? par->particle_capacity
                                                   : std::max<int64_t>(4096, 2 * static_cast<int64_t>(par->n_ref) * nc);
   if ((rc = ensure_capacity(c, cap0))) return rc;
@@ -881,7 +922,7 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
     const int32_t batch = std::min<int32_t>(n_steps - done, kBatchSteps);
     const int64_t step0 = c->step;
     for (int32_t k = 0; k < batch; ++k) {
-      rc = c->dim == 1 ? enqueue_step<1>(c) : enqueue_step<2>(c);
+      rc = enqueue(c);
       if (rc) return rc;
     }
     // one host synchronization per batch
@@ -1043,6 +1084,75 @@ int ugkwp_get_work(ugkwp_ctx *c, int64_t *n_transported) {
   return UGKWP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Reads the first n slots of a store to host arrays in FP64 with global
+// positions (the FP32 store holds positions relative to the cell anchor).
+template <class R>
+int read_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, std::vector<uint64_t> &P, std::vector<int> &C,
+               std::vector<double> &X, std::vector<double> &Y, std::vector<double> &U0, std::vector<double> &U1,
+               std::vector<double> &U2, std::vector<double> &M) {
+  std::vector<R> x(n), y(c->dim == 2 ? n : 0), u0(n), u1(n), u2(n);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(P.data(), s.pid, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(C.data(), s.cell, n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(x.data(), s.x, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    if (c->dim == 2) HIPCHK(hipMemcpyAsync(y.data(), s.y, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(u0.data(), s.ux, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(u1.data(), s.uy, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(u2.data(), s.uz, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(M.data(), s.m, n * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const bool rel = c->precision != 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double ax = rel ? c->h_anchor[2 * C[k]] : 0.0, ay = rel ? c->h_anchor[2 * C[k] + 1] : 0.0;
+    X[k] = rel ? ax + static_cast<double>(x[k]) : static_cast<double>(x[k]);
+    if (c->dim == 2) Y[k] = rel ? ay + static_cast<double>(y[k]) : static_cast<double>(y[k]);
+    U0[k] = u0[k];
+    U1[k] = u1[k];
+    U2[k] = u2[k];
+  }
+  return UGKWP_OK;
+}
+
+// Writes host arrays (FP64, global positions) to the first n slots.
+template <class R>
+int write_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, const std::vector<uint64_t> &P,
+                const std::vector<int> &C, const std::vector<double> &X, const std::vector<double> &Y,
+                const std::vector<double> &U0, const std::vector<double> &U1, const std::vector<double> &U2,
+                const std::vector<double> &M) {
+  std::vector<R> x(n), y(n), u0(n), u1(n), u2(n);
+  const bool rel = c->precision != 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double ax = rel ? c->h_anchor[2 * C[k]] : 0.0, ay = rel ? c->h_anchor[2 * C[k] + 1] : 0.0;
+    x[k] = static_cast<R>(rel ? X[k] - ax : X[k]);
+    y[k] = static_cast<R>(rel ? Y[k] - ay : Y[k]);
+    u0[k] = static_cast<R>(U0[k]);
+    u1[k] = static_cast<R>(U1[k]);
+    u2[k] = static_cast<R>(U2[k]);
+  }
+  const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(s.pid, P.data(), n * 8, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.cell, C.data(), n * 4, h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.x, x.data(), n * sizeof(R), h2d, c->stream));
+    if (c->dim == 2) HIPCHK(hipMemcpyAsync(s.y, y.data(), n * sizeof(R), h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.ux, u0.data(), n * sizeof(R), h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.uy, u1.data(), n * sizeof(R), h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.uz, u2.data(), n * sizeof(R), h2d, c->stream));
+    HIPCHK(hipMemcpyAsync(s.m, M.data(), n * 8, h2d, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x, double *u,
                         int64_t *n) {
   if (!c || !n) return UGKWP_EINVAL;
@@ -1052,18 +1162,9 @@ int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell,
   std::vector<uint64_t> P(np);
   std::vector<int> C(np);
   std::vector<double> X(np), Y(c->dim == 2 ? np : 0), U0(np), U1(np), U2(np), M(np);
-  const Store &s = c->A;
-  if (np > 0) {
-    HIPCHK(hipMemcpyAsync(P.data(), s.pid, np * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(C.data(), s.cell, np * 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(X.data(), s.x, np * 8, hipMemcpyDeviceToHost, c->stream));
-    if (c->dim == 2) HIPCHK(hipMemcpyAsync(Y.data(), s.y, np * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(U0.data(), s.ux, np * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(U1.data(), s.uy, np * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(U2.data(), s.uz, np * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(M.data(), s.m, np * 8, hipMemcpyDeviceToHost, c->stream));
-  }
-  HIPCHK(hipStreamSynchronize(c->stream));
+  const int rc = c->precision ? read_store(c, c->A32, np, P, C, X, Y, U0, U1, U2, M)
+                              : read_store(c, c->A, np, P, C, X, Y, U0, U1, U2, M);
+  if (rc) return rc;
   std::vector<int64_t> order(np);
   for (int64_t k = 0; k < np; ++k) order[k] = k;
   std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return P[a] < P[b]; });
@@ -1113,6 +1214,11 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     U0[j] = u[3 * k];
     U1[j] = u[3 * k + 1];
     U2[j] = u[3 * k + 2];
+    if (c->precision) {  // the tallies see the velocities as stored
+      U0[j] = static_cast<float>(U0[j]);
+      U1[j] = static_cast<float>(U1[j]);
+      U2[j] = static_cast<float>(U2[j]);
+    }
     const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]);
     const double q2 = U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j];
     double *mr = &Mr[C[j] * 5];
@@ -1128,18 +1234,10 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     sr[c->nw - 1] += M[j] * e;
     cnt[C[j]]++;
   }
-  const Store &s = c->A;
+  rc = c->precision ? write_store(c, c->A32, n, P, C, X, Y, U0, U1, U2, M)
+                    : write_store(c, c->A, n, P, C, X, Y, U0, U1, U2, M);
+  if (rc) return rc;
   const hipMemcpyKind h2d = hipMemcpyHostToDevice;
-  if (n > 0) {
-    HIPCHK(hipMemcpyAsync(s.pid, P.data(), n * 8, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.cell, C.data(), n * 4, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.x, X.data(), n * 8, h2d, c->stream));
-    if (c->dim == 2) HIPCHK(hipMemcpyAsync(s.y, Y.data(), n * 8, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.ux, U0.data(), n * 8, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.uy, U1.data(), n * 8, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.uz, U2.data(), n * 8, h2d, c->stream));
-    HIPCHK(hipMemcpyAsync(s.m, M.data(), n * 8, h2d, c->stream));
-  }
   HIPCHK(hipMemcpyAsync(c->S.Sret, Sr.data(), Sr.size() * 8, h2d, c->stream));
   HIPCHK(hipMemcpyAsync(c->S.Mraw, Mr.data(), Mr.size() * 8, h2d, c->stream));
   HIPCHK(hipMemcpyAsync(c->S.count, cnt.data(), cnt.size() * 4, h2d, c->stream));

@@ -48,6 +48,10 @@ struct Geo {
   const int *bcell, *bk, *btype; // [nb] interior cell, its local face, BC type
   const double *bdata;   // [nb*8]
   const int *wall_b;     // [nwall] boundary face id of each wall face
+  // mixed precision only (particle positions relative to a cell anchor):
+  const double2 *anchor; // [nc] anchor of each cell (its centroid)
+  const float4 *lfn32;   // [nc*NV] normal (x, y), offset n.(v_k - anchor) (z), crossing ratio (w)
+  const float2 *lda;     // [nc*NV] anchor of the cell minus anchor of the neighbour across face k
 };
 
 struct Params {
@@ -97,26 +101,35 @@ struct State {
 };
 enum : int { kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, kInfoN };
 
-struct Store {
-  double *x, *y, *ux, *uy, *uz, *m;
+// Particle store, structure of arrays.  R = double: global positions (the
+// FP64 path); R = float: positions relative to the cell's anchor and FP32
+// velocities (the mixed-precision path).  Masses stay FP64 in both.
+template <class R>
+struct StoreT {
+  R *x, *y, *ux, *uy, *uz;
+  double *m;
   uint64_t *pid;
   int *cell;
 };
+using Store = StoreT<double>;
+using Store32 = StoreT<float>;
 
 template <int DIM> __global__ void k_init_dt(Geo, Params, const double *, double *, int *);
 __global__ void k_init_ratio(Geo, const double *, double4 *);
+__global__ void k_init_mixed(Geo, float4 *, float2 *);
 template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
 template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
 __global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *, const int *);
 __global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
 __global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *);
-template <int DIM> __global__ void k_sample_draw(Geo, Params, State, Store, int64_t);
-template <int DIM> __global__ void k_sample_match(Geo, Params, State, Store, int64_t);
-template <int DIM> __global__ void k_sample_shakhov(Geo, Params, State, Store, int64_t);
-template <int DIM> __global__ void k_sample_ghosts(Geo, Params, State, Store, int64_t);
-template <int DIM, int NV> __global__ void k_transport(Geo, Params, State, Store, int64_t);
-template <int DIM> __global__ void k_scatter(State, Store, Store, int64_t);
-template <int DIM> __global__ void k_cell_tally(Geo, Store, const int64_t *, double *, double *, int, const int *);
+template <int DIM, class R> __global__ void k_sample_draw(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_sample_match(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_sample_ghosts(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, int NV, class R> __global__ void k_transport(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, int64_t);
+template <int DIM, class R>
+__global__ void k_cell_tally(Geo, StoreT<R>, const int64_t *, double *, double *, int, const int *);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State);
 template <int DIM> __global__ void k_surface(Geo, Params, State);

@@ -85,6 +85,25 @@ __device__ __forceinline__ uint64_t wave_group(int key, int &leader) {
   return mine;
 }
 
+// Mixed-precision store: positions relative to the cell's anchor.
+template <class R> struct IsF32 { static constexpr bool value = false; };
+template <> struct IsF32<float> { static constexpr bool value = true; };
+
+// Writes a global position (x, y) of a particle in `cell` to slot k: as is in
+// the FP64 store, relative to the cell's anchor in the FP32 store.
+template <int DIM, class R>
+__device__ __forceinline__ void store_position(const Geo &g, const StoreT<R> &s, int64_t k, int64_t cell, double x,
+                                               double y) {
+  if constexpr (IsF32<R>::value) {
+    const double2 a = g.anchor[cell];
+    s.x[k] = static_cast<float>(x - a.x);
+    if (DIM == 2) s.y[k] = static_cast<float>(y - a.y);
+  } else {
+    s.x[k] = x;
+    if (DIM == 2) s.y[k] = y;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a1: local time step from the initial field, Eq. (33), and Eq. (34)
 // ---------------------------------------------------------------------------
@@ -117,6 +136,27 @@ __global__ void k_init_ratio(Geo g, const double *__restrict__ dt, double4 *__re
   const int64_t i = l / g.NV;
   const int nb = g.lnb[l];
   lfn[l].w = nb >= 0 ? dt[nb] / dt[i] : 1.0;
+}
+
+// Mixed-precision tables: FP32 face data with offsets relative to the cell's
+// anchor, and the shift of anchors to the neighbour across each face (the
+// position of a particle crossing into it, relative to the new anchor, is
+// the old relative position plus this shift).
+__global__ void k_init_mixed(Geo g, float4 *__restrict__ lfn32, float2 *__restrict__ lda) {
+  const int64_t l = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (l >= g.nc * g.NV) return;
+  const int64_t i = l / g.NV;
+  const double4 f = g.lfn[l];
+  const double2 a = g.anchor[i];
+  lfn32[l] = make_float4(static_cast<float>(f.x), static_cast<float>(f.y),
+                         static_cast<float>(f.z - (f.x * a.x + f.y * a.y)), static_cast<float>(f.w));
+  const int nb = g.lnb[l];
+  float2 d = make_float2(0.0f, 0.0f);
+  if (nb >= 0) {
+    const double2 b = g.anchor[nb];
+    d = make_float2(static_cast<float>(a.x - b.x), static_cast<float>(a.y - b.y));
+  }
+  lda[l] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -427,8 +467,8 @@ __device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a
 // cell i is the last cell with noff[i] <= k (binary search over the exclusive
 // scan of the counts), j = k - noff[i].  Writes the position, the raw
 // deviation z (in the velocity slots), pid, cell and mass.
-template <int DIM>
-__device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, const State &st, const Store &out,
+template <int DIM, class R>
+__device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, const State &st, const StoreT<R> &out,
                                                 int64_t n_ret, int64_t step, int64_t k) {
   constexpr int NW = DIM + 2;
   int64_t lo = 0, hi = g.nc;
@@ -444,27 +484,26 @@ __device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, c
   double x, y;
   sample_position<DIM>(g, i, p.seed, pid, step, x, y);
   const int64_t o = n_ret + k;
-  out.x[o] = x;
-  if (DIM == 2) out.y[o] = y;
+  store_position<DIM, R>(g, out, o, i, x, y);
   if (p.Pr == 1.0) {
     // Maxwellian of W^h; with Pr != 1 k_sample_shakhov draws z
     double z[3];
     gauss3(p.seed, pid, step, kVel, 0, z);
-    out.ux[o] = z[0];
-    out.uy[o] = z[1];
-    out.uz[o] = z[2];
+    out.ux[o] = static_cast<R>(z[0]);
+    out.uy[o] = static_cast<R>(z[1]);
+    out.uz[o] = static_cast<R>(z[2]);
   }
   out.pid[o] = pid;
   out.cell[o] = static_cast<int>(i);
   out.m[o] = st.mnew[i];
 }
 
-template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, Store out, int64_t cap) {
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc], n_cellnew = st.noff[g.nc], step = *st.dstep;
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (k < n_cellnew && n_ret + k < cap) sample_draw_one<DIM>(g, p, st, out, n_ret, step, k);
+  if (k < n_cellnew && n_ret + k < cap) sample_draw_one<DIM, R>(g, p, st, out, n_ret, step, k);
 }
 
 // Shakhov deviations of the new particles (Pr != 1), one wavefront per 64
@@ -478,8 +517,8 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
 //     each, which evaluate 16 consecutive attempts of their particle at once
 //     and keep the lowest accepted one.
 constexpr uint32_t kShR = 4;
-template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, Store out, int64_t cap) {
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc], step = *st.dstep;
   int64_t end = st.noff[g.nc];
@@ -500,9 +539,9 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     if (!done) {
       double z[3];
       if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, pid, step, att, z)) {
-        out.ux[o] = z[0];
-        out.uy[o] = z[1];
-        out.uz[o] = z[2];
+        out.ux[o] = static_cast<R>(z[0]);
+        out.uy[o] = static_cast<R>(z[1]);
+        out.uz[o] = static_cast<R>(z[2]);
         done = true;
       }
     }
@@ -531,9 +570,9 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
           const int wr = seg != 0 ? __ffsll(static_cast<long long>(seg)) - 1 : static_cast<int>(63 - a);
           if (sl == wr) {
             const int64_t d = n_ret + base + src;
-            out.ux[d] = z[0];
-            out.uy[d] = z[1];
-            out.uz[d] = z[2];
+            out.ux[d] = static_cast<R>(z[0]);
+            out.uy[d] = static_cast<R>(z[1]);
+            out.uz[d] = static_cast<R>(z[2]);
           }
           gdone = true;
         } else {
@@ -549,8 +588,8 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
 // carries exactly the momentum and thermal energy of W^hp (Eq. (25)):
 // u = U^h + sqrt(R T^h) ((z - zbar) alpha), alpha = sqrt(3 N / sum |z - zbar|^2).
 // Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)).
-template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, Store out, int64_t cap) {
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   constexpr int NW = DIM + 2;
   const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (i >= g.nc || *st.halt) return;  // whole wavefront
@@ -588,10 +627,12 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       const int64_t k = base + j;
       const double w0 = (out.ux[k] - zm[0]) * alpha, w1 = (out.uy[k] - zm[1]) * alpha,
                    w2 = (out.uz[k] - zm[2]) * alpha;
-      const double u0 = h.ux + sig * w0, u1 = h.uy + sig * w1, u2 = sig * w2;
-      out.ux[k] = u0;
-      out.uy[k] = u1;
-      out.uz[k] = u2;
+      // the stored velocities (rounded in the FP32 store) enter the tally
+      const R r0 = static_cast<R>(h.ux + sig * w0), r1 = static_cast<R>(h.uy + sig * w1), r2 = static_cast<R>(sig * w2);
+      out.ux[k] = r0;
+      out.uy[k] = r1;
+      out.uz[k] = r2;
+      const double u0 = r0, u1 = r1, u2 = r2;
       const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
       snew[0] += mk;
       snew[1] += mk * u0;
@@ -611,8 +652,8 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
 // particles whose straight flight reaches the face within dt_i enter cell i
 // at the crossing point (tangential position wrapped along the face) with the
 // remaining time.  Entering particles are compacted by ballot and appended.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st, Store out, int64_t cap) {
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   constexpr int NW = DIM + 2;
   const int64_t b = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (b >= g.nb || *st.halt) return;
@@ -673,11 +714,10 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
     if (enter && gbase + pos + popc_below(mask) < cap) {
       const int64_t r = pos + popc_below(mask);
       const int64_t k = gbase + r;
-      out.x[k] = px;
-      if (DIM == 2) out.y[k] = py;
-      out.ux[k] = u0;
-      out.uy[k] = u1;
-      out.uz[k] = u2;
+      store_position<DIM, R>(g, out, k, i, px, py);
+      out.ux[k] = static_cast<R>(u0);
+      out.uy[k] = static_cast<R>(u1);
+      out.uz[k] = static_cast<R>(u2);
       out.m[k] = mk;
       out.pid[k] = pid;
       out.cell[k] = i;
@@ -697,57 +737,72 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
 // Then W^{p,+} Omega over every particle ending inside (Eq. (30)), the next
 // step's W^p Omega and counts over the kept (non-collided) ones.
 // ---------------------------------------------------------------------------
-template <int DIM, int NV>
-__device__ __forceinline__ void transport_one(const Geo &g, const Params &p, const State &st, const Store &s,
+template <class R> struct Face;
+template <> struct Face<double> { using type = double4; };
+template <> struct Face<float> { using type = float4; };
+
+// Face data of local face l for tracking: (n_x, n_y, offset c, ratio).  The
+// FP32 table's offset is relative to the cell's anchor.
+template <class R>
+__device__ __forceinline__ typename Face<R>::type load_face(const Geo &g, int64_t l) {
+  if constexpr (IsF32<R>::value) return g.lfn32[l];
+  else return g.lfn[l];
+}
+
+template <int DIM, int NV, class R>
+__device__ __forceinline__ void transport_one(const Geo &g, const Params &p, const State &st, const StoreT<R> &s,
                                               int64_t n_ret, int64_t gbase, int64_t n_total, int64_t step,
                                               int64_t k) {
   constexpr int NW = DIM + 2;
+  constexpr bool F32 = IsF32<R>::value;
+  using F4 = typename Face<R>::type;
   const bool active = k < n_total;
   int cell = -1;
   bool exited = false, collide = false;
-  double x = 0, y = 0, u0 = 0, u1 = 0, u2 = 0, m = 0;
+  R x = 0, y = 0, u0 = 0, u1 = 0, u2 = 0;
+  double m = 0;
   if (active) {
     cell = s.cell[k];
     x = s.x[k];
-    y = DIM == 2 ? s.y[k] : 0.0;
+    y = DIM == 2 ? s.y[k] : R(0);
     u0 = s.ux[k];
     u1 = s.uy[k];
     u2 = s.uz[k];
     m = s.m[k];
     const uint64_t pid = s.pid[k];
     // the cell's faces and neighbours, loaded together on entering a cell
-    double4 F[NV];
+    F4 F[NV];
     int nbr[NV];
     const double2 td = st.tdt[cell];
 #pragma unroll
     for (int kk = 0; kk < NV; ++kk) {
-      F[kk] = g.lfn[static_cast<int64_t>(cell) * NV + kk];
+      F[kk] = load_face<R>(g, static_cast<int64_t>(cell) * NV + kk);
       nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
     }
-    double t;
+    R t;
     if (k < n_ret) {
       double e0, e1;
       rng2(p.seed, pid, step, kFree, 0, e0, e1);
       const double sfree = -td.x * log(e0);
       collide = sfree < td.y;
-      t = collide ? sfree : td.y;
+      t = static_cast<R>(collide ? sfree : td.y);
     } else if (k < gbase) {
-      t = td.y;
+      t = static_cast<R>(td.y);
     } else {
-      t = st.tghost[k - gbase];
+      t = static_cast<R>(st.tghost[k - gbase]);
     }
     bool reflected = false;
     int ncross = 0, hits = 0;
     for (;;) {
-      double best = INFINITY;
+      R best = static_cast<R>(INFINITY);
       int kb = -1;
 #pragma unroll
       for (int kk = 0; kk < NV; ++kk) {
-        const double un = DIM == 2 ? u0 * F[kk].x + u1 * F[kk].y : u0 * F[kk].x;
-        if (un > 0.0) {
-          const double xn = DIM == 2 ? F[kk].x * x + F[kk].y * y : F[kk].x * x;
-          double te = (F[kk].z - xn) / un;
-          if (te < 0.0) te = 0.0;
+        const R un = DIM == 2 ? u0 * F[kk].x + u1 * F[kk].y : u0 * F[kk].x;
+        if (un > R(0)) {
+          const R xn = DIM == 2 ? F[kk].x * x + F[kk].y * y : F[kk].x * x;
+          R te = (F[kk].z - xn) / un;
+          if (te < R(0)) te = R(0);
           if (te < best) {
             best = te;
             kb = kk;
@@ -765,7 +820,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       }
       x = x + u0 * best;
       if (DIM == 2) y = y + u1 * best;
-      double4 f = F[0];
+      F4 f = F[0];
       int nb = nbr[0];
 #pragma unroll
       for (int kk = 1; kk < NV; ++kk)
@@ -774,13 +829,24 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
           nb = nbr[kk];
         }
       if (nb >= 0) {
-        const double r = f.w;
-        t = (t - best) * r;
-        m = m * r;
+        if constexpr (F32) {
+          // remaining time scales in FP32, the mass with the FP64 ratio;
+          // the position moves to the neighbour's anchor
+          const int64_t l = static_cast<int64_t>(cell) * NV + kb;
+          t = (t - best) * f.w;
+          m = m * g.lfn[l].w;
+          const float2 d = g.lda[l];
+          x = x + d.x;
+          if (DIM == 2) y = y + d.y;
+        } else {
+          const double r = f.w;
+          t = (t - best) * r;
+          m = m * r;
+        }
         cell = nb;
 #pragma unroll
         for (int kk = 0; kk < NV; ++kk) {
-          F[kk] = g.lfn[static_cast<int64_t>(cell) * NV + kk];
+          F[kk] = load_face<R>(g, static_cast<int64_t>(cell) * NV + kk);
           nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
         }
         continue;
@@ -795,8 +861,8 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       reflected = true;
       if (ty == kBcSymmetry) {
         if (DIM == 2) {
-          const double un = u0 * f.x + u1 * f.y;
-          const double n0 = u0 - 2.0 * un * f.x, n1 = u1 - 2.0 * un * f.y;
+          const R un = u0 * f.x + u1 * f.y;
+          const R n0 = u0 - R(2) * un * f.x, n1 = u1 - R(2) * un * f.y;
           u0 = n0;
           u1 = n1;
         } else {
@@ -813,20 +879,27 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       const double vn = sqrt(-2.0 * p.R * Tw * log(e0));
       box_muller(e1, e2, z0, z1);
       const double b0 = u0, b1 = u1, b2 = u2;
+      const double fx = f.x, fy = f.y;
+      double a0, a1, a2;
       if (DIM == 2) {
         const double vt = sw * z0;
-        u0 = -vn * f.x - vt * f.y;
-        u1 = -vn * f.y + vt * f.x;
-        u2 = sw * z1;
+        a0 = -vn * fx - vt * fy;
+        a1 = -vn * fy + vt * fx;
+        a2 = sw * z1;
       } else {
-        u0 = -vn * f.x;
-        u1 = sw * z0;
-        u2 = sw * z1;
+        a0 = -vn * fx;
+        a1 = sw * z0;
+        a2 = sw * z1;
       }
+      // the impulse uses the velocities as stored (rounded in FP32)
+      u0 = static_cast<R>(a0);
+      u1 = static_cast<R>(a1);
+      u2 = static_cast<R>(a2);
+      const double c0 = u0, c1 = u1, c2 = u2;
       const double eb = 0.5 * (b0 * b0 + b1 * b1 + b2 * b2);
-      const double ea = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-      atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - u0));
-      atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - u1));
+      const double ea = 0.5 * (c0 * c0 + c1 * c1 + c2 * c2);
+      atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
+      atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
       atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
     }
     s.x[k] = x;
@@ -844,11 +917,12 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   // collided particles end their flight here (Eq. (51)) and are dropped after
   // the tally; their share of W^{p,+} (Eq. (30)) is added directly
   if (inside && collide) {
-    const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    const double v0 = u0, v1 = u1, v2 = u2;
+    const double en = 0.5 * (v0 * v0 + v1 * v1 + v2 * v2);
     double *S = st.Scol + static_cast<int64_t>(cell) * NW;
     atomicAdd(&S[0], m);
-    atomicAdd(&S[1], m * u0);
-    if (DIM == 2) atomicAdd(&S[2], m * u1);
+    atomicAdd(&S[1], m * v0);
+    if (DIM == 2) atomicAdd(&S[2], m * v1);
     atomicAdd(&S[NW - 1], m * en);
   }
   // histogram of the kept particles per destination cell (one atomic per
@@ -874,8 +948,8 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
 // Four wavefronts per SIMD keep the triangle and quad kernels within 128
 // VGPRs without spills; polygons with more faces hold more face data per
 // lane and get up to 256.
-template <int DIM, int NV>
-__global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Params p, State st, Store s, int64_t cap) {
+template <int DIM, int NV, class R>
+__global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];
   const int64_t gbase = n_ret + st.noff[g.nc];
@@ -885,15 +959,15 @@ __global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Param
   // the grid covers the store capacity, which bounds every step's set
   const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
   if (base >= n_total) return;  // block-uniform: whole wavefronts take part in the grouping
-  transport_one<DIM, NV>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
+  transport_one<DIM, NV, R>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
 }
 
 // Re-sort (counting sort, scatter pass): cursor[c] starts at the exclusive
 // scan of the kept counts; each wavefront claims contiguous slots for its
 // lanes of equal destination with one atomic per group, all groups of the
 // wave in the same instruction.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_scatter(State st, Store a, Store b, int64_t cap) {
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R> b, int64_t cap) {
   if (*st.halt) return;
   const int64_t nt = st.roff[st.nc_scatter] + st.noff[st.nc_scatter] + *st.nghost;
   const int64_t n_total = nt < cap ? nt : cap;
@@ -927,8 +1001,8 @@ __global__ void __launch_bounds__(256) k_scatter(State st, Store a, Store b, int
 // sum m u_a |u|^2 and sum m u_a u_b that give the heat flux of Eq. (5) once
 // the next step's U is known.  Lane-strided partial sums in a fixed order,
 // then one butterfly per value: no atomics.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_cell_tally(Geo g, Store s, const int64_t *__restrict__ off,
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_cell_tally(Geo g, StoreT<R> s, const int64_t *__restrict__ off,
                                                     double *__restrict__ S, double *__restrict__ M, int raw,
                                                     const int *__restrict__ halt) {
   constexpr int NW = DIM + 2;
@@ -1229,24 +1303,34 @@ __global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ 
   template __global__ void k_init_dt<D>(Geo, Params, const double *, double *, int *);                  \
   template __global__ void k_cell_prep<D>(Geo, Params, State);                                           \
   template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
-  template __global__ void k_sample_draw<D>(Geo, Params, State, Store, int64_t);                          \
-  template __global__ void k_sample_match<D>(Geo, Params, State, Store, int64_t);                        \
-  template __global__ void k_sample_shakhov<D>(Geo, Params, State, Store, int64_t);                        \
-  template __global__ void k_sample_ghosts<D>(Geo, Params, State, Store, int64_t);                      \
-  template __global__ void k_transport<D, 2 * D>(Geo, Params, State, Store, int64_t);                   \
-  template __global__ void k_scatter<D>(State, Store, Store, int64_t);                                    \
-  template __global__ void k_cell_tally<D>(Geo, Store, const int64_t *, double *, double *, int,         \
-                                           const int *);                                                 \
   template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
   template __global__ void k_update<D>(Geo, Params, State);                                              \
   template __global__ void k_surface<D>(Geo, Params, State);
 UGK_INST(1)
 UGK_INST(2)
-#define UGK_INST_NV(N) template __global__ void k_transport<2, N>(Geo, Params, State, Store, int64_t);
-UGK_INST_NV(3)
-UGK_INST_NV(5)
-UGK_INST_NV(6)
-UGK_INST_NV(7)
-UGK_INST_NV(8)
+#define UGK_INST_P(D, R)                                                                                  \
+  template __global__ void k_sample_draw<D, R>(Geo, Params, State, StoreT<R>, int64_t);                  \
+  template __global__ void k_sample_match<D, R>(Geo, Params, State, StoreT<R>, int64_t);                 \
+  template __global__ void k_sample_shakhov<D, R>(Geo, Params, State, StoreT<R>, int64_t);               \
+  template __global__ void k_sample_ghosts<D, R>(Geo, Params, State, StoreT<R>, int64_t);                \
+  template __global__ void k_transport<D, 2 * D, R>(Geo, Params, State, StoreT<R>, int64_t);            \
+  template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, int64_t);                        \
+  template __global__ void k_cell_tally<D, R>(Geo, StoreT<R>, const int64_t *, double *, double *, int,  \
+                                              const int *);
+UGK_INST_P(1, double)
+UGK_INST_P(2, double)
+UGK_INST_P(1, float)
+UGK_INST_P(2, float)
+#define UGK_INST_NV(N, R) template __global__ void k_transport<2, N, R>(Geo, Params, State, StoreT<R>, int64_t);
+UGK_INST_NV(3, double)
+UGK_INST_NV(5, double)
+UGK_INST_NV(6, double)
+UGK_INST_NV(7, double)
+UGK_INST_NV(8, double)
+UGK_INST_NV(3, float)
+UGK_INST_NV(5, float)
+UGK_INST_NV(6, float)
+UGK_INST_NV(7, float)
+UGK_INST_NV(8, float)
 
 }  // namespace ugk

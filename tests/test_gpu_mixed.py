@@ -1,0 +1,114 @@
+"""The mixed-precision path (ugkwp_params.precision = 1): particle positions,
+stored relative to the cell's centroid, and velocities in FP32; masses,
+tallies, cell states and wave fluxes in FP64.
+
+Rounded positions change which face a particle leaves by, so integer outcomes
+are no longer those of the FP64 oracle.  The tests check what must still hold
+exactly -- the time-weighted content Sum Omega_i W_i / dt_i of a closed
+specular box (Eqs. (43), (53)) and every particle inside its cell -- and that
+time-averaged results agree with the FP64 path within the FP64 path's own
+spread between two random seeds."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from tests.test_gpu_parity import cell_volumes
+from tests.test_oracle_step import _closed_box
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(w, **kw):
+    from paper_2607_09552_amd import Solver
+    return Solver(w, **kw)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_mixed_closed_box_conserves_time_weighted_content(dim):
+    m = _closed_box(dim)
+    g = _solver(m, precision="mixed")
+    vol, dt = cell_volumes(m), g.dt()
+    assert dt.max() / dt.min() > 3.0
+    I0 = (vol[:, None] * g.fields() / dt[:, None]).sum(0)
+    for _ in range(25):
+        g.step(1)
+        I = (vol[:, None] * g.fields() / dt[:, None]).sum(0)
+        for c in (0, dim + 1):
+            assert abs(I[c] - I0[c]) <= 2e-13 * abs(I0[c]), (c, I[c], I0[c])
+    assert g.counts()[1]["total"] > 0
+
+
+def _outside(w, p):
+    """Distance outside the particle's (quadrilateral) cell over the cell's
+    size, per particle."""
+    cp, cn, xy = w["cell_ptr"], w["cell_nodes"], w["nodes"]
+    worst = np.zeros(len(p["pid"]))
+    cells = p["cell"]
+    assert np.all(np.diff(cp) == 4)
+    v = xy[cn.reshape(-1, 4)][cells]
+    size = np.sqrt(np.abs(cell_volumes(w)))[cells]
+    for k in range(4):
+        a, b = v[:, k], v[:, (k + 1) % 4]
+        e = b - a
+        ln = np.hypot(e[:, 0], e[:, 1])
+        # signed distance to the left of the CCW edge (inside >= 0)
+        d = (e[:, 0] * (p["x"][:, 1] - a[:, 1]) - e[:, 1] * (p["x"][:, 0] - a[:, 0])) / ln
+        worst = np.maximum(worst, -d / size)
+    return worst
+
+
+def test_mixed_particles_stay_in_their_cells():
+    w = wl.cylinder(n_theta=40, n_r=30, n_ref=50, Pr=1.0)
+    g = _solver(w, precision="mixed")
+    g.step(40)
+    p = g.particles()
+    assert len(p["pid"]) > 1000
+    out = _outside(w, p)
+    assert out.max() < 1e-5, out.max()
+
+
+def _shock_mean_density(precision, seed):
+    w = wl.shock1d()
+    w["seed"] = seed
+    g = _solver(w, precision=precision)
+    g.step(500)
+    acc = np.zeros(w["n_cells"])
+    for _ in range(30):
+        g.step(50)
+        acc += g.fields()[:, 0]
+    return acc / 30
+
+
+def test_mixed_shock_profile_matches_fp64_statistically():
+    """Density averaged over steps 550..2000 of the 1D Ma 3 shock."""
+    a64 = _shock_mean_density("f64", 1)
+    b64 = _shock_mean_density("f64", 2)
+    a32 = _shock_mean_density("mixed", 1)
+    b32 = _shock_mean_density("mixed", 3)
+    norm = np.linalg.norm(a64)
+    spread = np.linalg.norm(a64 - b64) / norm
+    assert spread > 0
+    for x in (a32, b32):
+        assert np.linalg.norm(x - a64) / norm < 3.0 * spread, (np.linalg.norm(x - a64) / norm, spread)
+
+
+def _cylinder_wall(precision, seed):
+    w = wl.cylinder(n_theta=40, n_r=30, n_ref=50, Pr=2.0 / 3.0, seed=seed)
+    g = _solver(w, precision=precision)
+    g.step(1500)
+    surf, cd = g.surface(1)
+    return surf[:, 3:6], cd
+
+
+def test_mixed_cylinder_wall_quantities_match_fp64_statistically():
+    """Cumulative-average C_p, C_F, C_Q and C_d of a coarse Ma 15 cylinder
+    (Shakhov sampling) after 1500 steps."""
+    a64, cda = _cylinder_wall("f64", 1)
+    b64, cdb = _cylinder_wall("f64", 2)
+    a32, cd32 = _cylinder_wall("mixed", 1)
+    for q in range(3):
+        scale = np.linalg.norm(a64[:, q])
+        spread = np.linalg.norm(a64[:, q] - b64[:, q]) / scale
+        err = np.linalg.norm(a32[:, q] - a64[:, q]) / scale
+        assert err < 3.0 * spread + 1e-3, (q, err, spread)
+    assert abs(cd32 - cda) < 3.0 * abs(cdb - cda) + 1e-3 * abs(cda)
