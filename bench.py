@@ -128,6 +128,47 @@ def time_to_residual(a):
     print(json.dumps(out))
 
 
+def precision_study(a):
+    """The Ma 10 flat plate (300 x 200, Kn 0.0169, N_ref 300) run for
+    --study-steps steps from the freestream start: FP64 with seeds 1 and 2 and
+    the mixed path with seeds 1 and 2.  Reports, for the cumulative-average
+    wall C_p, C_F, C_Q (relative L2 norm over the 240 wall faces) and C_d, the
+    mixed path's difference from FP64 seed 1 next to FP64's own difference
+    between the seeds (the statistical spread)."""
+    import numpy as np
+    import torch
+    from paper_2607_09552_amd import Solver
+    runs = {}
+    for prec, seed in (("f64", 1), ("f64", 2), ("mixed", 1), ("mixed", 2)):
+        w = workloads.flat_plate(seed=seed)
+        s = Solver(w, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(a.study_steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        surf, cd = s.surface(1)
+        runs[(prec, seed)] = (surf[:, 3:6].copy(), cd, s.work() / t)
+        print(f"# {prec} seed {seed}: {a.study_steps} steps in {t:.1f} s, C_d {cd:.5f}", file=sys.stderr, flush=True)
+        s.close()
+    ref, cd_ref, _ = runs[("f64", 1)]
+
+    def rel(x):
+        return [float(np.linalg.norm(x[:, q] - ref[:, q]) / np.linalg.norm(ref[:, q])) for q in range(3)]
+    out = {"study": "mixed-precision wall-quantity error, flat plate",
+           "config": {"workload": "flat plate 300x200, Ma 10, Kn 0.0169, VHS omega 0.74, Pr 1, Tw/Tinf 1 diffuse, "
+                                  "N_ref 300, LTS CFL 0.8", "steps": a.study_steps,
+                      "quantities": "cumulative averages over all steps from the freestream start"},
+           "fp64_seed_spread": {"Cp_CF_CQ_rel_l2": rel(runs[("f64", 2)][0]),
+                                "Cd_rel": abs(runs[("f64", 2)][1] - cd_ref) / abs(cd_ref)},
+           "mixed_seed1_vs_fp64_seed1": {"Cp_CF_CQ_rel_l2": rel(runs[("mixed", 1)][0]),
+                                         "Cd_rel": abs(runs[("mixed", 1)][1] - cd_ref) / abs(cd_ref)},
+           "mixed_seed2_vs_fp64_seed1": {"Cp_CF_CQ_rel_l2": rel(runs[("mixed", 2)][0]),
+                                         "Cd_rel": abs(runs[("mixed", 2)][1] - cd_ref) / abs(cd_ref)},
+           "particle_updates_per_s": {f"{k[0]} seed {k[1]}": v[2] for k, v in runs.items()}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +182,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--precision", choices=("f64", "mixed"), default="f64",
                     help="mixed: FP32 particle positions (cell-relative) and velocities, FP64 elsewhere")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="flat plate: wall-quantity error of the mixed path against FP64 and FP64's seed spread")
+    ap.add_argument("--study-steps", type=int, default=20000)
     ap.add_argument("--ttr", action="store_true",
                     help="time to residual: run from the freestream start until r_avg < --ttr-target")
     ap.add_argument("--ttr-target", type=float, default=1e-6)
@@ -162,6 +206,9 @@ def main():
 
     if a.ttr:
         time_to_residual(a)
+        return
+    if a.precision_study:
+        precision_study(a)
         return
     w = workload(a.kn)
     s = Solver(w, precision=a.precision)

@@ -211,6 +211,17 @@ def test_cylinder_full_size_sampled_steps():
     common_state_steps(w, [2, 400])
 
 
+def test_flat_plate_full_size_sampled_steps():
+    """The Ma 10 flat plate at full size (300 x 200 cells graded toward the
+    leading edge and the wall, N_ref 300, Kn 0.0169, inflow, far field,
+    outflow, symmetry and diffuse wall faces): two steps from the freestream
+    start and one step from the state after 300 steps, every particle and
+    cell compared."""
+    w = wl.flat_plate()
+    run_pair(w, [1, 2])
+    common_state_steps(w, [300])
+
+
 def test_capacity_growth_resumes_mid_batch():
     """A store far too small for the particle count: a step that does not fit
     is halted before it modifies anything, the store grows and the step is

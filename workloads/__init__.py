@@ -269,6 +269,61 @@ def cylinder(n_theta=200, n_r=150, r_out=15.0, h1=1e-4, Ma=15.0, Kn=0.01, omega=
     return m
 
 
+def flat_plate(n_up=60, n_plate=240, n_y=200, up=0.25, height=0.5, h_x=1e-3, h_y=5e-5, Ma=10.0, Kn=0.0169,
+               omega=0.74, Pr=1.0, Tw=1.0, n_ref=300, lts=1, seed=1, cfl=0.8):
+    """Hypersonic flow over a flat plate of length 1 with a sharp leading edge
+    at x = 0: x in [-up, 1], y in [0, height]; cells graded geometrically away
+    from the leading edge (first width h_x on both sides) and from the wall
+    (first height h_y).  Inflow (fixed freestream) on the left, far field on
+    top, zero-gradient outflow on the right, symmetry on y = 0 for x < 0 and an
+    isothermal diffuse wall on the plate."""
+    qu = _geometric_ratio(h_x, n_up, up)
+    qp = _geometric_ratio(h_x, n_plate, 1.0)
+    qy = _geometric_ratio(h_y, n_y, height)
+    xu = -graded(n_up, qu, h_x)[::-1]
+    xp = graded(n_plate, qp, h_x)
+    xs = np.concatenate([xu, xp[1:]])
+    ys = graded(n_y, qy, h_y)
+    X, Y = np.meshgrid(xs, ys)
+    nodes, quads = _quads_from_grid(X, Y)
+    ni1 = len(xs)
+    ni, nj = len(xs) - 1, len(ys) - 1
+    U = Ma * math.sqrt(GAMMA_MONATOMIC)
+    bf, bt, bd = [], [], []
+    free = [1.0, U, 0.0, 1.0]
+    for i in range(ni):  # bottom: symmetry upstream, wall on the plate
+        bf.append((i, i + 1))
+        if i < n_up:
+            bt.append(BC_SYMMETRY)
+            bd.append([0.0] * 4)
+        else:
+            bt.append(BC_WALL_DIFFUSE)
+            bd.append([Tw, 0.0, 0.0, 0.0])
+    for i in range(ni):  # top: far field
+        bf.append((nj * ni1 + i, nj * ni1 + i + 1))
+        bt.append(BC_FARFIELD)
+        bd.append(free)
+    for j in range(nj):  # left: inflow; right: outflow
+        bf.append((j * ni1, (j + 1) * ni1))
+        bt.append(BC_FARFIELD)
+        bd.append(free)
+        bf.append((j * ni1 + ni, (j + 1) * ni1 + ni))
+        bt.append(BC_OUTFLOW)
+        bd.append([0.0] * 4)
+    data = _bface_array(len(bf))
+    data[:, :4] = np.array(bd)
+    m = _finish2d(nodes, quads, np.array(bf), np.array(bt, dtype=np.int32), data)
+    m.update(
+        name="flat_plate",
+        stretch=(qu, qp, qy),
+        gas=dict(R=1.0, omega=omega, mu_ref=vhs_mu(Kn, 1.0, omega), T_ref=1.0, Pr=Pr, D=0),
+        ref=dict(rho_inf=1.0, u_inf=[U, 0.0], T_inf=1.0, L_ref=1.0),
+        W0=np.tile(conservative(1.0, U, 0.0, 1.0, 2), (m["n_cells"], 1)),
+        **base_params(cfl=cfl, n_ref=n_ref, lts=lts, seed=seed),
+    )
+    return m
+
+
 def uniform2d(mesh, rho=1.0, ux=0.0, uy=0.0, T=1.0, mu_ref=1e-3, omega=0.5, Pr=1.0, n_ref=50,
               lts=1, seed=1, cfl=0.8):
     m = dict(mesh)
