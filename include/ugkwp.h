@@ -95,13 +95,35 @@ typedef struct {
  * clockwise cell, bad parameters), ENUMERIC (invalid W0), EDEVICE, ENOMEM. */
 int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double *W0, ugkwp_ctx **out);
 
+/* A batch of independent cases in one context: the cases' meshes are joined
+ * into one disjoint mesh and every step advances all of them together.  Each
+ * case is computed exactly as if alone with its own parameters: its particle
+ * ids use its own cell and boundary-face numbering and its random numbers its
+ * own seed, so case k of a batch gives the results of ugkwp_init with
+ * meshes[k], params[k], W0[k].  All cases must share dim (2), the gas (R,
+ * omega, T_ref, Pr, D), cfl, n_ref, lts, precision and stream; mu_ref, seed,
+ * the freestream reference and capacity may differ.  W0[k] is
+ * [meshes[k].n_cells*4].  Errors as ugkwp_init, EINVAL for mismatched shared
+ * parameters. */
+int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_params *params,
+                     const double *const *W0, ugkwp_ctx **out);
+/* Cell range of case k in the joined mesh (fields and particles of the batch
+ * are indexed by it) and its range in the list of wall faces. */
+int ugkwp_case_range(ugkwp_ctx *ctx, int32_t case_id, int64_t *first_cell, int64_t *n_cells, int64_t *first_wall,
+                     int64_t *n_wall);
+/* Residuals (as ugkwp_residual) and wall quantities (as ugkwp_surface) of one
+ * case of a batch. */
+int ugkwp_case_residual(ugkwp_ctx *ctx, int32_t case_id, double *r_inst, double *r_avg);
+int ugkwp_case_surface(ugkwp_ctx *ctx, int32_t case_id, int32_t mode, double *out, int64_t cap, int64_t *n_wall,
+                       double *Cd);
+
 /* Advances n_steps UGKWP-LTS steps (Secs. III.C, IV.B).  Errors: ENUMERIC
  * (invalid cell state at the start of a step, runaway tracking), EOVERFLOW
  * (more than 2^20 particles born in one cell), ENOMEM, EDEVICE. */
 int ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps);
 
 /* Advances until the residual target is met: stops after the first step
- * n >= 100 whose r_avg (see ugkwp_residual) is below r_avg_target (the
+ * n >= 100 whose r_avg (see ugkwp_residual; every case's for a batch) is below r_avg_target (the
  * convergence rule used for time-to-residual), or after max_steps steps.
  * *converged = 1 if the target was met; the step count is that of
  * ugkwp_residual.  The test runs on the device after every step.  Errors as
@@ -110,7 +132,8 @@ int ugkwp_step_until(ugkwp_ctx *ctx, double r_avg_target, int32_t max_steps, int
 
 /* Residuals after the last step (the paper defines none; reading): r_inst is
  * the area-weighted RMS of the last density change over rho_inf, r_avg the
- * same for the running mean of the density over all steps.  step = steps done. */
+ * same for the running mean of the density over all steps.  step = steps done.
+ * For a batch: the largest over the cases. */
 int ugkwp_residual(ugkwp_ctx *ctx, double *r_inst, double *r_avg, int64_t *step);
 
 /* Wall quantities of Sec. V (diffuse-wall faces in boundary-list order):
@@ -118,6 +141,7 @@ int ugkwp_residual(ugkwp_ctx *ctx, double *r_inst, double *r_avg, int64_t *step)
  * coefficient C_d = F_d / (rho_inf U_inf^2 L_ref / 2) (Sec. V.B).
  * mode 0: last step; 1: mean over all steps; 2: exponential moving average
  * with alpha = 2/1001 (Sec. V.A).  out may be NULL to query n_wall.
+ * For a batch: case 0 (see ugkwp_case_surface).
  * Errors: ESTATE before the first step, EOVERFLOW if cap < n_wall. */
 int ugkwp_surface(ugkwp_ctx *ctx, int32_t mode, double *out, int64_t cap, int64_t *n_wall, double *Cd);
 

@@ -20,7 +20,7 @@ BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
 
 # Every entry point declared in include/ugkwp.h.
 ABI_SYMBOLS = (
-    "ugkwp_init", "ugkwp_step", "ugkwp_step_until", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
+    "ugkwp_init", "ugkwp_init_batch", "ugkwp_case_range", "ugkwp_case_residual", "ugkwp_case_surface", "ugkwp_step", "ugkwp_step_until", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
     "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_last_error", "ugkwp_free",
@@ -64,6 +64,10 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     vp, dp, i64p, i32p, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)
     L.ugkwp_init.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.POINTER(vp)]
+    L.ugkwp_init_batch.argtypes = [C.c_int32, C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(dp), C.POINTER(vp)]
+    L.ugkwp_case_range.argtypes = [vp, C.c_int32, i64p, i64p, i64p, i64p]
+    L.ugkwp_case_residual.argtypes = [vp, C.c_int32, dp, dp]
+    L.ugkwp_case_surface.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64, i64p, dp]
     L.ugkwp_step.argtypes = [vp, C.c_int32]
     L.ugkwp_step_until.argtypes = [vp, C.c_double, C.c_int32, i32p]
     L.ugkwp_residual.argtypes = [vp, dp, dp, i64p]
@@ -104,25 +108,54 @@ class Solver:
     or None for the library's own stream.
     """
 
-    def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64"):
+    def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64", batch=None):
         L = load_library()
-        self.dim = int(wl["dim"])
+        self._keep = []
+        if batch is None:
+            m, p, W = self._marshal(wl, W0, stream, particle_capacity, precision)
+            self.dim, self.nc, self.ncase = int(wl["dim"]), int(wl["n_cells"]), 1
+            h = C.c_void_p()
+            rc = L.ugkwp_init(C.byref(m), C.byref(p), _ptr(W), C.byref(h))
+        else:
+            # a batch of independent cases (2D): `batch` is a list of workloads
+            n = len(batch)
+            ms, ps = (_Mesh * n)(), (_Params * n)()
+            ws = (C.POINTER(C.c_double) * n)()
+            for k, w in enumerate(batch):
+                ms[k], ps[k], W = self._marshal(w, None, stream, particle_capacity, precision)
+                ws[k] = _ptr(W)
+            self.dim, self.nc, self.ncase = 2, int(sum(w["n_cells"] for w in batch)), n
+            h = C.c_void_p()
+            rc = L.ugkwp_init_batch(n, ms, ps, ws, C.byref(h))
         self.nw = self.dim + 2
-        self.nc = int(wl["n_cells"])
-        keep = []
+        self.h = h
+        if rc != OK:
+            msg = L.ugkwp_last_error(h).decode() if h.value else ""
+            self.close()
+            raise UgkwpError(rc, msg)
+
+    @classmethod
+    def batch(cls, workloads, **kw):
+        """One context holding independent cases; case k gives the results of
+        Solver(workloads[k]) (same seeds)."""
+        return cls(None, batch=list(workloads), **kw)
+
+    def _marshal(self, wl, W0, stream, particle_capacity, precision):
+        keep = self._keep
 
         def arr(a, dt):
             x = np.ascontiguousarray(a, dtype=dt)
             keep.append(x)
             return x
 
+        dim = int(wl["dim"])
         m = _Mesh()
-        m.dim = self.dim
+        m.dim = dim
         nodes = arr(wl["nodes"], np.float64).ravel()
-        m.n_nodes = len(nodes) // self.dim
+        m.n_nodes = len(nodes) // dim
         m.nodes = _vp(nodes)
-        m.n_cells = self.nc
-        if self.dim == 2:
+        m.n_cells = int(wl["n_cells"])
+        if dim == 2:
             m.cell_ptr = _vp(arr(wl["cell_ptr"], np.int64))
             m.cell_nodes = _vp(arr(wl["cell_nodes"], np.int64))
         bt = arr(wl["bface_type"], np.int32)
@@ -137,13 +170,26 @@ class Solver:
                     particle_capacity=particle_capacity, stream=stream,
                     precision={"f64": 0, "mixed": 1}[precision])
         W = arr(wl["W0"] if W0 is None else W0, np.float64).ravel()
-        h = C.c_void_p()
-        rc = L.ugkwp_init(C.byref(m), C.byref(p), _ptr(W), C.byref(h))
-        self.h = h
-        if rc != OK:
-            msg = L.ugkwp_last_error(h).decode() if h.value else ""
-            self.close()
-            raise UgkwpError(rc, msg)
+        return m, p, W
+
+    def case_range(self, k):
+        """(first cell, cells, first wall face, wall faces) of case k."""
+        v = [C.c_int64() for _ in range(4)]
+        self._check(load_library().ugkwp_case_range(self.h, k, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def case_residual(self, k):
+        a, b = C.c_double(), C.c_double()
+        self._check(load_library().ugkwp_case_residual(self.h, k, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def case_surface(self, k, mode=0):
+        L = load_library()
+        nw, cd = C.c_int64(), C.c_double()
+        self._check(L.ugkwp_case_surface(self.h, k, mode, None, 0, C.byref(nw), C.byref(cd)))
+        out = np.zeros((nw.value, 6))
+        self._check(L.ugkwp_case_surface(self.h, k, mode, _ptr(out), nw.value, C.byref(nw), C.byref(cd)))
+        return out, cd.value
 
     def _check(self, rc):
         if rc != OK:

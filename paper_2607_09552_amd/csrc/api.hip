@@ -73,6 +73,14 @@ struct ugkwp_ctx {
   float4 *lfn32 = nullptr;
   float2 *lda = nullptr;
   std::vector<double> h_anchor;  // [nc*2]
+  // cases (one unless built by ugkwp_init_batch)
+  int ncase = 1;
+  std::vector<int64_t> h_case_cell, h_case_bface;  // [ncase + 1]
+  std::vector<double> h_case_par;                  // [ncase * kCaseN]
+  int *ccase = nullptr;
+  int64_t *case_cell = nullptr, *case_bface = nullptr;
+  uint64_t *case_seed = nullptr;
+  double *case_par = nullptr;
   int64_t cap = 0, n_ret = 0, step = 0;
   int64_t last_total = 0, last_new = 0, last_need = 0, last_need_new = 0;
   int64_t est_total = 0, est_new = 0, est_kept = 0;  // byte-model estimates for the profiler
@@ -115,6 +123,12 @@ struct ugkwp_ctx {
     g.bdata = bdata;
     g.wall_b = wall_b;
     g.anchor = anchor;
+    g.ncase = ncase;
+    g.ccase = ccase;
+    g.case_cell = case_cell;
+    g.case_bface = case_bface;
+    g.case_seed = case_seed;
+    g.case_par = case_par;
     g.lfn32 = lfn32;
     g.lda = lda;
     return g;
@@ -583,8 +597,8 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
     z.add(S.Scol, nc * NW * 2);
     z.add(S.count, nc);
     z.add(S.wimp, std::max<int64_t>(nb, 1) * 3 * 2);
-    z.add(S.resid, 3 * 2);
-    z.add(S.cdsum, 2);
+    z.add(S.resid, 3 * 2 * c->ncase);
+    z.add(S.cdsum, 2 * c->ncase);
     z.add(S.nghost, 2);
     z.add(S.stats, kStatSlots * kStatN * 2);
     z.launch(c);
@@ -669,7 +683,8 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
     ProfScope ps(c, kKSurface, 150.0 * c->nwall);
     hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S);
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, c->stream, c->P, S, nc);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(std::min(1024, (c->ncase + 63) / 64 * 64)), 0, c->stream, g, c->P, S,
+                     nc);
   HIPCHK(hipGetLastError());
   swap_buffers(c);
   return UGKWP_OK;
@@ -712,19 +727,44 @@ int sync_counts(ugkwp_ctx *c) {
 // ===========================================================================
 extern "C" {
 
-int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, ugkwp_ctx **out) {
-  if (!out) return UGKWP_EINVAL;
-  *out = nullptr;
-  ugkwp_ctx *c = new (std::nothrow) ugkwp_ctx();
-  if (!c) return UGKWP_ENOMEM;
-  *out = c;
-  if (!mesh || !par || !W0) return set_err(c, UGKWP_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+
+bool params_ok(const ugkwp_params *par) {
+  return par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
+         par->D >= 0 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
+}
+
+// Per-case table row of a parameter set.
+void case_row(const ugkwp_params *q, double *row) {
+  const double U = std::sqrt(q->u_inf_x * q->u_inf_x + q->u_inf_y * q->u_inf_y);
+  row[kCaseMu] = q->mu_ref;
+  row[kCaseRho] = q->rho_inf;
+  row[kCaseT] = q->T_inf;
+  row[kCaseU] = U;
+  row[kCaseEx] = q->u_inf_x / U;
+  row[kCaseEy] = q->u_inf_y / U;
+  row[kCaseL] = q->L_ref;
+}
+
+// Builds a context for `mesh` (for a batch, the disjoint union of the cases'
+// meshes) with the shared parameters of `par` and, for a batch, the cases'
+// cell and boundary-face ranges, seeds and per-case table.
+int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, int ncase,
+              const std::vector<int64_t> &case_cell, const std::vector<int64_t> &case_bface,
+              const std::vector<uint64_t> &seeds, const std::vector<double> &case_par) {
   if (mesh->dim != 1 && mesh->dim != 2) return set_err(c, UGKWP_EINVAL, "dim must be 1 or 2");
-  if (mesh->n_cells <= 0 || mesh->n_cells >= (1 << 24) - 1 - mesh->n_bfaces)
-    return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces must be in [1, 2^24)");
-  if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-        par->D >= 0 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0))
-    return set_err(c, UGKWP_EINVAL, "invalid parameters");
+  if (mesh->n_cells <= 0 || mesh->n_cells >= (int64_t{1} << 31) - 1 - mesh->n_bfaces)
+    return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces must be in [1, 2^31)");
+  for (int k = 0; k < ncase; ++k)
+    if ((case_cell[k + 1] - case_cell[k]) + (case_bface[k + 1] - case_bface[k]) >= (1 << 24) - 1)
+      return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces of a case must be below 2^24");
+  if (!params_ok(par)) return set_err(c, UGKWP_EINVAL, "invalid parameters");
+  c->ncase = ncase;
+  c->h_case_cell = case_cell;
+  c->h_case_bface = case_bface;
+  c->h_case_par = case_par;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return set_err(c, UGKWP_EDEVICE, "no HIP device");
   c->dim = mesh->dim;
@@ -794,6 +834,15 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   std::vector<double4> fxi4(c->nf);
   for (int64_t f = 0; f < c->nf; ++f) fxi4[f] = make_double4(h.fxi[4 * f], h.fxi[4 * f + 1], h.fxi[4 * f + 2], h.fxi[4 * f + 3]);
   std::vector<double> bdata(mesh->bface_data, mesh->bface_data + nb * 8);
+  if (ncase > 1) {
+    std::vector<int> cc(nc);
+    for (int k = 0; k < ncase; ++k)
+      for (int64_t i = case_cell[k]; i < case_cell[k + 1]; ++i) cc[i] = k;
+    if ((rc = upload(c, &c->ccase, cc)) || (rc = upload(c, &c->case_cell, case_cell)) ||
+        (rc = upload(c, &c->case_bface, case_bface)) || (rc = upload(c, &c->case_seed, seeds)) ||
+        (rc = upload(c, &c->case_par, case_par)))
+      return rc;
+  }
   if ((rc = upload(c, &c->lfn, lfn4)) || (rc = upload(c, &c->lfs, lfs)) || (rc = upload(c, &c->lnb, h.lnb)) || (rc = upload(c, &c->lface, h.lface)) ||
       (rc = upload(c, &c->nv, h.nv)) || (rc = upload(c, &c->vol, h.vol)) || (rc = upload(c, &c->cverts, cv2)) ||
       (rc = upload(c, &c->fL, h.fL)) || (rc = upload(c, &c->fR, h.fR)) || (rc = upload(c, &c->fLL, h.fLL)) ||
@@ -814,9 +863,9 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
       dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
       dalloc(c, &S.nghost, 1) || dalloc(c, &S.count, nc) || dalloc(c, &S.coff, nc + 1) || dalloc(c, &S.Fs, c->nf * nw) ||
       dalloc(c, &S.rho_prev, nc) || dalloc(c, &S.rho_sum, nc) || dalloc(c, &S.rho_mean_prev, nc) ||
-      dalloc(c, &S.resid, 3) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
+      dalloc(c, &S.resid, 3 * ncase) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
       dalloc(c, &S.wlast, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.wsum, std::max<int64_t>(c->nwall, 1) * 3) ||
-      dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, 1) || dalloc(c, &S.scal, kScalN) ||
+      dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, ncase) || dalloc(c, &S.scal, ncase * kScalN) ||
       dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1) || dalloc(c, &S.halt, 1) ||
       dalloc(c, &S.dstep, 1) || dalloc(c, &S.info, kInfoN))
     return set_err(c, UGKWP_ENOMEM, "device allocation failed");
@@ -834,7 +883,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipMemsetAsync(S.wsum, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.wlast, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.wema, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.scal, 0, kScalN * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.scal, 0, ncase * kScalN * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.halt, 0, sizeof(int), c->stream));
@@ -863,10 +912,14 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   HIPCHK(hipGetLastError());
   if ((rc = check_flags(c))) return set_err(c, UGKWP_ENUMERIC, "invalid initial state");
   if (!c->lts) {
+    // global time step, Eq. (34): the minimum over each case's cells
     std::vector<double> dt(nc);
     HIPCHK(hipMemcpy(dt.data(), S.dt, nc * sizeof(double), hipMemcpyDeviceToHost));
-    const double m = *std::min_element(dt.begin(), dt.end());
-    std::fill(dt.begin(), dt.end(), m);
+    for (int k = 0; k < ncase; ++k) {
+      const auto a = dt.begin() + case_cell[k], b = dt.begin() + case_cell[k + 1];
+      const double m = *std::min_element(a, b);
+      std::fill(a, b, m);
+    }
     HIPCHK(hipMemcpy(S.dt, dt.data(), nc * sizeof(double), hipMemcpyHostToDevice));
   }
   Geo g2 = c->geo();
@@ -888,6 +941,84 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   if ((rc = ensure_capacity(c, cap0))) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
   return UGKWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, ugkwp_ctx **out) {
+  if (!out) return UGKWP_EINVAL;
+  *out = nullptr;
+  ugkwp_ctx *c = new (std::nothrow) ugkwp_ctx();
+  if (!c) return UGKWP_ENOMEM;
+  *out = c;
+  if (!mesh || !par || !W0) return set_err(c, UGKWP_EINVAL, "null argument");
+  if (!params_ok(par)) return set_err(c, UGKWP_EINVAL, "invalid parameters");
+  std::vector<double> row(kCaseN);
+  case_row(par, row.data());
+  return init_impl(c, mesh, par, W0, 1, {0, mesh->n_cells}, {0, mesh->n_bfaces}, {par->seed}, row);
+}
+
+int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_params *params,
+                     const double *const *W0, ugkwp_ctx **out) {
+  if (!out) return UGKWP_EINVAL;
+  *out = nullptr;
+  ugkwp_ctx *c = new (std::nothrow) ugkwp_ctx();
+  if (!c) return UGKWP_ENOMEM;
+  *out = c;
+  if (n_cases < 1 || !meshes || !params || !W0) return set_err(c, UGKWP_EINVAL, "null argument or no case");
+  const ugkwp_params &p0 = params[0];
+  const ugkwp_mesh &m0 = meshes[0];
+  for (int k = 0; k < n_cases; ++k) {
+    const ugkwp_params &q = params[k];
+    if (!params_ok(&q) || !W0[k] || meshes[k].dim != m0.dim)
+      return set_err(c, UGKWP_EINVAL, "case %d: invalid parameters, mesh or W0", k);
+    if (q.R != p0.R || q.omega != p0.omega || q.T_ref != p0.T_ref || q.Pr != p0.Pr || q.D != p0.D ||
+        q.cfl != p0.cfl || q.n_ref != p0.n_ref || q.lts != p0.lts || q.precision != p0.precision ||
+        q.stream != p0.stream)
+      return set_err(c, UGKWP_EINVAL, "case %d: gas, CFL, N_ref, LTS, precision and stream must equal case 0's", k);
+  }
+  // the disjoint union of the meshes
+  const int dim = m0.dim, nw = dim + 2;
+  std::vector<double> nodes, bdata, W;
+  std::vector<int64_t> cell_ptr{0}, cell_nodes, bnodes;
+  std::vector<int32_t> btype;
+  std::vector<int64_t> case_cell{0}, case_bface{0};
+  std::vector<uint64_t> seeds;
+  std::vector<double> cpar(static_cast<size_t>(n_cases) * kCaseN);
+  int64_t node_off = 0;
+  for (int k = 0; k < n_cases; ++k) {
+    const ugkwp_mesh &m = meshes[k];
+    if (dim == 1) return set_err(c, UGKWP_EINVAL, "batches are 2D");
+    nodes.insert(nodes.end(), m.nodes, m.nodes + m.n_nodes * dim);
+    for (int64_t i = 0; i < m.n_cells; ++i) cell_ptr.push_back(cell_ptr.back() + (m.cell_ptr[i + 1] - m.cell_ptr[i]));
+    for (int64_t q = 0; q < m.cell_ptr[m.n_cells]; ++q) cell_nodes.push_back(m.cell_nodes[q] + node_off);
+    for (int64_t q = 0; q < m.n_bfaces * dim; ++q) bnodes.push_back(m.bface_nodes[q] + node_off);
+    btype.insert(btype.end(), m.bface_type, m.bface_type + m.n_bfaces);
+    bdata.insert(bdata.end(), m.bface_data, m.bface_data + m.n_bfaces * 8);
+    W.insert(W.end(), W0[k], W0[k] + m.n_cells * nw);
+    node_off += m.n_nodes;
+    case_cell.push_back(case_cell.back() + m.n_cells);
+    case_bface.push_back(case_bface.back() + m.n_bfaces);
+    seeds.push_back(params[k].seed);
+    case_row(&params[k], &cpar[static_cast<size_t>(k) * kCaseN]);
+  }
+  ugkwp_mesh u{};
+  u.dim = dim;
+  u.n_nodes = node_off;
+  u.nodes = nodes.data();
+  u.n_cells = case_cell.back();
+  u.cell_ptr = cell_ptr.data();
+  u.cell_nodes = cell_nodes.data();
+  u.n_bfaces = case_bface.back();
+  u.bface_nodes = bnodes.data();
+  u.bface_type = btype.data();
+  u.bface_data = bdata.data();
+  ugkwp_params pu = p0;
+  pu.particle_capacity = 0;
+  for (int k = 0; k < n_cases; ++k) pu.particle_capacity += params[k].particle_capacity;
+  return init_impl(c, &u, &pu, W.data(), n_cases, case_cell, case_bface, seeds, cpar);
 }
 
 }  // extern "C"
@@ -995,46 +1126,87 @@ int ugkwp_step_until(ugkwp_ctx *c, double r_avg_target, int32_t max_steps, int32
 
 int ugkwp_residual(ugkwp_ctx *c, double *r_inst, double *r_avg, int64_t *step) {
   if (!c) return UGKWP_EINVAL;
-  double s[kScalN];
-  HIPCHK(hipMemcpyAsync(s, c->S.scal, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> s(c->ncase * kScalN);
+  HIPCHK(hipMemcpyAsync(s.data(), c->S.scal, s.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (r_inst) *r_inst = s[kScalRinst];
-  if (r_avg) *r_avg = s[kScalRavg];
+  double ri = 0.0, ra = 0.0;
+  for (int k = 0; k < c->ncase; ++k) {
+    ri = std::max(ri, s[k * kScalN + kScalRinst]);
+    ra = std::max(ra, s[k * kScalN + kScalRavg]);
+  }
+  if (r_inst) *r_inst = ri;
+  if (r_avg) *r_avg = ra;
   if (step) *step = c->step;
   return UGKWP_OK;
 }
 
-int ugkwp_surface(ugkwp_ctx *c, int32_t mode, double *out, int64_t cap, int64_t *n_wall, double *Cd) {
-  if (!c || mode < 0 || mode > 2) return UGKWP_EINVAL;
-  if (n_wall) *n_wall = c->nwall;
+int ugkwp_case_residual(ugkwp_ctx *c, int32_t case_id, double *r_inst, double *r_avg) {
+  if (!c || case_id < 0 || case_id >= c->ncase) return UGKWP_EINVAL;
+  double s[kScalN];
+  HIPCHK(hipMemcpyAsync(s, c->S.scal + case_id * kScalN, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (r_inst) *r_inst = s[kScalRinst];
+  if (r_avg) *r_avg = s[kScalRavg];
+  return UGKWP_OK;
+}
+
+int ugkwp_case_range(ugkwp_ctx *c, int32_t case_id, int64_t *first_cell, int64_t *n_cells, int64_t *first_wall,
+                     int64_t *n_wall) {
+  if (!c || case_id < 0 || case_id >= c->ncase) return UGKWP_EINVAL;
+  if (first_cell) *first_cell = c->h_case_cell[case_id];
+  if (n_cells) *n_cells = c->h_case_cell[case_id + 1] - c->h_case_cell[case_id];
+  // wall faces are listed in boundary-face order, so a case's are contiguous
+  int64_t w0 = 0, w1 = 0;
+  for (int64_t k = 0; k < c->nwall; ++k) {
+    const int b = c->h_wall_b[k];
+    if (b < c->h_case_bface[case_id]) w0 = k + 1;
+    if (b < c->h_case_bface[case_id + 1]) w1 = k + 1;
+  }
+  if (first_wall) *first_wall = w0;
+  if (n_wall) *n_wall = w1 - w0;
+  return UGKWP_OK;
+}
+
+int ugkwp_case_surface(ugkwp_ctx *c, int32_t case_id, int32_t mode, double *out, int64_t cap, int64_t *n_wall,
+                       double *Cd) {
+  if (!c || mode < 0 || mode > 2 || case_id < 0 || case_id >= c->ncase) return UGKWP_EINVAL;
+  int64_t w0 = 0, nwc = 0;
+  ugkwp_case_range(c, case_id, nullptr, nullptr, &w0, &nwc);
+  if (n_wall) *n_wall = nwc;
   if (c->step == 0) return set_err(c, UGKWP_ESTATE, "no step done yet");
   double s[kScalN];
-  HIPCHK(hipMemcpyAsync(s, c->S.scal, sizeof s, hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> w(std::max<int64_t>(c->nwall, 1) * 3);
+  HIPCHK(hipMemcpyAsync(s, c->S.scal + case_id * kScalN, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> w(std::max<int64_t>(nwc, 1) * 3);
   const double *src = mode == 0 ? c->S.wlast : mode == 1 ? c->S.wsum : c->S.wema;
-  HIPCHK(hipMemcpyAsync(w.data(), src, w.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (nwc > 0)
+    HIPCHK(hipMemcpyAsync(w.data(), src + 3 * w0, nwc * 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (Cd) *Cd = mode == 0 ? s[kScalCdLast] : mode == 1 ? s[kScalCdSum] / static_cast<double>(c->step) : s[kScalCdEma];
   if (!out) return UGKWP_OK;
-  if (cap < c->nwall) return set_err(c, UGKWP_EOVERFLOW, "surface buffer too small");
-  const Params &P = c->P;
-  const double qd = 0.5 * P.rho_inf * P.U_inf * P.U_inf;
-  const double pinf = P.rho_inf * P.R * P.T_inf;
+  if (cap < nwc) return set_err(c, UGKWP_EOVERFLOW, "surface buffer too small");
+  const double *cp = &c->h_case_par[static_cast<size_t>(case_id) * kCaseN];
+  const double rho_inf = cp[kCaseRho], U = cp[kCaseU];
+  const double qd = 0.5 * rho_inf * U * U;
+  const double pinf = rho_inf * c->P.R * cp[kCaseT];
   const double scale = mode == 1 ? 1.0 / static_cast<double>(c->step) : 1.0;
-  for (int64_t k = 0; k < c->nwall; ++k) {
+  for (int64_t q = 0; q < nwc; ++q) {
+    const int64_t k = w0 + q;
     const int b = c->h_wall_b[k];
     const int64_t l = static_cast<int64_t>(c->h_bcell[b]) * c->NV + c->h_bk[b];
     const int fs = c->h_lface[l];
     const int f = fs >= 0 ? fs : ~fs;
-    const double mx = c->h_face_mid[2 * f], my = c->h_face_mid[2 * f + 1];
-    out[6 * k + 0] = mx;
-    out[6 * k + 1] = my;
-    out[6 * k + 2] = c->h_lfn[l * 4 + 3];
-    out[6 * k + 3] = (w[3 * k] * scale - pinf) / qd;
-    out[6 * k + 4] = w[3 * k + 1] * scale / qd;
-    out[6 * k + 5] = w[3 * k + 2] * scale / (qd * P.U_inf);
+    out[6 * q + 0] = c->h_face_mid[2 * f];
+    out[6 * q + 1] = c->h_face_mid[2 * f + 1];
+    out[6 * q + 2] = c->h_lfn[l * 4 + 3];
+    out[6 * q + 3] = (w[3 * q] * scale - pinf) / qd;
+    out[6 * q + 4] = w[3 * q + 1] * scale / qd;
+    out[6 * q + 5] = w[3 * q + 2] * scale / (qd * U);
   }
   return UGKWP_OK;
+}
+
+int ugkwp_surface(ugkwp_ctx *c, int32_t mode, double *out, int64_t cap, int64_t *n_wall, double *Cd) {
+  return ugkwp_case_surface(c, 0, mode, out, cap, n_wall, Cd);
 }
 
 int ugkwp_get_fields(ugkwp_ctx *c, double *W) {

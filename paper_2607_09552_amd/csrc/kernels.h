@@ -25,6 +25,9 @@ constexpr int kStatSlots = 256;
 // W^h (U^h, sigma = sqrt(R T^h)), the 6 sigma cutoff, R T, the bound B and
 // the target's U, p and heat flux q.
 enum : int { kArUhx = 0, kArUhy, kArSig, kArCmax, kArRT, kArBnd, kArUx, kArUy, kArP, kArQx, kArQy, kArN };
+// Per-case values: viscosity at T_ref and the freestream reference
+// (density, temperature, speed, flow direction, length) of the coefficients.
+enum : int { kCaseMu = 0, kCaseRho, kCaseT, kCaseU, kCaseEx, kCaseEy, kCaseL, kCaseN };
 enum : int { kScalRinst = 0, kScalRavg, kScalCdLast, kScalCdSum, kScalCdEma, kScalTarget, kScalN };
 
 // Mesh tables (device pointers).  Local faces are padded to NV per cell:
@@ -48,6 +51,14 @@ struct Geo {
   const int *bcell, *bk, *btype; // [nb] interior cell, its local face, BC type
   const double *bdata;   // [nb*8]
   const int *wall_b;     // [nwall] boundary face id of each wall face
+  // batches of independent cases (a disjoint union of meshes); ccase is
+  // null for a single case, whose parameters are those of Params
+  int ncase;
+  const int *ccase;           // [nc] case of each cell
+  const int64_t *case_cell;   // [ncase + 1] first cell of each case
+  const int64_t *case_bface;  // [ncase + 1] first boundary face of each case
+  const uint64_t *case_seed;  // [ncase] Philox seed of each case
+  const double *case_par;     // [ncase * kCaseN] per-case gas and reference values
   // mixed precision only (particle positions relative to a cell anchor):
   const double2 *anchor; // [nc] anchor of each cell (its centroid)
   const float4 *lfn32;   // [nc*NV] normal (x, y), offset n.(v_k - anchor) (z), crossing ratio (w)
@@ -88,11 +99,11 @@ struct State {
   int64_t nc_scatter;                   // number of cells (for kernels without Geo)
   double *Fs;                           // [nf*NW] time-averaged face flux times s_j
   double *rho_prev, *rho_sum, *rho_mean_prev;
-  double *resid;                        // [3] residual sums
+  double *resid;                        // [ncase*3] residual sums
   double *wimp;                         // [nb*3] particle impulse x, y and energy at walls
   double *wlast, *wsum, *wema;          // [nwall*3] p, tau, q
-  double *cdsum;                        // drag of the step
-  double *scal;                         // [kScalN]
+  double *cdsum;                        // [ncase] drag of the step
+  double *scal;                         // [ncase*kScalN] per case (the target in case 0's slot)
   int64_t *stats;                       // [kStatSlots * kStatN]
   int *flags;
   int *halt;                            // nonzero: every kernel of later steps returns at once
@@ -133,7 +144,7 @@ __global__ void k_cell_tally(Geo, StoreT<R>, const int64_t *, double *, double *
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State);
 template <int DIM> __global__ void k_surface(Geo, Params, State);
-__global__ void k_finish(Params, State, int64_t);
+__global__ void k_finish(Geo, Params, State, int64_t);
 __global__ void k_check(Geo, State, int64_t, int64_t, int64_t);
 // Up to kZeroMax buffers cleared by one launch (32-bit words each).
 constexpr int kZeroMax = 12;

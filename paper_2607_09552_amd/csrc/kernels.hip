@@ -34,9 +34,20 @@ __device__ __forceinline__ bool prim_ok(const Prim<DIM> &s) {
 }
 
 // tau = mu / p (Eq. (3)), mu = mu_ref (T / T_ref)^omega.
-__device__ __forceinline__ double relax_time(const Params &p, double rho, double T) {
-  const double mu = p.mu_ref * pow(T / p.T_ref, p.omega);
+__device__ __forceinline__ double relax_time(const Params &p, double mu_ref, double rho, double T) {
+  const double mu = mu_ref * pow(T / p.T_ref, p.omega);
   return mu / (rho * p.R * T);
+}
+
+// Cases of a batch: every case is computed as if alone.  A particle's pid
+// uses its case's local cell and boundary-face numbering and its random
+// numbers its case's seed.
+__device__ __forceinline__ int case_of(const Geo &g, int64_t cell) { return g.ccase ? g.ccase[cell] : 0; }
+__device__ __forceinline__ uint64_t case_seed(const Geo &g, const Params &p, int cs) {
+  return g.ccase ? g.case_seed[cs] : p.seed;
+}
+__device__ __forceinline__ double case_val(const Geo &g, int cs, int k, double single) {
+  return g.ccase ? g.case_par[cs * kCaseN + k] : single;
 }
 
 template <int DIM>
@@ -179,7 +190,7 @@ __global__ void k_cell_prep(Geo g, Params p, State st) {
     st.E[i] = 0.0;
     st.hvalid[i] = 0;
   } else {
-    const double tau = relax_time(p, s.rho, s.T);
+    const double tau = relax_time(p, case_val(g, case_of(g, i), kCaseMu, p.mu_ref), s.rho, s.T);
     const double E = exp(-(st.dt[i] / tau));
     st.tau[i] = tau;
     st.E[i] = E;
@@ -274,7 +285,7 @@ __global__ void k_ghost_prep(Geo g, Params p, State st) {
     W[DIM + 1] = ke + 0.5 * p.Nd * d[0] * p.R * d[3];
     for (int q = 0; q < NW; ++q) Wh[q] = W[q];
     hv = 1;
-    tau = relax_time(p, d[0], d[3]);
+    tau = relax_time(p, case_val(g, case_of(g, i), kCaseMu, p.mu_ref), d[0], d[3]);
   } else if (ty == kBcOutflow) {
     for (int q = 0; q < NW; ++q) Wh[q] = W[q] = st.W[static_cast<int64_t>(i) * NW + q];
     hv = 1;
@@ -446,14 +457,14 @@ __device__ __forceinline__ void sample_position(const Geo &g, int64_t cell, uint
 // draws z (calls 2 att, 2 att + 1), rejects beyond 6 sigma, else accepts
 // with probability (1 + phi) / B.  z is set even when rejected.
 template <int DIM>
-__device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a, uint64_t pid, int64_t step,
-                                                uint32_t att, double z[3]) {
-  gauss3(p.seed, pid, step, kVel, 2 * att, z);
+__device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a, uint64_t seed, uint64_t pid,
+                                                int64_t step, uint32_t att, double z[3]) {
+  gauss3(seed, pid, step, kVel, 2 * att, z);
   const double sig = a[kArSig];
   const double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
   if (dz > a[kArCmax]) return false;
   double ea, eb;
-  rng2(p.seed, pid, step, kShakhov, att, ea, eb);
+  rng2(seed, pid, step, kShakhov, att, ea, eb);
   const double RT = a[kArRT];
   const double cx = (a[kArUhx] + sig * z[0]) - a[kArUx], cy = (a[kArUhy] + sig * z[1]) - a[kArUy];
   const double cz = sig * z[2];
@@ -479,16 +490,19 @@ __device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, c
   }
   const int64_t i = lo;
   const int64_t j = k - st.noff[i];
-  const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(i) << 20) |
+  const int cs = case_of(g, i);
+  const uint64_t seed = case_seed(g, p, cs);
+  const int64_t li = g.ccase ? i - g.case_cell[cs] : i;  // cell within its case
+  const uint64_t pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(li) << 20) |
                        static_cast<uint64_t>(j);
   double x, y;
-  sample_position<DIM>(g, i, p.seed, pid, step, x, y);
+  sample_position<DIM>(g, i, seed, pid, step, x, y);
   const int64_t o = n_ret + k;
   store_position<DIM, R>(g, out, o, i, x, y);
   if (p.Pr == 1.0) {
     // Maxwellian of W^h; with Pr != 1 k_sample_shakhov draws z
     double z[3];
-    gauss3(p.seed, pid, step, kVel, 0, z);
+    gauss3(seed, pid, step, kVel, 0, z);
     out.ux[o] = static_cast<R>(z[0]);
     out.uy[o] = static_cast<R>(z[1]);
     out.uz[o] = static_cast<R>(z[2]);
@@ -534,11 +548,12 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     pid = out.pid[o];
     cell = out.cell[o];
   }
+  const uint64_t seed = act ? case_seed(g, p, case_of(g, cell)) : 0;
   bool done = !act;
   for (uint32_t att = 0; att < kShR; ++att) {
     if (!done) {
       double z[3];
-      if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, pid, step, att, z)) {
+      if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step, att, z)) {
         out.ux[o] = static_cast<R>(z[0]);
         out.uy[o] = static_cast<R>(z[1]);
         out.uz[o] = static_cast<R>(z[2]);
@@ -555,6 +570,7 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     const int src = h ? __ffsll(static_cast<long long>(h)) - 1 : -1;
     for (int q = 0; q < 4 && hard; ++q) hard &= hard - 1;  // the chunk taken
     const uint64_t gpid = __shfl(pid, src < 0 ? 0 : src, 64);
+    const uint64_t gseed = __shfl(seed, src < 0 ? 0 : src, 64);
     const int gcell = __shfl(cell, src < 0 ? 0 : src, 64);
     const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
     bool gdone = src < 0;
@@ -563,7 +579,7 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
       const uint32_t att = a + static_cast<uint32_t>(sl);
       double z[3] = {0.0, 0.0, 0.0};
       bool acc = false;
-      if (!gdone && att < 64) acc = shakhov_attempt<DIM>(p, tab, gpid, step, att, z);
+      if (!gdone && att < 64) acc = shakhov_attempt<DIM>(p, tab, gseed, gpid, step, att, z);
       const uint64_t seg = (__ballot(acc) >> (grp * 16)) & 0xffffull;
       if (!gdone) {
         if (seg != 0 || a + 16 >= 64) {
@@ -671,6 +687,10 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
   const double dti = st.dt[i];
   const double2 *v = g.cverts + static_cast<int64_t>(i) * g.NV;
   const int nv = DIM == 2 ? g.nv[i] : 2;
+  // birth "cell" of an injected particle: the face after the case's cells
+  const int cs = case_of(g, i);
+  const uint64_t seed = case_seed(g, p, cs);
+  const int64_t gid = g.ccase ? (g.case_cell[cs + 1] - g.case_cell[cs]) + (b - g.case_bface[cs]) : g.nc + b;
   const double xa = DIM == 2 ? v[kf].x : v[kf].x, ya = DIM == 2 ? v[kf].y : 0.0;
   const double xb = DIM == 2 ? v[(kf + 1) % nv].x : 0.0, yb = DIM == 2 ? v[(kf + 1) % nv].y : 0.0;
   for (int j0 = 0; j0 < N; j0 += 64) {
@@ -679,10 +699,10 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
     double px = 0, py = 0, u0 = 0, u1 = 0, u2 = 0, tr = 0;
     uint64_t pid = 0;
     if (j < N) {
-      pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(g.nc + b) << 20) | static_cast<uint64_t>(j);
+      pid = (static_cast<uint64_t>(step) << 44) | (static_cast<uint64_t>(gid) << 20) | static_cast<uint64_t>(j);
       double e0, e1, z[3];
-      rng2(p.seed, pid, step, kPos, 0, e0, e1);
-      gauss3(p.seed, pid, step, kVel, 0, z);
+      rng2(seed, pid, step, kPos, 0, e0, e1);
+      gauss3(seed, pid, step, kVel, 0, z);
       u0 = s.ux + sg * z[0];
       u1 = s.uy + sg * z[1];
       u2 = sg * z[2];
@@ -770,6 +790,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
     u2 = s.uz[k];
     m = s.m[k];
     const uint64_t pid = s.pid[k];
+    const uint64_t seed = case_seed(g, p, case_of(g, cell));
     // the cell's faces and neighbours, loaded together on entering a cell
     F4 F[NV];
     int nbr[NV];
@@ -782,7 +803,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
     R t;
     if (k < n_ret) {
       double e0, e1;
-      rng2(p.seed, pid, step, kFree, 0, e0, e1);
+      rng2(seed, pid, step, kFree, 0, e0, e1);
       const double sfree = -td.x * log(e0);
       collide = sfree < td.y;
       t = static_cast<R>(collide ? sfree : td.y);
@@ -873,8 +894,8 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       const double Tw = g.bdata[8 * bf];
       const double sw = sqrt(p.R * Tw);
       double e0, e1, e2, e3, z0, z1;
-      rng2(p.seed, pid, step, kWall, static_cast<uint32_t>(2 * hits), e0, e1);
-      rng2(p.seed, pid, step, kWall, static_cast<uint32_t>(2 * hits + 1), e2, e3);
+      rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits), e0, e1);
+      rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits + 1), e2, e3);
       ++hits;
       const double vn = sqrt(-2.0 * p.R * Tw * log(e0));
       box_muller(e1, e2, z0, z1);
@@ -1164,11 +1185,12 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
         ok = prim_ok(prim<DIM>(Wn, p.NR));
       }
       if (!ok) {
-        const double rf = 1e-12 * p.rho_inf;
+        const int cs = case_of(g, i);
+        const double rf = 1e-12 * case_val(g, cs, kCaseRho, p.rho_inf);
 #pragma unroll
         for (int q = 0; q < NW; ++q) Wn[q] = 0.0;
         Wn[0] = rf;
-        Wn[NW - 1] = 0.5 * p.Nd * rf * p.R * p.T_inf;
+        Wn[NW - 1] = 0.5 * p.Nd * rf * p.R * case_val(g, cs, kCaseT, p.T_inf);
       }
     }
 #pragma unroll
@@ -1185,14 +1207,35 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
     st.rho_mean_prev[i] = mean;
     st.rho_prev[i] = rho;
   }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) r[q] = wave_sum(r[q]);
   const uint64_t gm = __ballot(guarded);
-  if (lane_id() == 0) {
+  if (lane_id() == 0 && gm)
+    atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[(blockIdx.x % kStatSlots) * kStatN + kStatGuard]),
+              static_cast<unsigned long long>(__popcll(gm)));
+  if (!g.ccase) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[q], r[q]);
-    if (gm) atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[(blockIdx.x % kStatSlots) * kStatN + kStatGuard]),
-                      static_cast<unsigned long long>(__popcll(gm)));
+    for (int q = 0; q < 3; ++q) r[q] = wave_sum(r[q]);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[q], r[q]);
+    }
+    return;
+  }
+  // a batch: the sums go to the case of each cell (the cells of a case are
+  // contiguous, so a wavefront holds one or two cases)
+  const int key = i < g.nc ? g.ccase[i] : -1;
+  uint64_t todo = __ballot(key >= 0);
+  while (todo) {
+    const int l = __ffsll(static_cast<long long>(todo)) - 1;
+    const int cs = __builtin_amdgcn_readlane(key, l);
+    const bool in = key == cs;
+    double v[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] = wave_sum(in ? r[q] : 0.0);
+    if (lane_id() == l) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[3 * cs + q], v[q]);
+    }
+    todo &= ~__ballot(in);
   }
 }
 
@@ -1222,8 +1265,9 @@ __global__ void k_surface(Geo g, Params p, State st) {
   v[0] = px * nx + py * ny;
   v[1] = py * nx - px * ny;
   v[2] = eF + st.wimp[3 * b + 2] / sdt;
-  const double ex = p.u_inf_x / p.U_inf, ey = p.u_inf_y / p.U_inf;
-  atomicAdd(st.cdsum, (px * ex + py * ey) * s);
+  const int cs = case_of(g, i);
+  const double ex = case_val(g, cs, kCaseEx, p.u_inf_x / p.U_inf), ey = case_val(g, cs, kCaseEy, p.u_inf_y / p.U_inf);
+  atomicAdd(&st.cdsum[cs], (px * ex + py * ey) * s);
   constexpr double a = 2.0 / 1001.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -1236,16 +1280,33 @@ __global__ void k_surface(Geo g, Params p, State st) {
 // scalar bookkeeping after a step: residuals, C_d (last, sum, EMA), the
 // step's particle counts, then the step counter advances (the step is
 // committed).  A runaway track halts later steps.
-__global__ void k_finish(Params p, State st, int64_t nc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || *st.halt) return;
+// Bookkeeping after a step: per case the residuals and C_d (last, sum,
+// EMA), one thread per case; then the step's particle counts, and the step
+// counter advances (the step is committed).  A runaway track halts later
+// steps; so does meeting the residual target (every case's r_avg below it).
+__global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
+  __shared__ int all_below;
+  if (blockIdx.x != 0 || *st.halt) return;
   const int64_t step = *st.dstep;
-  st.scal[kScalRinst] = sqrt(st.resid[0] / st.resid[1]) / p.rho_inf;
-  st.scal[kScalRavg] = sqrt(st.resid[2] / st.resid[1]) / p.rho_inf;
-  const double cd = *st.cdsum / (0.5 * p.rho_inf * p.U_inf * p.U_inf * p.L_ref);
-  constexpr double a = 2.0 / 1001.0;
-  st.scal[kScalCdLast] = cd;
-  st.scal[kScalCdSum] += cd;
-  st.scal[kScalCdEma] = step == 0 ? cd : a * cd + (1.0 - a) * st.scal[kScalCdEma];
+  const double tgt = st.scal[kScalTarget];
+  if (threadIdx.x == 0) all_below = 1;
+  __syncthreads();
+  for (int cs = threadIdx.x; cs < g.ncase; cs += blockDim.x) {
+    double *sc = st.scal + cs * kScalN;
+    const double rho_inf = case_val(g, cs, kCaseRho, p.rho_inf);
+    const double U = case_val(g, cs, kCaseU, p.U_inf), L = case_val(g, cs, kCaseL, p.L_ref);
+    const double *rs = st.resid + 3 * cs;
+    sc[kScalRinst] = sqrt(rs[0] / rs[1]) / rho_inf;
+    sc[kScalRavg] = sqrt(rs[2] / rs[1]) / rho_inf;
+    const double cd = st.cdsum[cs] / (0.5 * rho_inf * U * U * L);
+    constexpr double a = 2.0 / 1001.0;
+    sc[kScalCdLast] = cd;
+    sc[kScalCdSum] += cd;
+    sc[kScalCdEma] = step == 0 ? cd : a * cd + (1.0 - a) * sc[kScalCdEma];
+    if (!(sc[kScalRavg] < tgt)) atomicAnd(&all_below, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const int64_t nnew = st.noff[nc] + *st.nghost;
   const int64_t ntot = st.roff[nc] + nnew;
   st.info[kInfoTotal] = ntot;
@@ -1254,8 +1315,7 @@ __global__ void k_finish(Params p, State st, int64_t nc) {
   *st.dstep = step + 1;
   if (*st.flags & kFlagRunaway) *st.halt = 1;
   // convergence test: the first step n >= 100 with r_avg below the target
-  const double tgt = st.scal[kScalTarget];
-  if (tgt > 0.0 && step + 1 >= 100 && st.scal[kScalRavg] < tgt) {
+  if (tgt > 0.0 && step + 1 >= 100 && all_below) {
     *st.flags |= kFlagConverged;
     *st.halt = 1;
   }

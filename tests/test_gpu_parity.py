@@ -292,3 +292,79 @@ def r_at(w, n):
     r.vol = cell_volumes(w)
     r.step(n)
     return r
+
+
+def _batch_cases():
+    return [wl.cylinder(n_theta=24, n_r=16, Ma=5.0, Kn=0.1, Tw=1.0, n_ref=40, seed=11),
+            wl.cylinder(n_theta=30, n_r=20, Ma=10.0, Kn=0.02, Tw=0.5, n_ref=40, seed=12),
+            wl.cylinder(n_theta=20, n_r=12, Ma=15.0, Kn=0.05, Tw=0.2, n_ref=40, seed=13)]
+
+
+def _compare_case(g, k, r, pg, W, cnt, tag, tol):
+    """Case k of batch g against the oracle r of that case alone."""
+    c0, nck, _, _ = g.case_range(k)
+    assert nck == r.nc
+    assert _field_err(W[c0:c0 + nck], r.fields()) <= tol, tag
+    sel = (pg["cell"] >= c0) & (pg["cell"] < c0 + nck)
+    order = np.argsort(pg["pid"][sel], kind="stable")
+    pr = r.particles()
+    assert np.array_equal(pg["pid"][sel][order], pr["pid"]), tag
+    assert np.array_equal(pg["cell"][sel][order] - c0, pr["cell"]), tag
+    assert np.array_equal(cnt[c0:c0 + nck], r.counts()[0]), tag
+    return sel, order, c0, nck
+
+
+def test_batch_cases_equal_single_case_oracle():
+    """Three uneven cylinders (sizes, Ma, Kn, T_w and seeds differ) in one
+    batch.  Free run: each case's particle ids, cells and per-cell counts
+    equal those of the oracle running the case alone, fields within DRIFT,
+    wall quantities and residuals within 1e-8.  Then one step from the
+    batch's state at step 12 (loaded into a fresh batch and, case by case,
+    into fresh oracles) to the strict bar."""
+    from paper_2607_09552_amd import Solver
+    cases = _batch_cases()
+    g = Solver.batch(cases)
+    refs = [oracle.Oracle(w) for w in cases]
+    done = 0
+    for n in (1, 5, 12):
+        g.step(n - done)
+        for r in refs:
+            r.step(n - done)
+        done = n
+        W, pg, cnt = g.fields(), g.particles(), g.counts()[0]
+        for k, r in enumerate(refs):
+            _compare_case(g, k, r, pg, W, cnt, (n, k), DRIFT)
+            sg, cdg = g.case_surface(k, 1)
+            sr, cdr = r.surface(1)
+            assert np.allclose(sg, sr, rtol=1e-8, atol=1e-8 * np.abs(sr).max()), (n, k)
+            assert abs(cdg - cdr) <= 1e-8 * abs(cdr), (n, k)
+            ig, ag = g.case_residual(k)
+            ir, ar_, _ = r.residual()
+            assert abs(ig - ir) <= 1e-8 * ir and abs(ag - ar_) <= 1e-8 * ar_, (n, k)
+    # strict: one step from a common state
+    W, pg = g.fields(), g.particles()
+    g2 = Solver.batch(cases)
+    g2.set_fields(W)
+    g2.set_particles(pg["pid"], pg["cell"], pg["m"], pg["x"], pg["u"])
+    g2.set_step(12)
+    ors = []
+    for k, w in enumerate(cases):
+        c0, nck, _, _ = g.case_range(k)
+        r = oracle.Oracle(w)
+        r.vol = cell_volumes(w)
+        sel = (pg["cell"] >= c0) & (pg["cell"] < c0 + nck)
+        r.set_fields(W[c0:c0 + nck])
+        r.set_particles(pg["pid"][sel], pg["cell"][sel] - c0, pg["m"][sel], pg["x"][sel], pg["u"][sel])
+        r.set_step(12)
+        r.step(1)
+        ors.append(r)
+    g2.step(1)
+    W2, pg2, cnt2 = g2.fields(), g2.particles(), g2.counts()[0]
+    Smg, Spg = g2.tally()
+    for k, r in enumerate(ors):
+        sel, order, c0, nck = _compare_case(g2, k, r, pg2, W2, cnt2, ("common", k), TOL)
+        Smr, Spr = r.tally()
+        Wr = r.fields()
+        v = r.vol[:, None]
+        et = max(_field_err(Wr + Smg[c0:c0 + nck] / v, Wr + Smr / v), _field_err(Wr + Spg[c0:c0 + nck] / v, Wr + Spr / v))
+        assert et <= TOL, ("common tallies", k, et)

@@ -324,6 +324,25 @@ def flat_plate(n_up=60, n_plate=240, n_y=200, up=0.25, height=0.5, h_x=1e-3, h_y
     return m
 
 
+def cylinder_batch(n_cases=64, seed=2, n_ref=200, omega=0.81, Pr=2.0 / 3.0, lts=1, size=1.0):
+    """Independent cylinder cases of uneven size and flow: case k draws
+    u0..u3 uniform in [0, 1) (numpy generator seeded with `seed`):
+    s = 1 + 2 u0 gives an (80 s) x (60 s) O-grid (scaled by `size`),
+    Ma = 5 + 15 u1, Kn = 0.005 * 40^u2, T_w = 0.1 + 0.4 u3; Philox seed
+    1000 + k.  Otherwise as `cylinder`."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n_cases, 4))
+    cases = []
+    for k in range(n_cases):
+        s_ = 1.0 + 2.0 * u[k, 0]
+        nt = max(8, int(round(80 * s_ * size)))
+        nr = max(6, int(round(60 * s_ * size)))
+        m = cylinder(n_theta=nt, n_r=nr, Ma=5.0 + 15.0 * u[k, 1], Kn=0.005 * 40.0 ** u[k, 2], omega=omega, Pr=Pr,
+                     Tw=0.1 + 0.4 * u[k, 3], n_ref=n_ref, lts=lts, seed=1000 + k)
+        cases.append(m)
+    return cases
+
+
 def uniform2d(mesh, rho=1.0, ux=0.0, uy=0.0, T=1.0, mu_ref=1e-3, omega=0.5, Pr=1.0, n_ref=50,
               lts=1, seed=1, cfl=0.8):
     m = dict(mesh)
