@@ -180,6 +180,21 @@ int ugkwp_set_step(ugkwp_ctx *ctx, int64_t step);
  * after (W^{p,+} Omega) transport, Eq. (30), [n_cells*(dim+2)] each. */
 int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
 
+/* Launch tuning (results do not depend on it).  batch_steps: steps enqueued
+ * between two host synchronizations (1..1024); use_graph: replay captured
+ * HIP graphs of step pairs instead of launching each kernel (not while
+ * per-kernel timing is on); transport_block: threads per block of the
+ * particle transport (64, 128 or 256); shakhov_first: acceptance-rejection
+ * attempts every lane makes alone before the remaining particles are
+ * shared among 16 lanes each (1..63).  ugkwp_get_tuning returns the
+ * current values (defaults at init: 32, 1, 256, 4); ugkwp_set_tuning sets all
+ * four (EINVAL if one is out of range). */
+typedef struct {
+  int32_t batch_steps, use_graph, transport_block, shakhov_first;
+} ugkwp_tuning;
+int ugkwp_set_tuning(ugkwp_ctx *ctx, const ugkwp_tuning *t);
+int ugkwp_get_tuning(ugkwp_ctx *ctx, ugkwp_tuning *t);
+
 /* Per-kernel timing with HIP events on the library's stream.  enable = 1
  * starts accumulating for every kernel (and resets), 2 for the particle
  * transport kernel only (two events per step, for timing runs), 0 stops.  ugkwp_profile_read returns up

@@ -23,7 +23,7 @@ ABI_SYMBOLS = (
     "ugkwp_init", "ugkwp_init_batch", "ugkwp_case_range", "ugkwp_case_residual", "ugkwp_case_surface", "ugkwp_step", "ugkwp_step_until", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
     "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
-    "ugkwp_last_error", "ugkwp_free",
+    "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
 )
 
 
@@ -39,6 +39,11 @@ class _Mesh(C.Structure):
         ("cell_ptr", C.c_void_p), ("cell_nodes", C.c_void_p), ("n_bfaces", C.c_int64),
         ("bface_nodes", C.c_void_p), ("bface_type", C.c_void_p), ("bface_data", C.c_void_p),
     ]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("batch_steps", C.c_int32), ("use_graph", C.c_int32), ("transport_block", C.c_int32),
+                ("shakhov_first", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -83,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_set_fields.argtypes = [vp, dp]
     L.ugkwp_set_step.argtypes = [vp, C.c_int64]
     L.ugkwp_profile.argtypes = [vp, C.c_int32]
+    L.ugkwp_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    L.ugkwp_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.ugkwp_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_char_p), dp, i64p, dp, i32p]
     L.ugkwp_last_error.argtypes = [vp]
     L.ugkwp_last_error.restype = C.c_char_p
@@ -108,7 +115,7 @@ class Solver:
     or None for the library's own stream.
     """
 
-    def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64", batch=None):
+    def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64", batch=None, tuned=True):
         L = load_library()
         self._keep = []
         if batch is None:
@@ -133,6 +140,12 @@ class Solver:
             msg = L.ugkwp_last_error(h).decode() if h.value else ""
             self.close()
             raise UgkwpError(rc, msg)
+        if tuned:
+            from .autotune import load_tuning
+            name = (wl or batch[0]).get("name") if (wl or batch) else None
+            best = load_tuning(name) if name else None
+            if best:
+                self.set_tuning(**best)
 
     @classmethod
     def batch(cls, workloads, **kw):
@@ -280,6 +293,17 @@ class Solver:
         Sp = np.zeros((self.nc, self.nw))
         self._check(load_library().ugkwp_get_tally(self.h, _ptr(Sm), _ptr(Sp)))
         return Sm, Sp
+
+    def tuning(self):
+        t = _Tuning()
+        self._check(load_library().ugkwp_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = _Tuning(**cur)
+        self._check(load_library().ugkwp_set_tuning(self.h, C.byref(t)))
 
     def profile(self, enable=True, transport_only=False):
         mode = 0 if not enable else (2 if transport_only else 1)

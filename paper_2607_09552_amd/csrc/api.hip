@@ -13,8 +13,6 @@
 
 using namespace ugk;
 
-// steps enqueued between two host synchronizations
-constexpr int32_t kBatchSteps = 32;
 
 namespace {
 
@@ -90,7 +88,13 @@ struct ugkwp_ctx {
   int64_t *pinned = nullptr;     // host pinned mailbox
   std::vector<void *> allocs;
   // profiling
-  bool prof = false, prof_all = false;  // events around every kernel, or the transport only
+  bool prof = false, prof_all = false;
+  // tuning
+  int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_first = 4;
+  // captured graph of two steps and the launch arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;  // events around every kernel, or the transport only
   std::vector<hipEvent_t> ev_pool;
   std::vector<ProfRec> prof_pending;
   double prof_ms[kKCount] = {0};
@@ -462,15 +466,22 @@ int build_mesh(ugkwp_ctx *c, const ugkwp_mesh *m, HostMesh &h) {
 // ---------------------------------------------------------------------------
 // scan helper: out[0..n] = exclusive scan of in[0..n), out[n] = total
 // ---------------------------------------------------------------------------
+// Block sums of an exclusive scan of up to n values, reserved at init (no
+// allocation may happen while a graph is being captured).
+int reserve_scan(ugkwp_ctx *c, int64_t n) {
+  const int64_t nblocks = std::max<int64_t>(1, (n + kScanBlock) / kScanBlock);
+  if (nblocks + 1 <= c->scan_tmp_n) return UGKWP_OK;
+  dfree(c, c->scan_tmp);
+  c->scan_tmp = nullptr;
+  int rc = dalloc(c, &c->scan_tmp, static_cast<size_t>(nblocks + 1));
+  if (rc) return rc;
+  c->scan_tmp_n = nblocks + 1;
+  return UGKWP_OK;
+}
+
 int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
   const int64_t nblocks = std::max<int64_t>(1, (n + kScanBlock) / kScanBlock);
-  if (nblocks + 1 > c->scan_tmp_n) {
-    dfree(c, c->scan_tmp);
-    c->scan_tmp = nullptr;
-    int rc = dalloc(c, &c->scan_tmp, static_cast<size_t>(nblocks + 1));
-    if (rc) return rc;
-    c->scan_tmp_n = nblocks + 1;
-  }
+  if (nblocks + 1 > c->scan_tmp_n) return set_err(c, UGKWP_EDEVICE, "scan of %lld values exceeds its reserve", (long long)n);
   ProfScope ps(c, kKScan, 12.0 * static_cast<double>(n));
   hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanBlock), 0, c->stream, in, n, out, c->scan_tmp,
                      c->S.halt);
@@ -627,7 +638,8 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
   }
   if (c->P.Pr != 1.0) {
     ProfScope ps(c, kKSampleShakhov, 40.0 * c->est_new);
-    hipLaunchKernelGGL((k_sample_shakhov<DIM, R>), dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, A, c->cap);
+    hipLaunchKernelGGL((k_sample_shakhov<DIM, R>), dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, A, c->cap,
+                       static_cast<uint32_t>(c->shakhov_first));
   }
   {
     ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
@@ -643,7 +655,7 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
     // transport reads a record and writes x, (y), m, cell and the keep flag
     const double wr = DIM * static_cast<double>(sizeof(R)) + 16.0;
     ProfScope ps(c, kKTransport, (rec + wr) * c->est_total);
-    const dim3 gr(gcap), bl(256);
+    const dim3 gr(nblk(c->cover, c->transport_block)), bl(c->transport_block);
     if (DIM == 1) {
       hipLaunchKernelGGL((k_transport<DIM, 2, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap);
     } else {
@@ -897,6 +909,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
     HIPCHK(hipMemcpyAsync(S.rho_prev, r.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
+  if ((rc = reserve_scan(c, nc + nb))) return rc;
   void *pin = nullptr;
   HIPCHK(hipHostMalloc(&pin, 8 * sizeof(int64_t), hipHostMallocDefault));
   c->pinned = static_cast<int64_t *>(pin);
@@ -1030,11 +1043,53 @@ namespace {
 int plan_launches(ugkwp_ctx *c, int64_t need, int64_t need_new) {
   int rc = ensure_capacity(c, need);
   if (rc) return rc;
-  c->cover = std::min<int64_t>(c->cap, need + need / 8 + 65536);
-  c->cover_new = need_new + need_new / 8 + 16384;
+  // rounded up so that the launch arguments, and a captured graph, stay the
+  // same from batch to batch while the counts fluctuate
+  const int64_t q = int64_t{1} << 17, qn = int64_t{1} << 14;
+  c->cover = std::min<int64_t>(c->cap, (need + need / 8 + 65536 + q - 1) / q * q);
+  c->cover_new = (need_new + need_new / 8 + 16384 + qn - 1) / qn * qn;
   c->est_total = std::max<int64_t>(c->last_total, 1);
   c->est_new = std::max<int64_t>(c->last_new, 1);
   c->est_kept = std::max<int64_t>(c->n_ret, 1);
+  return UGKWP_OK;
+}
+
+void drop_graph(ugkwp_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey.clear();
+}
+
+// The launch arguments a two-step graph bakes in: buffer addresses (they
+// change when the store grows), capacity, grid coverage and tuning.
+std::vector<int64_t> graph_key(const ugkwp_ctx *c) {
+  return {reinterpret_cast<int64_t>(c->A.x), reinterpret_cast<int64_t>(c->B.x), reinterpret_cast<int64_t>(c->A32.x),
+          reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.rank),
+          c->cap, c->cover, c->cover_new, c->transport_block, c->shakhov_first};
+}
+
+// Captures two steps into a graph (the double-buffer swaps of two steps
+// leave every pointer as it was, so the graph can be replayed), unless one
+// with the same arguments exists.  The step sequence has no memset nodes.
+int ensure_graph(ugkwp_ctx *c) {
+  const std::vector<int64_t> key = graph_key(c);
+  if (c->gexec && key == c->gkey) return UGKWP_OK;
+  drop_graph(c);
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue(c);
+  if (!rc) rc = enqueue(c);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return set_err(c, UGKWP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  c->graph = gr;
+  HIPCHK(hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
+  c->gkey = key;
   return UGKWP_OK;
 }
 
@@ -1050,9 +1105,15 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
   if (rc) return rc;
   int32_t done = 0;
   while (done < n_steps) {
-    const int32_t batch = std::min<int32_t>(n_steps - done, kBatchSteps);
+    const int32_t batch = std::min<int32_t>(n_steps - done, c->batch_steps);
     const int64_t step0 = c->step;
-    for (int32_t k = 0; k < batch; ++k) {
+    int32_t k = 0;
+    if (c->use_graph && !c->prof && batch >= 2) {
+      rc = ensure_graph(c);
+      if (rc) return rc;
+      for (; k + 2 <= batch; k += 2) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    }
+    for (; k < batch; ++k) {
       rc = enqueue(c);
       if (rc) return rc;
     }
@@ -1446,6 +1507,28 @@ int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
   return UGKWP_OK;
 }
 
+int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
+  if (!c || !t) return UGKWP_EINVAL;
+  if (t->batch_steps < 1 || t->batch_steps > 1024 || (t->use_graph != 0 && t->use_graph != 1) ||
+      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) || t->shakhov_first < 1 ||
+      t->shakhov_first > 63)
+    return set_err(c, UGKWP_EINVAL, "tuning value out of range");
+  c->batch_steps = t->batch_steps;
+  c->use_graph = t->use_graph;
+  c->transport_block = t->transport_block;
+  c->shakhov_first = t->shakhov_first;
+  return UGKWP_OK;
+}
+
+int ugkwp_get_tuning(ugkwp_ctx *c, ugkwp_tuning *t) {
+  if (!c || !t) return UGKWP_EINVAL;
+  t->batch_steps = c->batch_steps;
+  t->use_graph = c->use_graph;
+  t->transport_block = c->transport_block;
+  t->shakhov_first = c->shakhov_first;
+  return UGKWP_OK;
+}
+
 int ugkwp_profile(ugkwp_ctx *c, int32_t enable) {
   if (!c) return UGKWP_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1482,6 +1565,7 @@ const char *ugkwp_last_error(const ugkwp_ctx *c) { return c ? c->err.c_str() : "
 void ugkwp_free(ugkwp_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (auto &r : c->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -135,7 +135,7 @@ __global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
 __global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *);
 template <int DIM, class R> __global__ void k_sample_draw(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_match(Geo, Params, State, StoreT<R>, int64_t);
-template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t, uint32_t);
 template <int DIM, class R> __global__ void k_sample_ghosts(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, int NV, class R> __global__ void k_transport(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, int64_t);

@@ -526,13 +526,14 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
 // varies widely (about B, the acceptance bound, and all 64 in near-vacuum
 // cells where B is huge), so a lane-per-particle loop would hold the whole
 // wavefront for its slowest particle.  Instead:
-//  1. every lane tries attempts 0..kShR-1 of its own particle;
+//  1. every lane tries attempts 0..first-1 of its own particle (first in
+//     [1, 63], a tuning parameter);
 //  2. the particles not yet accepted are finished four at a time, 16 lanes
 //     each, which evaluate 16 consecutive attempts of their particle at once
 //     and keep the lowest accepted one.
-constexpr uint32_t kShR = 4;
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
+__global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, StoreT<R> out, int64_t cap,
+                                                        uint32_t first) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc], step = *st.dstep;
   int64_t end = st.noff[g.nc];
@@ -550,7 +551,7 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
   }
   const uint64_t seed = act ? case_seed(g, p, case_of(g, cell)) : 0;
   bool done = !act;
-  for (uint32_t att = 0; att < kShR; ++att) {
+  for (uint32_t att = 0; att < first; ++att) {
     if (!done) {
       double z[3];
       if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step, att, z)) {
@@ -574,7 +575,7 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     const int gcell = __shfl(cell, src < 0 ? 0 : src, 64);
     const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
     bool gdone = src < 0;
-    uint32_t a = kShR;
+    uint32_t a = first;
     while (__ballot(!gdone)) {
       const uint32_t att = a + static_cast<uint32_t>(sl);
       double z[3] = {0.0, 0.0, 0.0};
@@ -1371,7 +1372,7 @@ UGK_INST(2)
 #define UGK_INST_P(D, R)                                                                                  \
   template __global__ void k_sample_draw<D, R>(Geo, Params, State, StoreT<R>, int64_t);                  \
   template __global__ void k_sample_match<D, R>(Geo, Params, State, StoreT<R>, int64_t);                 \
-  template __global__ void k_sample_shakhov<D, R>(Geo, Params, State, StoreT<R>, int64_t);               \
+  template __global__ void k_sample_shakhov<D, R>(Geo, Params, State, StoreT<R>, int64_t, uint32_t);     \
   template __global__ void k_sample_ghosts<D, R>(Geo, Params, State, StoreT<R>, int64_t);                \
   template __global__ void k_transport<D, 2 * D, R>(Geo, Params, State, StoreT<R>, int64_t);            \
   template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, int64_t);                        \

@@ -368,3 +368,36 @@ def test_batch_cases_equal_single_case_oracle():
         v = r.vol[:, None]
         et = max(_field_err(Wr + Smg[c0:c0 + nck] / v, Wr + Smr / v), _field_err(Wr + Spg[c0:c0 + nck] / v, Wr + Spr / v))
         assert et <= TOL, ("common tallies", k, et)
+
+
+def test_graph_replays_match_the_oracle():
+    """Steps replayed from captured two-step graphs (several replays per
+    call, odd step counts finished eagerly, host reads and synchronizations
+    between calls) give the oracle's results at every checkpoint, as the
+    eager launches do; a store that grows mid-run forces a new capture."""
+    w = wl.shock1d()
+    gg = _solver(w)
+    gg.set_tuning(use_graph=1, batch_steps=8)
+    ge = _solver(w)
+    ge.set_tuning(use_graph=0, batch_steps=8)
+    r = oracle.Oracle(w)
+    r.vol = cell_volumes(w)
+    done = 0
+    for n in (4, 9, 16, 40, 41, 100):
+        for s in (gg, ge):
+            s.step(n - done)
+        r.step(n - done)
+        done = n
+        compare(gg, r, f"graph, step {n}", TOL)
+        compare(ge, r, f"eager, step {n}", TOL)
+    w2 = wl.cylinder(n_theta=40, n_r=30, n_ref=50, Pr=2.0 / 3.0)
+    g2 = _solver(w2, particle_capacity=5000)
+    g2.set_tuning(use_graph=1, batch_steps=6)
+    r2 = oracle.Oracle(w2)
+    r2.vol = cell_volumes(w2)
+    done = 0
+    for n in (3, 10, 17):
+        g2.step(n - done)
+        r2.step(n - done)
+        done = n
+        compare(g2, r2, f"graph with growth, step {n}", DRIFT)
