@@ -169,13 +169,53 @@ def precision_study(a):
     print(json.dumps(out))
 
 
+def batch_bench(a):
+    """Throughput of a batch of independent uneven cylinder cases in one
+    context (one launch per kernel for all cases)."""
+    import torch
+    from paper_2607_09552_amd import Solver
+    cases = workloads.cylinder_batch(a.batch)
+    nc = int(sum(w["n_cells"] for w in cases))
+    s = Solver.batch(cases, precision=a.precision)
+    print(f"# batch of {a.batch} cases, {nc} cells; warmup {a.warmup} steps", file=sys.stderr, flush=True)
+    s.step(a.warmup)
+    s.profile(True, transport_only=True)
+    torch.cuda.synchronize()
+    w0 = s.work()
+    t0 = time.perf_counter()
+    s.step(a.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_upd = s.work() - w0
+    tr = s.profile_read()["transport"]
+    s.profile(False)
+    avg_ms = tr["ms"] / max(tr["launches"], 1)
+    bytes_per_launch = TRANSPORT_BYTES[a.precision] * n_upd / max(tr["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out = {"metric": "particle updates/s", "value": n_upd / elapsed, "unit": "particle updates/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if a.precision == "f64" else "f32 particles, f64 cells", "data": "synthetic",
+           "config": {"workload": f"batch of {a.batch} uneven cylinder cases (80x60 to 240x180 O-grids, Ma 5-20, "
+                                  f"Kn 0.005-0.2, Tw/Tinf 0.1-0.5, N_ref 200, LTS), one batched solve",
+                      "cases": a.batch, "cells": nc, "particles_per_step": n_upd / a.steps,
+                      "cell_steps_per_s": nc * a.steps / elapsed},
+           "roofline": {"bound": "hbm", "kernel": "transport", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     # the throughput settles once the bow shock has formed (about 3000 steps
     # from the freestream start); the default times the developed flow
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 1000; 100 with --batch)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 3000; 200 with --batch)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="N > 0: N uneven cylinder cases (80x60 to 240x180, Ma 5-20, Kn 0.005-0.2, N_ref 200) "
+                         "in one batched solve")
     ap.add_argument("--kn", type=float, default=0.01)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -190,6 +230,10 @@ def main():
     ap.add_argument("--ttr-target", type=float, default=1e-6)
     ap.add_argument("--ttr-max-steps", type=int, default=600000)
     a = ap.parse_args()
+    if a.steps is None:
+        a.steps = 100 if a.batch else 1000
+    if a.warmup is None:
+        a.warmup = 200 if a.batch else 3000
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is a "
               "domain-decomposition design, not built.", file=sys.stderr)
@@ -209,6 +253,9 @@ def main():
         return
     if a.precision_study:
         precision_study(a)
+        return
+    if a.batch:
+        batch_bench(a)
         return
     w = workload(a.kn)
     s = Solver(w, precision=a.precision)
