@@ -32,6 +32,8 @@
 #define P_POS 1u
 #define P_VEL 2u
 #define P_WALL 3u
+
+static int is_wall(int32_t ty) { return ty == REF_BC_WALL || ty == REF_BC_WALL_MAXWELL; }
 #define P_SHAKHOV 4u
 
 static const double TWO_PI = 6.283185307179586;
@@ -511,7 +513,7 @@ static int build_mesh(ref_ctx *c, const ref_mesh *m) {
   memcpy(c->btype, m->bface_type, sizeof(int32_t) * (size_t)nb);
   memcpy(c->bdata, m->bface_data, sizeof(double) * (size_t)nb * 8);
   for (int64_t b = 0; b < nb; ++b)
-    if (c->btype[b] < REF_BC_FARFIELD || c->btype[b] > REF_BC_SYMMETRY)
+    if ((c->btype[b] < REF_BC_FARFIELD || c->btype[b] > REF_BC_SYMMETRY) && c->btype[b] != REF_BC_WALL_MAXWELL)
       return fail(c, REF_EINVAL, "boundary face %lld has unknown type %d", (long long)b, c->btype[b]);
 
   if (c->dim == 1) {
@@ -719,12 +721,12 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   c->Fs = xcalloc((size_t)(c->nf * nw), sizeof(double));
   c->count = xcalloc((size_t)nc, sizeof(int32_t));
   c->wimp = xcalloc((size_t)c->nb * 3, sizeof(double));
-  for (int64_t b = 0; b < c->nb; ++b) if (c->btype[b] == REF_BC_WALL) c->nwall++;
+  for (int64_t b = 0; b < c->nb; ++b) if (is_wall(c->btype[b])) c->nwall++;
   c->wall_b = xcalloc((size_t)c->nwall, sizeof(int64_t));
   c->wsurf_last = xcalloc((size_t)c->nwall * 3, sizeof(double));
   c->wsurf_sum = xcalloc((size_t)c->nwall * 3, sizeof(double));
   c->wsurf_ema = xcalloc((size_t)c->nwall * 3, sizeof(double));
-  for (int64_t b = 0, w = 0; b < c->nb; ++b) if (c->btype[b] == REF_BC_WALL) c->wall_b[w++] = b;
+  for (int64_t b = 0, w = 0; b < c->nb; ++b) if (is_wall(c->btype[b])) c->wall_b[w++] = b;
   c->cap = 1024;
   c->P = xcalloc((size_t)c->cap, sizeof(particle));
   *out = c;
@@ -941,13 +943,28 @@ static int track(ref_ctx *c, particle *q, int64_t step, int32_t *ncross_out) {
       }
       continue;
     }
-    /* diffuse wall */
+    /* walls */
     double Tw = c->bdata[8 * b];
     double sw = sqrt(c->p.R * Tw);
     double e0, e1, e2, e3, z0, z1;
     draw2(c->p.seed, q->pid, step, P_WALL, (uint32_t)(2 * hits), &e0, &e1);
     draw2(c->p.seed, q->pid, step, P_WALL, (uint32_t)(2 * hits + 1), &e2, &e3);
     ++hits;
+    if (ty == REF_BC_WALL_MAXWELL && !(e3 < c->bdata[8 * b + 1])) {
+      /* specular part of the Maxwell wall: the impulse goes to the wall */
+      double ub[3] = {q->u[0], q->u[1], q->u[2]};
+      if (c->dim == 2) {
+        double un = q->u[0] * f[0] + q->u[1] * f[1];
+        q->u[0] = q->u[0] - 2.0 * un * f[0];
+        q->u[1] = q->u[1] - 2.0 * un * f[1];
+      } else {
+        q->u[0] = -q->u[0];
+      }
+      c->wimp[3 * b + 0] += q->m * (ub[0] - q->u[0]);
+      c->wimp[3 * b + 1] += q->m * (ub[1] - q->u[1]);
+      continue;
+    }
+    /* diffuse re-emission */
     double vn = sqrt(-2.0 * c->p.R * Tw * log(e0));
     box_muller(e1, e2, &z0, &z1);
     double ub[3] = {q->u[0], q->u[1], q->u[2]};
@@ -1122,7 +1139,8 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         for (int q = 0; q < nw; ++q) g->W[q] = g->Wh[q] = cs[i].W[q];
         g->hvalid = 1;
         g->tau = cs[i].tau;
-      } else if (ty == REF_BC_SYMMETRY) {
+      } else if (ty == REF_BC_SYMMETRY || ty == REF_BC_WALL_MAXWELL) {
+        /* mirror state (the specular part of a Maxwell wall) */
         for (int q = 0; q < nw; ++q) { g->W[q] = cs[i].W[q]; g->Wh[q] = cs[i].Wh[q]; }
         if (dim == 2) {
           double mn = cs[i].W[1] * f[0] + cs[i].W[2] * f[1];
@@ -1377,6 +1395,19 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         to_frame(c, cs[L].Wh, n2, hL);
         if (c->btype[b] == REF_BC_WALL) {
           ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, F);
+        } else if (c->btype[b] == REF_BC_WALL_MAXWELL) {
+          /* Maxwell's wall: alpha times the diffuse-wall flux plus (1 - alpha)
+           * times the specular (mirror-state) flux */
+          double Fd[4], Fs[4], wG[4], hG[4], dW0[4], z[4] = {0, 0, 0, 0};
+          double a = c->bdata[8 * b + 1];
+          ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, Fd);
+          to_frame(c, g->W, n2, wG);
+          to_frame(c, g->Wh, n2, hG);
+          for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xL);
+          ref_flux_interior(wL, wG, dW0, cs[L].hvalid ? hL : NULL, g->hvalid ? hG : NULL, z, z, cs[L].dt,
+                            cs[L].tau, g->dt, g->tau, K, c->p.Pr, Fe, Ff);
+          for (int q = 0; q < 4; ++q) Fs[q] = Fe[q] + Ff[q];
+          for (int q = 0; q < 4; ++q) F[q] = a * Fd[q] + (1.0 - a) * Fs[q];
         } else {
           double wG[4], hG[4], dW0[4], z[4] = {0, 0, 0, 0};
           to_frame(c, g->W, n2, wG);

@@ -32,7 +32,13 @@ extern "C" {
 #endif
 
 enum { REF_OK = 0, REF_EINVAL = -1, REF_ENOMEM = -2, REF_EOVERFLOW = -4, REF_ENUMERIC = -5 };
-enum { REF_BC_FARFIELD = 1, REF_BC_OUTFLOW = 2, REF_BC_WALL = 3, REF_BC_SYMMETRY = 4 };
+/* REF_BC_WALL_MAXWELL: isothermal wall with accommodation alpha (bface_data
+ * T_w, alpha), the boundary condition of the flat-plate case of Sec. V.B: a
+ * fraction alpha of what reaches it is re-emitted diffusely, the rest
+ * reflected specularly.  A particle hit re-emits diffusely when the fourth
+ * uniform of its two WALL draws is below alpha; the wave flux is alpha times
+ * the diffuse wall's plus (1 - alpha) times the mirror-state flux. */
+enum { REF_BC_FARFIELD = 1, REF_BC_OUTFLOW = 2, REF_BC_WALL = 3, REF_BC_SYMMETRY = 4, REF_BC_WALL_MAXWELL = 6 };
 
 typedef struct {
   int32_t dim;                 /* 1 or 2 */

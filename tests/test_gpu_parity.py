@@ -401,3 +401,26 @@ def test_graph_replays_match_the_oracle():
         r2.step(n - done)
         done = n
         compare(g2, r2, f"graph with growth, step {n}", DRIFT)
+
+
+def _polygon_cases():
+    far = [1.0, 1.2, 0.3, 1.0]
+    tri = wl.triangulated_box(wl.graded(14, 1.15), wl.graded(10, 1.2, 0.5), wl.BC_FARFIELD, far)
+    mixed = wl.triangulated_box(wl.graded(14, 1.15), wl.graded(10, 1.2, 0.5), wl.BC_FARFIELD, far, mixed=True)
+    hexa = wl.honeycomb_box(12, 10, 0.5, wl.BC_FARFIELD, far)
+    out = []
+    for k, m in enumerate((tri, mixed, hexa)):
+        w = wl.uniform2d(m, rho=1.0, ux=1.2, uy=0.3, T=1.0, mu_ref=0.05, n_ref=40, seed=20 + k)
+        w["W0"] = wl.perturbed_field(w, amp=0.1, seed=k)
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("k", [0, 1, 2], ids=["triangles", "triangles_and_quads", "clipped_hexagons"])
+def test_unstructured_polygon_meshes(k):
+    """Triangles (3 faces), triangles mixed with quadrilaterals (padded local
+    faces) and a box-clipped honeycomb (3 to 6 faces) with far-field
+    boundaries and a perturbed field."""
+    w = _polygon_cases()[k]
+    run_pair(w, [1, 3, 10])
+    common_state_steps(w, [5])

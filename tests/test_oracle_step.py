@@ -302,3 +302,62 @@ def test_shock_plateaus_continuum_limit():
     T = lambda k: (2 * (W[k, 2] - 0.5 * W[k, 1] ** 2 / W[k, 0])) / (3 * W[k, 0])
     assert abs(T(-1) / T(0) - 11 / 3) < 1e-8
     assert o.counts()[1]["total"] == 0
+
+
+def _cyl():
+    return wl.cylinder(n_theta=24, n_r=16, n_ref=40, Pr=1.0, Ma=5.0, Tw=0.5, Kn=0.1)
+
+
+def _run(w, n):
+    o = oracle.Oracle(w)
+    o.step(n)
+    return o.fields(), o.particles(), o
+
+
+def test_maxwell_wall_full_accommodation_is_the_diffuse_wall():
+    """alpha = 1: every hit re-emits diffusely (the accommodation draw is
+    below 1) and the wave flux is the diffuse wall's: identical runs."""
+    W1, p1, o1 = _run(_cyl(), 12)
+    W2, p2, o2 = _run(wl.with_maxwell_walls(_cyl(), 1.0), 12)
+    assert np.array_equal(W1, W2)
+    for k in ("pid", "cell", "m", "x", "u"):
+        assert np.array_equal(p1[k], p2[k]), k
+    assert np.array_equal(o1.surface(1)[0], o2.surface(1)[0])
+
+
+def test_maxwell_wall_zero_accommodation_is_specular():
+    """alpha = 0: particles reflect specularly and the wave flux is the
+    mirror-state flux, as on a symmetry face: identical fields and particles."""
+    w_sym = _cyl()
+    w_sym["bface_type"] = np.where(w_sym["bface_type"] == wl.BC_WALL_DIFFUSE, wl.BC_SYMMETRY, w_sym["bface_type"]).astype(np.int32)
+    W1, p1, _ = _run(w_sym, 12)
+    W2, p2, o2 = _run(wl.with_maxwell_walls(_cyl(), 0.0), 12)
+    assert np.array_equal(W1, W2)
+    for k in ("pid", "cell", "m", "x", "u"):
+        assert np.array_equal(p1[k], p2[k]), k
+    # the wall still takes the normal impulse of the reflected particles
+    assert np.abs(o2.surface(0)[0][:, 3]).max() > 0
+
+
+def test_maxwell_walls_conserve_time_weighted_mass():
+    """A closed box with Maxwell walls (alpha 0.5, wall temperature different
+    from the gas): mass is neither created nor lost at the walls, so
+    I = sum_i Omega_i rho_i / dt_i stays constant (Eqs. (43), (53)); energy
+    is exchanged with the walls."""
+    box = wl.box2d(wl.graded(5, 1.35), wl.graded(4, 1.6, 0.4), wl.BC_WALL_MAXWELL, [1.7, 0.5])
+    m = wl.uniform2d(box, mu_ref=0.05, n_ref=40, seed=3)
+    rng = np.random.default_rng(3)
+    n = m["n_cells"]
+    m["W0"] = wl.conservative(rng.uniform(0.6, 1.6, n), rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n),
+                              rng.uniform(0.7, 1.4, n), 2)
+    m["ref"]["u_inf"] = [1.0, 0.0]
+    o = oracle.Oracle(m)
+    vol, dt = cell_volumes(m), o.dt()
+    I0 = (vol * o.fields()[:, 0] / dt).sum()
+    E0 = (vol * o.fields()[:, 3] / dt).sum()
+    for _ in range(25):
+        o.step(1)
+        I = (vol * o.fields()[:, 0] / dt).sum()
+        assert abs(I - I0) <= 2e-13 * I0
+    assert abs((vol * o.fields()[:, 3] / dt).sum() - E0) > 1e-6 * E0  # heat exchange with the walls
+    assert o.counts()[1]["total"] > 0

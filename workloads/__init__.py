@@ -32,6 +32,7 @@ BC_FARFIELD = 1
 BC_OUTFLOW = 2
 BC_WALL_DIFFUSE = 3
 BC_SYMMETRY = 4
+BC_WALL_MAXWELL = 6  # bface_data: T_w, accommodation alpha
 
 GAMMA_MONATOMIC = 5.0 / 3.0
 
@@ -343,6 +344,19 @@ def cylinder_batch(n_cases=64, seed=2, n_ref=200, omega=0.81, Pr=2.0 / 3.0, lts=
     return cases
 
 
+def with_maxwell_walls(m, alpha):
+    """A copy of workload m whose diffuse walls become Maxwell walls with
+    accommodation alpha (same wall temperature)."""
+    w = dict(m)
+    bt = m["bface_type"].copy()
+    bd = m["bface_data"].copy()
+    sel = bt == BC_WALL_DIFFUSE
+    bt[sel] = BC_WALL_MAXWELL
+    bd[sel, 1] = alpha
+    w["bface_type"], w["bface_data"] = bt, bd
+    return w
+
+
 def uniform2d(mesh, rho=1.0, ux=0.0, uy=0.0, T=1.0, mu_ref=1e-3, omega=0.5, Pr=1.0, n_ref=50,
               lts=1, seed=1, cfl=0.8):
     m = dict(mesh)
@@ -354,6 +368,113 @@ def uniform2d(mesh, rho=1.0, ux=0.0, uy=0.0, T=1.0, mu_ref=1e-3, omega=0.5, Pr=1
         **base_params(cfl=cfl, n_ref=n_ref, lts=lts, seed=seed),
     )
     return m
+
+
+def _polygon_mesh(nodes, polys, bc, bc_data=None):
+    """Mesh of CCW convex polygons (lists of node ids); every open edge is a
+    boundary face of type bc."""
+    edges = {}
+    for k, poly in enumerate(polys):
+        for a, b in zip(poly, poly[1:] + poly[:1]):
+            key = (min(a, b), max(a, b))
+            edges[key] = edges.get(key, 0) + 1
+    bf = [e for e, n in edges.items() if n == 1]
+    bd = _bface_array(len(bf))
+    if bc_data is not None:
+        bd[:, : len(bc_data)] = bc_data
+    ptr = np.zeros(len(polys) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(p) for p in polys])
+    return dict(
+        dim=2,
+        nodes=np.ascontiguousarray(nodes, dtype=np.float64),
+        n_cells=len(polys),
+        cell_ptr=ptr,
+        cell_nodes=np.array([i for p in polys for i in p], dtype=np.int64),
+        bface_nodes=np.array(bf, dtype=np.int64).reshape(-1, 2),
+        bface_type=np.full(len(bf), bc, dtype=np.int32),
+        bface_data=bd,
+    )
+
+
+def triangulated_box(xs, ys, bc=BC_FARFIELD, bc_data=None, mixed=False):
+    """Tensor-product box with every quad split into two triangles along
+    alternating diagonals; with mixed=True only every other quad is split
+    (triangles and quadrilaterals in one mesh)."""
+    xs = np.asarray(xs, dtype=np.float64)
+    ys = np.asarray(ys, dtype=np.float64)
+    X, Y = np.meshgrid(xs, ys)
+    nodes = np.stack([X.ravel(), Y.ravel()], axis=1)
+    ni1 = len(xs)
+    polys = []
+    for j in range(len(ys) - 1):
+        for i in range(len(xs) - 1):
+            a, b = j * ni1 + i, j * ni1 + i + 1
+            c, d = b + ni1, a + ni1
+            if mixed and (i + j) % 2 == 0:
+                polys.append([a, b, c, d])
+            elif (i + j) % 2 == 0:
+                polys += [[a, b, c], [a, c, d]]
+            else:
+                polys += [[a, b, d], [b, c, d]]
+    return _polygon_mesh(nodes, polys, bc, bc_data)
+
+
+def honeycomb_box(nx, ny, h=1.0, bc=BC_FARFIELD, bc_data=None):
+    """Regular hexagons of side h clipped to the box [0, W] x [0, H] spanned
+    by nx x ny of them: hexagons inside, clipped convex polygons of 3 to 6
+    vertices at the edges."""
+    w = math.sqrt(3.0) * h
+    W, H = nx * w, ny * 1.5 * h
+    pts, polys = {}, []
+
+    def node(x, y):
+        key = (round(x, 9), round(y, 9))
+        if key not in pts:
+            pts[key] = len(pts)
+        return pts[key]
+
+    def clip(poly):
+        for axis, lim, keep_le in ((0, 0.0, False), (0, W, True), (1, 0.0, False), (1, H, True)):
+            out = []
+            for k in range(len(poly)):
+                p, q = poly[k], poly[(k + 1) % len(poly)]
+                pin = p[axis] <= lim + 1e-12 if keep_le else p[axis] >= lim - 1e-12
+                qin = q[axis] <= lim + 1e-12 if keep_le else q[axis] >= lim - 1e-12
+                if pin:
+                    out.append(p)
+                if pin != qin:
+                    t = (lim - p[axis]) / (q[axis] - p[axis])
+                    r = [p[0] + t * (q[0] - p[0]), p[1] + t * (q[1] - p[1])]
+                    r[axis] = lim
+                    out.append(tuple(r))
+            poly = out
+            if not poly:
+                return []
+        # drop repeated and collinear vertices
+        res = []
+        for k in range(len(poly)):
+            p0, p1, p2 = poly[k - 1], poly[k], poly[(k + 1) % len(poly)]
+            cross = (p1[0] - p0[0]) * (p2[1] - p1[1]) - (p1[1] - p0[1]) * (p2[0] - p1[0])
+            if abs(cross) > 1e-12 * h * h:
+                res.append(p1)
+        return res
+
+    for r in range(-1, ny + 2):
+        for c in range(-1, nx + 2):
+            cx = c * w + (w / 2 if r % 2 else 0.0)
+            cy = r * 1.5 * h
+            hexa = [(cx + h * math.cos(math.pi / 6 + k * math.pi / 3), cy + h * math.sin(math.pi / 6 + k * math.pi / 3))
+                    for k in range(6)]
+            poly = clip(hexa)
+            if len(poly) >= 3:
+                area = 0.5 * sum(poly[k][0] * poly[(k + 1) % len(poly)][1] - poly[(k + 1) % len(poly)][0] * poly[k][1]
+                                 for k in range(len(poly)))
+                if area > 1e-6 * h * h:
+                    polys.append([node(x, y) for x, y in poly])
+    nodes = np.zeros((len(pts), 2))
+    for (x, y), k in pts.items():
+        nodes[k] = (x, y)
+    return _polygon_mesh(nodes, polys, bc, bc_data)
 
 
 def graded(n, ratio, h0=1.0):
