@@ -50,7 +50,12 @@ enum { /* boundary face types */
   UGKWP_BC_FARFIELD = 1,     /* fixed ghost state; injects particles */
   UGKWP_BC_OUTFLOW = 2,      /* ghost = copy of the interior cell; injects */
   UGKWP_BC_WALL_DIFFUSE = 3, /* isothermal wall, diffuse reflection */
-  UGKWP_BC_SYMMETRY = 4      /* mirror ghost, specular particles */
+  UGKWP_BC_SYMMETRY = 4,     /* mirror ghost, specular particles */
+  UGKWP_BC_WALL_MAXWELL = 6  /* isothermal wall with accommodation alpha (Sec. V.B):
+                                a hit re-emits diffusely with probability alpha,
+                                else reflects specularly; wave flux alpha times
+                                the diffuse wall's plus (1 - alpha) times the
+                                mirror flux */
 };
 
 typedef struct ugkwp_ctx ugkwp_ctx;
@@ -66,7 +71,8 @@ typedef struct {
   int64_t n_bfaces;           /* every open edge (2D) / both end nodes (1D) */
   const int64_t *bface_nodes; /* [n_bfaces*dim] node ids of each boundary face */
   const int32_t *bface_type;  /* UGKWP_BC_* */
-  const double *bface_data;   /* [n_bfaces*8]: far field rho, U_x, U_y, T; wall T_w; else unused */
+  const double *bface_data;   /* [n_bfaces*8]: far field rho, U_x, U_y, T; wall T_w;
+                                 Maxwell wall T_w, alpha; else unused */
 } ugkwp_mesh;
 
 /* Gas (Sec. II: tau = mu/p, mu = mu_ref (T/T_ref)^omega), time stepping
@@ -136,7 +142,7 @@ int ugkwp_step_until(ugkwp_ctx *ctx, double r_avg_target, int32_t max_steps, int
  * For a batch: the largest over the cases. */
 int ugkwp_residual(ugkwp_ctx *ctx, double *r_inst, double *r_avg, int64_t *step);
 
-/* Wall quantities of Sec. V (diffuse-wall faces in boundary-list order):
+/* Wall quantities of Sec. V (diffuse and Maxwell wall faces in boundary-list order):
  * out[w*6 + 0..5] = face midpoint x, y, length, C_p, C_F, C_Q, and the drag
  * coefficient C_d = F_d / (rho_inf U_inf^2 L_ref / 2) (Sec. V.B).
  * mode 0: last step; 1: mean over all steps; 2: exponential moving average

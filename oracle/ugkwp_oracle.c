@@ -330,29 +330,39 @@ void ref_flux_interior(const double WL[4], const double WR[4], const double dW0[
   psi_mom(&mR, 0, 0, 0, pR);
   for (int q = 0; q < 4; ++q) W0[q] = sL.rho * pL[q] + sR.rho * pR[q];
   fstate s0 = face_state(W0, K);
-  double a[4], A[4], Wt[4], tmp[4];
-  ref_microslope(W0, dW0, K, Pr, a);
-  moments m0f, m0p, m0m;
-  set_moments(&m0f, s0.U, s0.V, s0.lam, K, 0);
-  set_moments(&m0p, s0.U, s0.V, s0.lam, K, +1);
-  set_moments(&m0m, s0.U, s0.V, s0.lam, K, -1);
-  psi_poly(&m0f, 1, a, tmp);
-  for (int q = 0; q < 4; ++q) Wt[q] = -s0.rho * tmp[q];
-  ref_microslope(W0, Wt, K, 1.0, A);
-
   double cL[8], cR[8];
   ref_time_coeffs(dtL, tauL, cL);
   ref_time_coeffs(dtR, tauR, cR);
-  double f1p[4], fap[4], fAp[4], f1m[4], fam[4], fAm[4];
-  psi_mom(&m0p, 1, 0, 0, f1p);
-  psi_poly(&m0p, 2, a, fap);
-  psi_poly(&m0p, 1, A, fAp);
-  psi_mom(&m0m, 1, 0, 0, f1m);
-  psi_poly(&m0m, 2, a, fam);
-  psi_poly(&m0m, 1, A, fAm);
-  for (int q = 0; q < 4; ++q)
-    Feq[q] = s0.rho * ((cL[0] * f1p[q] + cL[1] * fap[q]) + cL[2] * fAp[q]) +
-             s0.rho * ((cR[0] * f1m[q] + cR[1] * fam[q]) + cR[2] * fAm[q]);
+  /* Reading (the paper does not meet the case): when both sides move away
+   * from the face so fast that the interface holds no gas in FP64 -- W0's
+   * density below 1e-30 of the two sides' or not a valid Maxwellian, as for
+   * a cell leaving a wall or a symmetry face at high Mach number -- there is
+   * no equilibrium flux; likewise if the flux itself is not finite. */
+  if (!(W0[0] > 1e-30 * (sL.rho + sR.rho)) || !(s0.lam > 0.0) || !(s0.lam < HUGE_VAL)) {
+    for (int q = 0; q < 4; ++q) Feq[q] = 0.0;
+  } else {
+    double a[4], A[4], Wt[4], tmp[4];
+    ref_microslope(W0, dW0, K, Pr, a);
+    moments m0f, m0p, m0m;
+    set_moments(&m0f, s0.U, s0.V, s0.lam, K, 0);
+    set_moments(&m0p, s0.U, s0.V, s0.lam, K, +1);
+    set_moments(&m0m, s0.U, s0.V, s0.lam, K, -1);
+    psi_poly(&m0f, 1, a, tmp);
+    for (int q = 0; q < 4; ++q) Wt[q] = -s0.rho * tmp[q];
+    ref_microslope(W0, Wt, K, 1.0, A);
+    double f1p[4], fap[4], fAp[4], f1m[4], fam[4], fAm[4];
+    psi_mom(&m0p, 1, 0, 0, f1p);
+    psi_poly(&m0p, 2, a, fap);
+    psi_poly(&m0p, 1, A, fAp);
+    psi_mom(&m0m, 1, 0, 0, f1m);
+    psi_poly(&m0m, 2, a, fam);
+    psi_poly(&m0m, 1, A, fAm);
+    for (int q = 0; q < 4; ++q)
+      Feq[q] = s0.rho * ((cL[0] * f1p[q] + cL[1] * fap[q]) + cL[2] * fAp[q]) +
+               s0.rho * ((cR[0] * f1m[q] + cR[1] * fam[q]) + cR[2] * fAm[q]);
+    if (!isfinite(Feq[0]) || !isfinite(Feq[1]) || !isfinite(Feq[2]) || !isfinite(Feq[3]))
+      for (int q = 0; q < 4; ++q) Feq[q] = 0.0;
+  }
 
   for (int q = 0; q < 4; ++q) Ffr[q] = 0.0;
   if (WhL) {

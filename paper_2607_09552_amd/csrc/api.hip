@@ -810,7 +810,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
     c->own_stream = true;
   }
   for (int64_t b = 0; b < mesh->n_bfaces; ++b)
-    if (mesh->bface_type[b] < 1 || mesh->bface_type[b] > 4)
+    if ((mesh->bface_type[b] < 1 || mesh->bface_type[b] > 4) && mesh->bface_type[b] != UGKWP_BC_WALL_MAXWELL)
       return set_err(c, UGKWP_EINVAL, "boundary face %lld has unknown type", (long long)b);
   HostMesh h;
   int rc = build_mesh(c, mesh, h);
@@ -828,7 +828,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   c->h_lface = h.lface;
   std::vector<int> wall_b, btype(mesh->bface_type, mesh->bface_type + nb);
   for (int64_t b = 0; b < nb; ++b)
-    if (btype[b] == UGKWP_BC_WALL_DIFFUSE) wall_b.push_back(static_cast<int>(b));
+    if (btype[b] == UGKWP_BC_WALL_DIFFUSE || btype[b] == UGKWP_BC_WALL_MAXWELL) wall_b.push_back(static_cast<int>(b));
   c->h_wall_b = wall_b;
   c->nwall = static_cast<int64_t>(wall_b.size());
   // device geometry

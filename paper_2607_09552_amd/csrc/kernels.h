@@ -12,7 +12,8 @@ constexpr int kNoFace = INT32_MIN;   // lface entry of a padding local face
 constexpr int kScanBlock = 1024;
 constexpr int kMaxCross = 10000;
 
-enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4 };
+// kBcMaxwell: wall with accommodation alpha (data T_w, alpha), Sec. V.B
+enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4, kBcMaxwell = 6 };
 // kFlagConverged is not an error: the step that reached the residual target
 // (scal[kScalTarget] > 0) is done and later steps are skipped
 enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16, kFlagConverged = 32 };

@@ -289,7 +289,8 @@ __global__ void k_ghost_prep(Geo g, Params p, State st) {
   } else if (ty == kBcOutflow) {
     for (int q = 0; q < NW; ++q) Wh[q] = W[q] = st.W[static_cast<int64_t>(i) * NW + q];
     hv = 1;
-  } else if (ty == kBcSymmetry) {
+  } else if (ty == kBcSymmetry || ty == kBcMaxwell) {
+    // mirror state (also the specular part of a Maxwell wall)
     for (int q = 0; q < NW; ++q) {
       W[q] = st.W[static_cast<int64_t>(i) * NW + q];
       Wh[q] = st.Wh[static_cast<int64_t>(i) * NW + q];
@@ -898,6 +899,22 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits), e0, e1);
       rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits + 1), e2, e3);
       ++hits;
+      if (ty == kBcMaxwell && !(e3 < g.bdata[8 * bf + 1])) {
+        // specular part of a Maxwell wall; the impulse goes to the wall
+        const double b0 = u0, b1 = u1;
+        if (DIM == 2) {
+          const R un = u0 * f.x + u1 * f.y;
+          const R n0 = u0 - R(2) * un * f.x, n1 = u1 - R(2) * un * f.y;
+          u0 = n0;
+          u1 = n1;
+        } else {
+          u0 = -u0;
+        }
+        const double c0 = u0, c1 = u1;
+        atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
+        atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
+        continue;
+      }
       const double vn = sqrt(-2.0 * p.R * Tw * log(e0));
       box_muller(e1, e2, z0, z1);
       const double b0 = u0, b1 = u1, b2 = u2;
@@ -1118,7 +1135,8 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
     flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr, F);
   } else {
     const int b = -R - 1;
-    if (g.btype[b] == kBcWall) {
+    const int ty = g.btype[b];
+    if (ty == kBcWall) {
       flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, F);
     } else {
       double wG[4], hG[4], dW0[4];
@@ -1129,6 +1147,15 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
       for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xi.y);
       flux_interior(wL, wG, dW0, hvL ? hL : nullptr, st.ghvalid[b] ? hG : nullptr, z, z, st.dt[L], st.tau[L],
                     st.dt[L], st.gtau[b], K, p.Pr, F);
+      if (ty == kBcMaxwell) {
+        // alpha times the diffuse wall's flux plus (1 - alpha) times the
+        // mirror-state (specular) flux
+        double Fd[4];
+        flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, Fd);
+        const double a = g.bdata[8 * b + 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) F[q] = a * Fd[q] + (1.0 - a) * F[q];
+      }
     }
   }
   double Fl[4];

@@ -288,3 +288,26 @@ def test_lts_counterexample_values():
     lhs = sum(dR) / sum(dL)
     rhs = sum(r / l for r, l in zip(dR, dL)) / M
     assert lhs == Fr(vals["lhs"][0]) and rhs == Fr(vals["rhs"][0]) and lhs != rhs
+
+
+def test_vacuum_interface_carries_no_equilibrium_flux():
+    """Two states leaving the face at Mach ~30 relative to their thermal
+    speed (a cell and its mirror image behind a wall or symmetry face): the
+    interface density from the half-range moments is ~1e-230 of theirs, the
+    equilibrium flux is zero by the reading and everything stays finite; the
+    free-transport wave part is the (vanishing) upwind half-range moment.  A
+    state moving toward the face is unaffected (compared with quadrature)."""
+    K = 1
+    rho, U, T = 0.06, 12.56, 0.1438
+    E = 0.5 * rho * U * U + 0.5 * (K + 2) * rho * T
+    WL = np.array([rho, -rho * U, 0.0, E])  # leaves the face toward -n
+    WR = np.array([rho, rho * U, 0.0, E])   # its mirror leaves toward +n
+    dW0 = (WR - WL) / 2.0
+    Feq, Ffr = oracle.flux_interior(WL, WR, dW0, WL * 0.5, WR * 0.5, np.zeros(4), np.zeros(4),
+                                    1e-3, 0.02, 1e-3, 0.02, K, 2.0 / 3.0)
+    assert np.array_equal(Feq, np.zeros(4))
+    assert np.all(np.isfinite(Ffr)) and np.abs(Ffr).max() < 1e-200
+    # toward the face: the reading does not act
+    Feq2, _ = oracle.flux_interior(WR, WL, -dW0, None, None, np.zeros(4), np.zeros(4), 1e-3, 0.02, 1e-3, 0.02, K, 1.0)
+    Feq2_ref, _ = _brute_flux(WR, WL, -dW0, None, None, np.zeros(4), np.zeros(4), 1e-3, 0.02, 1e-3, 0.02, K)
+    assert np.allclose(Feq2, Feq2_ref, rtol=1e-9, atol=1e-9 * np.abs(Feq2_ref).max())
