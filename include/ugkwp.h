@@ -190,13 +190,13 @@ int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
  * between two host synchronizations (1..1024); use_graph: replay captured
  * HIP graphs of step pairs instead of launching each kernel (not while
  * per-kernel timing is on); transport_block: threads per block of the
- * particle transport (64, 128 or 256); shakhov_first: acceptance-rejection
- * attempts every lane makes alone before the remaining particles are
- * shared among 16 lanes each (1..63).  ugkwp_get_tuning returns the
+ * particle transport (64, 128 or 256); shakhov_lanes: lanes per new
+ * particle that evaluate its first Shakhov acceptance-rejection attempts
+ * together (1, 2, 4, 8 or 16).  ugkwp_get_tuning returns the
  * current values (defaults at init: 32, 1, 256, 4); ugkwp_set_tuning sets all
  * four (EINVAL if one is out of range). */
 typedef struct {
-  int32_t batch_steps, use_graph, transport_block, shakhov_first;
+  int32_t batch_steps, use_graph, transport_block, shakhov_lanes;
 } ugkwp_tuning;
 int ugkwp_set_tuning(ugkwp_ctx *ctx, const ugkwp_tuning *t);
 int ugkwp_get_tuning(ugkwp_ctx *ctx, ugkwp_tuning *t);

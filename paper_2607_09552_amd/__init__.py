@@ -43,7 +43,7 @@ class _Mesh(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("batch_steps", C.c_int32), ("use_graph", C.c_int32), ("transport_block", C.c_int32),
-                ("shakhov_first", C.c_int32)]
+                ("shakhov_lanes", C.c_int32)]
 
 
 class _Params(C.Structure):

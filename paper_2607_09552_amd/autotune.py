@@ -1,6 +1,7 @@
 """Launch-tuning sweep on the GPU (gfx950): steps per host synchronization,
-graph replay, transport block size and the Shakhov sampler's first-phase
-attempts (ugkwp_set_tuning; results do not depend on them).
+graph replay, transport block size and the lanes per particle of the
+Shakhov sampler's first phase (ugkwp_set_tuning; results do not depend on
+them).
 
 The flow keeps evolving while it is measured, so candidates are interleaved:
 each round times every candidate for a few steps in turn, and the median
@@ -26,7 +27,7 @@ SPACE = {
     "batch_steps": [8, 16, 32, 64],
     "use_graph": [0, 1],
     "transport_block": [64, 128, 256],
-    "shakhov_first": [2, 4, 8],
+    "shakhov_lanes": [1, 2, 4, 8, 16],
 }
 
 

@@ -90,7 +90,7 @@ struct ugkwp_ctx {
   // profiling
   bool prof = false, prof_all = false;
   // tuning
-  int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_first = 4;
+  int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4;
   // captured graph of two steps and the launch arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -638,8 +638,10 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
   }
   if (c->P.Pr != 1.0) {
     ProfScope ps(c, kKSampleShakhov, 40.0 * c->est_new);
-    hipLaunchKernelGGL((k_sample_shakhov<DIM, R>), dim3(gnew), dim3(256), 0, c->stream, g, c->P, S, A, c->cap,
-                       static_cast<uint32_t>(c->shakhov_first));
+    // one wavefront per 64 / shakhov_lanes new particles
+    const unsigned gsh = nblk((c->cover_new + 64 / c->shakhov_lanes - 1) / (64 / c->shakhov_lanes) * 64, 256);
+    hipLaunchKernelGGL((k_sample_shakhov<DIM, R>), dim3(gsh), dim3(256), 0, c->stream, g, c->P, S, A, c->cap,
+                       static_cast<uint32_t>(c->shakhov_lanes));
   }
   {
     ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
@@ -1067,7 +1069,7 @@ void drop_graph(ugkwp_ctx *c) {
 std::vector<int64_t> graph_key(const ugkwp_ctx *c) {
   return {reinterpret_cast<int64_t>(c->A.x), reinterpret_cast<int64_t>(c->B.x), reinterpret_cast<int64_t>(c->A32.x),
           reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.rank),
-          c->cap, c->cover, c->cover_new, c->transport_block, c->shakhov_first};
+          c->cap, c->cover, c->cover_new, c->transport_block, c->shakhov_lanes};
 }
 
 // Captures two steps into a graph (the double-buffer swaps of two steps
@@ -1510,13 +1512,13 @@ int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
 int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
   if (!c || !t) return UGKWP_EINVAL;
   if (t->batch_steps < 1 || t->batch_steps > 1024 || (t->use_graph != 0 && t->use_graph != 1) ||
-      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) || t->shakhov_first < 1 ||
-      t->shakhov_first > 63)
+      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) || (t->shakhov_lanes != 1 && t->shakhov_lanes != 2 && t->shakhov_lanes != 4 &&
+       t->shakhov_lanes != 8 && t->shakhov_lanes != 16))
     return set_err(c, UGKWP_EINVAL, "tuning value out of range");
   c->batch_steps = t->batch_steps;
   c->use_graph = t->use_graph;
   c->transport_block = t->transport_block;
-  c->shakhov_first = t->shakhov_first;
+  c->shakhov_lanes = t->shakhov_lanes;
   return UGKWP_OK;
 }
 
@@ -1525,7 +1527,7 @@ int ugkwp_get_tuning(ugkwp_ctx *c, ugkwp_tuning *t) {
   t->batch_steps = c->batch_steps;
   t->use_graph = c->use_graph;
   t->transport_block = c->transport_block;
-  t->shakhov_first = c->shakhov_first;
+  t->shakhov_lanes = c->shakhov_lanes;
   return UGKWP_OK;
 }
 

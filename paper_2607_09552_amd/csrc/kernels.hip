@@ -521,80 +521,93 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
   if (k < n_cellnew && n_ret + k < cap) sample_draw_one<DIM, R>(g, p, st, out, n_ret, step, k);
 }
 
-// Shakhov deviations of the new particles (Pr != 1), one wavefront per 64
-// consecutive new particles.  The result is that of the sequential rule: the
-// lowest accepted attempt of 0..63, else attempt 63.  The number of attempts
-// varies widely (about B, the acceptance bound, and all 64 in near-vacuum
-// cells where B is huge), so a lane-per-particle loop would hold the whole
-// wavefront for its slowest particle.  Instead:
-//  1. every lane tries attempts 0..first-1 of its own particle (first in
-//     [1, 63], a tuning parameter);
-//  2. the particles not yet accepted are finished four at a time, 16 lanes
-//     each, which evaluate 16 consecutive attempts of their particle at once
-//     and keep the lowest accepted one.
+// Shakhov deviations of the new particles (Pr != 1).  The result is that of
+// the sequential rule: the lowest accepted attempt of 0..63, else attempt 63.
+// An attempt is a long dependent chain (Philox, logarithms, sine/cosine) and
+// the number of attempts varies widely (about the acceptance bound B; all
+// 64 in near-vacuum cells where B is huge), so work is spread over lanes:
+//  1. a wavefront takes 64/K particles, K lanes each (K = `lanes`, a tuning
+//     parameter in {1, 2, 4, 8, 16}); the K lanes of a particle evaluate
+//     attempts 0..K-1 at once and keep the lowest accepted one;
+//  2. the particles not yet accepted are finished in the same way with L
+//     lanes each on attempts K, K + L, ...: four at a time with L = 16, or
+//     with L = 32 or 64 when only two or one remain (near-vacuum particles,
+//     which need every attempt, then take one or two rounds).
+// More lanes per particle means more wavefronts in flight to hide latency.
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, StoreT<R> out, int64_t cap,
-                                                        uint32_t first) {
+                                                        uint32_t lanes) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc], step = *st.dstep;
   int64_t end = st.noff[g.nc];
   if (end > cap - n_ret) end = cap - n_ret;
-  const int64_t base = ((blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6) << 6;
+  const int K1 = static_cast<int>(lanes), P1 = 64 / K1;
+  const int64_t base = ((blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6) * P1;
   if (base >= end) return;  // whole wavefront
   const int lane = lane_id();
-  const int64_t o = n_ret + base + lane;
-  const bool act = base + lane < end;
-  uint64_t pid = 0;
+  const int g1 = lane / K1, s1 = lane % K1;
+  const int64_t kp = base + g1;
+  const bool act = kp < end;
+  uint64_t pid = 0, seed = 0;
   int cell = 0;
   if (act) {
-    pid = out.pid[o];
-    cell = out.cell[o];
+    pid = out.pid[n_ret + kp];
+    cell = out.cell[n_ret + kp];
+    seed = case_seed(g, p, case_of(g, cell));
   }
-  const uint64_t seed = act ? case_seed(g, p, case_of(g, cell)) : 0;
-  bool done = !act;
-  for (uint32_t att = 0; att < first; ++att) {
-    if (!done) {
-      double z[3];
-      if (shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step, att, z)) {
-        out.ux[o] = static_cast<R>(z[0]);
-        out.uy[o] = static_cast<R>(z[1]);
-        out.uz[o] = static_cast<R>(z[2]);
-        done = true;
-      }
+  // phase 1
+  {
+    double z[3] = {0.0, 0.0, 0.0};
+    const bool acc = act && shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step,
+                                                 static_cast<uint32_t>(s1), z);
+    const uint64_t seg = (__ballot(acc) >> (g1 * K1)) & (K1 == 64 ? ~0ull : ((1ull << K1) - 1ull));
+    if (act && seg != 0 && s1 == __ffsll(static_cast<long long>(seg)) - 1) {
+      const int64_t o = n_ret + kp;
+      out.ux[o] = static_cast<R>(z[0]);
+      out.uy[o] = static_cast<R>(z[1]);
+      out.uz[o] = static_cast<R>(z[2]);
     }
-  }
-  uint64_t hard = __ballot(!done);
-  const int grp = lane >> 4, sl = lane & 15;
-  while (hard) {
-    // this group's particle: the grp-th remaining lane, if any
-    uint64_t h = hard;
-    for (int q = 0; q < grp && h; ++q) h &= h - 1;
-    const int src = h ? __ffsll(static_cast<long long>(h)) - 1 : -1;
-    for (int q = 0; q < 4 && hard; ++q) hard &= hard - 1;  // the chunk taken
-    const uint64_t gpid = __shfl(pid, src < 0 ? 0 : src, 64);
-    const uint64_t gseed = __shfl(seed, src < 0 ? 0 : src, 64);
-    const int gcell = __shfl(cell, src < 0 ? 0 : src, 64);
-    const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
-    bool gdone = src < 0;
-    uint32_t a = first;
-    while (__ballot(!gdone)) {
-      const uint32_t att = a + static_cast<uint32_t>(sl);
-      double z[3] = {0.0, 0.0, 0.0};
-      bool acc = false;
-      if (!gdone && att < 64) acc = shakhov_attempt<DIM>(p, tab, gseed, gpid, step, att, z);
-      const uint64_t seg = (__ballot(acc) >> (grp * 16)) & 0xffffull;
-      if (!gdone) {
-        if (seg != 0 || a + 16 >= 64) {
-          const int wr = seg != 0 ? __ffsll(static_cast<long long>(seg)) - 1 : static_cast<int>(63 - a);
-          if (sl == wr) {
-            const int64_t d = n_ret + base + src;
-            out.ux[d] = static_cast<R>(z[0]);
-            out.uy[d] = static_cast<R>(z[1]);
-            out.uz[d] = static_cast<R>(z[2]);
+    // one bit per particle still to do, at the first lane of its group
+    const uint64_t open = __ballot(act && seg == 0 && s1 == 0);
+    if (!open) return;
+    uint64_t hard = open;
+    while (hard) {
+      const int nh = __popcll(hard);
+      const int L = nh == 1 ? 64 : nh == 2 ? 32 : 16;  // lanes per particle (uniform)
+      const int grp = lane / L, sl = lane % L;
+      const uint64_t segm = L == 64 ? ~0ull : ((1ull << L) - 1ull);
+      // this group's particle: the grp-th remaining one, if any
+      uint64_t h = hard;
+      for (int q = 0; q < grp && h; ++q) h &= h - 1;
+      const int src = h ? __ffsll(static_cast<long long>(h)) - 1 : -1;
+      for (int q = 0; q < 64 / L && hard; ++q) hard &= hard - 1;  // the chunk taken
+      const int sv = src < 0 ? 0 : src;
+      const uint64_t gpid = __shfl(pid, sv, 64);
+      const uint64_t gseed = __shfl(seed, sv, 64);
+      const int gcell = __shfl(cell, sv, 64);
+      const int64_t gk = __shfl(kp, sv, 64);
+      const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
+      bool gdone = src < 0;
+      uint32_t a = static_cast<uint32_t>(K1);
+      while (__ballot(!gdone)) {
+        const uint32_t att = a + static_cast<uint32_t>(sl);
+        double w[3] = {0.0, 0.0, 0.0};
+        bool ok = false;
+        if (!gdone && att < 64) ok = shakhov_attempt<DIM>(p, tab, gseed, gpid, step, att, w);
+        const uint64_t sg = (__ballot(ok) >> (grp * L)) & segm;
+        if (!gdone) {
+          if (sg != 0 || a + static_cast<uint32_t>(L) >= 64) {
+            const int wr = sg != 0 ? __ffsll(static_cast<long long>(sg)) - 1 : static_cast<int>(63 - a);
+            if (sl == wr) {
+              const int64_t d = n_ret + gk;
+              out.ux[d] = static_cast<R>(w[0]);
+              out.uy[d] = static_cast<R>(w[1]);
+              out.uz[d] = static_cast<R>(w[2]);
+            }
+            gdone = true;
+          } else {
+            a += static_cast<uint32_t>(L);
           }
-          gdone = true;
-        } else {
-          a += 16;
         }
       }
     }
