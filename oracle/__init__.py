@@ -47,7 +47,7 @@ class _Params(C.Structure):
         ("R", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double), ("T_ref", C.c_double),
         ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32),
         ("lts", C.c_int32), ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double),
-        ("u_inf_y", C.c_double), ("T_inf", C.c_double), ("L_ref", C.c_double),
+        ("u_inf_y", C.c_double), ("T_inf", C.c_double), ("L_ref", C.c_double), ("wave_only", C.c_int32),
     ]
 
 
@@ -89,8 +89,8 @@ def lib():
         L.ref_moments_n.argtypes = [C.c_double, C.c_double, C.c_int, dp]
         L.ref_microslope.argtypes = [dp, dp, C.c_int, C.c_double, dp]
         L.ref_flux_interior.argtypes = [dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
-                                        C.c_double, C.c_int, C.c_double, dp, dp]
-        L.ref_flux_wall.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+                                        C.c_double, C.c_int, C.c_double, C.c_int, dp, dp]
+        L.ref_flux_wall.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, dp]
         L.ref_track_one.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, dp, dp, dp, C.c_double,
                                     ip32, ip32]
         _lib = L
@@ -139,22 +139,22 @@ def microslope(W, dW, K=1, Pr=1.0):
     return a
 
 
-def flux_interior(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K=1, Pr=1.0):
+def flux_interior(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K=1, Pr=1.0, wave_only=0):
     WL, WR, dW0 = _f64(WL), _f64(WR), _f64(dW0)
     WhL = None if WhL is None else _f64(WhL)
     WhR = None if WhR is None else _f64(WhR)
     dWhL, dWhR = _f64(dWhL), _f64(dWhR)
     Feq, Ffr = np.zeros(4), np.zeros(4)
     lib().ref_flux_interior(_p(WL), _p(WR), _p(dW0), _p(WhL), _p(WhR), _p(dWhL), _p(dWhR), dtL, tauL, dtR,
-                            tauR, K, Pr, _p(Feq), _p(Ffr))
+                            tauR, K, Pr, wave_only, _p(Feq), _p(Ffr))
     return Feq, Ffr
 
 
-def flux_wall(W, Wh, dt, tau, Tw, R=1.0, K=1):
+def flux_wall(W, Wh, dt, tau, Tw, R=1.0, K=1, wave_only=0):
     W = _f64(W)
     Wh = None if Wh is None else _f64(Wh)
     F = np.zeros(4)
-    lib().ref_flux_wall(_p(W), _p(Wh), dt, tau, Tw, R, K, _p(F))
+    lib().ref_flux_wall(_p(W), _p(Wh), dt, tau, Tw, R, K, wave_only, _p(F))
     return F
 
 
@@ -198,7 +198,8 @@ class Oracle:
         r = wl["ref"]
         p = _Params(R=g["R"], omega=g["omega"], mu_ref=g["mu_ref"], T_ref=g["T_ref"], Pr=g["Pr"], D=g["D"],
                     cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
-                    u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"])
+                    u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
+                    wave_only=int(wl.get("wave_only", 0)))
         W = _f64(wl["W0"] if W0 is None else W0).ravel()
         h = C.c_void_p()
         rc = L.ref_init(C.byref(m), C.byref(p), _p(W), C.byref(h))

@@ -320,7 +320,7 @@ void ref_microslope(const double W[4], const double dW[4], int K, double Pr, dou
 void ref_flux_interior(const double WL[4], const double WR[4], const double dW0[4],
                        const double *WhL, const double *WhR, const double dWhL[4],
                        const double dWhR[4], double dtL, double tauL, double dtR, double tauR,
-                       int K, double Pr, double Feq[4], double Ffr[4]) {
+                       int K, double Pr, int wave_only, double Feq[4], double Ffr[4]) {
   fstate sL = face_state(WL, K), sR = face_state(WR, K);
   moments mL, mR;
   set_moments(&mL, sL.U, sL.V, sL.lam, K, +1);
@@ -333,6 +333,12 @@ void ref_flux_interior(const double WL[4], const double WR[4], const double dW0[
   double cL[8], cR[8];
   ref_time_coeffs(dtL, tauL, cL);
   ref_time_coeffs(dtR, tauR, cR);
+  if (wave_only) {
+    cL[6] = cL[3];
+    cL[7] = cL[4];
+    cR[6] = cR[3];
+    cR[7] = cR[4];
+  }
   /* Reading (the paper does not meet the case): when both sides move away
    * from the face so fast that the interface holds no gas in FP64 -- W0's
    * density below 1e-30 of the two sides' or not a valid Maxwellian, as for
@@ -393,9 +399,13 @@ void ref_flux_interior(const double WL[4], const double WR[4], const double dW0[
  * abar g(W_i) + (dbar - E) g(W^h_i); the reflected half is a wall Maxwellian
  * at rest and T_w whose density makes the net wave mass flux zero. */
 void ref_flux_wall(const double W[4], const double *Wh, double dt, double tau, double Tw, double R,
-                   int K, double F[4]) {
+                   int K, int wave_only, double F[4]) {
   double co[8], t[4];
   ref_time_coeffs(dt, tau, co);
+  if (wave_only) {
+    co[6] = co[3];
+    co[7] = co[4];
+  }
   fstate s = face_state(W, K);
   moments m;
   set_moments(&m, s.U, s.V, s.lam, K, +1);
@@ -1101,7 +1111,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       for (int q = 0; q < nw; ++q) cs[i].W[q] = c->W[i * nw + q];
       cs[i].tau = relax_time(c, s.rho, s.T);
       cs[i].dt = c->dt[i];
-      cs[i].E = exp(-(c->dt[i] / cs[i].tau));
+      cs[i].E = c->p.wave_only ? 0.0 : exp(-(c->dt[i] / cs[i].tau));
     }
     if (rc) break;
 
@@ -1169,7 +1179,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         g->hvalid = 0;
         g->tau = cs[i].tau;
       }
-      g->E = exp(-(g->dt / g->tau));
+      g->E = c->p.wave_only ? 0.0 : exp(-(g->dt / g->tau));
     }
 
     /* (4) pre-transport set.  Retained particles keep their order (cell, pid).
@@ -1395,7 +1405,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
           pHR = HRf;
         }
         ref_flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, cs[L].dt, cs[L].tau, cs[R].dt, cs[R].tau, K,
-                          c->p.Pr, Fe, Ff);
+                          c->p.Pr, c->p.wave_only, Fe, Ff);
         for (int q = 0; q < 4; ++q) F[q] = Fe[q] + Ff[q];
       } else {
         int64_t b = -R - 1;
@@ -1404,18 +1414,18 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         to_frame(c, cs[L].W, n2, wL);
         to_frame(c, cs[L].Wh, n2, hL);
         if (c->btype[b] == REF_BC_WALL) {
-          ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, F);
+          ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, c->p.wave_only, F);
         } else if (c->btype[b] == REF_BC_WALL_MAXWELL) {
           /* Maxwell's wall: alpha times the diffuse-wall flux plus (1 - alpha)
            * times the specular (mirror-state) flux */
           double Fd[4], Fs[4], wG[4], hG[4], dW0[4], z[4] = {0, 0, 0, 0};
           double a = c->bdata[8 * b + 1];
-          ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, Fd);
+          ref_flux_wall(wL, cs[L].hvalid ? hL : NULL, cs[L].dt, cs[L].tau, c->bdata[8 * b], c->p.R, K, c->p.wave_only, Fd);
           to_frame(c, g->W, n2, wG);
           to_frame(c, g->Wh, n2, hG);
           for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xL);
           ref_flux_interior(wL, wG, dW0, cs[L].hvalid ? hL : NULL, g->hvalid ? hG : NULL, z, z, cs[L].dt,
-                            cs[L].tau, g->dt, g->tau, K, c->p.Pr, Fe, Ff);
+                            cs[L].tau, g->dt, g->tau, K, c->p.Pr, c->p.wave_only, Fe, Ff);
           for (int q = 0; q < 4; ++q) Fs[q] = Fe[q] + Ff[q];
           for (int q = 0; q < 4; ++q) F[q] = a * Fd[q] + (1.0 - a) * Fs[q];
         } else {
@@ -1424,7 +1434,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
           to_frame(c, g->Wh, n2, hG);
           for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xL);
           ref_flux_interior(wL, wG, dW0, cs[L].hvalid ? hL : NULL, g->hvalid ? hG : NULL, z, z, cs[L].dt,
-                            cs[L].tau, g->dt, g->tau, K, c->p.Pr, Fe, Ff);
+                            cs[L].tau, g->dt, g->tau, K, c->p.Pr, c->p.wave_only, Fe, Ff);
           for (int q = 0; q < 4; ++q) F[q] = Fe[q] + Ff[q];
         }
       }

@@ -61,6 +61,9 @@ typedef struct {
   int32_t lts;                 /* 1 local time steps, 0 global (dt_G = min dt_i) */
   uint64_t seed;
   double rho_inf, u_inf_x, u_inf_y, T_inf, L_ref; /* surface coefficients only */
+  int32_t wave_only;           /* 1: E = 0 (no particles, all gas in the waves:
+                                  the gas-kinetic scheme of the coarse warm-start
+                                  solves); 0: UGKWP */
 } ref_params;
 
 typedef struct ref_ctx ref_ctx;
@@ -102,10 +105,12 @@ void ref_microslope(const double W[4], const double dW[4], int K, double Pr, dou
 void ref_flux_interior(const double WL[4], const double WR[4], const double dW0[4],
                        const double *WhL, const double *WhR, const double dWhL[4],
                        const double dWhR[4], double dtL, double tauL, double dtR, double tauR,
-                       int K, double Pr, double Feq[4], double Ffr[4]);
+                       int K, double Pr, int wave_only, double Feq[4], double Ffr[4]);
 /* diffuse-wall face flux (face frame, normal out of the gas) */
 void ref_flux_wall(const double W[4], const double *Wh, double dt, double tau, double Tw, double R,
-                   int K, double F[4]);
+                   int K, int wave_only, double F[4]);
+/* wave_only: the free-transport wave carries all of g^h (coefficients dbar,
+   ebar instead of dbar - E, ebar + dt E / 2): no particles take a share */
 /* track one particle through the mesh of c for remaining time t, no RNG at
    symmetry faces; diffuse walls draw with (pid, step).  Returns 0 if it ends
    inside (cell_out), 1 if it left through a far-field/outflow face. */

@@ -361,3 +361,51 @@ def test_maxwell_walls_conserve_time_weighted_mass():
         assert abs(I - I0) <= 2e-13 * I0
     assert abs((vol * o.fields()[:, 3] / dt).sum() - E0) > 1e-6 * E0  # heat exchange with the walls
     assert o.counts()[1]["total"] > 0
+
+
+def test_wave_only_equals_ugkwp_in_the_continuum_limit():
+    """Where E = e^{-dt/tau} underflows to 0 (Kn 1e-9), UGKWP samples no
+    particles and its free-transport coefficients are dbar, ebar: the
+    wave-only scheme (E = 0 by definition) gives the same steps bit for bit,
+    up to the first step in which a cell's E is above the underflow."""
+    w = wl.shock1d(Kn=1e-9)
+    a = oracle.Oracle(w)
+    w2 = dict(w)
+    w2["wave_only"] = 1
+    b = oracle.Oracle(w2)
+    n = 0
+    while n < 30:
+        a.step(1)
+        b.step(1)
+        if a.counts()[1]["new"]:
+            break  # e^{-dt/tau} above the underflow somewhere: UGKWP samples
+        n += 1
+        assert np.array_equal(a.fields(), b.fields()), n
+    assert n >= 5 and b.counts()[1]["total"] == 0
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_wave_only_preserves_uniform_flow_and_time_weighted_content(dim):
+    """Wave-only (no particles) at a Knudsen number where UGKWP would sample
+    particles: a uniform flow stays uniform on graded LTS meshes, and a closed
+    specular box conserves sum Omega W / dt (Eqs. (43), (53))."""
+    if dim == 1:
+        m = wl.uniform1d(wl.graded(12, 1.25), rho=1.2, U=0.7, T=1.5, mu_ref=0.05)
+    else:
+        box = wl.box2d(wl.graded(6, 1.3), wl.graded(5, 1.5, 0.3), wl.BC_FARFIELD, [1.2, 0.7, -0.4, 1.5])
+        m = wl.uniform2d(box, rho=1.2, ux=0.7, uy=-0.4, T=1.5, mu_ref=0.05)
+    m["wave_only"] = 1
+    o = oracle.Oracle(m)
+    W0 = o.fields()
+    o.step(10)
+    assert o.counts()[1]["total"] == 0
+    assert np.max(np.abs(o.fields() - W0) / np.abs(W0).max(axis=0)) < 1e-13
+    c = _closed_box(dim)
+    c["wave_only"] = 1
+    o = oracle.Oracle(c)
+    vol, dt = cell_volumes(c), o.dt()
+    I0 = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+    o.step(25)
+    I = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+    for q in (0, dim + 1):
+        assert abs(I[q] - I0[q]) <= 2e-13 * abs(I0[q])
