@@ -92,6 +92,9 @@ typedef struct {
                                  particle positions (relative to the cell's
                                  centroid) and velocities in FP32, masses,
                                  tallies, cells and fluxes in FP64 */
+  int32_t wave_only;          /* 1: E = 0 -- no particles, the free-transport wave
+                                 carries all of g^h (the gas-kinetic scheme of the
+                                 coarse solves behind a warm start); 0: UGKWP */
 } ugkwp_params;
 
 /* Builds faces and geometry, uploads the state and computes the local time
@@ -129,12 +132,13 @@ int ugkwp_case_surface(ugkwp_ctx *ctx, int32_t case_id, int32_t mode, double *ou
 int ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps);
 
 /* Advances until the residual target is met: stops after the first step
- * n >= 100 whose r_avg (see ugkwp_residual; every case's for a batch) is below r_avg_target (the
- * convergence rule used for time-to-residual), or after max_steps steps.
- * *converged = 1 if the target was met; the step count is that of
- * ugkwp_residual.  The test runs on the device after every step.  Errors as
- * ugkwp_step; EINVAL if r_avg_target <= 0. */
-int ugkwp_step_until(ugkwp_ctx *ctx, double r_avg_target, int32_t max_steps, int32_t *converged);
+ * n >= 100 whose r_avg (see ugkwp_residual; every case's for a batch) is
+ * below target (the convergence rule used for time-to-residual), or after
+ * max_steps steps.  Wave-only runs (params.wave_only) test r_inst instead:
+ * they carry no particle noise.  *converged = 1 if the target was met; the
+ * step count is that of ugkwp_residual.  The test runs on the device after
+ * every step.  Errors as ugkwp_step; EINVAL if target <= 0. */
+int ugkwp_step_until(ugkwp_ctx *ctx, double target, int32_t max_steps, int32_t *converged);
 
 /* Residuals after the last step (the paper defines none; reading): r_inst is
  * the area-weighted RMS of the last density change over rho_inf, r_avg the

@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(HERE, "libugkwp.so")
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
 
-# Every entry point declared in include/ugkwp.h.
+# Every entry point declared in include/ugkwp.h and include/ugkwp_mlp.h.
 ABI_SYMBOLS = (
     "ugkwp_init", "ugkwp_init_batch", "ugkwp_case_range", "ugkwp_case_residual", "ugkwp_case_surface", "ugkwp_step", "ugkwp_step_until", "ugkwp_residual", "ugkwp_surface", "ugkwp_get_fields",
     "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
+    "ugkwp_mlp_layer", "ugkwp_mlp_gemm_acc", "ugkwp_mlp_act_backward", "ugkwp_mlp_adam", "ugkwp_mlp_to_bf16",
+    "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode",
 )
 
 
@@ -52,8 +54,14 @@ class _Params(C.Structure):
         ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32), ("lts", C.c_int32),
         ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double), ("u_inf_y", C.c_double),
         ("T_inf", C.c_double), ("L_ref", C.c_double), ("particle_capacity", C.c_int64), ("stream", C.c_void_p),
-        ("precision", C.c_int32),
+        ("precision", C.c_int32), ("wave_only", C.c_int32),
     ]
+
+
+class WsCase(C.Structure):
+    """ugkwp_ws_case: flow parameters and free stream of one warm-start case."""
+    _fields_ = [("Ma", C.c_double), ("Kn", C.c_double), ("Tw", C.c_double), ("rho_inf", C.c_double),
+                ("U_inf", C.c_double), ("T_inf", C.c_double), ("R", C.c_double), ("D", C.c_int32)]
 
 
 _lib = None
@@ -66,6 +74,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_09552_amd.build`")
+    # torch bundles a HIP runtime under the same soname as the system one; the
+    # first to load serves the whole process, and torch cannot use the system
+    # runtime.  Loading torch first makes the library and torch share its.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, dp, i64p, i32p, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)
     L.ugkwp_init.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.POINTER(vp)]
@@ -95,6 +110,15 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_last_error.restype = C.c_char_p
     L.ugkwp_free.argtypes = [vp]
     L.ugkwp_free.restype = None
+    i64, i32, f32 = C.c_int64, C.c_int32, C.c_float
+    L.ugkwp_mlp_layer.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp, vp, vp, vp, vp]
+    L.ugkwp_mlp_gemm_acc.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp]
+    L.ugkwp_mlp_act_backward.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp, vp]
+    L.ugkwp_mlp_adam.argtypes = [vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, i64, vp, vp, vp]
+    L.ugkwp_mlp_to_bf16.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.ugkwp_mlp_mse_grad.argtypes = [vp, vp, i64, i64, i64, f32, vp, vp, vp]
+    L.ugkwp_ws_features.argtypes = [vp, i32, i32, i32, i32, C.POINTER(WsCase), i64, vp, vp, vp, vp]
+    L.ugkwp_ws_decode.argtypes = [vp, i64, vp, i64, C.POINTER(WsCase), vp, vp]
     _lib = L
     return L
 
@@ -181,7 +205,7 @@ class Solver:
                     cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
                     u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
                     particle_capacity=particle_capacity, stream=stream,
-                    precision={"f64": 0, "mixed": 1}[precision])
+                    precision={"f64": 0, "mixed": 1}[precision], wave_only=int(wl.get("wave_only", 0)))
         W = arr(wl["W0"] if W0 is None else W0, np.float64).ravel()
         return m, p, W
 
@@ -211,11 +235,12 @@ class Solver:
     def step(self, n=1):
         self._check(load_library().ugkwp_step(self.h, n))
 
-    def step_until(self, r_avg_target, max_steps):
-        """Steps until the first step n >= 100 with r_avg < r_avg_target or
-        max_steps steps; returns (converged, steps done in total)."""
+    def step_until(self, target, max_steps):
+        """Steps until the first step n >= 100 with r_avg < target (r_inst in
+        wave-only runs) or max_steps steps; returns (converged, steps done in
+        total)."""
         conv = C.c_int32()
-        self._check(load_library().ugkwp_step_until(self.h, r_avg_target, max_steps, C.byref(conv)))
+        self._check(load_library().ugkwp_step_until(self.h, target, max_steps, C.byref(conv)))
         return bool(conv.value), self.residual()[2]
 
     def fields(self):

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libugkwp.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "mlp.hip")]
 
 # -ffp-contract=off: every product and sum rounds on its own, in source order.
 # The target-feature switch keeps the compiler from forming packed FP32 ops.

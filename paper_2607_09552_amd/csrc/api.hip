@@ -797,6 +797,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   P.K = 1 + par->D;
   P.cfl = par->cfl;
   P.n_ref = par->n_ref;
+  P.wave_only = par->wave_only ? 1 : 0;
   P.seed = par->seed;
   P.rho_inf = par->rho_inf;
   P.u_inf_x = par->u_inf_x;
@@ -991,6 +992,7 @@ int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_para
       return set_err(c, UGKWP_EINVAL, "case %d: invalid parameters, mesh or W0", k);
     if (q.R != p0.R || q.omega != p0.omega || q.T_ref != p0.T_ref || q.Pr != p0.Pr || q.D != p0.D ||
         q.cfl != p0.cfl || q.n_ref != p0.n_ref || q.lts != p0.lts || q.precision != p0.precision ||
+        q.wave_only != p0.wave_only ||
         q.stream != p0.stream)
       return set_err(c, UGKWP_EINVAL, "case %d: gas, CFL, N_ref, LTS, precision and stream must equal case 0's", k);
   }
@@ -1175,11 +1177,11 @@ int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
   return run_steps(c, n_steps, false, nullptr);
 }
 
-int ugkwp_step_until(ugkwp_ctx *c, double r_avg_target, int32_t max_steps, int32_t *converged) {
-  if (!c || max_steps < 0 || !(r_avg_target > 0.0) || !converged) return UGKWP_EINVAL;
+int ugkwp_step_until(ugkwp_ctx *c, double target, int32_t max_steps, int32_t *converged) {
+  if (!c || max_steps < 0 || !(target > 0.0) || !converged) return UGKWP_EINVAL;
   if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
   if (c->step + max_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
-  HIPCHK(hipMemcpyAsync(c->S.scal + kScalTarget, &r_avg_target, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->S.scal + kScalTarget, &target, sizeof(double), hipMemcpyHostToDevice, c->stream));
   const int rc = run_steps(c, max_steps, true, converged);
   const double off = 0.0;
   HIPCHK(hipMemcpyAsync(c->S.scal + kScalTarget, &off, sizeof(double), hipMemcpyHostToDevice, c->stream));

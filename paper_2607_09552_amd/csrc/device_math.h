@@ -241,7 +241,7 @@ __device__ __forceinline__ void microslope(const double W[4], const double dW[4]
 __device__ __forceinline__ void flux_interior(const double WL[4], const double WR[4], const double dW0[4],
                                               const double *WhL, const double *WhR, const double dWhL[4],
                                               const double dWhR[4], double dtL, double tauL, double dtR,
-                                              double tauR, int K, double Pr, double F[4]) {
+                                              double tauR, int K, double Pr, int wave_only, double F[4]) {
   const FState sL = fstate(WL, K), sR = fstate(WR, K);
   Mom m;
   double pL[4], pR[4], W0[4];
@@ -252,7 +252,13 @@ __device__ __forceinline__ void flux_interior(const double WL[4], const double W
 #pragma unroll
   for (int q = 0; q < 4; ++q) W0[q] = sL.rho * pL[q] + sR.rho * pR[q];
   const FState s0 = fstate(W0, K);
-  const Coef cL = time_coef(dtL, tauL), cR = time_coef(dtR, tauR);
+  Coef cL = time_coef(dtL, tauL), cR = time_coef(dtR, tauR);
+  if (wave_only) {  // no particles take a share of the free transport
+    cL.f0 = cL.d;
+    cL.f1 = cL.e;
+    cR.f0 = cR.d;
+    cR.f1 = cR.e;
+  }
   double Feq[4] = {0.0, 0.0, 0.0, 0.0};
   // an interface the two sides leave so fast that it holds no gas in FP64
   // (W0's density below 1e-30 of theirs or not a valid Maxwellian) carries
@@ -312,8 +318,12 @@ __device__ __forceinline__ void flux_interior(const double WL[4], const double W
 // abar g(W) + (dbar - E) g(W^h); reflected half: wall Maxwellian at rest and
 // T_w with the density that makes the net wave mass flux zero.
 __device__ __forceinline__ void flux_wall(const double W[4], const double *Wh, double dt, double tau, double Tw,
-                                          double R, int K, double F[4]) {
-  const Coef co = time_coef(dt, tau);
+                                          double R, int K, int wave_only, double F[4]) {
+  Coef co = time_coef(dt, tau);
+  if (wave_only) {
+    co.f0 = co.d;
+    co.f1 = co.e;
+  }
   Mom m;
   double t[4];
   const FState s = fstate(W, K);

@@ -73,6 +73,7 @@ struct Params {
   int K;       // lumped degrees of freedom in the face frame, 1 + D
   double cfl;
   int n_ref;
+  int wave_only;  // E = 0: no particles, the waves carry all of g^h
   uint64_t seed;
   double rho_inf, u_inf_x, u_inf_y, U_inf, T_inf, L_ref;
 };

@@ -191,7 +191,7 @@ __global__ void k_cell_prep(Geo g, Params p, State st) {
     st.hvalid[i] = 0;
   } else {
     const double tau = relax_time(p, case_val(g, case_of(g, i), kCaseMu, p.mu_ref), s.rho, s.T);
-    const double E = exp(-(st.dt[i] / tau));
+    const double E = p.wave_only ? 0.0 : exp(-(st.dt[i] / tau));
     st.tau[i] = tau;
     st.E[i] = E;
     st.tdt[i] = make_double2(tau, st.dt[i]);
@@ -311,7 +311,7 @@ __global__ void k_ghost_prep(Geo g, Params p, State st) {
     hv = st.hvalid[i];
   }
   const double dti = st.dt[i];
-  const double E = exp(-(dti / tau));
+  const double E = p.wave_only ? 0.0 : exp(-(dti / tau));
   for (int q = 0; q < NW; ++q) {
     st.gW[b * NW + q] = W[q];
     st.gWh[b * NW + q] = Wh[q];
@@ -1145,12 +1145,13 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
       reconstruct(okf ? hRR : nullptr, xi.w, hR, xi.z, hL, xi.y, HRf, shr);
       pHR = HRf;
     }
-    flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr, F);
+    flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr,
+                  p.wave_only, F);
   } else {
     const int b = -R - 1;
     const int ty = g.btype[b];
     if (ty == kBcWall) {
-      flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, F);
+      flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, F);
     } else {
       double wG[4], hG[4], dW0[4];
       const double z[4] = {0, 0, 0, 0};
@@ -1159,12 +1160,12 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xi.y);
       flux_interior(wL, wG, dW0, hvL ? hL : nullptr, st.ghvalid[b] ? hG : nullptr, z, z, st.dt[L], st.tau[L],
-                    st.dt[L], st.gtau[b], K, p.Pr, F);
+                    st.dt[L], st.gtau[b], K, p.Pr, p.wave_only, F);
       if (ty == kBcMaxwell) {
         // alpha times the diffuse wall's flux plus (1 - alpha) times the
         // mirror-state (specular) flux
         double Fd[4];
-        flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, Fd);
+        flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, Fd);
         const double a = g.bdata[8 * b + 1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) F[q] = a * Fd[q] + (1.0 - a) * F[q];
@@ -1324,7 +1325,8 @@ __global__ void k_surface(Geo g, Params p, State st) {
 // Bookkeeping after a step: per case the residuals and C_d (last, sum,
 // EMA), one thread per case; then the step's particle counts, and the step
 // counter advances (the step is committed).  A runaway track halts later
-// steps; so does meeting the residual target (every case's r_avg below it).
+// steps; so does meeting the residual target (every case's r_avg, r_inst in
+// wave-only runs, below it).
 __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
   __shared__ int all_below;
   if (blockIdx.x != 0 || *st.halt) return;
@@ -1344,7 +1346,9 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
     sc[kScalCdLast] = cd;
     sc[kScalCdSum] += cd;
     sc[kScalCdEma] = step == 0 ? cd : a * cd + (1.0 - a) * sc[kScalCdEma];
-    if (!(sc[kScalRavg] < tgt)) atomicAnd(&all_below, 0);
+    // particle runs test the running mean's residual (the particle noise
+    // floors the instantaneous one); wave-only runs have no noise
+    if (!((p.wave_only ? sc[kScalRinst] : sc[kScalRavg]) < tgt)) atomicAnd(&all_below, 0);
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -1355,7 +1359,7 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
   st.info[kInfoSumTotal] += ntot;
   *st.dstep = step + 1;
   if (*st.flags & kFlagRunaway) *st.halt = 1;
-  // convergence test: the first step n >= 100 with r_avg below the target
+  // convergence test: the first step n >= 100 with the residual below the target
   if (tgt > 0.0 && step + 1 >= 100 && all_below) {
     *st.flags |= kFlagConverged;
     *st.halt = 1;

@@ -1,0 +1,387 @@
+// Dense layers of the warm-start network on the matrix cores (gfx950):
+// BF16 operands, FP32 accumulation with v_mfma_f32_32x32x16_bf16.
+//
+// One kernel computes C[M x N] = A[M x K] * B[N x K]^T for row-major A and B
+// (both contiguous along K, so a lane's eight operand values are one 16-byte
+// load), either into a plain output with the layer epilogue (bias, GELU,
+// BF16 copies, optionally transposed) or, split along K, accumulated into an
+// FP32 output with atomics (the weight gradient, whose K is the batch).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ugkwp_mlp.h"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// case values of the feature map, parameters already normalized
+struct WsCase {
+  double ma_n, kn_n, tw_n, rho_inf, U_inf, T_inf, R;
+  int D;
+};
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// Each wavefront computes one 32 x 32 tile of C over the K range
+// [k_begin, k_end) (a multiple of 16).  Lane l holds A[row0 + l % 32][k + 8 (l / 32) .. + 7]
+// and B[col0 + l % 32][same k]; the accumulator's element i of lane l is
+// C[row0 + 8 (i / 4) + 4 (l / 32) + i % 4][col0 + l % 32].
+__device__ __forceinline__ f32x16 tile_mma(const uint16_t *__restrict__ A, int64_t lda, const uint16_t *__restrict__ B,
+                                           int64_t ldb, int64_t row0, int64_t col0, int64_t k_begin, int64_t k_end) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const uint16_t *pa = A + (row0 + r) * lda + 8 * h;
+  const uint16_t *pb = B + (col0 + r) * ldb + 8 * h;
+  f32x16 acc = {};
+  for (int64_t k = k_begin; k < k_end; k += 16) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k);
+    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(pb + k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Layer: Z = A B^T + bias; with act, Y = GELU(Z) else Y = Z.  Writes Z (FP32,
+// optional), Y as FP32 (optional), as BF16 (optional) and as transposed BF16
+// [N x M] (optional).  Grid: (M / 32) x (N / 32) wavefronts, 4 per block.
+__global__ void __launch_bounds__(256) k_layer(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                               const float *__restrict__ bias, int64_t M, int64_t N, int64_t K,
+                                               int act, float *__restrict__ Z, float *__restrict__ Y32,
+                                               uint16_t *__restrict__ Y16, uint16_t *__restrict__ YT16) {
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  const int64_t tiles_n = N / 32;
+  if (wave >= (M / 32) * tiles_n) return;
+  const int64_t row0 = (wave / tiles_n) * 32, col0 = (wave % tiles_n) * 32;
+  const f32x16 acc = tile_mma(A, K, B, K, row0, col0, 0, K);
+  const int lane = threadIdx.x & 63;
+  const int64_t col = col0 + (lane & 31);
+  const float bc = bias ? bias[col] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t row = row0 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
+    const float z = acc[i] + bc;
+    const float y = act ? gelu(z) : z;
+    if (Z) Z[row * N + col] = z;
+    if (Y32) Y32[row * N + col] = y;
+    const uint16_t yb = f2bf(y);
+    if (Y16) Y16[row * N + col] = yb;
+    if (YT16) YT16[col * M + row] = yb;
+  }
+}
+
+// Weight gradient: G[M x N] += A B^T over K split into chunks of kc; one
+// wavefront per (tile, chunk), FP32 atomics into G (cleared by the caller).
+__global__ void __launch_bounds__(256) k_gemm_splitk(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                                     int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                     float *__restrict__ G) {
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  const int64_t tiles = (M / 32) * (N / 32);
+  const int64_t chunks = (K + kc - 1) / kc;
+  if (wave >= tiles * chunks) return;
+  const int64_t t = wave % tiles, ch = wave / tiles;
+  const int64_t tiles_n = N / 32;
+  const int64_t row0 = (t / tiles_n) * 32, col0 = (t % tiles_n) * 32;
+  const int64_t k0 = ch * kc, k1 = k0 + kc < K ? k0 + kc : K;
+  const f32x16 acc = tile_mma(A, K, B, K, row0, col0, k0, k1);
+  const int lane = threadIdx.x & 63;
+  const int64_t col = col0 + (lane & 31);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t row = row0 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
+    atomicAdd(&G[row * N + col], acc[i]);
+  }
+}
+
+// dZ = dY * GELU'(Z) (or dY without activation); writes dZ as BF16 [M x N]
+// and transposed [N x M], and adds the column sums to db (cleared by the
+// caller).  One thread per element of a column-major walk so that a
+// wavefront covers 64 rows of one column (coalesced transposed store).
+__global__ void __launch_bounds__(256) k_act_backward(const float *__restrict__ dY, const float *__restrict__ Z,
+                                                      int64_t M, int64_t N, int act, uint16_t *__restrict__ dZ16,
+                                                      uint16_t *__restrict__ dZT16, float *__restrict__ db) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  float v = 0.0f;
+  int64_t col = -1;
+  if (e < M * N) {
+    col = e / M;
+    const int64_t row = e % M;
+    const float g = dY[row * N + col];
+    v = act ? g * gelu_grad(Z[row * N + col]) : g;
+    const uint16_t b = f2bf(v);
+    dZ16[row * N + col] = b;
+    dZT16[col * M + row] = b;
+  }
+  // column sums: lanes of one column in a wavefront add together
+  const int64_t c0 = __shfl(col, 0, 64);
+  const bool uniform = __all(col == c0);
+  if (uniform) {
+    float s = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0 && c0 >= 0) atomicAdd(&db[c0], s);
+  } else if (col >= 0) {
+    atomicAdd(&db[col], v);
+  }
+}
+
+// Adam (Kingma and Ba) on FP32 master weights w, moments m, v; step t >= 1;
+// writes the BF16 copy and, for a matrix [R x C] (C > 1), its transpose.
+__global__ void __launch_bounds__(256) k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                              const float *__restrict__ g, int64_t n, int64_t cols, float lr,
+                                              float b1, float b2, float eps, float c1, float c2,
+                                              uint16_t *__restrict__ w16, uint16_t *__restrict__ wT16) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  const uint16_t b = f2bf(wi);
+  if (w16) w16[i] = b;
+  if (wT16) {
+    const int64_t rows = n / cols, r = i / cols, c = i % cols;
+    wT16[c * rows + r] = b;
+  }
+}
+
+// Loss gradient of the mean squared error over the first n_out of N output
+// columns: dY = scale (Y - T) there, 0 in the padding; loss += sum (Y - T)^2
+// (one atomic per wavefront).
+__global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T,
+                                                  int64_t M, int64_t N, int64_t n_out, float scale,
+                                                  float *__restrict__ dY, float *__restrict__ loss) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  float sq = 0.0f;
+  if (e < M * N) {
+    const int64_t r = e / N, c = e % N;
+    float g = 0.0f;
+    if (c < n_out) {
+      const float d = Y[e] - T[r * n_out + c];
+      g = scale * d;
+      sq = d * d;
+    }
+    dY[e] = g;
+  }
+  if (loss) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss, sq);
+  }
+}
+
+// Normalized primitives (ln rho/rho_inf, u/U_inf, v/U_inf, ln T/T_inf) of a
+// conservative 2D state with rho E = rho |U|^2 / 2 + (3 + D) rho R T / 2.
+__device__ __forceinline__ void norm_prim(const double *w, const WsCase &c, double p[4]) {
+  const double rho = w[0], u = w[1] / rho, v = w[2] / rho;
+  const double T = (w[3] / rho - 0.5 * (u * u + v * v)) / (0.5 * (3 + c.D) * c.R);
+  p[0] = log(rho / c.rho_inf);
+  p[1] = u / c.U_inf;
+  p[2] = v / c.U_inf;
+  p[3] = log(T / c.T_inf);
+}
+
+// Feature rows of the fine O-grid (cell (I, J) at row J nft + I): columns 0-3
+// the coarse normalized primitives interpolated bilinearly in cell-index
+// space (periodic in the angular index, clamped in the radial one), 4-6 the
+// normalized case parameters, 7-14 sin/cos(2 pi k s) (k = 1..4,
+// s = (I + 1/2)/nft), 15 2 r - 1 and 16-21 sin/cos(pi k r) (k = 1..3,
+// r = (J + 1/2)/nfr), 22-31 zero; rows from nft nfr to `rows` are zero.
+__global__ void __launch_bounds__(256) k_ws_features(const double *__restrict__ Wc, int nct, int ncr, int nft,
+                                                     int nfr, WsCase c, int64_t rows, uint16_t *__restrict__ X16,
+                                                     uint16_t *__restrict__ XT16, float *__restrict__ P32) {
+  const int64_t row = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (row >= rows) return;
+  float f[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) f[k] = 0.0f;
+  const int64_t nf = static_cast<int64_t>(nft) * nfr;
+  if (row < nf) {
+    const int I = static_cast<int>(row % nft), J = static_cast<int>(row / nft);
+    double y = (J + 0.5) * ncr / nfr - 0.5;
+    y = y < 0.0 ? 0.0 : (y > ncr - 1.0 ? ncr - 1.0 : y);
+    int j0 = static_cast<int>(floor(y));
+    if (j0 > ncr - 2) j0 = ncr - 2;
+    const double b = y - j0;
+    const double x = (I + 0.5) * nct / nft - 0.5;
+    const int i0 = static_cast<int>(floor(x));
+    const double a = x - i0;
+    const int i0m = ((i0 % nct) + nct) % nct, i1m = (i0m + 1) % nct;
+    double p00[4], p01[4], p10[4], p11[4];
+    norm_prim(Wc + 4 * (static_cast<int64_t>(j0) * nct + i0m), c, p00);
+    norm_prim(Wc + 4 * (static_cast<int64_t>(j0) * nct + i1m), c, p01);
+    norm_prim(Wc + 4 * (static_cast<int64_t>(j0 + 1) * nct + i0m), c, p10);
+    norm_prim(Wc + 4 * (static_cast<int64_t>(j0 + 1) * nct + i1m), c, p11);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double v = (1 - a) * (1 - b) * p00[k] + a * (1 - b) * p01[k] + (1 - a) * b * p10[k] + a * b * p11[k];
+      f[k] = static_cast<float>(v);
+      if (P32) P32[row * 4 + k] = static_cast<float>(v);
+    }
+    f[4] = static_cast<float>(c.ma_n);
+    f[5] = static_cast<float>(c.kn_n);
+    f[6] = static_cast<float>(c.tw_n);
+    const double s = (I + 0.5) / nft, r = (J + 0.5) / nfr;
+    constexpr double kPi = 3.141592653589793238;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      f[5 + 2 * k] = static_cast<float>(sin(2.0 * kPi * k * s));
+      f[6 + 2 * k] = static_cast<float>(cos(2.0 * kPi * k * s));
+    }
+    f[15] = static_cast<float>(2.0 * r - 1.0);
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+      f[14 + 2 * k] = static_cast<float>(sin(kPi * k * r));
+      f[15 + 2 * k] = static_cast<float>(cos(kPi * k * r));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const uint16_t b = f2bf(f[k]);
+    X16[row * 32 + k] = b;
+    if (XT16) XT16[k * rows + row] = b;
+  }
+}
+
+// Initial field from the network output: p = P + Y[:, 0:4] (Y rows of ldy
+// floats), rho = rho_inf e^p0, u = U_inf p1, v = U_inf p2, T = T_inf e^p3,
+// written as conservative FP64 (rho, rho u, rho v, rho E).
+__global__ void __launch_bounds__(256) k_ws_decode(const float *__restrict__ Y, int64_t ldy,
+                                                   const float *__restrict__ P, int64_t n, WsCase c,
+                                                   double *__restrict__ W) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = static_cast<double>(P[i * 4 + k]) + static_cast<double>(Y[i * ldy + k]);
+  const double rho = c.rho_inf * exp(p[0]), u = c.U_inf * p[1], v = c.U_inf * p[2], T = c.T_inf * exp(p[3]);
+  W[4 * i + 0] = rho;
+  W[4 * i + 1] = rho * u;
+  W[4 * i + 2] = rho * v;
+  W[4 * i + 3] = 0.5 * rho * (u * u + v * v) + 0.5 * (3 + c.D) * rho * c.R * T;
+}
+
+// BF16 copies of an FP32 [rows x cols] matrix: w16 same layout, wT16 transposed.
+__global__ void __launch_bounds__(256) k_to_bf16(const float *__restrict__ w, int64_t n, int64_t cols,
+                                                 uint16_t *__restrict__ w16, uint16_t *__restrict__ wT16) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const uint16_t b = f2bf(w[i]);
+  if (w16) w16[i] = b;
+  if (wT16) wT16[(i % cols) * (n / cols) + i / cols] = b;
+}
+
+int64_t blocks_for_waves(int64_t waves) { return (waves + 3) / 4; }
+
+bool case_ok(const ugkwp_ws_case *c) {
+  return c && c->rho_inf > 0.0 && c->U_inf > 0.0 && c->T_inf > 0.0 && c->R > 0.0 && c->D >= 0 && c->Kn > 0.0;
+}
+
+WsCase make_case(const ugkwp_ws_case *c) {
+  WsCase w;
+  w.ma_n = (c->Ma - 12.5) / 7.5;
+  const double lc = 0.5 * (log(0.005) + log(0.2)), lh = 0.5 * log(40.0);
+  w.kn_n = (log(c->Kn) - lc) / lh;
+  w.tw_n = (c->Tw - 0.3) / 0.2;
+  w.rho_inf = c->rho_inf;
+  w.U_inf = c->U_inf;
+  w.T_inf = c->T_inf;
+  w.R = c->R;
+  w.D = c->D;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugkwp_mlp_layer(const uint16_t *A, const uint16_t *B, const float *bias, int64_t M, int64_t N, int64_t K,
+                    int32_t act, float *Z, float *Y32, uint16_t *Y16, uint16_t *YT16, void *stream) {
+  if (!A || !B || M <= 0 || N <= 0 || K <= 0 || M % 32 || N % 32 || K % 16) return -1;
+  const int64_t waves = (M / 32) * (N / 32);
+  hipLaunchKernelGGL(k_layer, dim3(static_cast<unsigned>(blocks_for_waves(waves))), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), A, B, bias, M, N, K, act, Z, Y32, Y16, YT16);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_gemm_acc(const uint16_t *A, const uint16_t *B, int64_t M, int64_t N, int64_t K, int64_t k_chunk,
+                       float *G, void *stream) {
+  if (!A || !B || !G || M <= 0 || N <= 0 || K <= 0 || M % 32 || N % 32 || K % 16 || k_chunk <= 0 ||
+      k_chunk % 16)
+    return -1;
+  const int64_t waves = (M / 32) * (N / 32) * ((K + k_chunk - 1) / k_chunk);
+  hipLaunchKernelGGL(k_gemm_splitk, dim3(static_cast<unsigned>(blocks_for_waves(waves))), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), A, B, M, N, K, k_chunk, G);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_act_backward(const float *dY, const float *Z, int64_t M, int64_t N, int32_t act, uint16_t *dZ16,
+                           uint16_t *dZT16, float *db, void *stream) {
+  if (!dY || !dZ16 || !dZT16 || !db || (act && !Z) || M <= 0 || N <= 0) return -1;
+  const int64_t n = M * N;
+  hipLaunchKernelGGL(k_act_backward, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), dY, Z, M, N, act, dZ16, dZT16, db);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, int64_t cols, float lr, float beta1,
+                   float beta2, float eps, int64_t t, uint16_t *w16, uint16_t *wT16, void *stream) {
+  if (!w || !m || !v || !g || n <= 0 || cols <= 0 || n % cols || t < 1) return -1;
+  const float c1 = 1.0f - powf(beta1, static_cast<float>(t)), c2 = 1.0f - powf(beta2, static_cast<float>(t));
+  hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), w, m, v, g, n, cols, lr, beta1, beta2, eps, c1, c2, w16, wT16);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_to_bf16(const float *w, int64_t n, int64_t cols, uint16_t *w16, uint16_t *wT16, void *stream) {
+  if (!w || n <= 0 || cols <= 0 || n % cols || (!w16 && !wT16)) return -1;
+  hipLaunchKernelGGL(k_to_bf16, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), w, n, cols, w16, wT16);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_mse_grad(const float *Y, const float *T, int64_t M, int64_t N, int64_t n_out, float scale, float *dY,
+                       float *loss, void *stream) {
+  if (!Y || !T || !dY || M <= 0 || N <= 0 || n_out <= 0 || n_out > N) return -1;
+  const int64_t n = M * N;
+  hipLaunchKernelGGL(k_mse_grad, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), Y, T, M, N, n_out, scale, dY, loss);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_ws_features(const double *Wc, int32_t nct, int32_t ncr, int32_t nft, int32_t nfr,
+                      const ugkwp_ws_case *c, int64_t rows, uint16_t *X16, uint16_t *XT16, float *P32, void *stream) {
+  if (!Wc || !X16 || !case_ok(c) || nct < 2 || ncr < 2 || nft < 1 || nfr < 1 ||
+      rows < static_cast<int64_t>(nft) * nfr || rows % 32)
+    return -1;
+  hipLaunchKernelGGL(k_ws_features, dim3(static_cast<unsigned>((rows + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), Wc, nct, ncr, nft, nfr, make_case(c), rows, X16, XT16, P32);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_ws_decode(const float *Y, int64_t ldy, const float *P32, int64_t n, const ugkwp_ws_case *c, double *W,
+                    void *stream) {
+  if (!Y || !P32 || !W || !case_ok(c) || n <= 0 || ldy < 4) return -1;
+  hipLaunchKernelGGL(k_ws_decode, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), Y, ldy, P32, n, make_case(c), W);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // extern "C"

@@ -1,0 +1,495 @@
+"""Learned warm start of steady cylinder runs.
+
+The method fixes the local time steps from the initial field and marches to
+a steady state (Sec. IV, Eq. (33); the test cases of Sec. V start from the
+free stream).  A better initial field shortens the march.  This module
+predicts one:
+
+  1. a coarse solve of the same case on a 40 x 30 O-grid whose nodes are
+     every fifth node of the fine 200 x 150 grid, with this library's solver
+     in wave-only mode (no particles: the gas-kinetic scheme), run until
+     r_inst < 1e-6;
+  2. features per fine cell (ugkwp_ws_features): the coarse normalized
+     primitives interpolated bilinearly in cell-index space, the case
+     parameters (Ma, Kn, T_w) and a Fourier encoding of the cell indices;
+  3. a multilayer perceptron (32 -> 256 -> 256 -> 256 -> 32, GELU) whose
+     first four outputs correct the interpolated primitives
+     (ugkwp_ws_decode turns them into the conservative initial field).
+
+Training fits the corrections to time-averaged steady fields of full UGKWP
+runs of sampled cases (mean squared error, Adam).  Every arithmetic step of
+inference and training runs in the library's kernels (dense layers on the
+BF16 matrix cores); torch only holds device memory and clears gradient
+buffers.
+
+Command line (GPU): ``python -m paper_2607_09552_amd.warmstart data|train|eval``.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import Solver, UgkwpError, WsCase, load_library
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+WEIGHTS = os.path.join(HERE, "warmstart_weights.npz")
+WIDTHS = (32, 256, 256, 256, 32)
+N_OUT = 4
+FINE = (200, 150)
+COARSE = (40, 30)
+# ranges of the sampled cases
+MA_RANGE, KN_RANGE, TW_RANGE = (5.0, 20.0), (0.005, 0.2), (0.1, 0.5)
+
+
+def _vp(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _chk(rc, what):
+    if rc != 0:
+        raise UgkwpError(rc, what)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def use_own_stream():
+    """Make a fresh (default-priority) stream torch's current one, so that the
+    solver, these kernels and torch's own work are ordered on one stream."""
+    import torch
+    torch.cuda.set_device(0)
+    torch.cuda.set_stream(torch.cuda.Stream())
+
+
+def draws(n, seed):
+    """n cases (Ma, Kn, T_w): Ma and T_w uniform, Kn log-uniform over the
+    ranges above (numpy generator seeded with `seed`)."""
+    u = np.random.default_rng(seed).random((n, 3))
+    ma = MA_RANGE[0] + (MA_RANGE[1] - MA_RANGE[0]) * u[:, 0]
+    kn = KN_RANGE[0] * (KN_RANGE[1] / KN_RANGE[0]) ** u[:, 1]
+    tw = TW_RANGE[0] + (TW_RANGE[1] - TW_RANGE[0]) * u[:, 2]
+    return np.stack([ma, kn, tw], axis=1)
+
+
+def fine_case(Ma, Kn, Tw, n_ref=400, seed=1):
+    import workloads
+    return workloads.cylinder(n_theta=FINE[0], n_r=FINE[1], Ma=Ma, Kn=Kn, Tw=Tw, n_ref=n_ref, seed=seed)
+
+
+def coarse_case(Ma, Kn, Tw):
+    """Wave-only case on the O-grid made of every fifth fine node: same outer
+    radius, first cell height the sum of the first five fine ones."""
+    import workloads
+    f = workloads.ogrid(FINE[0], FINE[1])[3]
+    rt, rr = FINE[0] // COARSE[0], FINE[1] // COARSE[1]
+    h1 = 1e-4 * (f ** rr - 1.0) / (f - 1.0)
+    assert rt * COARSE[0] == FINE[0] and rr * COARSE[1] == FINE[1]
+    w = workloads.cylinder(n_theta=COARSE[0], n_r=COARSE[1], h1=h1, Ma=Ma, Kn=Kn, Tw=Tw, n_ref=1, seed=1)
+    w["wave_only"] = 1
+    return w
+
+
+def ws_case(wl, Ma, Kn, Tw):
+    """Warm-start case record of workload wl (its free stream and gas)."""
+    g, r = wl["gas"], wl["ref"]
+    return WsCase(Ma=Ma, Kn=Kn, Tw=Tw, rho_inf=r["rho_inf"], U_inf=math.hypot(*r["u_inf"]), T_inf=r["T_inf"],
+                  R=g["R"], D=g["D"])
+
+
+def cylinder_ws_case(Ma, Kn, Tw):
+    """Warm-start case record of the cylinder workload (rho_inf = T_inf = R = 1,
+    U_inf = Ma sqrt(5/3), monatomic) without building its mesh."""
+    import workloads
+    return WsCase(Ma=Ma, Kn=Kn, Tw=Tw, rho_inf=1.0, U_inf=Ma * math.sqrt(workloads.GAMMA_MONATOMIC), T_inf=1.0,
+                  R=1.0, D=0)
+
+
+def coarse_solve(cases, max_steps=40000, tol=1e-6):
+    """Wave-only coarse solves of cases [(Ma, Kn, T_w)] in one batch; returns
+    (device fields [n_case, ncr nct, 4] FP64, steps, converged, seconds)."""
+    import torch
+    wls = [coarse_case(*c) for c in cases]
+    s = Solver.batch(wls, stream=_stream().value, tuned=False)
+    try:
+        t0 = time.perf_counter()
+        conv, steps = s.step_until(tol, max_steps)
+        W = s.fields_device()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        s.close()
+    return W.view(len(cases), COARSE[0] * COARSE[1], 4), steps, conv, dt
+
+
+def _bf16_buf(*shape):
+    import torch
+    return torch.empty(shape, dtype=torch.int16, device="cuda")
+
+
+class MLP:
+    """FP32 master weights W_l [out x in], b_l [out]; BF16 copies W_l and
+    W_l^T for the matrix-core layers; Adam moments."""
+
+    def __init__(self, widths=WIDTHS, seed=0, weights=None):
+        import torch
+        load_library()
+        self.widths = tuple(widths)
+        rng = np.random.default_rng(seed)
+        self.W, self.b = [], []
+        for l, (i, o) in enumerate(zip(widths[:-1], widths[1:])):
+            if weights is not None:
+                w, b = weights[f"W{l}"], weights[f"b{l}"]
+            else:
+                scale = math.sqrt(2.0 / i) * (0.1 if l == len(widths) - 2 else 1.0)
+                w, b = rng.standard_normal((o, i)) * scale, np.zeros(o)
+            self.W.append(torch.tensor(np.asarray(w, np.float32), device="cuda").contiguous())
+            self.b.append(torch.tensor(np.asarray(b, np.float32), device="cuda").contiguous())
+        self.W16 = [_bf16_buf(*w.shape) for w in self.W]
+        self.WT16 = [_bf16_buf(w.shape[1], w.shape[0]) for w in self.W]
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.gW = [torch.zeros_like(w) for w in self.W]
+        self.gb = [torch.zeros_like(b) for b in self.b]
+        self.t = 0
+        self._bufs = {}
+        self._sync_bf16()
+
+    def _sync_bf16(self):
+        L, st = load_library(), _stream()
+        for w, w16, wt16 in zip(self.W, self.W16, self.WT16):
+            _chk(L.ugkwp_mlp_to_bf16(_vp(w), w.numel(), w.shape[1], _vp(w16), _vp(wt16), st), "to_bf16")
+
+    def weights(self):
+        out = {}
+        for l, (w, b) in enumerate(zip(self.W, self.b)):
+            out[f"W{l}"] = w.detach().cpu().numpy()
+            out[f"b{l}"] = b.detach().cpu().numpy()
+        return out
+
+    def save(self, path, meta=None):
+        np.savez(path, **self.weights(), meta=json.dumps(meta or {}))
+
+    @classmethod
+    def load(cls, path=WEIGHTS):
+        z = np.load(path)
+        ws = {k: z[k] for k in z.files if k != "meta"}
+        n = len([k for k in ws if k.startswith("W")])
+        widths = [ws["W0"].shape[1]] + [ws[f"W{l}"].shape[0] for l in range(n)]
+        return cls(widths=widths, weights=ws)
+
+    def _buffers(self, M):
+        import torch
+        if M in self._bufs:
+            return self._bufs[M]
+        wd = self.widths
+        nl = len(wd) - 1
+        b = dict(
+            H16=[None] + [_bf16_buf(M, wd[l]) for l in range(1, nl)],
+            HT16=[None] + [_bf16_buf(wd[l], M) for l in range(1, nl)],
+            Z=[torch.empty((M, wd[l + 1]), dtype=torch.float32, device="cuda") for l in range(nl)],
+            Y=torch.empty((M, wd[-1]), dtype=torch.float32, device="cuda"),
+            dY=torch.empty((M, max(wd)), dtype=torch.float32, device="cuda"),
+            dH=torch.empty((M, max(wd)), dtype=torch.float32, device="cuda"),
+            dZ16=_bf16_buf(M * max(wd)),
+            dZT16=_bf16_buf(M * max(wd)),
+            loss=torch.zeros(1, dtype=torch.float32, device="cuda"),
+        )
+        self._bufs = {M: b}  # one batch size at a time
+        return b
+
+    def forward(self, X16, M, train=False):
+        """Network output [M x 32] FP32 for BF16 features X16 [M x 32]."""
+        L, st = load_library(), _stream()
+        b = self._buffers(M)
+        nl = len(self.widths) - 1
+        H = X16
+        for l in range(nl):
+            last = l == nl - 1
+            _chk(L.ugkwp_mlp_layer(_vp(H), _vp(self.W16[l]), _vp(self.b[l]), M, self.widths[l + 1], self.widths[l],
+                                   0 if last else 1, _vp(b["Z"][l]) if (train and not last) else None,
+                                   _vp(b["Y"]) if last else None, None if last else _vp(b["H16"][l + 1]),
+                                   _vp(b["HT16"][l + 1]) if (train and not last) else None, st), "layer")
+            if not last:
+                H = b["H16"][l + 1]
+        return b["Y"]
+
+    def train_step(self, X16, XT16, T, M, lr, beta1=0.9, beta2=0.999, eps=1e-8, k_chunk=512):
+        """One Adam step on the mean squared error of the first four outputs
+        against T [M x 4]; returns the device loss (sum of squares)."""
+        L, st = load_library(), _stream()
+        wd = self.widths
+        nl = len(wd) - 1
+        b = self._buffers(M)
+        Y = self.forward(X16, M, train=True)
+        b["loss"].zero_()
+        dY = b["dY"]
+        _chk(L.ugkwp_mlp_mse_grad(_vp(Y), _vp(T), M, wd[-1], N_OUT, 2.0 / (M * N_OUT), _vp(dY), _vp(b["loss"]), st),
+             "mse_grad")
+        for g in self.gW + self.gb:
+            g.zero_()
+        G = dY  # gradient w.r.t. the current layer's output, [M x out]
+        for l in range(nl - 1, -1, -1):
+            o, i = wd[l + 1], wd[l]
+            Hin, HinT = (X16, XT16) if l == 0 else (b["H16"][l], b["HT16"][l])
+            _chk(L.ugkwp_mlp_act_backward(_vp(G), _vp(b["Z"][l]) if l < nl - 1 else None, M, o,
+                                          1 if l < nl - 1 else 0, _vp(b["dZ16"]), _vp(b["dZT16"]), _vp(self.gb[l]),
+                                          st), "act_backward")
+            _chk(L.ugkwp_mlp_gemm_acc(_vp(b["dZT16"]), _vp(HinT), o, i, M, k_chunk, _vp(self.gW[l]), st),
+                 "gemm_acc")
+            if l > 0:
+                dH = b["dH"] if G.data_ptr() != b["dH"].data_ptr() else b["dY"]
+                _chk(L.ugkwp_mlp_layer(_vp(b["dZ16"]), _vp(self.WT16[l]), None, M, i, o, 0, None, _vp(dH), None,
+                                       None, st), "layer_backward")
+                G = dH
+        self.t += 1
+        for l in range(nl):
+            w = self.W[l]
+            _chk(L.ugkwp_mlp_adam(_vp(w), _vp(self.mW[l]), _vp(self.vW[l]), _vp(self.gW[l]), w.numel(), w.shape[1],
+                                  lr, beta1, beta2, eps, self.t, _vp(self.W16[l]), _vp(self.WT16[l]), st), "adam")
+            bb = self.b[l]
+            _chk(L.ugkwp_mlp_adam(_vp(bb), _vp(self.mb[l]), _vp(self.vb[l]), _vp(self.gb[l]), bb.numel(), bb.numel(),
+                                  lr, beta1, beta2, eps, self.t, None, None, st), "adam")
+        return b["loss"]
+
+
+def features(Wc, case, rows, XT=True):
+    """Device features of the fine grid for one case from its coarse fields
+    Wc (device [ncr nct, 4] FP64): (X16 [rows x 32], XT16 or None, P32)."""
+    import torch
+    L = load_library()
+    nf = FINE[0] * FINE[1]
+    X16 = _bf16_buf(rows, 32)
+    XT16 = _bf16_buf(32, rows) if XT else None
+    P32 = torch.empty((nf, 4), dtype=torch.float32, device="cuda")
+    _chk(L.ugkwp_ws_features(_vp(Wc), COARSE[0], COARSE[1], FINE[0], FINE[1], C.byref(case), rows, _vp(X16),
+                             _vp(XT16) if XT else None, _vp(P32), _stream()), "features")
+    return X16, XT16, P32
+
+
+def predict(mlp, Wc, case):
+    """Fine initial field (host [nf x 4] FP64) for one case."""
+    import torch
+    L = load_library()
+    nf = FINE[0] * FINE[1]
+    rows = (nf + 31) // 32 * 32
+    X16, _, P32 = features(Wc, case, rows, XT=False)
+    Y = mlp.forward(X16, rows)
+    W = torch.empty((nf, 4), dtype=torch.float64, device="cuda")
+    _chk(L.ugkwp_ws_decode(_vp(Y), Y.shape[1], _vp(P32), nf, C.byref(case), _vp(W), _stream()), "decode")
+    return W.cpu().numpy()
+
+
+def warm_start(Ma, Kn, Tw, mlp=None, wl=None):
+    """Initial field for the fine case (Ma, Kn, T_w): coarse wave-only solve,
+    features, network, decode.  Returns (W0 [nf x 4] host, info)."""
+    import torch
+    mlp = mlp or MLP.load()
+    t0 = time.perf_counter()
+    Wc, steps, conv, _ = coarse_solve([(Ma, Kn, Tw)])
+    W0 = predict(mlp, Wc[0], ws_case(wl or fine_case(Ma, Kn, Tw, n_ref=1), Ma, Kn, Tw))
+    torch.cuda.synchronize()
+    return W0, dict(coarse_steps=steps, coarse_converged=conv, seconds=time.perf_counter() - t0)
+
+
+def _norm_prim(W, wl):
+    g, r = wl["gas"], wl["ref"]
+    rho = W[:, 0]
+    u, v = W[:, 1] / rho, W[:, 2] / rho
+    T = (W[:, 3] / rho - 0.5 * (u * u + v * v)) / (0.5 * (3 + g["D"]) * g["R"])
+    U = math.hypot(*r["u_inf"])
+    return np.stack([np.log(rho / r["rho_inf"]), u / U, v / U, np.log(T / r["T_inf"])], axis=1)
+
+
+# ---------------------------------------------------------------- command line
+
+
+def cmd_data(a):
+    """Steady fields of sampled cases: coarse wave-only solves and time-averaged
+    fine UGKWP runs (mixed precision, n_ref particles per cell), in batches."""
+    import torch
+    use_own_stream()
+    cases = np.concatenate([draws(a.n_train, 3), draws(a.n_test, 4)])
+    n = len(cases)
+    print(f"coarse wave-only solves: {n} cases", flush=True)
+    Wc, steps, conv, dt = coarse_solve([tuple(c) for c in cases], max_steps=a.coarse_max)
+    print(f"  steps {steps} converged {conv} {dt:.1f} s", flush=True)
+    nf = FINE[0] * FINE[1]
+    P = np.zeros((n, nf, 4), dtype=np.float16)
+    for b0 in range(0, n, a.batch):
+        idx = list(range(b0, min(n, b0 + a.batch)))
+        wls = [fine_case(*cases[k], n_ref=a.n_ref, seed=2000 + k) for k in idx]
+        t0 = time.perf_counter()
+        s = Solver.batch(wls, stream=_stream().value, precision="mixed", tuned=False)
+        acc = torch.zeros((s.nc, 4), dtype=torch.float64, device="cuda")
+        s.step(a.transient)
+        torch.cuda.synchronize()
+        print(f"  cases {idx[0]}-{idx[-1]}: {a.transient} steps {time.perf_counter() - t0:.1f} s", flush=True)
+        for k in range(a.average // a.every):
+            s.step(a.every)
+            acc += s.fields_device()
+            if (k + 1) % max(1, (a.average // a.every) // 4) == 0:
+                torch.cuda.synchronize()
+                print(f"    averaged {(k + 1) * a.every} steps {time.perf_counter() - t0:.1f} s", flush=True)
+        acc /= a.average // a.every
+        Wm = acc.cpu().numpy()
+        for j, k in enumerate(idx):
+            c0, ncells = s.case_range(j)[:2]
+            P[k] = _norm_prim(Wm[c0:c0 + ncells], wls[j]).astype(np.float16)
+        s.close()
+        del acc
+        torch.cuda.empty_cache()
+    np.savez(a.out, cases=cases, n_train=a.n_train, coarse=Wc.cpu().numpy(), fine=P, n_ref=a.n_ref,
+             transient=a.transient, average=a.average, coarse_steps=steps)
+    print(f"wrote {a.out}", flush=True)
+
+
+def cmd_train(a):
+    import torch
+    use_own_stream()
+    z = np.load(a.data)
+    cases, ntr = z["cases"], int(z["n_train"])
+    coarse = torch.tensor(z["coarse"], device="cuda")
+    fine = z["fine"].astype(np.float32)
+    nf = FINE[0] * FINE[1]
+    # assemble the features and the target corrections of every case
+    Xs, XTs, Ts = [], [], []
+    for k in range(len(cases)):
+        c = cylinder_ws_case(*cases[k])
+        X16, _, P32 = features(coarse[k], c, nf + (-nf) % 32, XT=False)
+        Xs.append(X16[:nf].cpu().numpy())
+        Ts.append(fine[k] - P32.cpu().numpy())
+    X = np.stack(Xs)  # [n, nf, 32] int16 (BF16 bits)
+    T = np.stack(Ts).astype(np.float32)
+    Xtr, Ttr = X[:ntr].reshape(-1, 32), T[:ntr].reshape(-1, 4)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(len(Xtr))
+    M = a.batch
+    nb = len(Xtr) // M
+    Xb = Xtr[perm[: nb * M]].reshape(nb, M, 32)
+    Tb = Ttr[perm[: nb * M]].reshape(nb, M, 4)
+    Xd = torch.tensor(Xb, device="cuda")
+    XTd = torch.tensor(np.ascontiguousarray(Xb.transpose(0, 2, 1)), device="cuda")
+    Td = torch.tensor(Tb, device="cuda")
+    mlp = MLP(seed=a.seed)
+    print(f"training: {nb} batches of {M}, {a.steps} steps", flush=True)
+    t0 = time.perf_counter()
+    hist = []
+    for it in range(a.steps):
+        lr = a.lr * 0.5 * (1.0 + math.cos(math.pi * it / a.steps))
+        j = it % nb
+        loss = mlp.train_step(Xd[j], XTd[j], Td[j], M, lr)
+        if (it + 1) % a.log_every == 0 or it == 0:
+            v = float(loss.item()) / (M * N_OUT)
+            hist.append((it + 1, v))
+            print(f"  step {it + 1} loss {v:.4e} lr {lr:.2e} {time.perf_counter() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    # per-case errors: coarse upsample alone vs corrected
+    def case_err(k):
+        rows = nf + (-nf) % 32
+        Xk = torch.tensor(np.concatenate([X[k], np.zeros((rows - nf, 32), np.int16)]), device="cuda")
+        Y = mlp.forward(Xk, rows)[:nf, :4].cpu().numpy()
+        e_up = np.sqrt(np.mean(T[k] ** 2, axis=0))
+        e_nn = np.sqrt(np.mean((T[k] - Y) ** 2, axis=0))
+        return e_up, e_nn
+
+    rep = {}
+    for name, ks in (("train", range(min(ntr, 16))), ("held_out", range(ntr, len(cases)))):
+        eu, en = zip(*[case_err(k) for k in ks])
+        rep[name] = dict(rms_upsampled=np.mean(eu, axis=0).tolist(), rms_network=np.mean(en, axis=0).tolist())
+        print(f"  {name}: RMS error (ln rho, u, v, ln T) upsampled {np.round(rep[name]['rms_upsampled'], 4)} "
+              f"network {np.round(rep[name]['rms_network'], 4)}", flush=True)
+    meta = dict(steps=a.steps, batch=M, lr=a.lr, seconds=train_s, history=hist, errors=rep,
+                data=dict(n_train=ntr, n_test=len(cases) - ntr, n_ref=int(z["n_ref"]), transient=int(z["transient"]),
+                          average=int(z["average"])))
+    mlp.save(a.out, meta)
+    print(f"wrote {a.out} ({train_s:.1f} s)", flush=True)
+
+
+def cmd_eval(a):
+    """Time to residual (r_avg < target) from the free stream and from the
+    warm start, same case, same precision."""
+    import torch
+    use_own_stream()
+    mlp = MLP.load(a.weights)
+    out = []
+    cases = [(a.ma, a.kn, a.tw)] if a.ma else [tuple(c) for c in draws(a.n_test, 4)[: a.n_cases]]
+    for (Ma, Kn, Tw) in cases:
+        wl = fine_case(Ma, Kn, Tw, n_ref=a.n_ref, seed=1)
+        res = dict(Ma=Ma, Kn=Kn, Tw=Tw, n_ref=a.n_ref, precision=a.precision)
+        for start in a.starts.split(","):
+            W0, info = (None, dict(seconds=0.0)) if start == "free" else warm_start(Ma, Kn, Tw, mlp, wl)
+            s = Solver(wl, W0=W0, stream=_stream().value, precision=a.precision)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                conv, steps = s.step_until(a.target, a.max_steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                cd = s.surface(1)[1]
+            finally:
+                s.close()
+            res[start] = dict(converged=conv, steps=int(steps), seconds=dt, start_seconds=info["seconds"],
+                              cd_mean=cd)
+            print(f"  Ma {Ma:.2f} Kn {Kn:.4f} Tw {Tw:.3f} {start}: converged {conv} steps {steps} {dt:.1f} s "
+                  f"(+{info['seconds']:.2f} s start) C_d {cd:.4f}", flush=True)
+        out.append(res)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2607_09552_amd.warmstart")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    d = sub.add_parser("data")
+    d.add_argument("--n-train", type=int, default=128)
+    d.add_argument("--n-test", type=int, default=16)
+    d.add_argument("--n-ref", type=int, default=100)
+    d.add_argument("--batch", type=int, default=48)
+    d.add_argument("--transient", type=int, default=3000)
+    d.add_argument("--average", type=int, default=2000)
+    d.add_argument("--every", type=int, default=10)
+    d.add_argument("--coarse-max", type=int, default=40000)
+    d.add_argument("--out", default="ws_data.npz")
+    t = sub.add_parser("train")
+    t.add_argument("--data", default="ws_data.npz")
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--batch", type=int, default=8192)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--log-every", type=int, default=500)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--ma", type=float, default=0.0)
+    e.add_argument("--kn", type=float, default=0.01)
+    e.add_argument("--tw", type=float, default=0.2)
+    e.add_argument("--n-test", type=int, default=16)
+    e.add_argument("--n-cases", type=int, default=2)
+    e.add_argument("--n-ref", type=int, default=400)
+    e.add_argument("--precision", default="mixed")
+    e.add_argument("--starts", default="free,warm")
+    e.add_argument("--target", type=float, default=1e-6)
+    e.add_argument("--max-steps", type=int, default=200000)
+    e.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    sys.path.insert(0, ROOT)
+    {"data": cmd_data, "train": cmd_train, "eval": cmd_eval}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -437,3 +437,13 @@ def test_maxwell_wall_parity():
     sr, cdr = r.surface(1)
     assert np.allclose(sg, sr, rtol=1e-8, atol=1e-8 * np.abs(sr).max())
     common_state_steps(w, [0, 7])
+
+
+def test_wave_only_parity():
+    """The gas-kinetic (wave-only, E = 0) scheme on a coarse 40 x 30 cylinder
+    at Ma 15: no particles; fields against the oracle's wave-only run."""
+    w = wl.cylinder(n_theta=40, n_r=30, n_ref=50, Pr=2.0 / 3.0)
+    w["wave_only"] = 1
+    g, r, _ = run_pair(w, [1, 10, 60])
+    assert g.counts()[1]["total"] == 0
+    common_state_steps(w, [0, 30])
