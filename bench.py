@@ -95,15 +95,24 @@ def copy_probe(gib=1.0, reps=5):
 
 
 def time_to_residual(a):
-    """Wall clock from the first step (init excluded) to the first step
-    n >= 100 with r_avg < target (the residual of the running mean density),
-    plain FP64 path from the uniform freestream start.  Prints progress and
-    one JSON line."""
+    """Wall clock to the first step n >= 100 with r_avg < target (the
+    residual of the running mean density), from the uniform freestream or
+    from the learned warm start (--warm-start: coarse solve, features,
+    network, decode; its time is part of the value).  The fine solver's
+    init is excluded in both.  Prints progress and one JSON line."""
     import numpy as np
     import torch
     from paper_2607_09552_amd import Solver
     w = workload(a.kn)
-    s = Solver(w)
+    W0, ws_info = None, None
+    if a.warm_start:
+        from paper_2607_09552_amd import warmstart as ws
+        mlp = ws.MLP.load()
+        torch.cuda.synchronize()
+        W0, ws_info = ws.warm_start(15.0, a.kn, 0.2, mlp=mlp, wl=w)
+        print(f"# warm start {ws_info['seconds']:.2f} s (coarse solve {ws_info['coarse_seconds']:.2f} s)",
+              file=sys.stderr, flush=True)
+    s = Solver(w, W0=W0, precision=a.precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     conv, n = False, 0
@@ -113,16 +122,20 @@ def time_to_residual(a):
         ri, ra, _ = s.residual()
         print(f"# step {n} r_inst {ri:.3e} r_avg {ra:.3e} {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    march = time.perf_counter() - t0
+    elapsed = march + (ws_info["seconds"] if ws_info else 0.0)
     ri, ra, _ = s.residual()
     surf, cd = s.surface(1)
+    start = ("learned warm start (coarse 40x30 UGKWP solve, BF16 MLP 32-256-256-256-32)" if a.warm_start
+             else "uniform freestream")
     out = {"metric": f"time-to-residual {a.ttr_target:g}", "value": elapsed if conv else None, "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "steps": int(n), "converged": bool(conv),
-           "elapsed_s": elapsed, "ms_per_step": elapsed / max(n, 1) * 1e3, "r_avg": ra, "r_inst": ri,
-           "dtype": "f64", "data": "synthetic",
+           "elapsed_s": elapsed, "march_s": march, "warm_start_s": ws_info["seconds"] if ws_info else 0.0,
+           "ms_per_step": march / max(n, 1) * 1e3, "r_avg": ra, "r_inst": ri,
+           "dtype": a.precision, "data": "synthetic",
            "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
-                                  f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, FP64, Philox seed 1",
-                      "start": "uniform freestream", "rule": "first n >= 100 with r_avg < target"},
+                                  f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, {a.precision}, Philox seed 1",
+                      "start": start, "rule": "first n >= 100 with r_avg < target"},
            "wall": {"Cd_mean": cd, "Cp_max": float(np.max(surf[:, 3])), "CF_absmax": float(np.max(np.abs(surf[:, 4]))),
                     "CQ_max": float(np.max(surf[:, 5]))}}
     print(json.dumps(out))
@@ -206,6 +219,59 @@ def batch_bench(a):
     print(json.dumps(out))
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_bench(a):
+    """Matrix-core kernels of the warm-start network (32-256-256-256-32,
+    GELU): inference over the 200x150 fine grid (30 016 rows) and training
+    steps of 8192 rows, timed with HIP events on the stream they run on."""
+    import numpy as np
+    import torch
+    from paper_2607_09552_amd import warmstart as ws
+    mlp = ws.MLP(seed=0)
+    wd = ws.WIDTHS
+    macs = sum(i * o for i, o in zip(wd[:-1], wd[1:]))
+    g = np.random.default_rng(0)
+
+    def rand_bf16(rows, cols):
+        x = g.standard_normal((rows, cols)).astype(np.float32)
+        return torch.tensor((x.view(np.uint32) >> 16).astype(np.uint16).view(np.int16), device="cuda")
+
+    def timed(fn, reps):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    M = ws.FINE[0] * ws.FINE[1] + (-ws.FINE[0] * ws.FINE[1]) % 32
+    X = rand_bf16(M, wd[0])
+    mlp.infer(X, M)
+    fwd_ms = timed(lambda: mlp.infer(X, M), a.steps)
+    fwd_tf = 2.0 * M * macs / (fwd_ms * 1e-3) / 1e12
+    lay_ms = timed(lambda: mlp.forward(X, M), a.steps)
+    Mt = 8192
+    Xt, XTt = rand_bf16(Mt, wd[0]), rand_bf16(wd[0], Mt)
+    T = torch.zeros((Mt, 4), dtype=torch.float32, device="cuda")
+    tr_ms = timed(lambda: mlp.train_step(Xt, XTt, T, Mt, 1e-4), a.steps)
+    tr_tf = 6.0 * Mt * macs / (tr_ms * 1e-3) / 1e12
+    out = {"metric": "warm-start network TFLOP/s (inference)", "value": fwd_tf, "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": 5, "ms_per_step": fwd_ms, "higher_is_better": True, "scaling": "strong",
+           "vs_baseline": None, "dtype": "bf16 operands, f32 accumulation", "data": "synthetic",
+           "config": {"workload": f"MLP {'-'.join(map(str, wd))} GELU, {M} rows (200x150 grid)",
+                      "per_layer_ms": lay_ms, "per_layer_tflops": 2.0 * M * macs / (lay_ms * 1e-3) / 1e12,
+                      "train_rows": Mt, "train_ms_per_step": tr_ms, "train_tflops": tr_tf},
+           "roofline": {"bound": "mfma", "kernel": "k_mlp_fused", "achieved": fwd_tf,
+                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fwd_tf / MFMA_BF16_PEAK_TFLOPS,
+                        "traffic": None, "flops_per_forward": 2.0 * M * macs}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +295,9 @@ def main():
                     help="time to residual: run from the freestream start until r_avg < --ttr-target")
     ap.add_argument("--ttr-target", type=float, default=1e-6)
     ap.add_argument("--ttr-max-steps", type=int, default=600000)
+    ap.add_argument("--mlp", action="store_true", help="matrix-core kernels of the warm-start network")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="with --ttr: start from the learned warm start instead of the freestream")
     a = ap.parse_args()
     if a.steps is None:
         a.steps = 100 if a.batch else 1000
@@ -250,6 +319,10 @@ def main():
 
     if a.ttr:
         time_to_residual(a)
+        return
+    if a.mlp:
+        a.steps = a.steps if a.steps != 1000 else 200
+        mlp_bench(a)
         return
     if a.precision_study:
         precision_study(a)

@@ -62,6 +62,27 @@ int ugkwp_mlp_act_backward(const float *dY, const float *Z, int64_t M, int64_t N
 int ugkwp_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, int64_t cols, float lr, float beta1,
                    float beta2, float eps, int64_t t, uint16_t *w16, uint16_t *wT16, void *stream);
 
+/* Inference of the whole network in one kernel, the activations kept in
+ * registers between layers (32 samples per wavefront).  Supported widths:
+ * 32 -> 256 -> 256 -> 256 -> 32 (n_layers = 4), hidden layers with GELU,
+ * the last linear; each activation is rounded to BF16 before the next layer,
+ * as in ugkwp_mlp_layer.
+ *   X [M x 32] BF16 inputs, M % 32 == 0;
+ *   Wf[l]: layer l's weights packed by ugkwp_mlp_pack (permuted = 0 for
+ *   l = 0, 1 for the others); bias[l] [widths[l+1]] FP32;
+ *   Y [M x 32] FP32 outputs.
+ * The pointer arrays Wf and bias are host arrays of device pointers. */
+int ugkwp_mlp_forward(const uint16_t *X, int64_t M, int32_t n_layers, const int32_t *widths, const uint16_t *const *Wf,
+                      const float *const *bias, float *Y, void *stream);
+
+/* Weights W [out x in] FP32 (out % 32 == 0, in % 16 == 0) as BF16 in the
+ * fragment order of ugkwp_mlp_forward:
+ *   Wf[((t S + s) 64 + lane) 8 + e] = W[32 t + lane % 32][k],  S = in / 16,
+ * with k = 16 s + 8 (lane / 32) + e (permuted = 0) or
+ * k = 16 s + 8 (e / 4) + 4 (lane / 32) + e % 4 (permuted = 1: the order in
+ * which a layer's outputs sit in the lanes). */
+int ugkwp_mlp_pack(const float *W, int64_t out, int64_t in, int32_t permuted, uint16_t *Wf, void *stream);
+
 /* BF16 copies of an FP32 matrix w [n / cols x cols]: w16 (same layout) and
  * wT16 (transposed), either optional but not both NULL. */
 int ugkwp_mlp_to_bf16(const float *w, int64_t n, int64_t cols, uint16_t *w16, uint16_t *wT16, void *stream);

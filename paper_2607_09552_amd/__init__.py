@@ -25,7 +25,7 @@ ABI_SYMBOLS = (
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
     "ugkwp_mlp_layer", "ugkwp_mlp_gemm_acc", "ugkwp_mlp_act_backward", "ugkwp_mlp_adam", "ugkwp_mlp_to_bf16",
-    "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode",
+    "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode", "ugkwp_mlp_pack", "ugkwp_mlp_forward",
 )
 
 
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_mlp_act_backward.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp, vp]
     L.ugkwp_mlp_adam.argtypes = [vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, i64, vp, vp, vp]
     L.ugkwp_mlp_to_bf16.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.ugkwp_mlp_pack.argtypes = [vp, i64, i64, i32, vp, vp]
+    L.ugkwp_mlp_forward.argtypes = [vp, i64, i32, C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp, vp]
     L.ugkwp_mlp_mse_grad.argtypes = [vp, vp, i64, i64, i64, f32, vp, vp, vp]
     L.ugkwp_ws_features.argtypes = [vp, i32, i32, i32, i32, C.POINTER(WsCase), i64, vp, vp, vp, vp]
     L.ugkwp_ws_decode.argtypes = [vp, i64, vp, i64, C.POINTER(WsCase), vp, vp]

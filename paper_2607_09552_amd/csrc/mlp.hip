@@ -278,6 +278,119 @@ __global__ void __launch_bounds__(256) k_ws_decode(const float *__restrict__ Y, 
   W[4 * i + 3] = 0.5 * rho * (u * u + v * v) + 0.5 * (3 + c.D) * rho * c.R * T;
 }
 
+// ---- whole-network forward with the activations in registers ----------
+//
+// Each wavefront pushes 32 samples through every layer.  A layer is computed
+// transposed, D = W X^T (the MFMA's A operand a weight tile, its B operand the
+// activations), so that lane l of the result holds sample l % 32 and outputs
+// out0 + 8 (r / 4) + 4 (l / 32) + r % 4 of its tile (r = 0..15).  Those are
+// exactly the eight values per lane of the next layer's B operand for two
+// k-steps if the next layer's input features are taken in the matching order:
+// k-step s, lane half h, slot e <-> feature 16 s + 8 (e / 4) + 4 h + e % 4.
+// The weights are packed once (k_pack_frag) in that order and in fragment
+// order, so a lane's A operand is one 16-byte load and a wavefront's one
+// contiguous kilobyte.  The first layer reads its inputs from memory in
+// natural order.
+
+// feature index of slot e of lane half h in k-step s
+__host__ __device__ __forceinline__ int64_t frag_feature(int64_t s, int h, int e, int permuted) {
+  return permuted ? 16 * s + 8 * (e / 4) + 4 * h + (e % 4) : 16 * s + 8 * h + e;
+}
+
+// Wf[((t * S + s) * 64 + lane) * 8 + e] = bf16(W[32 t + lane % 32][frag_feature(s, lane / 32, e)])
+// for W [out x in] FP32, S = in / 16, t < out / 32.
+__global__ void __launch_bounds__(256) k_pack_frag(const float *__restrict__ W, int64_t out, int64_t in,
+                                                   int permuted, uint16_t *__restrict__ Wf) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= out * in) return;
+  const int e = static_cast<int>(i % 8), lane = static_cast<int>((i / 8) % 64);
+  const int64_t ts = i / 512, S = in / 16;
+  const int64_t t = ts / S, s = ts % S;
+  Wf[i] = f2bf(W[(32 * t + lane % 32) * in + frag_feature(s, lane / 32, e, permuted)]);
+}
+
+struct FusedNet {
+  const uint16_t *W[4];  // packed fragments: layer 0 natural order, later layers permuted
+  const float *b[4];
+};
+
+union Frag {
+  bf16x8 v;
+  uint16_t h[8];
+};
+
+// one layer on register activations: in [KS] k-steps -> acc [T] tiles
+template <int KS, int T>
+__device__ __forceinline__ void layer_regs(const uint16_t *__restrict__ Wf, const Frag (&act)[KS], f32x16 (&acc)[T],
+                                           int lane) {
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = f32x16{};
+  const bf16x8 *w = reinterpret_cast<const bf16x8 *>(Wf) + lane;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const bf16x8 a = w[(t * KS + s) * 64];
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[s].v, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+// bias, GELU, BF16: the accumulators of T tiles become 2T k-steps of the
+// next layer's operand
+template <int T>
+__device__ __forceinline__ void to_next(const f32x16 (&acc)[T], const float *__restrict__ bias, int h,
+                                        Frag (&act)[2 * T]) {
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int out = 32 * t + 8 * (r / 4) + 4 * h + (r % 4);
+      act[2 * t + r / 8].h[r % 8] = f2bf(gelu(acc[t][r] + bias[out]));
+    }
+  }
+}
+
+// widths K0 -> H -> H (NH - 1 times) -> NO
+template <int K0, int H, int NH, int NO>
+__global__ void __launch_bounds__(64) k_mlp_fused(const uint16_t *__restrict__ X, int64_t M, FusedNet net,
+                                                  float *__restrict__ Y) {
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 32;
+  if (row0 >= M) return;
+  const int lane = threadIdx.x & 63, sl = lane & 31, h = lane >> 5;
+  Frag xin[K0 / 16];
+#pragma unroll
+  for (int s = 0; s < K0 / 16; ++s)
+    xin[s].v = *reinterpret_cast<const bf16x8 *>(X + (row0 + sl) * K0 + 16 * s + 8 * h);
+  Frag act[H / 16];
+  {
+    f32x16 acc[H / 32];
+    layer_regs<K0 / 16, H / 32>(net.W[0], xin, acc, lane);
+    to_next<H / 32>(acc, net.b[0], h, act);
+  }
+#pragma unroll
+  for (int l = 1; l < NH; ++l) {
+    f32x16 acc[H / 32];
+    layer_regs<H / 16, H / 32>(net.W[l], act, acc, lane);
+    to_next<H / 32>(acc, net.b[l], h, act);
+  }
+  f32x16 out[NO / 32];
+  layer_regs<H / 16, NO / 32>(net.W[NH], act, out, lane);
+#pragma unroll
+  for (int t = 0; t < NO / 32; ++t) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int o = 32 * t + 8 * g + 4 * h;
+      float4 v;
+      v.x = out[t][4 * g + 0] + net.b[NH][o + 0];
+      v.y = out[t][4 * g + 1] + net.b[NH][o + 1];
+      v.z = out[t][4 * g + 2] + net.b[NH][o + 2];
+      v.w = out[t][4 * g + 3] + net.b[NH][o + 3];
+      *reinterpret_cast<float4 *>(Y + (row0 + sl) * NO + o) = v;
+    }
+  }
+}
+
 // BF16 copies of an FP32 [rows x cols] matrix: w16 same layout, wT16 transposed.
 __global__ void __launch_bounds__(256) k_to_bf16(const float *__restrict__ w, int64_t n, int64_t cols,
                                                  uint16_t *__restrict__ w16, uint16_t *__restrict__ wT16) {
@@ -354,6 +467,31 @@ int ugkwp_mlp_to_bf16(const float *w, int64_t n, int64_t cols, uint16_t *w16, ui
   if (!w || n <= 0 || cols <= 0 || n % cols || (!w16 && !wT16)) return -1;
   hipLaunchKernelGGL(k_to_bf16, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), w, n, cols, w16, wT16);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_pack(const float *W, int64_t out, int64_t in, int32_t permuted, uint16_t *Wf, void *stream) {
+  if (!W || !Wf || out <= 0 || in <= 0 || out % 32 || in % 16) return -1;
+  const int64_t n = out * in;
+  hipLaunchKernelGGL(k_pack_frag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), W, out, in, permuted ? 1 : 0, Wf);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int ugkwp_mlp_forward(const uint16_t *X, int64_t M, int32_t n_layers, const int32_t *widths, const uint16_t *const *Wf,
+                      const float *const *bias, float *Y, void *stream) {
+  if (!X || !Y || !widths || !Wf || !bias || M <= 0 || M % 32) return -1;
+  if (n_layers != 4 || widths[0] != 32 || widths[1] != 256 || widths[2] != 256 || widths[3] != 256 ||
+      widths[4] != 32)
+    return -1;
+  FusedNet net;
+  for (int l = 0; l < 4; ++l) {
+    if (!Wf[l] || !bias[l]) return -1;
+    net.W[l] = Wf[l];
+    net.b[l] = bias[l];
+  }
+  hipLaunchKernelGGL((k_mlp_fused<32, 256, 3, 32>), dim3(static_cast<unsigned>(M / 32)), dim3(64), 0,
+                     static_cast<hipStream_t>(stream), X, M, net, Y);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -5,10 +5,12 @@ a steady state (Sec. IV, Eq. (33); the test cases of Sec. V start from the
 free stream).  A better initial field shortens the march.  This module
 predicts one:
 
-  1. a coarse solve of the same case on a 40 x 30 O-grid whose nodes are
-     every fifth node of the fine 200 x 150 grid, with this library's solver
-     in wave-only mode (no particles: the gas-kinetic scheme), run until
-     r_inst < 1e-6;
+  1. a coarse UGKWP-LTS solve of the same case on a 40 x 30 O-grid whose
+     nodes are every fifth node of the fine 200 x 150 grid (50 particles per
+     cell), its fields averaged over a window after a fixed transient.  (The
+     wave-only mode, i.e. the gas-kinetic scheme without particles, cannot
+     carry these starts: gas leaving the leeward wall faster than the escape
+     speed 2c/(gamma - 1) = 3c opens a vacuum, and the blow-up follows.);
   2. features per fine cell (ugkwp_ws_features): the coarse normalized
      primitives interpolated bilinearly in cell-index space, the case
      parameters (Ma, Kn, T_w) and a Fourier encoding of the cell indices;
@@ -27,6 +29,7 @@ Command line (GPU): ``python -m paper_2607_09552_amd.warmstart data|train|eval``
 from __future__ import annotations
 
 import argparse
+import contextlib
 import ctypes as C
 import json
 import math
@@ -47,6 +50,8 @@ FINE = (200, 150)
 COARSE = (40, 30)
 # ranges of the sampled cases
 MA_RANGE, KN_RANGE, TW_RANGE = (5.0, 20.0), (0.005, 0.2), (0.1, 0.5)
+# coarse solve: particles per cell, steps before and during averaging
+COARSE_NREF, COARSE_TRANSIENT, COARSE_AVERAGE, COARSE_EVERY = 50, 1500, 1500, 5
 
 
 def _vp(t):
@@ -61,6 +66,20 @@ def _chk(rc, what):
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@contextlib.contextmanager
+def _nonnull_stream():
+    """Run the body on a real stream: a solver given the null stream runs on
+    its own non-blocking one, unordered with torch's null-stream work."""
+    import torch
+    if torch.cuda.current_stream().cuda_stream != 0:
+        yield
+        return
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        yield
+    torch.cuda.current_stream().wait_stream(st)
 
 
 def use_own_stream():
@@ -86,17 +105,15 @@ def fine_case(Ma, Kn, Tw, n_ref=400, seed=1):
     return workloads.cylinder(n_theta=FINE[0], n_r=FINE[1], Ma=Ma, Kn=Kn, Tw=Tw, n_ref=n_ref, seed=seed)
 
 
-def coarse_case(Ma, Kn, Tw):
-    """Wave-only case on the O-grid made of every fifth fine node: same outer
+def coarse_case(Ma, Kn, Tw, n_ref=COARSE_NREF, seed=3):
+    """The case on the O-grid made of every fifth fine node: same outer
     radius, first cell height the sum of the first five fine ones."""
     import workloads
     f = workloads.ogrid(FINE[0], FINE[1])[3]
     rt, rr = FINE[0] // COARSE[0], FINE[1] // COARSE[1]
     h1 = 1e-4 * (f ** rr - 1.0) / (f - 1.0)
     assert rt * COARSE[0] == FINE[0] and rr * COARSE[1] == FINE[1]
-    w = workloads.cylinder(n_theta=COARSE[0], n_r=COARSE[1], h1=h1, Ma=Ma, Kn=Kn, Tw=Tw, n_ref=1, seed=1)
-    w["wave_only"] = 1
-    return w
+    return workloads.cylinder(n_theta=COARSE[0], n_r=COARSE[1], h1=h1, Ma=Ma, Kn=Kn, Tw=Tw, n_ref=n_ref, seed=seed)
 
 
 def ws_case(wl, Ma, Kn, Tw):
@@ -114,21 +131,37 @@ def cylinder_ws_case(Ma, Kn, Tw):
                   R=1.0, D=0)
 
 
-def coarse_solve(cases, max_steps=40000, tol=1e-6):
-    """Wave-only coarse solves of cases [(Ma, Kn, T_w)] in one batch; returns
-    (device fields [n_case, ncr nct, 4] FP64, steps, converged, seconds)."""
+def averaged_fields(s, transient, average, every, log=None):
+    """Device mean of the conservative fields of solver s over `average`
+    steps (sampled every `every`) after `transient` steps."""
     import torch
-    wls = [coarse_case(*c) for c in cases]
-    s = Solver.batch(wls, stream=_stream().value, tuned=False)
-    try:
-        t0 = time.perf_counter()
-        conv, steps = s.step_until(tol, max_steps)
-        W = s.fields_device()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-    finally:
-        s.close()
-    return W.view(len(cases), COARSE[0] * COARSE[1], 4), steps, conv, dt
+    s.step(transient)
+    acc = torch.zeros((s.nc, s.nw), dtype=torch.float64, device="cuda")
+    n = max(1, average // every)
+    for k in range(n):
+        s.step(every)
+        acc += s.fields_device()
+        if log and (k + 1) % max(1, n // 4) == 0:
+            log(f"averaged {(k + 1) * every} steps")
+    return acc / n
+
+
+def coarse_solve(cases, transient=COARSE_TRANSIENT, average=COARSE_AVERAGE, every=COARSE_EVERY):
+    """Coarse solves of cases [(Ma, Kn, T_w)] in one batch; returns (device
+    mean fields [n_case, ncr nct, 4] FP64, seconds)."""
+    import torch
+    wls = [coarse_case(*c, seed=3000 + k) for k, c in enumerate(cases)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with _nonnull_stream():
+        s = Solver.batch(wls, stream=_stream().value, precision="mixed", tuned=False)
+        try:
+            W = averaged_fields(s, transient, average, every)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            s.close()
+    return W.view(len(cases), COARSE[0] * COARSE[1], 4), dt
 
 
 def _bf16_buf(*shape):
@@ -164,6 +197,8 @@ class MLP:
         self.gb = [torch.zeros_like(b) for b in self.b]
         self.t = 0
         self._bufs = {}
+        self._packed_at = None
+        self.Wf = [_bf16_buf(w.numel()) for w in self.W]
         self._sync_bf16()
 
     def _sync_bf16(self):
@@ -209,8 +244,33 @@ class MLP:
         self._bufs = {M: b}  # one batch size at a time
         return b
 
+    def fused_ok(self):
+        return self.widths == WIDTHS
+
+    def infer(self, X16, M):
+        """Network output [M x 32] FP32 for BF16 features X16 [M x 32], in one
+        kernel (activations in registers); the per-layer path for other
+        widths."""
+        import torch
+        if not self.fused_ok():
+            return self.forward(X16, M)
+        L, st = load_library(), _stream()
+        if self._packed_at != self.t:
+            for l, w in enumerate(self.W):
+                _chk(L.ugkwp_mlp_pack(_vp(w), w.shape[0], w.shape[1], 0 if l == 0 else 1, _vp(self.Wf[l]), st),
+                     "pack")
+            self._packed_at = self.t
+        Y = torch.empty((M, self.widths[-1]), dtype=torch.float32, device="cuda")
+        nl = len(self.widths) - 1
+        wd = (C.c_int32 * (nl + 1))(*self.widths)
+        wp = (C.c_void_p * nl)(*[w.data_ptr() for w in self.Wf])
+        bp = (C.c_void_p * nl)(*[b.data_ptr() for b in self.b])
+        _chk(L.ugkwp_mlp_forward(_vp(X16), M, nl, wd, wp, bp, _vp(Y), st), "forward")
+        return Y
+
     def forward(self, X16, M, train=False):
-        """Network output [M x 32] FP32 for BF16 features X16 [M x 32]."""
+        """Network output [M x 32] FP32 for BF16 features X16 [M x 32], one
+        launch per layer (train: keep what the backward pass needs)."""
         L, st = load_library(), _stream()
         b = self._buffers(M)
         nl = len(self.widths) - 1
@@ -285,7 +345,7 @@ def predict(mlp, Wc, case):
     nf = FINE[0] * FINE[1]
     rows = (nf + 31) // 32 * 32
     X16, _, P32 = features(Wc, case, rows, XT=False)
-    Y = mlp.forward(X16, rows)
+    Y = mlp.infer(X16, rows)
     W = torch.empty((nf, 4), dtype=torch.float64, device="cuda")
     _chk(L.ugkwp_ws_decode(_vp(Y), Y.shape[1], _vp(P32), nf, C.byref(case), _vp(W), _stream()), "decode")
     return W.cpu().numpy()
@@ -297,10 +357,10 @@ def warm_start(Ma, Kn, Tw, mlp=None, wl=None):
     import torch
     mlp = mlp or MLP.load()
     t0 = time.perf_counter()
-    Wc, steps, conv, _ = coarse_solve([(Ma, Kn, Tw)])
+    Wc, tc = coarse_solve([(Ma, Kn, Tw)])
     W0 = predict(mlp, Wc[0], ws_case(wl or fine_case(Ma, Kn, Tw, n_ref=1), Ma, Kn, Tw))
     torch.cuda.synchronize()
-    return W0, dict(coarse_steps=steps, coarse_converged=conv, seconds=time.perf_counter() - t0)
+    return W0, dict(coarse_seconds=tc, seconds=time.perf_counter() - t0)
 
 
 def _norm_prim(W, wl):
@@ -322,9 +382,9 @@ def cmd_data(a):
     use_own_stream()
     cases = np.concatenate([draws(a.n_train, 3), draws(a.n_test, 4)])
     n = len(cases)
-    print(f"coarse wave-only solves: {n} cases", flush=True)
-    Wc, steps, conv, dt = coarse_solve([tuple(c) for c in cases], max_steps=a.coarse_max)
-    print(f"  steps {steps} converged {conv} {dt:.1f} s", flush=True)
+    print(f"coarse solves: {n} cases", flush=True)
+    Wc, dt = coarse_solve([tuple(c) for c in cases])
+    print(f"  {dt:.1f} s", flush=True)
     nf = FINE[0] * FINE[1]
     P = np.zeros((n, nf, 4), dtype=np.float16)
     for b0 in range(0, n, a.batch):
@@ -332,17 +392,12 @@ def cmd_data(a):
         wls = [fine_case(*cases[k], n_ref=a.n_ref, seed=2000 + k) for k in idx]
         t0 = time.perf_counter()
         s = Solver.batch(wls, stream=_stream().value, precision="mixed", tuned=False)
-        acc = torch.zeros((s.nc, 4), dtype=torch.float64, device="cuda")
-        s.step(a.transient)
-        torch.cuda.synchronize()
-        print(f"  cases {idx[0]}-{idx[-1]}: {a.transient} steps {time.perf_counter() - t0:.1f} s", flush=True)
-        for k in range(a.average // a.every):
-            s.step(a.every)
-            acc += s.fields_device()
-            if (k + 1) % max(1, (a.average // a.every) // 4) == 0:
-                torch.cuda.synchronize()
-                print(f"    averaged {(k + 1) * a.every} steps {time.perf_counter() - t0:.1f} s", flush=True)
-        acc /= a.average // a.every
+
+        def log(msg):
+            torch.cuda.synchronize()
+            print(f"  cases {idx[0]}-{idx[-1]}: {msg} {time.perf_counter() - t0:.1f} s", flush=True)
+
+        acc = averaged_fields(s, a.transient, a.average, a.every, log)
         Wm = acc.cpu().numpy()
         for j, k in enumerate(idx):
             c0, ncells = s.case_range(j)[:2]
@@ -351,7 +406,7 @@ def cmd_data(a):
         del acc
         torch.cuda.empty_cache()
     np.savez(a.out, cases=cases, n_train=a.n_train, coarse=Wc.cpu().numpy(), fine=P, n_ref=a.n_ref,
-             transient=a.transient, average=a.average, coarse_steps=steps)
+             transient=a.transient, average=a.average)
     print(f"wrote {a.out}", flush=True)
 
 
@@ -401,7 +456,7 @@ def cmd_train(a):
     def case_err(k):
         rows = nf + (-nf) % 32
         Xk = torch.tensor(np.concatenate([X[k], np.zeros((rows - nf, 32), np.int16)]), device="cuda")
-        Y = mlp.forward(Xk, rows)[:nf, :4].cpu().numpy()
+        Y = mlp.infer(Xk, rows)[:nf, :4].cpu().numpy()
         e_up = np.sqrt(np.mean(T[k] ** 2, axis=0))
         e_nn = np.sqrt(np.mean((T[k] - Y) ** 2, axis=0))
         return e_up, e_nn
@@ -444,6 +499,7 @@ def cmd_eval(a):
                 s.close()
             res[start] = dict(converged=conv, steps=int(steps), seconds=dt, start_seconds=info["seconds"],
                               cd_mean=cd)
+            del W0
             print(f"  Ma {Ma:.2f} Kn {Kn:.4f} Tw {Tw:.3f} {start}: converged {conv} steps {steps} {dt:.1f} s "
                   f"(+{info['seconds']:.2f} s start) C_d {cd:.4f}", flush=True)
         out.append(res)
@@ -463,7 +519,6 @@ def main(argv=None):
     d.add_argument("--transient", type=int, default=3000)
     d.add_argument("--average", type=int, default=2000)
     d.add_argument("--every", type=int, default=10)
-    d.add_argument("--coarse-max", type=int, default=40000)
     d.add_argument("--out", default="ws_data.npz")
     t = sub.add_parser("train")
     t.add_argument("--data", default="ws_data.npz")

@@ -50,11 +50,13 @@ def host(t):
     return t.cpu().numpy()
 
 
-def within_bf16_ulp(got16, want64, ulps=1):
-    """BF16 results within `ulps` units in the last place of the FP64 values."""
+def within_bf16_ulp(got16, want64, abs_tol=0.0):
+    """BF16 results within one unit in the last place of the FP64 values, plus
+    abs_tol: the error the FP32 value had before rounding (cancellation makes
+    it large relative to small results)."""
     got = vals(got16)
-    ulp = np.maximum(np.abs(want64), 1e-30) * 2.0 ** -7
-    return np.all(np.abs(got - want64) <= ulps * ulp + 1e-30)
+    ulp = np.abs(want64) * 2.0 ** -7
+    return np.all(np.abs(got - want64) <= ulp + abs_tol)
 
 
 @pytest.mark.parametrize("M,N,K,act", [(96, 64, 48, 1), (32, 256, 256, 1), (160, 32, 256, 0)])
@@ -80,7 +82,7 @@ def test_layer_forward(M, N, K, act):
     # the BF16 copy is the rounding of the FP32 result, and its transpose
     assert np.array_equal(vals(y16), ref.bf16(host(Y)))
     assert np.array_equal(host(YT16), y16.T)
-    assert within_bf16_ulp(y16, Yr)
+    assert within_bf16_ulp(y16, Yr, abs_tol=1.2 * bound + 1e-7)
 
 
 def test_layer_rejects_bad_shapes():
@@ -101,7 +103,8 @@ def test_gemm_acc_split_k(K, kc):
     B = ref.bf16(g.standard_normal((N, K)))
     G0 = g.standard_normal((M, N)).astype(np.float32)
     G = dev(G0)
-    assert lib().ugkwp_mlp_gemm_acc(vp(dev(bits(A))), vp(dev(bits(B))), M, N, K, kc, vp(G), None) == 0
+    dA, dB = dev(bits(A)), dev(bits(B))  # held until the kernel has run
+    assert lib().ugkwp_mlp_gemm_acc(vp(dA), vp(dB), M, N, K, kc, vp(G), None) == 0
     want = G0 + A @ B.T
     bound = 1e-5 * (np.abs(A) @ np.abs(B).T) * (K / 256 + 1) + 1e-6 * np.abs(G0)
     assert np.all(np.abs(host(G) - want) <= bound)
@@ -117,12 +120,16 @@ def test_act_backward(act):
     dZ16 = torch.empty((M, N), dtype=torch.int16, device="cuda")
     dZT16 = torch.empty((N, M), dtype=torch.int16, device="cuda")
     db = torch.zeros(N, dtype=torch.float32, device="cuda")
-    rc = lib().ugkwp_mlp_act_backward(vp(dev(dY, torch.float32)), vp(dev(Z, torch.float32)), M, N, act, vp(dZ16),
-                                      vp(dZT16), vp(db), None)
+    ddY, dZ = dev(dY, torch.float32), dev(Z, torch.float32)
+    rc = lib().ugkwp_mlp_act_backward(vp(ddY), vp(dZ), M, N, act, vp(dZ16), vp(dZT16), vp(db), None)
     assert rc == 0
     want = dY * ref.gelu_grad(Z) if act else dY
     d16 = host(dZ16)
-    assert within_bf16_ulp(d16, want)
+    if act:
+        # FP32 erf and exp: GELU' within 1e-6 absolute (it has a root near -0.75)
+        assert within_bf16_ulp(d16, want, abs_tol=1e-6 * np.abs(dY))
+    else:
+        assert np.array_equal(vals(d16), ref.bf16(dY))
     assert np.array_equal(host(dZT16), d16.T)
     assert np.allclose(host(db), want.sum(0), rtol=1e-5, atol=1e-5 * np.abs(want).sum(0).max())
 
@@ -140,7 +147,8 @@ def test_adam_and_bf16_copies():
     L = lib()
     for t in range(1, 4):
         gr = g.standard_normal((R, Cc)).astype(np.float32).astype(np.float64)
-        assert L.ugkwp_mlp_adam(vp(dw), vp(dm), vp(dv), vp(dev(gr, torch.float32)), R * Cc, Cc, 1e-2, 0.9, 0.999,
+        dg = dev(gr, torch.float32)
+        assert L.ugkwp_mlp_adam(vp(dw), vp(dm), vp(dv), vp(dg), R * Cc, Cc, 1e-2, 0.9, 0.999,
                                 1e-8, t, vp(w16), vp(wT16), None) == 0
         w, m, v = ref.adam(w, m, v, gr, t, lr=1e-2)
         got = host(dw)
@@ -161,8 +169,8 @@ def test_mse_grad():
     T = g.standard_normal((M, n_out)).astype(np.float32).astype(np.float64)
     dY = torch.empty((M, N), dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    assert lib().ugkwp_mlp_mse_grad(vp(dev(Y, torch.float32)), vp(dev(T, torch.float32)), M, N, n_out,
-                                    2.0 / (M * n_out), vp(dY), vp(loss), None) == 0
+    dYin, dT = dev(Y, torch.float32), dev(T, torch.float32)
+    assert lib().ugkwp_mlp_mse_grad(vp(dYin), vp(dT), M, N, n_out, 2.0 / (M * n_out), vp(dY), vp(loss), None) == 0
     lr_, gr = ref.mse(Y, T, n_out)
     assert np.allclose(host(dY), gr, rtol=1e-6, atol=1e-9)
     assert abs(host(loss)[0] / (M * n_out) - lr_) <= 1e-5 * lr_
@@ -186,8 +194,8 @@ def test_training_step_gradients_and_update():
     mlp.b = [b + torch.tensor(0.1 * g.standard_normal(b.shape[0]), dtype=torch.float32, device="cuda")
              for b in mlp.b]
     params = _mlp_ref_params(mlp)
-    xb = dev(bits(X))
-    mlp.train_step(xb, dev(np.ascontiguousarray(bits(X).T)), dev(T, torch.float32), M, lr=0.0)
+    xb, xt, tt = dev(bits(X)), dev(np.ascontiguousarray(bits(X).T)), dev(T, torch.float32)
+    mlp.train_step(xb, xt, tt, M, lr=0.0)
     Y, cache = ref.forward(params, X, q=ref.bf16)
     _, dY = ref.mse(Y, T, 4)
     grads, _ = ref.backward(params, cache, dY, q=ref.bf16)
@@ -199,7 +207,7 @@ def test_training_step_gradients_and_update():
     # lr = 0 left the weights; a real step is Adam on the device gradients
     assert all(np.array_equal(mlp.W[l].cpu().numpy(), params[l][0].astype(np.float32)) for l in range(4))
     gws = [mlp.gW[l].cpu().numpy().astype(np.float64) for l in range(4)]
-    mlp.train_step(xb, dev(np.ascontiguousarray(bits(X).T)), dev(T, torch.float32), M, lr=1e-3)
+    mlp.train_step(xb, xt, tt, M, lr=1e-3)
     torch.cuda.synchronize()
     # t = 2 moments from two gradients: the first (gws) and the second (same
     # weights, same batch: the same gradient up to accumulation order)
@@ -256,23 +264,65 @@ def test_features_and_decode(nct, ncr, nft, nfr):
     XT16 = torch.empty((32, rows), dtype=torch.int16, device="cuda")
     P32 = torch.empty((nf, 4), dtype=torch.float32, device="cuda")
     L = lib()
-    assert L.ugkwp_ws_features(vp(dev(Wc)), nct, ncr, nft, nfr, C.byref(case), rows, vp(X16), vp(XT16), vp(P32),
+    dWc = dev(Wc)
+    assert L.ugkwp_ws_features(vp(dWc), nct, ncr, nft, nfr, C.byref(case), rows, vp(X16), vp(XT16), vp(P32),
                                None) == 0
     Xr, Pr = ref.features(Wc, nct, ncr, nft, nfr, (Ma, Kn, Tw, 1.0, U, 1.0, 1.0, 0), rows=rows)
     x16 = host(X16)
     assert np.all(x16[nf:] == 0)
     assert np.array_equal(host(XT16), x16.T)
     # BF16 of the FP32 rounding of the FP64 value: within one BF16 ulp (zeros exact)
-    assert within_bf16_ulp(x16[:nf], Xr[:nf])
+    assert within_bf16_ulp(x16[:nf], Xr[:nf], abs_tol=1e-7)
     assert np.allclose(host(P32), Pr, rtol=1e-6, atol=1e-6)
     # decode of a correction
     g = np.random.default_rng(3)
     Y = (0.1 * g.standard_normal((nf, 32))).astype(np.float32)
     W = torch.empty((nf, 4), dtype=torch.float64, device="cuda")
-    assert L.ugkwp_ws_decode(vp(dev(Y)), 32, vp(P32), nf, C.byref(case), vp(W), None) == 0
+    dY = dev(Y)
+    assert L.ugkwp_ws_decode(vp(dY), 32, vp(P32), nf, C.byref(case), vp(W), None) == 0
     want = ref.decode(Y.astype(np.float64), host(P32).astype(np.float64), 1.0, U, 1.0)
     assert np.allclose(host(W), want, rtol=1e-13, atol=1e-13)
     bad = WsCase(Ma=Ma, Kn=-1.0, Tw=Tw, rho_inf=1.0, U_inf=U, T_inf=1.0, R=1.0, D=0)
-    assert L.ugkwp_ws_features(vp(dev(Wc)), nct, ncr, nft, nfr, C.byref(bad), rows, vp(X16), None, None, None) == -1
-    assert L.ugkwp_ws_features(vp(dev(Wc)), nct, ncr, nft, nfr, C.byref(case), nf - 1, vp(X16), None, None,
+    assert L.ugkwp_ws_features(vp(dWc), nct, ncr, nft, nfr, C.byref(bad), rows, vp(X16), None, None, None) == -1
+    assert L.ugkwp_ws_features(vp(dWc), nct, ncr, nft, nfr, C.byref(case), nf - 1, vp(X16), None, None,
                                None) == -1
+
+
+def test_fused_forward_matches_layers_and_reference():
+    """The one-kernel forward (activations in registers, permuted K order)
+    against the per-layer kernels and the FP64 reference with BF16 rounding
+    of the activations."""
+    import torch
+    from paper_2607_09552_amd.warmstart import MLP
+    g = np.random.default_rng(31)
+    M = 96
+    X = ref.bf16(g.standard_normal((M, 32)))
+    mlp = MLP(seed=5)
+    mlp.b = [b + torch.tensor(0.1 * g.standard_normal(b.shape[0]), dtype=torch.float32, device="cuda")
+             for b in mlp.b]
+    xb = dev(bits(X))
+    Yf = host(mlp.infer(xb, M)).astype(np.float64)
+    Yl = host(mlp.forward(xb, M)).astype(np.float64)
+    Yr, _ = ref.forward(_mlp_ref_params(mlp), X, q=ref.bf16)
+    scale = np.abs(Yr).max()
+    # FP32 accumulation in another order can flip an activation's BF16
+    # rounding: differences stay at that level
+    assert np.max(np.abs(Yf - Yr)) <= 2e-2 * scale
+    assert np.max(np.abs(Yf - Yl)) <= 2e-2 * scale
+    assert np.median(np.abs(Yf - Yr)) <= 1e-4 * scale
+    # packing: layer 1's fragments are the BF16 weights in the permuted order
+    Wf = host(mlp.Wf[1]).reshape(-1, 64, 8)
+    W1 = mlp.W[1].cpu().numpy().astype(np.float64)
+    S = W1.shape[1] // 16
+    for t, s_, lane, e in ((0, 0, 0, 0), (3, 5, 37, 6), (7, 15, 63, 7), (2, 9, 31, 3)):
+        h = lane // 32
+        k = 16 * s_ + 8 * (e // 4) + 4 * h + e % 4
+        assert vals(Wf[t * S + s_, lane, e]) == ref.bf16(W1[32 * t + lane % 32, k])
+    L = lib()
+    wd = (C.c_int32 * 5)(32, 256, 128, 256, 32)
+    wp = (C.c_void_p * 4)(*[w.data_ptr() for w in mlp.Wf])
+    bp = (C.c_void_p * 4)(*[b.data_ptr() for b in mlp.b])
+    Y = torch.empty((M, 32), dtype=torch.float32, device="cuda")
+    assert L.ugkwp_mlp_forward(vp(xb), M, 4, wd, wp, bp, vp(Y), None) == -1
+    wd[2] = 256
+    assert L.ugkwp_mlp_forward(vp(xb), M - 1, 4, wd, wp, bp, vp(Y), None) == -1
