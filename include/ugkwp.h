@@ -80,7 +80,7 @@ typedef struct {
  * the Philox seed, and the freestream used for C_p, C_F, C_Q, C_d (Sec. V). */
 typedef struct {
   double R, omega, mu_ref, T_ref, Pr;
-  int32_t D;                  /* internal degrees of freedom (0: monatomic) */
+  int32_t D;                  /* internal degrees of freedom (0: monatomic); D > 0 only with wave_only = 1 (particles carry no internal energy), else EINVAL */
   double cfl;
   int32_t n_ref;
   int32_t lts;                /* 1 local time steps, 0 global dt_G = min dt_i */

@@ -722,9 +722,15 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   c->p = *par;
   c->K = 1 + par->D;
   c->N = 3 + par->D;
-  if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0)) {
+  if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
+        par->D >= 0)) {
     *out = c;
     return fail(c, REF_EINVAL, "invalid parameters");
+  }
+  /* particles carry (m, x, u) only: internal energy needs the wave-only mode */
+  if (par->D > 0 && !par->wave_only) {
+    *out = c;
+    return fail(c, REF_EINVAL, "internal degrees of freedom (D > 0) need wave_only: particles carry no internal energy");
   }
   int rc = build_mesh(c, m);
   if (rc) { *out = c; return rc; }

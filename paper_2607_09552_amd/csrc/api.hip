@@ -745,9 +745,11 @@ extern "C" {
 
 namespace {
 
+// D > 0 only without particles: a particle carries (m, x, u) and no
+// internal energy
 bool params_ok(const ugkwp_params *par) {
   return par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-         par->D >= 0 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
+         par->D >= 0 && (par->D == 0 || par->wave_only) && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
 }
 
 // Per-case table row of a parameter set.

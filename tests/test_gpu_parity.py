@@ -192,6 +192,14 @@ def test_edge_cases():
     box = wl.box2d(wl.graded(17, 1.05), wl.graded(13, 1.1, 0.3), wl.BC_FARFIELD, [1.0, 0.8, 0.1, 1.2])
     w = wl.uniform2d(box, rho=1.0, ux=0.8, uy=0.1, T=1.2, mu_ref=0.02, n_ref=40, seed=9)
     run_pair(w, [1, 3, 12])
+    # internal degrees of freedom are refused with particles (they carry no
+    # internal energy), accepted without
+    from paper_2607_09552_amd import Solver, UgkwpError
+    w["gas"] = dict(w["gas"], D=2)
+    with pytest.raises(UgkwpError, match="invalid parameters"):
+        Solver(w)
+    w["wave_only"] = 1
+    Solver(w).close()
 
 
 def test_shakhov_parity():

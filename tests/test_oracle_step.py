@@ -409,3 +409,26 @@ def test_wave_only_preserves_uniform_flow_and_time_weighted_content(dim):
     I = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
     for q in (0, dim + 1):
         assert abs(I[q] - I0[q]) <= 2e-13 * abs(I0[q])
+
+
+def test_internal_dof_only_without_particles():
+    """Particles carry (m, x, u) and no internal energy, so D > 0 is refused
+    unless the run is wave-only; wave-only with D = 2 conserves the
+    time-weighted content of a closed box (the wave flux's K = 1 + D
+    moments are pinned against quadrature in the primitive tests)."""
+    c = _closed_box(2)
+    c["gas"] = dict(c["gas"], D=2)
+    with pytest.raises(RuntimeError, match="internal degrees of freedom"):
+        oracle.Oracle(c)
+    c["wave_only"] = 1
+    rho = c["W0"][:, 0]
+    u, v = c["W0"][:, 1] / rho, c["W0"][:, 2] / rho
+    T = (c["W0"][:, 3] / rho - 0.5 * (u * u + v * v)) / 1.5
+    c["W0"] = wl.conservative(rho, u, v, T, 2, D=2)
+    o = oracle.Oracle(c)
+    vol, dt = cell_volumes(c), o.dt()
+    I0 = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+    o.step(20)
+    I = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
+    for q in (0, 3):
+        assert abs(I[q] - I0[q]) <= 2e-13 * abs(I0[q])
