@@ -315,6 +315,18 @@ class Solver:
         self._check(L.ugkwp_surface(self.h, mode, _ptr(out), nw.value, C.byref(nw), C.byref(cd)))
         return out, cd.value
 
+    def stagnation(self, point, mode=2, case=0):
+        """Wall pressure and heat-flux coefficients (C_p, C_Q) at a wall point
+        (the stagnation point, Sec. V.A), linearly interpolated between the
+        centres of the two wall faces nearest to it; mode as ugkwp_surface
+        (2: the EMA with alpha = 2/1001, the paper's convergence monitor;
+        interpolation and EMA commute)."""
+        out, _ = self.case_surface(case, mode) if self.ncase > 1 else self.surface(mode)
+        d = np.hypot(out[:, 0] - point[0], out[:, 1] - point[1])
+        a, b = np.argsort(d, kind="stable")[:2]
+        wa = d[b] / (d[a] + d[b])
+        return wa * out[a, 3] + (1.0 - wa) * out[b, 3], wa * out[a, 5] + (1.0 - wa) * out[b, 5]
+
     def tally(self):
         Sm = np.zeros((self.nc, self.nw))
         Sp = np.zeros((self.nc, self.nw))

@@ -436,6 +436,26 @@ def test_unstructured_polygon_meshes(k):
     common_state_steps(w, [5])
 
 
+def test_stagnation_monitor_interpolates_the_ema():
+    """C_p and C_Q at the stagnation node (x = -1, y = 0) of the O-grid are
+    the mean of the two wall faces beside it (equal distances), for the EMA
+    (mode 2) as for the last step; the EMA follows a = 2/1001 (Sec. V.A)."""
+    from paper_2607_09552_amd import Solver
+    w = wl.cylinder(n_theta=24, n_r=16, n_ref=40, Ma=5.0, Tw=1.0, Kn=0.1)
+    g = Solver(w)
+    g.step(1)
+    ema = np.array(g.stagnation((-1.0, 0.0), mode=2))
+    for _ in range(3):
+        g.step(1)
+        last = np.array(g.stagnation((-1.0, 0.0), mode=0))
+        ema = 2.0 / 1001.0 * last + (1.0 - 2.0 / 1001.0) * ema
+    got = np.array(g.stagnation((-1.0, 0.0), mode=2))
+    assert np.allclose(got, ema, rtol=1e-12, atol=0)
+    surf, _ = g.surface(2)
+    nt = w["n_theta"]
+    assert np.allclose(got, 0.5 * (surf[0, [3, 5]] + surf[nt - 1, [3, 5]]), rtol=1e-12)
+
+
 def test_maxwell_wall_parity():
     """Cylinder with Maxwell walls of accommodation 0.85 (the flat-plate
     boundary condition of Sec. V.B), Shakhov sampling."""
