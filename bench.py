@@ -68,7 +68,7 @@ def cpu_baseline(w, state, steps):
     W, p, step0 = state
     o = oracle.Oracle(w)
     o.set_fields(W)
-    o.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"])
+    o.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"], p["ei"])
     o.set_step(step0)
     n_upd = 0
     t0 = time.perf_counter()

@@ -80,7 +80,7 @@ typedef struct {
  * the Philox seed, and the freestream used for C_p, C_F, C_Q, C_d (Sec. V). */
 typedef struct {
   double R, omega, mu_ref, T_ref, Pr;
-  int32_t D;                  /* internal degrees of freedom (0: monatomic); D > 0 only with wave_only = 1 (particles carry no internal energy), else EINVAL */
+  int32_t D;                  /* internal degrees of freedom (0: monatomic, up to 64); particles then carry |xi|^2 / 2 */
   double cfl;
   int32_t n_ref;
   int32_t lts;                /* 1 local time steps, 0 global dt_G = min dt_i */
@@ -173,13 +173,15 @@ int ugkwp_get_counts(ugkwp_ctx *ctx, int32_t *count, int64_t *n_total, int64_t *
 int ugkwp_get_work(ugkwp_ctx *ctx, int64_t *n_transported);
 /* Retained particles sorted by pid: pid = step << 44 | birth cell << 20 | j
  * (birth cell >= n_cells marks a boundary face), cell, mass, position
- * [n*dim], velocity [n*3].  Pointers may be NULL; *n is set even when
- * cap is too small (then EOVERFLOW). */
+ * [n*dim], velocity [n*3], internal energy per unit mass |xi|^2 / 2 [n]
+ * (0 when D = 0).  Pointers may be NULL; *n is set even when cap is too
+ * small (then EOVERFLOW). */
 int ugkwp_get_particles(ugkwp_ctx *ctx, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x,
-                        double *u, int64_t *n);
-/* Replaces the retained set (host arrays as in ugkwp_get_particles). */
+                        double *u, double *ei, int64_t *n);
+/* Replaces the retained set (host arrays as in ugkwp_get_particles; ei may
+ * be NULL: zero internal energy). */
 int ugkwp_set_particles(ugkwp_ctx *ctx, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
-                        const double *x, const double *u);
+                        const double *x, const double *u, const double *ei);
 /* Restart support: replace W ([n_cells*(dim+2)] host; the local time steps
  * stay those of the initial field, Eq. (33)) and the step counter that keys
  * the random numbers.  With ugkwp_set_particles this restores a state saved

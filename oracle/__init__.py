@@ -67,8 +67,8 @@ def lib():
         L.ref_set_fields.argtypes = [C.c_void_p, dp]
         L.ref_get_dt.argtypes = [C.c_void_p, dp]
         L.ref_get_counts.argtypes = [C.c_void_p, ip32, ip64, ip64, ip64, ip64]
-        L.ref_get_particles.argtypes = [C.c_void_p, C.c_int64, up64, ip32, dp, dp, dp, ip64]
-        L.ref_set_particles.argtypes = [C.c_void_p, C.c_int64, up64, ip32, dp, dp, dp]
+        L.ref_get_particles.argtypes = [C.c_void_p, C.c_int64, up64, ip32, dp, dp, dp, dp, ip64]
+        L.ref_set_particles.argtypes = [C.c_void_p, C.c_int64, up64, ip32, dp, dp, dp, dp]
         L.ref_residual.argtypes = [C.c_void_p, dp, dp, ip64]
         L.ref_surface.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64, ip64, dp]
         L.ref_get_tally.argtypes = [C.c_void_p, dp, dp]
@@ -241,23 +241,25 @@ class Oracle:
 
     def particles(self):
         n = C.c_int64()
-        lib().ref_get_particles(self.h, 0, None, None, None, None, None, C.byref(n))
+        lib().ref_get_particles(self.h, 0, None, None, None, None, None, None, C.byref(n))
         k = n.value
         pid = np.zeros(k, dtype=np.uint64)
         cell = np.zeros(k, dtype=np.int32)
         m = np.zeros(k)
         x = np.zeros((k, self.dim))
         u = np.zeros((k, 3))
+        ei = np.zeros(k)
         self._check(lib().ref_get_particles(self.h, k, _p(pid, C.c_uint64), _p(cell, C.c_int32), _p(m), _p(x),
-                                            _p(u), C.byref(n)))
-        return dict(pid=pid, cell=cell, m=m, x=x, u=u)
+                                            _p(u), _p(ei), C.byref(n)))
+        return dict(pid=pid, cell=cell, m=m, x=x, u=u, ei=ei)
 
-    def set_particles(self, pid, cell, m, x, u):
+    def set_particles(self, pid, cell, m, x, u, ei=None):
         pid = np.ascontiguousarray(pid, dtype=np.uint64)
         cell = np.ascontiguousarray(cell, dtype=np.int32)
         m, x, u = _f64(m), _f64(x), _f64(u)
+        ei = None if ei is None else _f64(ei)
         self._check(lib().ref_set_particles(self.h, len(pid), _p(pid, C.c_uint64), _p(cell, C.c_int32), _p(m),
-                                            _p(x), _p(u)))
+                                            _p(x), _p(u), None if ei is None else _p(ei)))
 
     def set_step(self, n):
         lib().ref_set_step(self.h, n)

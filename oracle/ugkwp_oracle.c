@@ -35,6 +35,10 @@
 
 static int is_wall(int32_t ty) { return ty == REF_BC_WALL || ty == REF_BC_WALL_MAXWELL; }
 #define P_SHAKHOV 4u
+#define P_INTERNAL 5u
+/* wall hit h of a particle draws its internal energy from INTERNAL calls
+ * WALL_INTERNAL_CALL0 + h ceil(D/2) + j; birth uses calls j */
+#define WALL_INTERNAL_CALL0 256u
 
 static const double TWO_PI = 6.283185307179586;
 static const double PI = 3.141592653589793;
@@ -44,6 +48,7 @@ typedef struct {
   int32_t cell;  /* current cell (interior id) */
   int32_t flags;
   double x[2], u[3], m, t; /* t: remaining free-transport time */
+  double ei;                /* internal energy per unit mass, |xi|^2 / 2 (0 when D = 0) */
 } particle;
 
 struct ref_ctx {
@@ -723,14 +728,9 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   c->K = 1 + par->D;
   c->N = 3 + par->D;
   if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-        par->D >= 0)) {
+        par->D >= 0 && par->D <= 64)) {
     *out = c;
     return fail(c, REF_EINVAL, "invalid parameters");
-  }
-  /* particles carry (m, x, u) only: internal energy needs the wave-only mode */
-  if (par->D > 0 && !par->wave_only) {
-    *out = c;
-    return fail(c, REF_EINVAL, "internal degrees of freedom (D > 0) need wave_only: particles carry no internal energy");
   }
   int rc = build_mesh(c, m);
   if (rc) { *out = c; return rc; }
@@ -809,7 +809,7 @@ static int push_particle(ref_ctx *c, const particle *q) {
 }
 
 static void psi_particle(const ref_ctx *c, const particle *q, double *out) {
-  double e = 0.5 * (q->u[0] * q->u[0] + q->u[1] * q->u[1] + q->u[2] * q->u[2]);
+  double e = 0.5 * (q->u[0] * q->u[0] + q->u[1] * q->u[1] + q->u[2] * q->u[2]) + q->ei;
   out[0] = q->m;
   out[1] = q->m * q->u[0];
   if (c->dim == 2) {
@@ -855,6 +855,22 @@ static void sample_position(const ref_ctx *c, int64_t cell, uint64_t pid, int64_
   }
   x[0] = (x0 + b1 * (xa - x0)) + b2 * (xb - x0);
   x[1] = (y0 + b1 * (ya - y0)) + b2 * (yb - y0);
+}
+
+/* Internal energy in units of R T of the D internal degrees of freedom of
+ * Eq. (1): eta = |z|^2 / 2 for D standard normal deviates, taken in order
+ * from Box-Muller pairs of INTERNAL draws call0, call0 + 1, ... (the second
+ * deviate of the last pair unused when D is odd); |xi|^2 / 2 = R T eta. */
+static double internal_eta(const ref_ctx *c, uint64_t pid, int64_t step, uint32_t call0) {
+  double s = 0.0;
+  for (int j = 0; 2 * j < c->p.D; ++j) {
+    double e0, e1, z0, z1;
+    draw2(c->p.seed, pid, step, P_INTERNAL, call0 + (uint32_t)j, &e0, &e1);
+    box_muller(e0, e1, &z0, &z1);
+    s += z0 * z0;
+    if (2 * j + 1 < c->p.D) s += z1 * z1;
+  }
+  return 0.5 * s;
 }
 
 /* Three Gaussian velocity components from two VEL draws (call offset 2a). */
@@ -990,10 +1006,14 @@ static int track(ref_ctx *c, particle *q, int64_t step, int32_t *ncross_out) {
       c->wimp[3 * b + 1] += q->m * (ub[1] - q->u[1]);
       continue;
     }
-    /* diffuse re-emission */
+    /* diffuse re-emission; internal energy from the wall temperature */
     double vn = sqrt(-2.0 * c->p.R * Tw * log(e0));
     box_muller(e1, e2, &z0, &z1);
     double ub[3] = {q->u[0], q->u[1], q->u[2]};
+    double eib = q->ei;
+    if (c->p.D > 0)
+      q->ei = (c->p.R * Tw) *
+              internal_eta(c, q->pid, step, WALL_INTERNAL_CALL0 + (uint32_t)((hits - 1) * ((c->p.D + 1) / 2)));
     if (c->dim == 2) {
       double vt = sw * z0;
       q->u[0] = -vn * f[0] - vt * f[1];
@@ -1008,7 +1028,7 @@ static int track(ref_ctx *c, particle *q, int64_t step, int32_t *ncross_out) {
     double ea = 0.5 * (q->u[0] * q->u[0] + q->u[1] * q->u[1] + q->u[2] * q->u[2]);
     c->wimp[3 * b + 0] += q->m * (ub[0] - q->u[0]);
     c->wimp[3 * b + 1] += q->m * (ub[1] - q->u[1]);
-    c->wimp[3 * b + 2] += q->m * (eb - ea);
+    c->wimp[3 * b + 2] += q->m * ((eb + eib) - (ea + q->ei));
   }
 }
 
@@ -1131,7 +1151,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       if (c->p.Pr != 1.0) {
         prim_t s = prim(c, c->W + q->cell * nw);
         double cx = q->u[0] - s.ux, cy = q->u[1] - s.uy, cz = q->u[2];
-        double h = 0.5 * (cx * cx + cy * cy + cz * cz);
+        double h = 0.5 * (cx * cx + cy * cy + cz * cz) + q->ei;
         Qh[2 * q->cell] += q->m * cx * h;
         Qh[2 * q->cell + 1] += q->m * cy * h;
       }
@@ -1233,7 +1253,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
        * scaled so that the set carries exactly the momentum and the thermal
        * energy (3 R T^h / 2 per unit mass) of W^hp. */
       int64_t first = c->np;
-      double zs[3] = {0.0, 0.0, 0.0};
+      double zs[3] = {0.0, 0.0, 0.0}, es = 0.0;
       for (int64_t j = 0; j < N; ++j) {
         particle q;
         memset(&q, 0, sizeof q);
@@ -1245,6 +1265,10 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         sample_position(c, i, q.pid, n, q.x);
         sample_deviation(c, q.pid, n, Uh, h.T, sp, q.u);
         for (int d = 0; d < 3; ++d) zs[d] += q.u[d];
+        if (c->p.D > 0) {
+          q.ei = internal_eta(c, q.pid, n, 0);
+          es += q.ei;
+        }
         if ((rc = push_particle(c, &q))) break;
         c->n_new++;
       }
@@ -1258,12 +1282,17 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
           for (int d = 0; d < 3; ++d) S += (c->P[k].u[d] - zm[d]) * (c->P[k].u[d] - zm[d]);
         alpha = sqrt((3.0 * (double)N) / S);
       }
+      /* the internal energies are scaled the same way to carry exactly
+       * D R T^h / 2 per unit mass */
+      double beta = 1.0;
+      if (N >= 2 && c->p.D > 0) beta = (0.5 * (double)c->p.D * (double)N) / es;
       for (int64_t k = first; k < c->np; ++k) {
         double *u = c->P[k].u;
         double w0 = (u[0] - zm[0]) * alpha, w1 = (u[1] - zm[1]) * alpha, w2 = (u[2] - zm[2]) * alpha;
         u[0] = Uh[0] + sig * w0;
         u[1] = Uh[1] + sig * w1;
         u[2] = sig * w2;
+        if (c->p.D > 0) c->P[k].ei = (c->p.R * h.T) * (beta * c->P[k].ei);
       }
     }
     if (rc) break;
@@ -1330,6 +1359,7 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         q.flags = F_GHOST;
         q.m = mk;
         q.t = c->dt[i] - tc;
+        if (c->p.D > 0) q.ei = (c->p.R * s.T) * internal_eta(c, q.pid, n, 0);
         if ((rc = push_particle(c, &q))) break;
         c->n_new++;
       }
@@ -1579,7 +1609,7 @@ static int cmp_pid(const void *a, const void *b) {
 }
 
 int ref_get_particles(const ref_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x,
-                      double *u, int64_t *n) {
+                      double *u, double *ei, int64_t *n) {
   *n = c->np;
   if (cap < c->np) return REF_EOVERFLOW;
   particle *tmp = xcalloc((size_t)c->np, sizeof(particle));
@@ -1591,13 +1621,14 @@ int ref_get_particles(const ref_ctx *c, int64_t cap, uint64_t *pid, int32_t *cel
     if (m) m[k] = tmp[k].m;
     for (int d = 0; d < c->dim; ++d) if (x) x[k * c->dim + d] = tmp[k].x[d];
     for (int d = 0; d < 3; ++d) if (u) u[k * 3 + d] = tmp[k].u[d];
+    if (ei) ei[k] = tmp[k].ei;
   }
   free(tmp);
   return REF_OK;
 }
 
 int ref_set_particles(ref_ctx *c, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
-                      const double *x, const double *u) {
+                      const double *x, const double *u, const double *ei) {
   c->np = 0;
   for (int64_t k = 0; k < n; ++k) {
     particle q;
@@ -1608,6 +1639,7 @@ int ref_set_particles(ref_ctx *c, int64_t n, const uint64_t *pid, const int32_t 
     q.m = m[k];
     for (int d = 0; d < c->dim; ++d) q.x[d] = x[k * c->dim + d];
     for (int d = 0; d < 3; ++d) q.u[d] = u[k * 3 + d];
+    q.ei = ei ? ei[k] : 0.0;
     int rc = push_particle(c, &q);
     if (rc) return rc;
   }

@@ -55,7 +55,8 @@ typedef struct {
 
 typedef struct {
   double R, omega, mu_ref, T_ref, Pr;
-  int32_t D;                   /* internal degrees of freedom */
+  int32_t D;                   /* internal degrees of freedom (0..64); particles carry
+                                  |xi|^2 / 2 drawn at the local temperature */
   double cfl;
   int32_t n_ref;
   int32_t lts;                 /* 1 local time steps, 0 global (dt_G = min dt_i) */
@@ -75,10 +76,12 @@ int ref_set_fields(ref_ctx *c, const double *W);
 int ref_get_dt(const ref_ctx *c, double *dt);
 int ref_get_counts(const ref_ctx *c, int32_t *count, int64_t *n_total, int64_t *n_new,
                    int64_t *n_removed, int64_t *n_exited);
+/* ei: internal energy per unit mass |xi|^2 / 2 of each particle (D > 0);
+   may be NULL (read: skipped; write: 0) */
 int ref_get_particles(const ref_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell, double *m,
-                      double *x, double *u, int64_t *n);
+                      double *x, double *u, double *ei, int64_t *n);
 int ref_set_particles(ref_ctx *c, int64_t n, const uint64_t *pid, const int32_t *cell,
-                      const double *m, const double *x, const double *u);
+                      const double *m, const double *x, const double *u, const double *ei);
 int ref_residual(const ref_ctx *c, double *r_inst, double *r_avg, int64_t *step);
 int ref_surface(const ref_ctx *c, int32_t mode, double *out, int64_t cap, int64_t *n_wall,
                 double *Cd);

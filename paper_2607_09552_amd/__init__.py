@@ -97,8 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_get_dt.argtypes = [vp, dp]
     L.ugkwp_get_counts.argtypes = [vp, i32p, i64p, i64p, i64p, i64p, i64p]
     L.ugkwp_get_work.argtypes = [vp, i64p]
-    L.ugkwp_get_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp, i64p]
-    L.ugkwp_set_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp]
+    L.ugkwp_get_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp, dp, i64p]
+    L.ugkwp_set_particles.argtypes = [vp, C.c_int64, u64p, i32p, dp, dp, dp, dp]
     L.ugkwp_get_tally.argtypes = [vp, dp, dp]
     L.ugkwp_set_fields.argtypes = [vp, dp]
     L.ugkwp_set_step.argtypes = [vp, C.c_int64]
@@ -277,23 +277,25 @@ class Solver:
     def particles(self):
         L = load_library()
         n = C.c_int64()
-        L.ugkwp_get_particles(self.h, 0, None, None, None, None, None, C.byref(n))
+        L.ugkwp_get_particles(self.h, 0, None, None, None, None, None, None, C.byref(n))
         k = n.value
         pid = np.zeros(k, dtype=np.uint64)
         cell = np.zeros(k, dtype=np.int32)
         m = np.zeros(k)
         x = np.zeros((k, self.dim))
         u = np.zeros((k, 3))
+        ei = np.zeros(k)
         self._check(L.ugkwp_get_particles(self.h, k, _ptr(pid, C.c_uint64), _ptr(cell, C.c_int32), _ptr(m), _ptr(x),
-                                          _ptr(u), C.byref(n)))
-        return dict(pid=pid, cell=cell, m=m, x=x, u=u)
+                                          _ptr(u), _ptr(ei), C.byref(n)))
+        return dict(pid=pid, cell=cell, m=m, x=x, u=u, ei=ei)
 
-    def set_particles(self, pid, cell, m, x, u):
+    def set_particles(self, pid, cell, m, x, u, ei=None):
         pid = np.ascontiguousarray(pid, dtype=np.uint64)
         cell = np.ascontiguousarray(cell, dtype=np.int32)
         m, x, u = (np.ascontiguousarray(a, dtype=np.float64) for a in (m, x, u))
+        ei = None if ei is None else np.ascontiguousarray(ei, dtype=np.float64)
         self._check(load_library().ugkwp_set_particles(self.h, len(pid), _ptr(pid, C.c_uint64),
-                                                       _ptr(cell, C.c_int32), _ptr(m), _ptr(x), _ptr(u)))
+                                                       _ptr(cell, C.c_int32), _ptr(m), _ptr(x), _ptr(u), _ptr(ei)))
 
     def set_fields(self, W):
         W = np.ascontiguousarray(W, dtype=np.float64)

@@ -41,6 +41,7 @@ struct DBuf {
 
 struct ugkwp_ctx {
   int dim = 0, nw = 0, NV = 0;
+  int feat = 0;  // transport specialization: kFeatEi (D > 0) | kFeatMaxwell (a Maxwell wall face exists)
   int64_t nc = 0, nf = 0, nb = 0, nwall = 0;
   Params P{};
   int lts = 1;
@@ -501,6 +502,7 @@ int alloc_store(ugkwp_ctx *c, StoreT<R> &s, int64_t n) {
   rc |= dalloc(c, &s.ux, n);
   rc |= dalloc(c, &s.uy, n);
   rc |= dalloc(c, &s.uz, n);
+  if (c->P.D > 0) rc |= dalloc(c, &s.ei, n);
   rc |= dalloc(c, &s.m, n);
   rc |= dalloc(c, &s.pid, n);
   rc |= dalloc(c, &s.cell, n);
@@ -514,6 +516,7 @@ void free_store(ugkwp_ctx *c, StoreT<R> &s) {
   dfree(c, s.ux);
   dfree(c, s.uy);
   dfree(c, s.uz);
+  dfree(c, s.ei);
   dfree(c, s.m);
   dfree(c, s.pid);
   dfree(c, s.cell);
@@ -529,6 +532,7 @@ int copy_store(ugkwp_ctx *c, const StoreT<R> &from, const StoreT<R> &to, int64_t
   HIPCHK(hipMemcpyAsync(to.ux, from.ux, dr, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.uy, from.uy, dr, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.uz, from.uz, dr, hipMemcpyDeviceToDevice, c->stream));
+  if (from.ei) HIPCHK(hipMemcpyAsync(to.ei, from.ei, dr, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.m, from.m, d8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.pid, from.pid, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(to.cell, from.cell, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -597,6 +601,22 @@ struct Zeroer {
 // size depends only on host-known constants (mesh sizes, capacity, grid
 // estimates); the particle counts live on the device.  The host swaps the
 // double-buffered pointers; after a halted batch it restores their parity.
+// The transport specialization for the context's features.
+template <int DIM, int NV, class R>
+void launch_transport(ugkwp_ctx *c, const Geo &g, const State &S, const StoreT<R> &A, dim3 gr, dim3 bl) {
+  switch (c->feat) {
+    case 0: hipLaunchKernelGGL((k_transport<DIM, NV, R, 0>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+    case kFeatEi: hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+    case kFeatMaxwell:
+      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap);
+      break;
+    default:
+      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi | kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A,
+                         c->cap);
+      break;
+  }
+}
+
 template <int DIM, class R>
 int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
   const int NW = DIM + 2;
@@ -658,16 +678,16 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
     const double wr = DIM * static_cast<double>(sizeof(R)) + 16.0;
     ProfScope ps(c, kKTransport, (rec + wr) * c->est_total);
     const dim3 gr(nblk(c->cover, c->transport_block)), bl(c->transport_block);
-    if (DIM == 1) {
-      hipLaunchKernelGGL((k_transport<DIM, 2, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap);
+    if constexpr (DIM == 1) {
+      launch_transport<DIM, 2, R>(c, g, S, A, gr, bl);
     } else {
       switch (c->NV) {
-        case 3: hipLaunchKernelGGL((k_transport<2, 3, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-        case 4: hipLaunchKernelGGL((k_transport<2, 4, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-        case 5: hipLaunchKernelGGL((k_transport<2, 5, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-        case 6: hipLaunchKernelGGL((k_transport<2, 6, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-        case 7: hipLaunchKernelGGL((k_transport<2, 7, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-        default: hipLaunchKernelGGL((k_transport<2, 8, R>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+        case 3: launch_transport<2, 3, R>(c, g, S, A, gr, bl); break;
+        case 4: launch_transport<2, 4, R>(c, g, S, A, gr, bl); break;
+        case 5: launch_transport<2, 5, R>(c, g, S, A, gr, bl); break;
+        case 6: launch_transport<2, 6, R>(c, g, S, A, gr, bl); break;
+        case 7: launch_transport<2, 7, R>(c, g, S, A, gr, bl); break;
+        default: launch_transport<2, 8, R>(c, g, S, A, gr, bl); break;
       }
     }
   }
@@ -745,11 +765,9 @@ extern "C" {
 
 namespace {
 
-// D > 0 only without particles: a particle carries (m, x, u) and no
-// internal energy
 bool params_ok(const ugkwp_params *par) {
   return par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-         par->D >= 0 && (par->D == 0 || par->wave_only) && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
+         par->D >= 0 && par->D <= 64 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
 }
 
 // Per-case table row of a parameter set.
@@ -797,6 +815,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   P.Nd = static_cast<double>(3 + par->D);
   P.NR = P.Nd * par->R;
   P.K = 1 + par->D;
+  P.D = par->D;
   P.cfl = par->cfl;
   P.n_ref = par->n_ref;
   P.wave_only = par->wave_only ? 1 : 0;
@@ -832,8 +851,11 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   c->h_anchor = h.cen;
   c->h_lface = h.lface;
   std::vector<int> wall_b, btype(mesh->bface_type, mesh->bface_type + nb);
-  for (int64_t b = 0; b < nb; ++b)
+  c->feat = c->P.D > 0 ? kFeatEi : 0;
+  for (int64_t b = 0; b < nb; ++b) {
     if (btype[b] == UGKWP_BC_WALL_DIFFUSE || btype[b] == UGKWP_BC_WALL_MAXWELL) wall_b.push_back(static_cast<int>(b));
+    if (btype[b] == UGKWP_BC_WALL_MAXWELL) c->feat |= kFeatMaxwell;
+  }
   c->h_wall_b = wall_b;
   c->nwall = static_cast<int64_t>(wall_b.size());
   // device geometry
@@ -1332,8 +1354,8 @@ namespace {
 template <class R>
 int read_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, std::vector<uint64_t> &P, std::vector<int> &C,
                std::vector<double> &X, std::vector<double> &Y, std::vector<double> &U0, std::vector<double> &U1,
-               std::vector<double> &U2, std::vector<double> &M) {
-  std::vector<R> x(n), y(c->dim == 2 ? n : 0), u0(n), u1(n), u2(n);
+               std::vector<double> &U2, std::vector<double> &M, std::vector<double> &EI) {
+  std::vector<R> x(n), y(c->dim == 2 ? n : 0), u0(n), u1(n), u2(n), ei(s.ei ? n : 0);
   if (n > 0) {
     HIPCHK(hipMemcpyAsync(P.data(), s.pid, n * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(C.data(), s.cell, n * 4, hipMemcpyDeviceToHost, c->stream));
@@ -1343,6 +1365,7 @@ int read_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, std::vector<uint64_t
     HIPCHK(hipMemcpyAsync(u1.data(), s.uy, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(u2.data(), s.uz, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(M.data(), s.m, n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (s.ei) HIPCHK(hipMemcpyAsync(ei.data(), s.ei, n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const bool rel = c->precision != 0;
@@ -1353,6 +1376,7 @@ int read_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, std::vector<uint64_t
     U0[k] = u0[k];
     U1[k] = u1[k];
     U2[k] = u2[k];
+    EI[k] = s.ei ? static_cast<double>(ei[k]) : 0.0;
   }
   return UGKWP_OK;
 }
@@ -1362,8 +1386,8 @@ template <class R>
 int write_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, const std::vector<uint64_t> &P,
                 const std::vector<int> &C, const std::vector<double> &X, const std::vector<double> &Y,
                 const std::vector<double> &U0, const std::vector<double> &U1, const std::vector<double> &U2,
-                const std::vector<double> &M) {
-  std::vector<R> x(n), y(n), u0(n), u1(n), u2(n);
+                const std::vector<double> &M, const std::vector<double> &EI) {
+  std::vector<R> x(n), y(n), u0(n), u1(n), u2(n), ei(n);
   const bool rel = c->precision != 0;
   for (int64_t k = 0; k < n; ++k) {
     const double ax = rel ? c->h_anchor[2 * C[k]] : 0.0, ay = rel ? c->h_anchor[2 * C[k] + 1] : 0.0;
@@ -1372,6 +1396,7 @@ int write_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, const std::vector<u
     u0[k] = static_cast<R>(U0[k]);
     u1[k] = static_cast<R>(U1[k]);
     u2[k] = static_cast<R>(U2[k]);
+    ei[k] = static_cast<R>(EI[k]);
   }
   const hipMemcpyKind h2d = hipMemcpyHostToDevice;
   if (n > 0) {
@@ -1383,6 +1408,7 @@ int write_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, const std::vector<u
     HIPCHK(hipMemcpyAsync(s.uy, u1.data(), n * sizeof(R), h2d, c->stream));
     HIPCHK(hipMemcpyAsync(s.uz, u2.data(), n * sizeof(R), h2d, c->stream));
     HIPCHK(hipMemcpyAsync(s.m, M.data(), n * 8, h2d, c->stream));
+    if (s.ei) HIPCHK(hipMemcpyAsync(s.ei, ei.data(), n * sizeof(R), h2d, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   return UGKWP_OK;
@@ -1393,16 +1419,16 @@ int write_store(ugkwp_ctx *c, const StoreT<R> &s, int64_t n, const std::vector<u
 extern "C" {
 
 int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell, double *m, double *x, double *u,
-                        int64_t *n) {
+                        double *ei, int64_t *n) {
   if (!c || !n) return UGKWP_EINVAL;
   const int64_t np = c->n_ret;
   *n = np;
   if (cap < np) return set_err(c, UGKWP_EOVERFLOW, "particle buffer too small");
   std::vector<uint64_t> P(np);
   std::vector<int> C(np);
-  std::vector<double> X(np), Y(c->dim == 2 ? np : 0), U0(np), U1(np), U2(np), M(np);
-  const int rc = c->precision ? read_store(c, c->A32, np, P, C, X, Y, U0, U1, U2, M)
-                              : read_store(c, c->A, np, P, C, X, Y, U0, U1, U2, M);
+  std::vector<double> X(np), Y(c->dim == 2 ? np : 0), U0(np), U1(np), U2(np), M(np), EI(np);
+  const int rc = c->precision ? read_store(c, c->A32, np, P, C, X, Y, U0, U1, U2, M, EI)
+                              : read_store(c, c->A, np, P, C, X, Y, U0, U1, U2, M, EI);
   if (rc) return rc;
   std::vector<int64_t> order(np);
   for (int64_t k = 0; k < np; ++k) order[k] = k;
@@ -1421,12 +1447,13 @@ int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell,
       u[3 * j + 1] = U1[k];
       u[3 * j + 2] = U2[k];
     }
+    if (ei) ei[j] = EI[k];
   }
   return UGKWP_OK;
 }
 
 int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
-                        const double *x, const double *u) {
+                        const double *x, const double *u, const double *ei) {
   if (!c || n < 0 || (n > 0 && (!pid || !cell || !m || !x || !u))) return UGKWP_EINVAL;
   std::vector<int64_t> order(n);
   for (int64_t k = 0; k < n; ++k) {
@@ -1440,7 +1467,7 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
   if (rc) return rc;
   std::vector<uint64_t> P(n);
   std::vector<int> C(n);
-  std::vector<double> X(n), Y(n), U0(n), U1(n), U2(n), M(n);
+  std::vector<double> X(n), Y(n), U0(n), U1(n), U2(n), M(n), EI(n, 0.0);
   std::vector<double> Sr(c->nc * c->nw, 0.0), Mr(c->nc * 5, 0.0);
   std::vector<int> cnt(c->nc, 0);
   for (int64_t j = 0; j < n; ++j) {
@@ -1453,16 +1480,19 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     U0[j] = u[3 * k];
     U1[j] = u[3 * k + 1];
     U2[j] = u[3 * k + 2];
+    if (ei && c->P.D > 0) EI[j] = ei[k];
     if (c->precision) {  // the tallies see the velocities as stored
       U0[j] = static_cast<float>(U0[j]);
       U1[j] = static_cast<float>(U1[j]);
       U2[j] = static_cast<float>(U2[j]);
+      EI[j] = static_cast<float>(EI[j]);
     }
-    const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]);
+    const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]) + EI[j];
     const double q2 = U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j];
+    const double q2i = q2 + 2.0 * EI[j];
     double *mr = &Mr[C[j] * 5];
-    mr[0] += M[j] * U0[j] * q2;
-    mr[1] += M[j] * U1[j] * q2;
+    mr[0] += M[j] * U0[j] * q2i;
+    mr[1] += M[j] * U1[j] * q2i;
     mr[2] += M[j] * U0[j] * U0[j];
     mr[3] += M[j] * U0[j] * U1[j];
     mr[4] += M[j] * U1[j] * U1[j];
@@ -1473,8 +1503,8 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     sr[c->nw - 1] += M[j] * e;
     cnt[C[j]]++;
   }
-  rc = c->precision ? write_store(c, c->A32, n, P, C, X, Y, U0, U1, U2, M)
-                    : write_store(c, c->A, n, P, C, X, Y, U0, U1, U2, M);
+  rc = c->precision ? write_store(c, c->A32, n, P, C, X, Y, U0, U1, U2, M, EI)
+                    : write_store(c, c->A, n, P, C, X, Y, U0, U1, U2, M, EI);
   if (rc) return rc;
   const hipMemcpyKind h2d = hipMemcpyHostToDevice;
   HIPCHK(hipMemcpyAsync(c->S.Sret, Sr.data(), Sr.size() * 8, h2d, c->stream));

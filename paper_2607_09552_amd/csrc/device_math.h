@@ -14,7 +14,7 @@ constexpr double kTwoPi = 6.283185307179586;
 constexpr double kPi = 3.141592653589793;
 
 // RNG purposes: counter word 3 = purpose << 24 | call index.
-enum : uint32_t { kFree = 0, kPos = 1, kVel = 2, kWall = 3, kShakhov = 4 };
+enum : uint32_t { kFree = 0, kPos = 1, kVel = 2, kWall = 3, kShakhov = 4, kInternal = 5 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 multiplies
@@ -74,6 +74,25 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t pid, int64_t step
   rng2(seed, pid, step, purpose, c + 1, e2, e3);
   box_muller(e0, e1, z[0], z[1]);
   box_muller(e2, e3, z[2], spare);
+}
+
+// Internal energy in units of R T of D internal degrees of freedom (the
+// Maxwellian's internal part, Eq. (1)): half the sum of squares of D standard
+// normal deviates, taken in order from Box-Muller pairs of INTERNAL draws
+// call0, call0 + 1, ... (the second deviate of the last pair unused when D is
+// odd).  Birth uses calls from 0, the h-th wall hit calls from
+// kWallInternalCall0 + h ceil(D/2).
+constexpr uint32_t kWallInternalCall0 = 256;
+__device__ __forceinline__ double internal_eta(uint64_t seed, uint64_t pid, int64_t step, uint32_t call0, int D) {
+  double s = 0.0;
+  for (int j = 0; 2 * j < D; ++j) {
+    double e0, e1, z0, z1;
+    rng2(seed, pid, step, kInternal, call0 + static_cast<uint32_t>(j), e0, e1);
+    box_muller(e0, e1, z0, z1);
+    s += z0 * z0;
+    if (2 * j + 1 < D) s += z1 * z1;
+  }
+  return 0.5 * s;
 }
 
 // ---------------------------------------------------------------------------

@@ -71,6 +71,7 @@ struct Params {
   double Nd;   // 3 + D velocity-like degrees of freedom
   double NR;   // Nd * R
   int K;       // lumped degrees of freedom in the face frame, 1 + D
+  int D;       // internal degrees of freedom; particles carry |xi|^2 / 2 when D > 0
   double cfl;
   int n_ref;
   int wave_only;  // E = 0: no particles, the waves carry all of g^h
@@ -120,6 +121,7 @@ enum : int { kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, k
 template <class R>
 struct StoreT {
   R *x, *y, *ux, *uy, *uz;
+  R *ei;  // internal energy per unit mass |xi|^2 / 2 (D > 0); nullptr when D = 0
   double *m;
   uint64_t *pid;
   int *cell;
@@ -139,7 +141,11 @@ template <int DIM, class R> __global__ void k_sample_draw(Geo, Params, State, St
 template <int DIM, class R> __global__ void k_sample_match(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t, uint32_t);
 template <int DIM, class R> __global__ void k_sample_ghosts(Geo, Params, State, StoreT<R>, int64_t);
-template <int DIM, int NV, class R> __global__ void k_transport(Geo, Params, State, StoreT<R>, int64_t);
+// Transport specializations: the monatomic, diffuse-wall kernel carries no
+// code for the optional features (their registers would cost occupancy).
+enum : int { kFeatEi = 1, kFeatMaxwell = 2 };  // particles carry |xi|^2 / 2; Maxwell wall faces exist
+template <int DIM, int NV, class R, int FEAT>
+__global__ void k_transport(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, int64_t);
 template <int DIM, class R>
 __global__ void k_cell_tally(Geo, StoreT<R>, const int64_t *, double *, double *, int, const int *);

@@ -508,6 +508,7 @@ __device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, c
     out.uy[o] = static_cast<R>(z[1]);
     out.uz[o] = static_cast<R>(z[2]);
   }
+  if (out.ei) out.ei[o] = static_cast<R>(internal_eta(seed, pid, step, 0, p.D));  // eta; scaled in k_sample_match
   out.pid[o] = pid;
   out.cell[o] = static_cast<int>(i);
   out.m[o] = st.mnew[i];
@@ -636,16 +637,19 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
     const double sig = sqrt(p.R * h.T);
     const double mk = st.mnew[i];
     double zm[3] = {0.0, 0.0, 0.0};
-    double alpha = 1.0;
+    double alpha = 1.0, beta = 1.0;
     if (N >= 2) {
-      double zs[3] = {0.0, 0.0, 0.0};
+      double zs[3] = {0.0, 0.0, 0.0}, es = 0.0;
       for (int j = lane; j < N; j += 64) {
         zs[0] += out.ux[base + j];
         zs[1] += out.uy[base + j];
         zs[2] += out.uz[base + j];
+        if (out.ei) es += out.ei[base + j];
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) zm[d] = wave_sum(zs[d]) / static_cast<double>(N);
+      // the internal energies are scaled to carry exactly D R T^h / 2 per unit mass
+      if (out.ei) beta = (0.5 * static_cast<double>(p.D) * static_cast<double>(N)) / wave_sum(es);
       double S = 0.0;
       for (int j = lane; j < N; j += 64) {
         const double a0 = out.ux[base + j] - zm[0], a1 = out.uy[base + j] - zm[1], a2 = out.uz[base + j] - zm[2];
@@ -663,8 +667,14 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       out.ux[k] = r0;
       out.uy[k] = r1;
       out.uz[k] = r2;
+      double ei = 0.0;
+      if (out.ei) {
+        const R re = static_cast<R>((p.R * h.T) * (beta * static_cast<double>(out.ei[k])));
+        out.ei[k] = re;
+        ei = re;
+      }
       const double u0 = r0, u1 = r1, u2 = r2;
-      const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+      const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2) + ei;
       snew[0] += mk;
       snew[1] += mk * u0;
       if (DIM == 2) snew[2] += mk * u1;
@@ -753,6 +763,7 @@ __global__ void __launch_bounds__(256) k_sample_ghosts(Geo g, Params p, State st
       out.ux[k] = static_cast<R>(u0);
       out.uy[k] = static_cast<R>(u1);
       out.uz[k] = static_cast<R>(u2);
+      if (out.ei) out.ei[k] = static_cast<R>((p.R * s.T) * internal_eta(seed, pid, step, 0, p.D));
       out.m[k] = mk;
       out.pid[k] = pid;
       out.cell[k] = i;
@@ -784,7 +795,7 @@ __device__ __forceinline__ typename Face<R>::type load_face(const Geo &g, int64_
   else return g.lfn[l];
 }
 
-template <int DIM, int NV, class R>
+template <int DIM, int NV, class R, int FEAT>
 __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, const State &st, const StoreT<R> &s,
                                               int64_t n_ret, int64_t gbase, int64_t n_total, int64_t step,
                                               int64_t k) {
@@ -794,7 +805,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   const bool active = k < n_total;
   int cell = -1;
   bool exited = false, collide = false;
-  R x = 0, y = 0, u0 = 0, u1 = 0, u2 = 0;
+  R x = 0, y = 0, u0 = 0, u1 = 0, u2 = 0, ei = 0;
   double m = 0;
   if (active) {
     cell = s.cell[k];
@@ -803,6 +814,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
     u0 = s.ux[k];
     u1 = s.uy[k];
     u2 = s.uz[k];
+    if constexpr ((FEAT & kFeatEi) != 0) ei = s.ei[k];
     m = s.m[k];
     const uint64_t pid = s.pid[k];
     const uint64_t seed = case_seed(g, p, case_of(g, cell));
@@ -912,7 +924,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits), e0, e1);
       rng2(seed, pid, step, kWall, static_cast<uint32_t>(2 * hits + 1), e2, e3);
       ++hits;
-      if (ty == kBcMaxwell && !(e3 < g.bdata[8 * bf + 1])) {
+      if ((FEAT & kFeatMaxwell) != 0 && ty == kBcMaxwell && !(e3 < g.bdata[8 * bf + 1])) {
         // specular part of a Maxwell wall; the impulse goes to the wall
         const double b0 = u0, b1 = u1;
         if (DIM == 2) {
@@ -952,7 +964,18 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       const double ea = 0.5 * (c0 * c0 + c1 * c1 + c2 * c2);
       atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
       atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
-      atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
+      if constexpr ((FEAT & kFeatEi) != 0) {
+        // internal energy from the wall temperature (draws of this hit)
+        const double eib = ei;
+        ei = static_cast<R>((p.R * Tw) *
+                            internal_eta(seed, pid, step,
+                                         kWallInternalCall0 + static_cast<uint32_t>((hits - 1) * ((p.D + 1) / 2)),
+                                         p.D));
+        const double eia = ei;
+        atomicAdd(&st.wimp[3 * bf + 2], m * ((eb + eib) - (ea + eia)));
+      } else {
+        atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
+      }
     }
     s.x[k] = x;
     if (DIM == 2) s.y[k] = y;
@@ -960,6 +983,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       s.ux[k] = u0;
       s.uy[k] = u1;
       s.uz[k] = u2;
+      if constexpr ((FEAT & kFeatEi) != 0) s.ei[k] = ei;
     }
     s.m[k] = m;
     s.cell[k] = cell;
@@ -970,7 +994,8 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   // the tally; their share of W^{p,+} (Eq. (30)) is added directly
   if (inside && collide) {
     const double v0 = u0, v1 = u1, v2 = u2;
-    const double en = 0.5 * (v0 * v0 + v1 * v1 + v2 * v2);
+    double en = 0.5 * (v0 * v0 + v1 * v1 + v2 * v2);
+    if constexpr ((FEAT & kFeatEi) != 0) en = en + static_cast<double>(ei);
     double *S = st.Scol + static_cast<int64_t>(cell) * NW;
     atomicAdd(&S[0], m);
     atomicAdd(&S[1], m * v0);
@@ -998,10 +1023,11 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
 }
 
 // Four wavefronts per SIMD keep the triangle and quad kernels within 128
-// VGPRs without spills; polygons with more faces hold more face data per
-// lane and get up to 256.
-template <int DIM, int NV, class R>
-__global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
+// VGPRs; polygons with more faces hold more face data per lane, and particles
+// with internal energy more state, and get up to 256.
+template <int DIM, int NV, class R, int FEAT>
+__global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 2)
+    k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];
   const int64_t gbase = n_ret + st.noff[g.nc];
@@ -1011,7 +1037,7 @@ __global__ void __launch_bounds__(256, NV <= 4 ? 4 : 2) k_transport(Geo g, Param
   // the grid covers the store capacity, which bounds every step's set
   const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
   if (base >= n_total) return;  // block-uniform: whole wavefronts take part in the grouping
-  transport_one<DIM, NV, R>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
+  transport_one<DIM, NV, R, FEAT>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
 }
 
 // Re-sort (counting sort, scatter pass): cursor[c] starts at the exclusive
@@ -1041,6 +1067,7 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
   b.ux[d] = a.ux[k];
   b.uy[d] = a.uy[k];
   b.uz[d] = a.uz[k];
+  if (a.ei) b.ei[d] = a.ei[k];
   b.m[d] = a.m[k];
   b.pid[d] = a.pid[k];
   b.cell[d] = c;
@@ -1067,14 +1094,18 @@ __global__ void __launch_bounds__(256) k_cell_tally(Geo g, StoreT<R> s, const in
 #pragma unroll 4
   for (int64_t k = a + lane_id(); k < b; k += 64) {
     const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
+    const double ei = s.ei ? static_cast<double>(s.ei[k]) : 0.0;
     const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
     v[0] += m;
     v[1] += m * u0;
     if (DIM == 2) v[2] += m * u1;
-    v[NW - 1] += m * (0.5 * q2);
+    v[NW - 1] += m * (0.5 * q2 + ei);
     if (raw) {
-      r[0] += m * u0 * q2;
-      r[1] += m * u1 * q2;
+      // sum m u_a (|u|^2 + 2 e_i): with the energy tally it gives the heat
+      // flux of Eq. (5) including the internal part
+      const double q2i = q2 + 2.0 * ei;
+      r[0] += m * u0 * q2i;
+      r[1] += m * u1 * q2i;
       r[2] += m * u0 * u0;
       r[3] += m * u0 * u1;
       r[4] += m * u1 * u1;
@@ -1418,7 +1449,6 @@ UGK_INST(2)
   template __global__ void k_sample_match<D, R>(Geo, Params, State, StoreT<R>, int64_t);                 \
   template __global__ void k_sample_shakhov<D, R>(Geo, Params, State, StoreT<R>, int64_t, uint32_t);     \
   template __global__ void k_sample_ghosts<D, R>(Geo, Params, State, StoreT<R>, int64_t);                \
-  template __global__ void k_transport<D, 2 * D, R>(Geo, Params, State, StoreT<R>, int64_t);            \
   template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, int64_t);                        \
   template __global__ void k_cell_tally<D, R>(Geo, StoreT<R>, const int64_t *, double *, double *, int,  \
                                               const int *);
@@ -1426,16 +1456,21 @@ UGK_INST_P(1, double)
 UGK_INST_P(2, double)
 UGK_INST_P(1, float)
 UGK_INST_P(2, float)
-#define UGK_INST_NV(N, R) template __global__ void k_transport<2, N, R>(Geo, Params, State, StoreT<R>, int64_t);
-UGK_INST_NV(3, double)
-UGK_INST_NV(5, double)
-UGK_INST_NV(6, double)
-UGK_INST_NV(7, double)
-UGK_INST_NV(8, double)
-UGK_INST_NV(3, float)
-UGK_INST_NV(5, float)
-UGK_INST_NV(6, float)
-UGK_INST_NV(7, float)
-UGK_INST_NV(8, float)
+#define UGK_INST_T(D, N, R, F) template __global__ void k_transport<D, N, R, F>(Geo, Params, State, StoreT<R>, int64_t);
+#define UGK_INST_TF(D, N, R) UGK_INST_T(D, N, R, 0) UGK_INST_T(D, N, R, 1) UGK_INST_T(D, N, R, 2) UGK_INST_T(D, N, R, 3)
+UGK_INST_TF(1, 2, double)
+UGK_INST_TF(1, 2, float)
+UGK_INST_TF(2, 3, double)
+UGK_INST_TF(2, 4, double)
+UGK_INST_TF(2, 5, double)
+UGK_INST_TF(2, 6, double)
+UGK_INST_TF(2, 7, double)
+UGK_INST_TF(2, 8, double)
+UGK_INST_TF(2, 3, float)
+UGK_INST_TF(2, 4, float)
+UGK_INST_TF(2, 5, float)
+UGK_INST_TF(2, 6, float)
+UGK_INST_TF(2, 7, float)
+UGK_INST_TF(2, 8, float)
 
 }  // namespace ugk

@@ -319,35 +319,59 @@ union Frag {
   uint16_t h[8];
 };
 
-// one layer on register activations: in [KS] k-steps -> acc [T] tiles
-template <int KS, int T>
-__device__ __forceinline__ void layer_regs(const uint16_t *__restrict__ Wf, const Frag (&act)[KS], f32x16 (&acc)[T],
-                                           int lane) {
-#pragma unroll
-  for (int t = 0; t < T; ++t) acc[t] = f32x16{};
+// one layer on register activations: in [KS] k-steps -> acc [T] tiles,
+// the accumulators starting from the bias (a lane's 16 outputs of a tile are
+// four runs of four consecutive features: four 16-byte loads).  The weight
+// fragments are fetched PF k-steps ahead (a ring of PF + 1 sets); scheduling
+// barriers keep each step's fetches ahead of its matrix-core work, so the L2
+// latency hides behind the earlier steps.
+template <int KS, int T, int PF = 3>
+__device__ __forceinline__ void layer_regs(const uint16_t *__restrict__ Wf, const float *__restrict__ bias,
+                                           const Frag (&act)[KS], f32x16 (&acc)[T], int lane) {
+  const int h = lane >> 5;
   const bf16x8 *w = reinterpret_cast<const bf16x8 *>(Wf) + lane;
+  bf16x8 ring[PF + 1][T];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
+  for (int p = 0; p < PF; ++p) {
+    if (p < KS) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const bf16x8 a = w[(t * KS + s) * 64];
-      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[s].v, acc[t], 0, 0, 0);
+      for (int t = 0; t < T; ++t) ring[p][t] = w[(t * KS + p) * 64];
     }
   }
-}
-
-// bias, GELU, BF16: the accumulators of T tiles become 2T k-steps of the
-// next layer's operand
-template <int T>
-__device__ __forceinline__ void to_next(const f32x16 (&acc)[T], const float *__restrict__ bias, int h,
-                                        Frag (&act)[2 * T]) {
 #pragma unroll
   for (int t = 0; t < T; ++t) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int out = 32 * t + 8 * (r / 4) + 4 * h + (r % 4);
-      act[2 * t + r / 8].h[r % 8] = f2bf(gelu(acc[t][r] + bias[out]));
+    for (int g = 0; g < 4; ++g) {
+      const float4 b = *reinterpret_cast<const float4 *>(bias + 32 * t + 8 * g + 4 * h);
+      acc[t][4 * g + 0] = b.x;
+      acc[t][4 * g + 1] = b.y;
+      acc[t][4 * g + 2] = b.z;
+      acc[t][4 * g + 3] = b.w;
     }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    if (s + PF < KS) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) ring[(s + PF) % (PF + 1)][t] = w[(t * KS + s + PF) * 64];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ring[s % (PF + 1)][t], act[s].v, acc[t], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// GELU and BF16: the accumulators of T tiles become 2T k-steps of the next
+// layer's operand
+template <int T>
+__device__ __forceinline__ void to_next(const f32x16 (&acc)[T], Frag (&act)[2 * T]) {
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) act[2 * t + r / 8].h[r % 8] = f2bf(gelu(acc[t][r]));
   }
 }
 
@@ -365,27 +389,27 @@ __global__ void __launch_bounds__(64) k_mlp_fused(const uint16_t *__restrict__ X
   Frag act[H / 16];
   {
     f32x16 acc[H / 32];
-    layer_regs<K0 / 16, H / 32>(net.W[0], xin, acc, lane);
-    to_next<H / 32>(acc, net.b[0], h, act);
+    layer_regs<K0 / 16, H / 32>(net.W[0], net.b[0], xin, acc, lane);
+    to_next<H / 32>(acc, act);
   }
 #pragma unroll
   for (int l = 1; l < NH; ++l) {
     f32x16 acc[H / 32];
-    layer_regs<H / 16, H / 32>(net.W[l], act, acc, lane);
-    to_next<H / 32>(acc, net.b[l], h, act);
+    layer_regs<H / 16, H / 32>(net.W[l], net.b[l], act, acc, lane);
+    to_next<H / 32>(acc, act);
   }
   f32x16 out[NO / 32];
-  layer_regs<H / 16, NO / 32>(net.W[NH], act, out, lane);
+  layer_regs<H / 16, NO / 32>(net.W[NH], net.b[NH], act, out, lane);
 #pragma unroll
   for (int t = 0; t < NO / 32; ++t) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int o = 32 * t + 8 * g + 4 * h;
       float4 v;
-      v.x = out[t][4 * g + 0] + net.b[NH][o + 0];
-      v.y = out[t][4 * g + 1] + net.b[NH][o + 1];
-      v.z = out[t][4 * g + 2] + net.b[NH][o + 2];
-      v.w = out[t][4 * g + 3] + net.b[NH][o + 3];
+      v.x = out[t][4 * g + 0];
+      v.y = out[t][4 * g + 1];
+      v.z = out[t][4 * g + 2];
+      v.w = out[t][4 * g + 3];
       *reinterpret_cast<float4 *>(Y + (row0 + sl) * NO + o) = v;
     }
   }

@@ -482,9 +482,27 @@ def cmd_eval(a):
     mlp = MLP.load(a.weights)
     out = []
     cases = [(a.ma, a.kn, a.tw)] if a.ma else [tuple(c) for c in draws(a.n_test, 4)[: a.n_cases]]
+    n0, n1 = (int(x) for x in a.reference.split(",")) if a.reference else (0, 0)
     for (Ma, Kn, Tw) in cases:
         wl = fine_case(Ma, Kn, Tw, n_ref=a.n_ref, seed=1)
         res = dict(Ma=Ma, Kn=Kn, Tw=Tw, n_ref=a.n_ref, precision=a.precision)
+        ref = None
+        if n1 > n0 > 0:
+            # the wall coefficients' mean over steps n0 < n <= n1 of a plain
+            # FP64 run from the free stream (from the library's running means)
+            s = Solver(wl, stream=_stream().value)
+            try:
+                s.step(n0)
+                m0 = s.surface(1)[0][:, 3:6].copy()
+                t0 = time.perf_counter()
+                for k in range(n0, n1, 10000):
+                    s.step(min(10000, n1 - k))
+                    print(f"  reference: {min(k + 10000, n1)} steps {time.perf_counter() - t0:.1f} s", flush=True)
+                m1 = s.surface(1)[0][:, 3:6].copy()
+            finally:
+                s.close()
+            ref = (n1 * m1 - n0 * m0) / (n1 - n0)
+            res["reference"] = dict(steps=[n0, n1], precision="f64", start="free stream")
         for start in a.starts.split(","):
             W0, info = (None, dict(seconds=0.0)) if start == "free" else warm_start(Ma, Kn, Tw, mlp, wl)
             s = Solver(wl, W0=W0, stream=_stream().value, precision=a.precision)
@@ -494,11 +512,16 @@ def cmd_eval(a):
                 conv, steps = s.step_until(a.target, a.max_steps)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
-                cd = s.surface(1)[1]
+                surf, cd = s.surface(1)
             finally:
                 s.close()
             res[start] = dict(converged=conv, steps=int(steps), seconds=dt, start_seconds=info["seconds"],
                               cd_mean=cd)
+            if ref is not None:
+                # relative L2 over the wall faces of the running means at convergence
+                d = np.linalg.norm(surf[:, 3:6] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+                res[start].update(dCp=float(d[0]), dCF=float(d[1]), dCQ=float(d[2]))
+                print(f"    wall means vs reference: dCp {d[0]:.3e} dCF {d[1]:.3e} dCQ {d[2]:.3e}", flush=True)
             del W0
             print(f"  Ma {Ma:.2f} Kn {Kn:.4f} Tw {Tw:.3f} {start}: converged {conv} steps {steps} {dt:.1f} s "
                   f"(+{info['seconds']:.2f} s start) C_d {cd:.4f}", flush=True)
@@ -540,6 +563,8 @@ def main(argv=None):
     e.add_argument("--starts", default="free,warm")
     e.add_argument("--target", type=float, default=1e-6)
     e.add_argument("--max-steps", type=int, default=200000)
+    e.add_argument("--reference", default="",
+                   help="N0,N1: compare the wall means with a plain FP64 run's mean over steps N0..N1")
     e.add_argument("--out", default="")
     a = ap.parse_args(argv)
     sys.path.insert(0, ROOT)

@@ -77,6 +77,11 @@ def compare(g, r, tag="", tol=TOL):
     k = int(np.argmax(dm)) if len(dm) else 0
     assert tol > TOL or len(dm) == 0 or dm[k] <= 1e-10, (f"{tag}: particle mass error {dm[k]:.3e} of the cell content (cell {pr['cell'][k]}, "
                             f"rho {Wr[pr['cell'][k], 0]:.3e}, m {pr['m'][k]:.3e})")
+    # internal energies (D > 0) on the scale of their cell's thermal energy
+    if np.any(pr["ei"] != 0):
+        T_scale = (Wr[pr["cell"], -1] / Wr[pr["cell"], 0])
+        de = np.max(np.abs(pg["ei"] - pr["ei"]) / T_scale)
+        assert de <= (1e-10 if tol <= TOL else 1e-6), f"{tag}: internal energy error {de:.3e}"
     e = _field_err(g.fields(), Wr)
     assert e <= tol, f"{tag}: field error {e:.3e}"
     # tallies enter the update as S / Omega next to W: compare on W's scale
@@ -123,7 +128,7 @@ def common_state_steps(w, at_steps):
         for s in (g, r):
             s.set_fields(W)
             if len(p["pid"]):
-                s.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"])
+                s.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"], p["ei"])
             s.set_step(n)
         g.step(1)
         r.step(1)
@@ -192,14 +197,11 @@ def test_edge_cases():
     box = wl.box2d(wl.graded(17, 1.05), wl.graded(13, 1.1, 0.3), wl.BC_FARFIELD, [1.0, 0.8, 0.1, 1.2])
     w = wl.uniform2d(box, rho=1.0, ux=0.8, uy=0.1, T=1.2, mu_ref=0.02, n_ref=40, seed=9)
     run_pair(w, [1, 3, 12])
-    # internal degrees of freedom are refused with particles (they carry no
-    # internal energy), accepted without
+    # the number of internal degrees of freedom is bounded
     from paper_2607_09552_amd import Solver, UgkwpError
-    w["gas"] = dict(w["gas"], D=2)
+    w["gas"] = dict(w["gas"], D=65)
     with pytest.raises(UgkwpError, match="invalid parameters"):
         Solver(w)
-    w["wave_only"] = 1
-    Solver(w).close()
 
 
 def test_shakhov_parity():
@@ -355,7 +357,7 @@ def test_batch_cases_equal_single_case_oracle():
     W, pg = g.fields(), g.particles()
     g2 = Solver.batch(cases)
     g2.set_fields(W)
-    g2.set_particles(pg["pid"], pg["cell"], pg["m"], pg["x"], pg["u"])
+    g2.set_particles(pg["pid"], pg["cell"], pg["m"], pg["x"], pg["u"], pg["ei"])
     g2.set_step(8)
     ors = []
     for k, w in enumerate(cases):
@@ -364,7 +366,8 @@ def test_batch_cases_equal_single_case_oracle():
         r.vol = cell_volumes(w)
         sel = (pg["cell"] >= c0) & (pg["cell"] < c0 + nck)
         r.set_fields(W[c0:c0 + nck])
-        r.set_particles(pg["pid"][sel], pg["cell"][sel] - c0, pg["m"][sel], pg["x"][sel], pg["u"][sel])
+        r.set_particles(pg["pid"][sel], pg["cell"][sel] - c0, pg["m"][sel], pg["x"][sel], pg["u"][sel],
+                        pg["ei"][sel])
         r.set_step(8)
         r.step(1)
         ors.append(r)
@@ -454,6 +457,18 @@ def test_stagnation_monitor_interpolates_the_ema():
     surf, _ = g.surface(2)
     nt = w["n_theta"]
     assert np.allclose(got, 0.5 * (surf[0, [3, 5]] + surf[nt - 1, [3, 5]]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("Pr", [1.0, 0.72])
+def test_diatomic_parity(Pr):
+    """D = 2 (a diatomic gas's rotational degrees of freedom): particles carry
+    |xi|^2 / 2, drawn at birth, at diffuse walls and on far-field entry, matched
+    per set, tallied and carried through the re-sort; with Pr != 1 it enters
+    the Shakhov heat flux.  Free run and common states against the oracle."""
+    w = wl.with_internal_dof(wl.cylinder(n_theta=24, n_r=16, n_ref=40, Pr=Pr, Ma=5.0, Tw=1.0, Kn=0.1), 2)
+    g, r, _ = run_pair(w, [1, 3, 8])
+    assert np.any(g.particles()["ei"] > 0)
+    common_state_steps(w, [0, 4])
 
 
 def test_maxwell_wall_parity():

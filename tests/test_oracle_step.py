@@ -411,24 +411,62 @@ def test_wave_only_preserves_uniform_flow_and_time_weighted_content(dim):
         assert abs(I[q] - I0[q]) <= 2e-13 * abs(I0[q])
 
 
-def test_internal_dof_only_without_particles():
-    """Particles carry (m, x, u) and no internal energy, so D > 0 is refused
-    unless the run is wave-only; wave-only with D = 2 conserves the
-    time-weighted content of a closed box (the wave flux's K = 1 + D
-    moments are pinned against quadrature in the primitive tests)."""
-    c = _closed_box(2)
-    c["gas"] = dict(c["gas"], D=2)
-    with pytest.raises(RuntimeError, match="internal degrees of freedom"):
-        oracle.Oracle(c)
-    c["wave_only"] = 1
-    rho = c["W0"][:, 0]
-    u, v = c["W0"][:, 1] / rho, c["W0"][:, 2] / rho
-    T = (c["W0"][:, 3] / rho - 0.5 * (u * u + v * v)) / 1.5
-    c["W0"] = wl.conservative(rho, u, v, T, 2, D=2)
-    o = oracle.Oracle(c)
-    vol, dt = cell_volumes(c), o.dt()
+def _diatomic(m, D):
+    return wl.with_internal_dof(m, D)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_diatomic_closed_box_conserves_time_weighted_content(dim):
+    """D = 2 with particles carrying internal energy: Eqs. (43), (53) keep
+    sum_i Omega_i W_i / dt_i of a specular box (mass and energy) exactly, so
+    every tally, sample and impulse accounts for the internal part."""
+    m = _diatomic(_closed_box(dim, mu=0.2), 2)
+    o = oracle.Oracle(m)
+    vol, dt = cell_volumes(m), o.dt()
     I0 = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
-    o.step(20)
+    for _ in range(20):
+        o.step(1)
+    assert o.counts()[1]["total"] > 0 and np.any(o.particles()["ei"] > 0)
     I = (vol[:, None] * o.fields() / dt[:, None]).sum(0)
-    for q in (0, 3):
+    for q in (0, dim + 1):
         assert abs(I[q] - I0[q]) <= 2e-13 * abs(I0[q])
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_diatomic_new_sets_carry_equipartition_and_gamma_law(D):
+    """After one collisionless step in a specular box no particle is removed
+    and no wall redraws: each cell's new set carries exactly D R T / 2 per
+    unit mass of internal energy (moment matching, as the 3 R T / 2 of the
+    velocities), and the pooled internal energies follow the Gamma(D/2) law
+    of the Maxwellian's internal part, Eq. (1): mean D/2, variance D/2 in
+    units of R T."""
+    box = wl.box2d(wl.graded(6, 1.2), wl.graded(5, 1.3, 0.4), wl.BC_SYMMETRY)
+    m = _diatomic(wl.uniform2d(box, T=1.3, mu_ref=50.0, n_ref=400, seed=4), D)
+    o = oracle.Oracle(m)
+    o.step(1)
+    p = o.particles()
+    assert len(p["pid"]) == o.counts()[1]["new"]
+    born = (p["pid"] >> np.uint64(20)) & np.uint64((1 << 24) - 1)
+    eta = p["ei"] / 1.3
+    for c in range(m["n_cells"]):
+        # a cell's set is born with equal masses (crossings rescale them since)
+        assert abs(np.mean(eta[born == c]) - D / 2) < 1e-12
+    assert abs(eta.mean() - D / 2) < 1e-12
+    assert abs(eta.var() / (D / 2) - 1.0) < 0.06
+
+
+def test_diatomic_gas_between_walls_at_its_temperature_stays_there():
+    """A rarefied D = 2 gas at rest at T = 1 between diffuse walls at T_w = 1:
+    re-emission draws the internal energy at T_w, so no heat flows on
+    average; dropping or mis-drawing it would cool the gas by up to 2/5."""
+    box = wl.box2d(wl.graded(4, 1.0), wl.graded(4, 1.0), wl.BC_WALL_DIFFUSE, [1.0])
+    m = _diatomic(wl.uniform2d(box, T=1.0, mu_ref=5.0, n_ref=300, seed=7), 2)
+    o = oracle.Oracle(m)
+    Ts = []
+    for _ in range(60):
+        o.step(1)
+        W = o.fields()
+        rho = W[:, 0]
+        ke = 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / rho ** 2
+        Ts.append(np.sum(W[:, 3] - rho * ke) / np.sum(2.5 * rho))
+    assert abs(np.mean(Ts[20:]) - 1.0) < 0.02

@@ -357,6 +357,25 @@ def with_maxwell_walls(m, alpha):
     return w
 
 
+def with_internal_dof(m, D):
+    """A copy of workload m for a gas with D internal degrees of freedom: the
+    same density, velocity and temperature fields (the energy gains
+    D rho R T / 2)."""
+    w = dict(m)
+    w["gas"] = dict(m["gas"], D=D)
+    W = np.asarray(m["W0"], dtype=np.float64)
+    dim = int(m["dim"])
+    R = m["gas"]["R"]
+    D0 = m["gas"]["D"]
+    rho = W[:, 0]
+    u = W[:, 1] / rho
+    v = W[:, 2] / rho if dim == 2 else np.zeros_like(rho)
+    ke = 0.5 * (u * u + v * v)
+    T = (W[:, -1] / rho - ke) / (0.5 * (3 + D0) * R)
+    w["W0"] = conservative(rho, u, v, T, dim, D=D, R=R)
+    return w
+
+
 def uniform2d(mesh, rho=1.0, ux=0.0, uy=0.0, T=1.0, mu_ref=1e-3, omega=0.5, Pr=1.0, n_ref=50,
               lts=1, seed=1, cfl=0.8):
     m = dict(mesh)
