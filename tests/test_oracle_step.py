@@ -470,3 +470,42 @@ def test_diatomic_gas_between_walls_at_its_temperature_stays_there():
         ke = 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / rho ** 2
         Ts.append(np.sum(W[:, 3] - rho * ke) / np.sum(2.5 * rho))
     assert abs(np.mean(Ts[20:]) - 1.0) < 0.02
+
+
+def test_residuals_follow_their_definition():
+    """R19 recomputed outside the oracle from the fields it reports:
+    r_inst^n = sqrt(sum Omega (rho^n - rho^{n-1})^2 / sum Omega) / rho_inf and
+    r_avg^n the same for the running mean rho_bar^n = (1/n) sum_{k=1..n} rho^k."""
+    w = wl.cylinder(n_theta=16, n_r=12, n_ref=30, Ma=4.0, Kn=0.05, Tw=1.0)
+    o = oracle.Oracle(w)
+    vol = cell_volumes(w)
+    rho = [o.fields()[:, 0]]
+    means = []
+    for n in range(1, 7):
+        o.step(1)
+        rho.append(o.fields()[:, 0])
+        means.append(np.mean(rho[1:], axis=0))
+        ri, ra, steps = o.residual()
+        assert steps == n
+        want_i = np.sqrt(np.sum(vol * (rho[n] - rho[n - 1]) ** 2) / np.sum(vol))
+        assert abs(ri - want_i) <= 1e-12 * want_i
+        if n >= 2:
+            want_a = np.sqrt(np.sum(vol * (means[-1] - means[-2]) ** 2) / np.sum(vol))
+            assert abs(ra - want_a) <= 1e-10 * want_a
+
+
+def test_gas_at_rest_presses_its_own_pressure_on_diffuse_walls():
+    """R20 against kinetic theory: a gas at rest at T between diffuse walls at
+    T exerts p = rho R T on the walls with no shear and no heat flux, so with
+    the reference state equal to the gas state C_p, C_F and C_Q average to 0
+    (a wave or particle part of the wall flux missing or doubled would put
+    C_p near -/+ 2 with q_ref = rho U_ref^2 / 2, U_ref = 1 = sqrt(p / rho))."""
+    box = wl.box2d(wl.graded(4, 1.0), wl.graded(4, 1.0), wl.BC_WALL_DIFFUSE, [1.0])
+    m = wl.uniform2d(box, T=1.0, mu_ref=0.5, n_ref=400, seed=11)
+    o = oracle.Oracle(m)
+    o.step(150)
+    surf, _ = o.surface(1)
+    L = surf[:, 2]
+    for col in (3, 4, 5):
+        mean = np.sum(surf[:, col] * L) / np.sum(L)
+        assert abs(mean) < 0.05, (col, mean)
