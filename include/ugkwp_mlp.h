@@ -63,7 +63,8 @@ int ugkwp_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, int6
                    float beta2, float eps, int64_t t, uint16_t *w16, uint16_t *wT16, void *stream);
 
 /* Inference of the whole network in one kernel, the activations kept in
- * registers between layers (32 samples per wavefront).  Supported widths:
+ * registers between layers (32 samples per wavefront, four wavefronts per
+ * block; each layer's weights are staged once per block in LDS: 128 KiB).  Supported widths:
  * 32 -> 256 -> 256 -> 256 -> 32 (n_layers = 4), hidden layers with GELU,
  * the last linear; each activation is rounded to BF16 before the next layer,
  * as in ugkwp_mlp_layer.

@@ -1022,11 +1022,13 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   }
 }
 
-// Four wavefronts per SIMD keep the triangle and quad kernels within 128
-// VGPRs; polygons with more faces hold more face data per lane, and particles
-// with internal energy more state, and get up to 256.
+// Three wavefronts per SIMD give the triangle and quad kernels up to 168
+// VGPRs, enough to hold a cell's faces without spilling (with four, 128
+// VGPRs spill; measured slower); polygons with more faces hold more face
+// data per lane, and particles with internal energy more state, and get up
+// to 256.
 template <int DIM, int NV, class R, int FEAT>
-__global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 2)
+__global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 3 : 2)
     k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];

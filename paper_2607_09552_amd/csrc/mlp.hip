@@ -288,9 +288,9 @@ __global__ void __launch_bounds__(256) k_ws_decode(const float *__restrict__ Y, 
 // k-steps if the next layer's input features are taken in the matching order:
 // k-step s, lane half h, slot e <-> feature 16 s + 8 (e / 4) + 4 h + e % 4.
 // The weights are packed once (k_pack_frag) in that order and in fragment
-// order, so a lane's A operand is one 16-byte load and a wavefront's one
-// contiguous kilobyte.  The first layer reads its inputs from memory in
-// natural order.
+// order, so a layer's weights are one contiguous array that a block copies
+// to LDS with 16-byte loads, and a lane's A operand is one 16-byte LDS read.
+// The first layer reads its inputs from memory in natural order.
 
 // feature index of slot e of lane half h in k-step s
 __host__ __device__ __forceinline__ int64_t frag_feature(int64_t s, int h, int e, int permuted) {
@@ -319,25 +319,15 @@ union Frag {
   uint16_t h[8];
 };
 
-// one layer on register activations: in [KS] k-steps -> acc [T] tiles,
+// One layer on register activations: in [KS] k-steps -> acc [T] tiles,
 // the accumulators starting from the bias (a lane's 16 outputs of a tile are
-// four runs of four consecutive features: four 16-byte loads).  The weight
-// fragments are fetched PF k-steps ahead (a ring of PF + 1 sets); scheduling
-// barriers keep each step's fetches ahead of its matrix-core work, so the L2
-// latency hides behind the earlier steps.
-template <int KS, int T, int PF = 3>
-__device__ __forceinline__ void layer_regs(const uint16_t *__restrict__ Wf, const float *__restrict__ bias,
-                                           const Frag (&act)[KS], f32x16 (&acc)[T], int lane) {
+// four runs of four consecutive features: four 16-byte loads), the weight
+// fragments read from the layer's copy in LDS (lane l's 16 bytes of a
+// fragment are consecutive: conflict-free ds_read_b128).
+template <int KS, int T>
+__device__ __forceinline__ void layer_lds(const bf16x8 *__restrict__ lds, const float *__restrict__ bias,
+                                          const Frag (&act)[KS], f32x16 (&acc)[T], int lane) {
   const int h = lane >> 5;
-  const bf16x8 *w = reinterpret_cast<const bf16x8 *>(Wf) + lane;
-  bf16x8 ring[PF + 1][T];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    if (p < KS) {
-#pragma unroll
-      for (int t = 0; t < T; ++t) ring[p][t] = w[(t * KS + p) * 64];
-    }
-  }
 #pragma unroll
   for (int t = 0; t < T; ++t) {
 #pragma unroll
@@ -349,19 +339,28 @@ __device__ __forceinline__ void layer_regs(const uint16_t *__restrict__ Wf, cons
       acc[t][4 * g + 3] = b.w;
     }
   }
-  __builtin_amdgcn_sched_barrier(0);
+  const bf16x8 *w = lds + lane;
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    if (s + PF < KS) {
-#pragma unroll
-      for (int t = 0; t < T; ++t) ring[(s + PF) % (PF + 1)][t] = w[(t * KS + s + PF) * 64];
-    }
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < T; ++t)
-      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ring[s % (PF + 1)][t], act[s].v, acc[t], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[(t * KS + s) * 64], act[s].v, acc[t], 0, 0, 0);
   }
+}
+
+// The block's copy of one layer's packed fragments (n chunks of 16 bytes, a
+// multiple of 64): each wavefront copies whole kilobytes with direct
+// global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes land at
+// the chunk's base + 16 l), all in flight at once and through no registers.
+// The first barrier lets the previous layer's reads finish; the wait and the
+// second barrier publish the copy.
+__device__ __forceinline__ void stage_layer(const uint16_t *__restrict__ Wf, int n, bf16x8 *lds) {
+  const bf16x8 *src = reinterpret_cast<const bf16x8 *>(Wf);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  for (int c = wv; c < n / 64; c += nw) __builtin_amdgcn_global_load_lds(src + c * 64 + lane, &lds[c * 64], 16, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 }
 
 // GELU and BF16: the accumulators of T tiles become 2T k-steps of the next
@@ -375,31 +374,43 @@ __device__ __forceinline__ void to_next(const f32x16 (&acc)[T], Frag (&act)[2 * 
   }
 }
 
-// widths K0 -> H -> H (NH - 1 times) -> NO
+// widths K0 -> H -> H (NH - 1 times) -> NO.  A block of four wavefronts
+// (128 rows) stages each layer's weights in LDS once (the H x H layer: 128 KiB
+// of gfx950's 160 KiB), so the weights cross L2 once per block instead of once
+// per wavefront, and the matrix cores wait on LDS instead of L2.
 template <int K0, int H, int NH, int NO>
-__global__ void __launch_bounds__(64) k_mlp_fused(const uint16_t *__restrict__ X, int64_t M, FusedNet net,
+__global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *__restrict__ X, int64_t M, FusedNet net,
                                                   float *__restrict__ Y) {
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 32;
-  if (row0 >= M) return;
+  __shared__ bf16x8 lds[(H / 32) * (H / 16) * 64];
   const int lane = threadIdx.x & 63, sl = lane & 31, h = lane >> 5;
+  const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * 32;
+  const bool active = row0 < M;  // M % 32 == 0: a wavefront's rows are all in or all out
   Frag xin[K0 / 16];
-#pragma unroll
-  for (int s = 0; s < K0 / 16; ++s)
-    xin[s].v = *reinterpret_cast<const bf16x8 *>(X + (row0 + sl) * K0 + 16 * s + 8 * h);
   Frag act[H / 16];
-  {
+  if (active) {
+#pragma unroll
+    for (int s = 0; s < K0 / 16; ++s)
+      xin[s].v = *reinterpret_cast<const bf16x8 *>(X + (row0 + sl) * K0 + 16 * s + 8 * h);
+  }
+  stage_layer(net.W[0], (H / 32) * (K0 / 16) * 64, lds);
+  if (active) {
     f32x16 acc[H / 32];
-    layer_regs<K0 / 16, H / 32>(net.W[0], net.b[0], xin, acc, lane);
+    layer_lds<K0 / 16, H / 32>(lds, net.b[0], xin, acc, lane);
     to_next<H / 32>(acc, act);
   }
 #pragma unroll
   for (int l = 1; l < NH; ++l) {
-    f32x16 acc[H / 32];
-    layer_regs<H / 16, H / 32>(net.W[l], net.b[l], act, acc, lane);
-    to_next<H / 32>(acc, act);
+    stage_layer(net.W[l], (H / 32) * (H / 16) * 64, lds);
+    if (active) {
+      f32x16 acc[H / 32];
+      layer_lds<H / 16, H / 32>(lds, net.b[l], act, acc, lane);
+      to_next<H / 32>(acc, act);
+    }
   }
+  stage_layer(net.W[NH], (NO / 32) * (H / 16) * 64, lds);
+  if (!active) return;
   f32x16 out[NO / 32];
-  layer_regs<H / 16, NO / 32>(net.W[NH], net.b[NH], act, out, lane);
+  layer_lds<H / 16, NO / 32>(lds, net.b[NH], act, out, lane);
 #pragma unroll
   for (int t = 0; t < NO / 32; ++t) {
 #pragma unroll
@@ -514,7 +525,7 @@ int ugkwp_mlp_forward(const uint16_t *X, int64_t M, int32_t n_layers, const int3
     net.W[l] = Wf[l];
     net.b[l] = bias[l];
   }
-  hipLaunchKernelGGL((k_mlp_fused<32, 256, 3, 32>), dim3(static_cast<unsigned>(M / 32)), dim3(64), 0,
+  hipLaunchKernelGGL((k_mlp_fused<32, 256, 3, 32>), dim3(static_cast<unsigned>((M / 32 + 3) / 4)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), X, M, net, Y);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
