@@ -24,17 +24,31 @@ struct WsCase {
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-// round to nearest even
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+// BF16 bits of an FP32 value, rounded to nearest even (gfx950's
+// v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
+
+// Standard normal distribution function Phi(z) = (1 + erf(z / sqrt 2)) / 2 with
+// erf from Abramowitz and Stegun 7.1.26 (|error| <= 1.5e-7, below FP32
+// arithmetic noise at BF16 outputs): for x >= 0,
+// erf x = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) e^{-x^2}, t = 1 / (1 + p x);
+// odd in x.  About a dozen instructions instead of the library's erff.
+__device__ __forceinline__ float phi_cdf(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));  // v_rcp_f32, ~1 ulp
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  const float e = 1.0f - poly * t * __expf(-x * x);  // erf(|z| / sqrt 2)
+  return 0.5f + 0.5f * copysignf(e, z);
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 
+// d/dz z Phi(z) = Phi(z) + z phi(z), phi the standard normal density
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return phi_cdf(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // Each wavefront computes one 32 x 32 tile of C over the K range
@@ -109,33 +123,47 @@ __global__ void __launch_bounds__(256) k_gemm_splitk(const uint16_t *__restrict_
 
 // dZ = dY * GELU'(Z) (or dY without activation); writes dZ as BF16 [M x N]
 // and transposed [N x M], and adds the column sums to db (cleared by the
-// caller).  One thread per element of a column-major walk so that a
-// wavefront covers 64 rows of one column (coalesced transposed store).
+// caller).  A block takes a tile of 64 rows x 32 columns: reads and the
+// row-major write go along rows (32 consecutive columns), the transposed
+// write goes through a padded LDS tile so that it runs along the 64 rows,
+// and the column sums are reduced in LDS: one atomic per column per tile.
 __global__ void __launch_bounds__(256) k_act_backward(const float *__restrict__ dY, const float *__restrict__ Z,
                                                       int64_t M, int64_t N, int act, uint16_t *__restrict__ dZ16,
                                                       uint16_t *__restrict__ dZT16, float *__restrict__ db) {
-  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  float v = 0.0f;
-  int64_t col = -1;
-  if (e < M * N) {
-    col = e / M;
-    const int64_t row = e % M;
-    const float g = dY[row * N + col];
-    v = act ? g * gelu_grad(Z[row * N + col]) : g;
-    const uint16_t b = f2bf(v);
-    dZ16[row * N + col] = b;
-    dZT16[col * M + row] = b;
-  }
-  // column sums: lanes of one column in a wavefront add together
-  const int64_t c0 = __shfl(col, 0, 64);
-  const bool uniform = __all(col == c0);
-  if (uniform) {
-    float s = v;
+  __shared__ uint16_t tile[64][33];
+  __shared__ float part[8][32];
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64, col0 = static_cast<int64_t>(blockIdx.y) * 32;
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;  // column, row group (8 rows apart)
+  const int64_t col = col0 + c;
+  float sum = 0.0f;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0 && c0 >= 0) atomicAdd(&db[c0], s);
-  } else if (col >= 0) {
-    atomicAdd(&db[col], v);
+  for (int k = 0; k < 8; ++k) {
+    const int r = g + 8 * k;
+    const int64_t row = row0 + r;
+    uint16_t b = 0;
+    if (row < M && col < N) {
+      const float gy = dY[row * N + col];
+      const float v = act ? gy * gelu_grad(Z[row * N + col]) : gy;
+      b = f2bf(v);
+      dZ16[row * N + col] = b;
+      sum += v;
+    }
+    tile[r][c] = b;
+  }
+  part[g][c] = sum;
+  __syncthreads();
+  if (threadIdx.x < 32 && col < N) {
+    float s8 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s8 += part[q][threadIdx.x];
+    atomicAdd(&db[col], s8);
+  }
+  const int r = threadIdx.x & 63, q4 = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int cc = q4 + 4 * k;
+    const int64_t row = row0 + r, cg = col0 + cc;
+    if (row < M && cg < N) dZT16[cg * M + row] = tile[r][cc];
   }
 }
 
@@ -181,9 +209,13 @@ __global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ Y, c
     dY[e] = g;
   }
   if (loss) {
+    // one atomic per block: wavefront butterflies, then the four partials
+    __shared__ float wsum[4];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, sq);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
   }
 }
 
@@ -483,9 +515,8 @@ int ugkwp_mlp_gemm_acc(const uint16_t *A, const uint16_t *B, int64_t M, int64_t 
 int ugkwp_mlp_act_backward(const float *dY, const float *Z, int64_t M, int64_t N, int32_t act, uint16_t *dZ16,
                            uint16_t *dZT16, float *db, void *stream) {
   if (!dY || !dZ16 || !dZT16 || !db || (act && !Z) || M <= 0 || N <= 0) return -1;
-  const int64_t n = M * N;
-  hipLaunchKernelGGL(k_act_backward, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), dY, Z, M, N, act, dZ16, dZT16, db);
+  hipLaunchKernelGGL(k_act_backward, dim3(static_cast<unsigned>((M + 63) / 64), static_cast<unsigned>((N + 31) / 32)),
+                     dim3(256), 0, static_cast<hipStream_t>(stream), dY, Z, M, N, act, dZ16, dZT16, db);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

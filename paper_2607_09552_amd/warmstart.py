@@ -285,18 +285,20 @@ class MLP:
                 H = b["H16"][l + 1]
         return b["Y"]
 
-    def train_step(self, X16, XT16, T, M, lr, beta1=0.9, beta2=0.999, eps=1e-8, k_chunk=512):
+    def train_step(self, X16, XT16, T, M, lr, beta1=0.9, beta2=0.999, eps=1e-8, k_chunk=512, want_loss=True):
         """One Adam step on the mean squared error of the first four outputs
-        against T [M x 4]; returns the device loss (sum of squares)."""
+        against T [M x 4]; returns the device loss (sum of squares), or None
+        without want_loss."""
         L, st = load_library(), _stream()
         wd = self.widths
         nl = len(wd) - 1
         b = self._buffers(M)
         Y = self.forward(X16, M, train=True)
-        b["loss"].zero_()
+        if want_loss:
+            b["loss"].zero_()
         dY = b["dY"]
-        _chk(L.ugkwp_mlp_mse_grad(_vp(Y), _vp(T), M, wd[-1], N_OUT, 2.0 / (M * N_OUT), _vp(dY), _vp(b["loss"]), st),
-             "mse_grad")
+        _chk(L.ugkwp_mlp_mse_grad(_vp(Y), _vp(T), M, wd[-1], N_OUT, 2.0 / (M * N_OUT), _vp(dY),
+                                  _vp(b["loss"]) if want_loss else None, st), "mse_grad")
         for g in self.gW + self.gb:
             g.zero_()
         G = dY  # gradient w.r.t. the current layer's output, [M x out]
@@ -321,7 +323,7 @@ class MLP:
             bb = self.b[l]
             _chk(L.ugkwp_mlp_adam(_vp(bb), _vp(self.mb[l]), _vp(self.vb[l]), _vp(self.gb[l]), bb.numel(), bb.numel(),
                                   lr, beta1, beta2, eps, self.t, None, None, st), "adam")
-        return b["loss"]
+        return b["loss"] if want_loss else None
 
 
 def features(Wc, case, rows, XT=True):
@@ -444,8 +446,9 @@ def cmd_train(a):
     for it in range(a.steps):
         lr = a.lr * 0.5 * (1.0 + math.cos(math.pi * it / a.steps))
         j = it % nb
-        loss = mlp.train_step(Xd[j], XTd[j], Td[j], M, lr)
-        if (it + 1) % a.log_every == 0 or it == 0:
+        log = (it + 1) % a.log_every == 0 or it == 0
+        loss = mlp.train_step(Xd[j], XTd[j], Td[j], M, lr, want_loss=log)
+        if log:
             v = float(loss.item()) / (M * N_OUT)
             hist.append((it + 1, v))
             print(f"  step {it + 1} loss {v:.4e} lr {lr:.2e} {time.perf_counter() - t0:.1f} s", flush=True)
