@@ -382,7 +382,7 @@ def cmd_data(a):
     fine UGKWP runs (mixed precision, n_ref particles per cell), in batches."""
     import torch
     use_own_stream()
-    cases = np.concatenate([draws(a.n_train, 3), draws(a.n_test, 4)])
+    cases = np.concatenate([draws(a.n_train, a.train_seed), draws(a.n_test, 4)])
     n = len(cases)
     print(f"coarse solves: {n} cases", flush=True)
     Wc, dt = coarse_solve([tuple(c) for c in cases])
@@ -408,17 +408,24 @@ def cmd_data(a):
         del acc
         torch.cuda.empty_cache()
     np.savez(a.out, cases=cases, n_train=a.n_train, coarse=Wc.cpu().numpy(), fine=P, n_ref=a.n_ref,
-             transient=a.transient, average=a.average)
+             transient=a.transient, average=a.average, train_seed=a.train_seed)
     print(f"wrote {a.out}", flush=True)
 
 
 def cmd_train(a):
     import torch
     use_own_stream()
-    z = np.load(a.data)
-    cases, ntr = z["cases"], int(z["n_train"])
-    coarse = torch.tensor(z["coarse"], device="cuda")
-    fine = z["fine"].astype(np.float32)
+    # one or more data files: the training cases of all, the held-out cases of
+    # the first
+    zs = [np.load(f) for f in a.data.split(",")]
+    z = zs[0]
+    parts = [(zz["cases"][: int(zz["n_train"])], zz["coarse"][: int(zz["n_train"])], zz["fine"][: int(zz["n_train"])])
+             for zz in zs]
+    ntr = sum(len(p[0]) for p in parts)
+    n0 = int(z["n_train"])
+    cases = np.concatenate([p[0] for p in parts] + [z["cases"][n0:]])
+    coarse = torch.tensor(np.concatenate([p[1] for p in parts] + [z["coarse"][n0:]]), device="cuda")
+    fine = np.concatenate([p[2] for p in parts] + [z["fine"][n0:]]).astype(np.float32)
     nf = FINE[0] * FINE[1]
     # assemble the features and the target corrections of every case
     Xs, XTs, Ts = [], [], []
@@ -472,7 +479,7 @@ def cmd_train(a):
               f"network {np.round(rep[name]['rms_network'], 4)}", flush=True)
     meta = dict(steps=a.steps, batch=M, lr=a.lr, seconds=train_s, history=hist, errors=rep,
                 data=dict(n_train=ntr, n_test=len(cases) - ntr, n_ref=int(z["n_ref"]), transient=int(z["transient"]),
-                          average=int(z["average"])))
+                          average=int(z["average"]), files=a.data))
     mlp.save(a.out, meta)
     print(f"wrote {a.out} ({train_s:.1f} s)", flush=True)
 
@@ -540,6 +547,7 @@ def main(argv=None):
     d = sub.add_parser("data")
     d.add_argument("--n-train", type=int, default=128)
     d.add_argument("--n-test", type=int, default=16)
+    d.add_argument("--train-seed", type=int, default=3)
     d.add_argument("--n-ref", type=int, default=100)
     d.add_argument("--batch", type=int, default=48)
     d.add_argument("--transient", type=int, default=3000)
@@ -547,7 +555,7 @@ def main(argv=None):
     d.add_argument("--every", type=int, default=10)
     d.add_argument("--out", default="ws_data.npz")
     t = sub.add_parser("train")
-    t.add_argument("--data", default="ws_data.npz")
+    t.add_argument("--data", default="ws_data.npz", help="one or more data files, comma-separated")
     t.add_argument("--steps", type=int, default=6000)
     t.add_argument("--batch", type=int, default=8192)
     t.add_argument("--lr", type=float, default=1e-3)
