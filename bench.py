@@ -283,6 +283,8 @@ def main():
                     help="N > 0: N uneven cylinder cases (80x60 to 240x180, Ma 5-20, Kn 0.005-0.2, N_ref 200) "
                          "in one batched solve")
     ap.add_argument("--kn", type=float, default=0.01)
+    ap.add_argument("--workload", choices=("cylinder", "plate"), default="cylinder",
+                    help="plate: the Ma 10 flat plate (300x200, N_ref 300) instead of the cylinder")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
@@ -330,7 +332,7 @@ def main():
     if a.batch:
         batch_bench(a)
         return
-    w = workload(a.kn)
+    w = workload(a.kn) if a.workload == "cylinder" else workloads.flat_plate(seed=1)
     s = Solver(w, precision=a.precision)
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
     s.step(a.warmup)
@@ -364,7 +366,7 @@ def main():
     # particles one launch transports on average over the timed steps
     bytes_per_launch = TRANSPORT_BYTES[a.precision] * n_upd / max(tr["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tpp = traffic_per_particle(a.precision)
+    tpp = traffic_per_particle(a.precision) if a.workload == "cylinder" else None  # counters taken on the cylinder
     traffic = None if tpp is None else tpp * n_upd / max(tr["launches"], 1)
     kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),
                     GBs=round(v["bytes"] / max(v["ms"], 1e-12) * 1e-6, 1) if v["ms"] > 0 else None)
@@ -387,9 +389,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "f64" else "f32 particles, f64 cells",
         "data": "synthetic",
-        "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
-                               f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, "
-                               f"{'FP64' if a.precision == 'f64' else 'FP32 particle push'}, Philox seed 1",
+        "config": {"workload": (f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
+                                f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, " if a.workload == "cylinder" else
+                                "flat plate 300x200, Ma 10, Kn 0.0169, VHS omega 0.74, Pr 1, Tw/Tinf 1 diffuse, "
+                                "N_ref 300, LTS CFL 0.8, ")
+                               + f"{'FP64' if a.precision == 'f64' else 'FP32 particle push'}, Philox seed 1",
                    "cells": int(w["n_cells"]),
                    "particles_per_step": n_upd / a.steps,
                    "cell_steps_per_s": w["n_cells"] * a.steps / elapsed},
