@@ -23,9 +23,13 @@ def _solver(w, **kw):
     return Solver(w, **kw)
 
 
-@pytest.mark.parametrize("dim", [1, 2])
-def test_mixed_closed_box_conserves_time_weighted_content(dim):
+@pytest.mark.parametrize("dim,D", [(1, 0), (2, 0), (2, 2)])
+def test_mixed_closed_box_conserves_time_weighted_content(dim, D):
+    """Also with internal energy (D = 2, stored in FP32 like the velocities):
+    the tallies see the stored values, so the content is still exact."""
     m = _closed_box(dim)
+    if D:
+        m = wl.with_internal_dof(m, D)
     g = _solver(m, precision="mixed")
     vol, dt = cell_volumes(m), g.dt()
     assert dt.max() / dt.min() > 3.0
