@@ -104,6 +104,7 @@ def time_to_residual(a):
     import torch
     from paper_2607_09552_amd import Solver
     w = workload(a.kn)
+    w["dt_source"] = {"initial": 0, "freestream": 1}[a.dt_source]
     W0, ws_info = None, None
     if a.warm_start:
         from paper_2607_09552_amd import warmstart as ws
@@ -135,7 +136,7 @@ def time_to_residual(a):
            "dtype": a.precision, "data": "synthetic",
            "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
                                   f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, {a.precision}, Philox seed 1",
-                      "start": start, "rule": "first n >= 100 with r_avg < target"},
+                      "start": start, "dt_from": a.dt_source, "rule": "first n >= 100 with r_avg < target"},
            "wall": {"Cd_mean": cd, "Cp_max": float(np.max(surf[:, 3])), "CF_absmax": float(np.max(np.abs(surf[:, 4]))),
                     "CQ_max": float(np.max(surf[:, 5]))}}
     print(json.dumps(out))
@@ -297,6 +298,9 @@ def main():
                     help="time to residual: run from the freestream start until r_avg < --ttr-target")
     ap.add_argument("--ttr-target", type=float, default=1e-6)
     ap.add_argument("--ttr-max-steps", type=int, default=600000)
+    ap.add_argument("--dt-source", choices=["initial", "freestream"], default="initial",
+                    help="with --ttr: the state the local time steps are taken from (Eq. (33)): the initial "
+                         "field (the paper) or the freestream, which gives a warm start the freestream start's steps")
     ap.add_argument("--mlp", action="store_true", help="matrix-core kernels of the warm-start network")
     ap.add_argument("--warm-start", action="store_true",
                     help="with --ttr: start from the learned warm start instead of the freestream")

@@ -95,10 +95,16 @@ typedef struct {
   int32_t wave_only;          /* 1: E = 0 -- no particles, the free-transport wave
                                  carries all of g^h (the gas-kinetic scheme of the
                                  coarse solves behind a warm start); 0: UGKWP */
+  int32_t dt_source;          /* state Eq. (33) takes dt_i from: 0 the initial
+                                 field W0 (Sec. IV.B), 1 the freestream reference
+                                 (rho_inf, u_inf, T_inf) in every cell, so that
+                                 runs from different initial fields share one
+                                 set of time steps */
 } ugkwp_params;
 
 /* Builds faces and geometry, uploads the state and computes the local time
- * steps dt_i from W0 (Eq. (33)), fixed for the whole run; the particle set
+ * steps dt_i from W0 (Eq. (33); from the freestream when dt_source = 1),
+ * fixed for the whole run; the particle set
  * starts empty (W^p = 0, Sec. III.C).  W0 is [n_cells*(dim+2)] host memory.
  * Errors: EINVAL (mesh not matching its boundary list, non-convex or
  * clockwise cell, bad parameters), ENUMERIC (invalid W0), EDEVICE, ENOMEM. */
@@ -111,7 +117,7 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double 
  * own seed, so case k of a batch gives the results of ugkwp_init with
  * meshes[k], params[k], W0[k].  All cases must share dim (2), the gas (R,
  * omega, T_ref, Pr, D), cfl, n_ref, lts, precision and stream; mu_ref, seed,
- * the freestream reference and capacity may differ.  W0[k] is
+ * the freestream reference, dt_source and capacity may differ.  W0[k] is
  * [meshes[k].n_cells*4].  Errors as ugkwp_init, EINVAL for mismatched shared
  * parameters. */
 int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_params *params,

@@ -48,6 +48,7 @@ class _Params(C.Structure):
         ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32),
         ("lts", C.c_int32), ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double),
         ("u_inf_y", C.c_double), ("T_inf", C.c_double), ("L_ref", C.c_double), ("wave_only", C.c_int32),
+        ("dt_source", C.c_int32),
     ]
 
 
@@ -199,7 +200,7 @@ class Oracle:
         p = _Params(R=g["R"], omega=g["omega"], mu_ref=g["mu_ref"], T_ref=g["T_ref"], Pr=g["Pr"], D=g["D"],
                     cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
                     u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
-                    wave_only=int(wl.get("wave_only", 0)))
+                    wave_only=int(wl.get("wave_only", 0)), dt_source=int(wl.get("dt_source", 0)))
         W = _f64(wl["W0"] if W0 is None else W0).ravel()
         h = C.c_void_p()
         rc = L.ref_init(C.byref(m), C.byref(p), _p(W), C.byref(h))

@@ -728,7 +728,7 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   c->K = 1 + par->D;
   c->N = 3 + par->D;
   if (!(par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-        par->D >= 0 && par->D <= 64)) {
+        par->D >= 0 && par->D <= 64 && (par->dt_source == 0 || (par->dt_source == 1 && par->T_inf > 0)))) {
     *out = c;
     return fail(c, REF_EINVAL, "invalid parameters");
   }
@@ -758,11 +758,17 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   *out = c;
 
   /* Eq. (33): dt_i = N_CFL Omega_i / sum_j (|U_i| + 3 sqrt(R T_i)) s_j from the
-   * initial field; Eq. (34): dt_G = min_i dt_i (used everywhere under GTS). */
+   * initial field (or, with dt_source = 1, with U and T of the freestream in
+   * every cell); Eq. (34): dt_G = min_i dt_i (used everywhere under GTS). */
   double dtg = INFINITY;
   for (int64_t i = 0; i < nc; ++i) {
     prim_t s = prim(c, c->W + i * nw);
     if (!prim_ok(s)) return fail(c, REF_ENUMERIC, "invalid initial state in cell %lld", (long long)i);
+    if (c->p.dt_source) {
+      s.ux = c->p.u_inf_x;
+      s.uy = c->dim == 2 ? c->p.u_inf_y : 0.0;
+      s.T = c->p.T_inf;
+    }
     double speed = c->dim == 2 ? sqrt(s.ux * s.ux + s.uy * s.uy) : fabs(s.ux);
     double a = speed + 3.0 * sqrt(c->p.R * s.T);
     double S = 0.0;

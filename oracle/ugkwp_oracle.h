@@ -65,6 +65,8 @@ typedef struct {
   int32_t wave_only;           /* 1: E = 0 (no particles, all gas in the waves:
                                   the gas-kinetic scheme of the coarse warm-start
                                   solves); 0: UGKWP */
+  int32_t dt_source;           /* Eq. (33) reads 0: the initial field, 1: the
+                                  freestream (rho_inf, u_inf, T_inf) */
 } ref_params;
 
 typedef struct ref_ctx ref_ctx;

@@ -54,7 +54,7 @@ class _Params(C.Structure):
         ("Pr", C.c_double), ("D", C.c_int32), ("cfl", C.c_double), ("n_ref", C.c_int32), ("lts", C.c_int32),
         ("seed", C.c_uint64), ("rho_inf", C.c_double), ("u_inf_x", C.c_double), ("u_inf_y", C.c_double),
         ("T_inf", C.c_double), ("L_ref", C.c_double), ("particle_capacity", C.c_int64), ("stream", C.c_void_p),
-        ("precision", C.c_int32), ("wave_only", C.c_int32),
+        ("precision", C.c_int32), ("wave_only", C.c_int32), ("dt_source", C.c_int32),
     ]
 
 
@@ -207,7 +207,8 @@ class Solver:
                     cfl=wl["cfl"], n_ref=wl["n_ref"], lts=wl["lts"], seed=wl["seed"], rho_inf=r["rho_inf"],
                     u_inf_x=r["u_inf"][0], u_inf_y=r["u_inf"][1], T_inf=r["T_inf"], L_ref=r["L_ref"],
                     particle_capacity=particle_capacity, stream=stream,
-                    precision={"f64": 0, "mixed": 1}[precision], wave_only=int(wl.get("wave_only", 0)))
+                    precision={"f64": 0, "mixed": 1}[precision], wave_only=int(wl.get("wave_only", 0)),
+                    dt_source=int(wl.get("dt_source", 0)))
         W = arr(wl["W0"] if W0 is None else W0, np.float64).ravel()
         return m, p, W
 

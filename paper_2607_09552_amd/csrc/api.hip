@@ -767,7 +767,28 @@ namespace {
 
 bool params_ok(const ugkwp_params *par) {
   return par->R > 0 && par->mu_ref > 0 && par->T_ref > 0 && par->Pr > 0 && par->cfl > 0 && par->n_ref > 0 &&
-         par->D >= 0 && par->D <= 64 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0;
+         par->D >= 0 && par->D <= 64 && par->rho_inf > 0 && par->T_inf > 0 && par->L_ref > 0 &&
+         (par->dt_source == 0 || par->dt_source == 1);
+}
+
+// The state Eq. (33) reads for a case: its initial field W0 (dt_source 0), or
+// its freestream reference state repeated over its n cells (dt_source 1), so
+// that a start from another field keeps the freestream start's time steps.
+void dt_field(const ugkwp_params *q, int dim, int64_t n, const double *W0, std::vector<double> &out) {
+  const int nw = dim + 2;
+  if (n <= 0) return;
+  if (q->dt_source == 0) {
+    out.insert(out.end(), W0, W0 + n * nw);
+    return;
+  }
+  const double rho = q->rho_inf, ux = q->u_inf_x, uy = dim == 2 ? q->u_inf_y : 0.0;
+  const double E = rho * (0.5 * (ux * ux + uy * uy) + 0.5 * (3 + q->D) * q->R * q->T_inf);
+  for (int64_t i = 0; i < n; ++i) {
+    out.push_back(rho);
+    out.push_back(rho * ux);
+    if (dim == 2) out.push_back(rho * uy);
+    out.push_back(E);
+  }
 }
 
 // Per-case table row of a parameter set.
@@ -785,8 +806,8 @@ void case_row(const ugkwp_params *q, double *row) {
 // Builds a context for `mesh` (for a batch, the disjoint union of the cases'
 // meshes) with the shared parameters of `par` and, for a batch, the cases'
 // cell and boundary-face ranges, seeds and per-case table.
-int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, int ncase,
-              const std::vector<int64_t> &case_cell, const std::vector<int64_t> &case_bface,
+int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0, const double *Wdt,
+              int ncase, const std::vector<int64_t> &case_cell, const std::vector<int64_t> &case_bface,
               const std::vector<uint64_t> &seeds, const std::vector<double> &case_par) {
   if (mesh->dim != 1 && mesh->dim != 2) return set_err(c, UGKWP_EINVAL, "dim must be 1 or 2");
   if (mesh->n_cells <= 0 || mesh->n_cells >= (int64_t{1} << 31) - 1 - mesh->n_bfaces)
@@ -942,15 +963,22 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   c->pinned = static_cast<int64_t *>(pin);
   // a1: local time steps
   const Geo g = c->geo();
+  double *Wd = S.W;
+  if (Wdt != W0) {
+    if ((rc = dalloc(c, &Wd, nc * nw))) return rc;
+    HIPCHK(hipMemcpyAsync(Wd, Wdt, nc * nw * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
   {
     ProfScope ps(c, kKInitDt, 80.0 * nc);
     if (c->dim == 1)
-      hipLaunchKernelGGL(k_init_dt<1>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, S.W, S.dt, S.flags);
+      hipLaunchKernelGGL(k_init_dt<1>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, Wd, S.dt, S.flags);
     else
-      hipLaunchKernelGGL(k_init_dt<2>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, S.W, S.dt, S.flags);
+      hipLaunchKernelGGL(k_init_dt<2>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, P, Wd, S.dt, S.flags);
   }
   HIPCHK(hipGetLastError());
-  if ((rc = check_flags(c))) return set_err(c, UGKWP_ENUMERIC, "invalid initial state");
+  rc = check_flags(c);
+  if (Wd != S.W) dfree(c, Wd);
+  if (rc) return set_err(c, UGKWP_ENUMERIC, "invalid initial state");
   if (!c->lts) {
     // global time step, Eq. (34): the minimum over each case's cells
     std::vector<double> dt(nc);
@@ -997,7 +1025,11 @@ int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *par, const double *W0
   if (!params_ok(par)) return set_err(c, UGKWP_EINVAL, "invalid parameters");
   std::vector<double> row(kCaseN);
   case_row(par, row.data());
-  return init_impl(c, mesh, par, W0, 1, {0, mesh->n_cells}, {0, mesh->n_bfaces}, {par->seed}, row);
+  if (mesh->dim != 1 && mesh->dim != 2) return set_err(c, UGKWP_EINVAL, "dim must be 1 or 2");
+  std::vector<double> Wdt;
+  if (par->dt_source) dt_field(par, mesh->dim, mesh->n_cells, W0, Wdt);
+  return init_impl(c, mesh, par, W0, par->dt_source ? Wdt.data() : W0, 1, {0, mesh->n_cells}, {0, mesh->n_bfaces},
+                   {par->seed}, row);
 }
 
 int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_params *params,
@@ -1012,7 +1044,7 @@ int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_para
   const ugkwp_mesh &m0 = meshes[0];
   for (int k = 0; k < n_cases; ++k) {
     const ugkwp_params &q = params[k];
-    if (!params_ok(&q) || !W0[k] || meshes[k].dim != m0.dim)
+    if (!params_ok(&q) || !W0[k] || meshes[k].dim != m0.dim || meshes[k].n_cells <= 0)
       return set_err(c, UGKWP_EINVAL, "case %d: invalid parameters, mesh or W0", k);
     if (q.R != p0.R || q.omega != p0.omega || q.T_ref != p0.T_ref || q.Pr != p0.Pr || q.D != p0.D ||
         q.cfl != p0.cfl || q.n_ref != p0.n_ref || q.lts != p0.lts || q.precision != p0.precision ||
@@ -1022,7 +1054,7 @@ int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_para
   }
   // the disjoint union of the meshes
   const int dim = m0.dim, nw = dim + 2;
-  std::vector<double> nodes, bdata, W;
+  std::vector<double> nodes, bdata, W, Wdt;
   std::vector<int64_t> cell_ptr{0}, cell_nodes, bnodes;
   std::vector<int32_t> btype;
   std::vector<int64_t> case_cell{0}, case_bface{0};
@@ -1039,6 +1071,7 @@ int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_para
     btype.insert(btype.end(), m.bface_type, m.bface_type + m.n_bfaces);
     bdata.insert(bdata.end(), m.bface_data, m.bface_data + m.n_bfaces * 8);
     W.insert(W.end(), W0[k], W0[k] + m.n_cells * nw);
+    dt_field(&params[k], dim, m.n_cells, W0[k], Wdt);
     node_off += m.n_nodes;
     case_cell.push_back(case_cell.back() + m.n_cells);
     case_bface.push_back(case_bface.back() + m.n_bfaces);
@@ -1059,7 +1092,7 @@ int ugkwp_init_batch(int32_t n_cases, const ugkwp_mesh *meshes, const ugkwp_para
   ugkwp_params pu = p0;
   pu.particle_capacity = 0;
   for (int k = 0; k < n_cases; ++k) pu.particle_capacity += params[k].particle_capacity;
-  return init_impl(c, &u, &pu, W.data(), n_cases, case_cell, case_bface, seeds, cpar);
+  return init_impl(c, &u, &pu, W.data(), Wdt.data(), n_cases, case_cell, case_bface, seeds, cpar);
 }
 
 }  // extern "C"

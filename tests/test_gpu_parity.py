@@ -93,12 +93,15 @@ def compare(g, r, tag="", tol=TOL):
     return e
 
 
-def run_pair(w, checkpoints, W0=None, tol=DRIFT):
+def run_pair(w, checkpoints, W0=None, tol=DRIFT, dt_rtol=0.0):
     """Free-running GPU and oracle runs compared at the checkpoints."""
     g = _solver(w, W0=W0)
     r = oracle.Oracle(w, W0=W0)
     r.vol = cell_volumes(w)
-    assert np.array_equal(g.dt(), r.dt()), "local time steps differ"
+    if dt_rtol == 0.0:
+        assert np.array_equal(g.dt(), r.dt()), "local time steps differ"
+    else:
+        assert np.allclose(g.dt(), r.dt(), rtol=dt_rtol, atol=0.0), "local time steps differ"
     done = 0
     errs = []
     for n in checkpoints:
@@ -202,6 +205,40 @@ def test_edge_cases():
     w["gas"] = dict(w["gas"], D=65)
     with pytest.raises(UgkwpError, match="invalid parameters"):
         Solver(w)
+
+
+def test_dt_from_freestream_parity():
+    """Eq. (33) read from the freestream (dt_source 1) on a start that is not
+    the freestream: the time steps match the oracle's, which takes |U| and T of
+    the reference state directly, to a few ulps (the library recovers them from
+    a conservative freestream state); they equal a uniform start's, and each
+    case of a batch that mixes both readings has its single-case steps.  Steps
+    from that start then follow the oracle to the usual bars."""
+    from paper_2607_09552_amd import Solver, UgkwpError
+    w = wl.cylinder(n_theta=24, n_r=16, n_ref=40, Pr=2.0 / 3.0, Ma=5.0, Tw=1.0, Kn=0.1)
+    rng = np.random.default_rng(11)
+    n = w["n_cells"]
+    f = 1.0 + 0.2 * rng.random(n)
+    dT = 0.5 * w["ref"]["T_inf"] * rng.random(n)
+    W0 = w["W0"] * f[:, None]
+    W0[:, 3] += W0[:, 0] * 0.5 * (3 + w["gas"]["D"]) * w["gas"]["R"] * dT
+    w1 = dict(w, dt_source=1)
+    g = _solver(w1, W0=W0)
+    dt1 = g.dt()
+    r = oracle.Oracle(w1, W0=W0)
+    assert np.allclose(dt1, r.dt(), rtol=1e-15, atol=0.0)
+    r.close()
+    assert np.allclose(dt1, _solver(w).dt(), rtol=1e-15, atol=0.0)
+    dt0 = _solver(w, W0=W0).dt()
+    assert np.abs(dt0 / dt1 - 1.0).max() > 1e-3
+    b = Solver.batch([dict(w1, W0=W0), dict(w, W0=W0)])
+    dtb = b.dt()
+    assert np.array_equal(dtb[:n], dt1) and np.array_equal(dtb[n:], dt0)
+    g.close()
+    b.close()
+    run_pair(w1, [1, 3, 8], W0=W0, dt_rtol=1e-15)
+    with pytest.raises(UgkwpError, match="invalid parameters"):
+        Solver(dict(w, dt_source=2))
 
 
 def test_shakhov_parity():

@@ -49,6 +49,37 @@ def test_cfl_time_step_closed_form():
 
 
 @pytest.mark.parametrize("dim", [1, 2])
+def test_cfl_time_step_from_freestream_closed_form(dim):
+    """Eq. (33) read with the freestream's |U| and T in every cell: the
+    closed form on rectangles (segments in 1D) with the reference state's
+    speed, whatever the initial field; the paper's reading (from W0) on the
+    same non-uniform field gives other, field-dependent steps."""
+    rng = np.random.default_rng(5)
+    xs = wl.graded(4, 1.5)
+    if dim == 1:
+        m = wl.uniform1d(xs, rho=1.3, U=0.4, T=2.0)
+        hs = [(xs[i + 1] - xs[i], None) for i in range(4)]
+    else:
+        ys = wl.graded(3, 2.0, 0.5)
+        m = wl.uniform2d(wl.box2d(xs, ys, wl.BC_SYMMETRY), rho=1.3, ux=0.4, uy=-0.3, T=2.0)
+        hs = [(xs[i + 1] - xs[i], ys[j + 1] - ys[j]) for j in range(3) for i in range(4)]
+    m["ref"] = dict(m["ref"], rho_inf=0.7, u_inf=[1.5, -2.0], T_inf=0.6)
+    W0 = m["W0"] * (1.0 + 0.3 * rng.random(m["W0"].shape))
+    m["dt_source"] = 1
+    dt = oracle.Oracle(m, W0=W0).dt()
+    U = 1.5 if dim == 1 else 2.5
+    a = U + 3 * math.sqrt(0.6)
+    for k, (hx, hy) in enumerate(hs):
+        ref = 0.8 * hx / (a * 2) if dim == 1 else 0.8 * hx * hy / (a * (2 * hx + 2 * hy))
+        assert abs(dt[k] - ref) <= 1e-15 * ref
+    m["dt_source"] = 0
+    assert not np.allclose(oracle.Oracle(m, W0=W0).dt(), dt)
+    m["dt_source"] = 2
+    with pytest.raises(RuntimeError, match="invalid parameters"):
+        oracle.Oracle(m)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
 def test_uniform_state_preserved_gks_limit(dim):
     """Continuum limit (tau -> 0: E = 0, no particles): a uniform flow is a
     steady solution on graded LTS meshes up to round-off."""
