@@ -7,7 +7,7 @@ are no longer those of the FP64 oracle.  The tests check what must still hold
 exactly -- the time-weighted content Sum Omega_i W_i / dt_i of a closed
 specular box (Eqs. (43), (53)) and every particle inside its cell -- and that
 time-averaged results agree with the FP64 path within the FP64 path's own
-spread between two random seeds."""
+spread between random seeds."""
 import numpy as np
 import pytest
 
@@ -106,13 +106,27 @@ def _cylinder_wall(precision, seed):
 
 def test_mixed_cylinder_wall_quantities_match_fp64_statistically():
     """Cumulative-average C_p, C_F, C_Q and C_d of a coarse Ma 15 cylinder
-    (Shakhov sampling) after 1500 steps."""
-    a64, cda = _cylinder_wall("f64", 1)
-    b64, cdb = _cylinder_wall("f64", 2)
-    a32, cd32 = _cylinder_wall("mixed", 1)
+    (Shakhov sampling) after 1500 steps, six seeds in each precision.  Two
+    runs from one seed part ways within the run (the order of the GPU's
+    atomic sums suffices: FP64 with two launch shapes gives C_d 1.843 and
+    1.851), so each run is one independent draw of these statistics.  The
+    two precisions' means must agree to within the standard error of their
+    difference, estimated from the seeds' pooled variance: C_d within 4 of
+    them (a two-sided t bound, p < 0.3 % for 10 degrees of freedom), each
+    wall distribution within 3 in norm over the wall faces."""
+    seeds = range(1, 7)
+    n = len(seeds)
+    runs = {p: [_cylinder_wall(p, s) for s in seeds] for p in ("f64", "mixed")}
+    surf = {p: np.stack([r[0] for r in runs[p]]) for p in runs}
+    cd = {p: np.array([r[1] for r in runs[p]]) for p in runs}
+
+    def diff_and_se(a, b):
+        var = 0.5 * (a.var(axis=0, ddof=1) + b.var(axis=0, ddof=1))
+        return a.mean(axis=0) - b.mean(axis=0), np.sqrt(2.0 * var / n)
+
     for q in range(3):
-        scale = np.linalg.norm(a64[:, q])
-        spread = np.linalg.norm(a64[:, q] - b64[:, q]) / scale
-        err = np.linalg.norm(a32[:, q] - a64[:, q]) / scale
-        assert err < 3.0 * spread + 1e-3, (q, err, spread)
-    assert abs(cd32 - cda) < 3.0 * abs(cdb - cda) + 1e-3 * abs(cda)
+        d, se = diff_and_se(surf["mixed"][:, :, q], surf["f64"][:, :, q])
+        ratio = np.linalg.norm(d) / np.linalg.norm(se)
+        assert ratio < 3.0, (q, ratio)
+    d, se = diff_and_se(cd["mixed"], cd["f64"])
+    assert se > 0 and abs(d) < 4.0 * se, (d, se)

@@ -448,11 +448,28 @@ def test_graph_replays_match_the_oracle():
     r2 = oracle.Oracle(w2)
     r2.vol = cell_volumes(w2)
     done = 0
-    for n in (3, 10, 17):
+    for n in (3, 10):
         g2.step(n - done)
         r2.step(n - done)
         done = n
         compare(g2, r2, f"graph with growth, step {n}", DRIFT)
+    # The free runs' fields drift apart with the order of the GPU's atomic
+    # sums; the strict bar is taken from a common state: the graph run's state
+    # at step 10 loaded into a fresh graph-mode context, whose small store
+    # grows on loading, and the oracle, then one two-step graph replay.
+    W, p = g2.fields(), g2.particles()
+    g3 = _solver(w2, particle_capacity=5000)
+    g3.set_tuning(use_graph=1, batch_steps=2)
+    r3 = oracle.Oracle(w2)
+    r3.vol = r2.vol
+    for s in (g3, r3):
+        s.set_fields(W)
+        s.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"], p["ei"])
+        s.set_step(10)
+    g3.step(2)
+    r3.step(2)
+    e = compare(g3, r3, "two graph steps from the state at step 10", TOL)
+    print(f"graph, two steps from a common state: field error {e:.3e}")
 
 
 def _polygon_cases():
