@@ -818,15 +818,23 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
     m = s.m[k];
     const uint64_t pid = s.pid[k];
     const uint64_t seed = case_seed(g, p, case_of(g, cell));
-    // the cell's faces and neighbours, loaded together on entering a cell
-    F4 F[NV];
+    // the cell's face normals, offsets and neighbours, loaded together on
+    // entering a cell and again after a reflection (so that they are dead in
+    // the reflection code); a face's ratio is loaded when it is crossed
+    R Fx[NV], Fy[NV], Fz[NV];
     int nbr[NV];
     const double2 td = st.tdt[cell];
+    auto load_cell = [&](int c) {
 #pragma unroll
-    for (int kk = 0; kk < NV; ++kk) {
-      F[kk] = load_face<R>(g, static_cast<int64_t>(cell) * NV + kk);
-      nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
-    }
+      for (int kk = 0; kk < NV; ++kk) {
+        const F4 f = load_face<R>(g, static_cast<int64_t>(c) * NV + kk);
+        Fx[kk] = f.x;
+        Fy[kk] = f.y;
+        Fz[kk] = f.z;
+        nbr[kk] = g.lnb[static_cast<int64_t>(c) * NV + kk];
+      }
+    };
+    load_cell(cell);
     R t;
     if (k < n_ret) {
       double e0, e1;
@@ -846,10 +854,10 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       int kb = -1;
 #pragma unroll
       for (int kk = 0; kk < NV; ++kk) {
-        const R un = DIM == 2 ? u0 * F[kk].x + u1 * F[kk].y : u0 * F[kk].x;
+        const R un = DIM == 2 ? u0 * Fx[kk] + u1 * Fy[kk] : u0 * Fx[kk];
         if (un > R(0)) {
-          const R xn = DIM == 2 ? F[kk].x * x + F[kk].y * y : F[kk].x * x;
-          R te = (F[kk].z - xn) / un;
+          const R xn = DIM == 2 ? Fx[kk] * x + Fy[kk] * y : Fx[kk] * x;
+          R te = (Fz[kk] - xn) / un;
           if (te < R(0)) te = R(0);
           if (te < best) {
             best = te;
@@ -868,35 +876,32 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       }
       x = x + u0 * best;
       if (DIM == 2) y = y + u1 * best;
-      F4 f = F[0];
+      R fnx = Fx[0], fny = Fy[0];
       int nb = nbr[0];
 #pragma unroll
       for (int kk = 1; kk < NV; ++kk)
         if (kb == kk) {
-          f = F[kk];
+          fnx = Fx[kk];
+          fny = Fy[kk];
           nb = nbr[kk];
         }
       if (nb >= 0) {
+        const int64_t l = static_cast<int64_t>(cell) * NV + kb;
+        load_cell(nb);
         if constexpr (F32) {
           // remaining time scales in FP32, the mass with the FP64 ratio;
           // the position moves to the neighbour's anchor
-          const int64_t l = static_cast<int64_t>(cell) * NV + kb;
-          t = (t - best) * f.w;
+          t = (t - best) * g.lfn32[l].w;
           m = m * g.lfn[l].w;
           const float2 d = g.lda[l];
           x = x + d.x;
           if (DIM == 2) y = y + d.y;
         } else {
-          const double r = f.w;
+          const double r = g.lfn[l].w;
           t = (t - best) * r;
           m = m * r;
         }
         cell = nb;
-#pragma unroll
-        for (int kk = 0; kk < NV; ++kk) {
-          F[kk] = load_face<R>(g, static_cast<int64_t>(cell) * NV + kk);
-          nbr[kk] = g.lnb[static_cast<int64_t>(cell) * NV + kk];
-        }
         continue;
       }
       const int bf = -nb - 1;
@@ -909,13 +914,14 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       reflected = true;
       if (ty == kBcSymmetry) {
         if (DIM == 2) {
-          const R un = u0 * f.x + u1 * f.y;
-          const R n0 = u0 - R(2) * un * f.x, n1 = u1 - R(2) * un * f.y;
+          const R un = u0 * fnx + u1 * fny;
+          const R n0 = u0 - R(2) * un * fnx, n1 = u1 - R(2) * un * fny;
           u0 = n0;
           u1 = n1;
         } else {
           u0 = -u0;
         }
+        load_cell(cell);
         continue;
       }
       const double Tw = g.bdata[8 * bf];
@@ -928,8 +934,8 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
         // specular part of a Maxwell wall; the impulse goes to the wall
         const double b0 = u0, b1 = u1;
         if (DIM == 2) {
-          const R un = u0 * f.x + u1 * f.y;
-          const R n0 = u0 - R(2) * un * f.x, n1 = u1 - R(2) * un * f.y;
+          const R un = u0 * fnx + u1 * fny;
+          const R n0 = u0 - R(2) * un * fnx, n1 = u1 - R(2) * un * fny;
           u0 = n0;
           u1 = n1;
         } else {
@@ -938,12 +944,13 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
         const double c0 = u0, c1 = u1;
         atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
         atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
+        load_cell(cell);
         continue;
       }
       const double vn = sqrt(-2.0 * p.R * Tw * log(e0));
       box_muller(e1, e2, z0, z1);
       const double b0 = u0, b1 = u1, b2 = u2;
-      const double fx = f.x, fy = f.y;
+      const double fx = fnx, fy = fny;
       double a0, a1, a2;
       if (DIM == 2) {
         const double vt = sw * z0;
@@ -976,6 +983,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       } else {
         atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
       }
+      load_cell(cell);
     }
     s.x[k] = x;
     if (DIM == 2) s.y[k] = y;
@@ -1022,13 +1030,15 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
   }
 }
 
-// Three wavefronts per SIMD give the triangle and quad kernels up to 168
-// VGPRs, enough to hold a cell's faces without spilling (with four, 128
-// VGPRs spill; measured slower); polygons with more faces hold more face
+// The tracking is bound by the latency of its dependent loads, so occupancy
+// pays: the triangle and quad kernels run four wavefronts per SIMD (up to
+// 128 VGPRs) without spilling because only a cell's normals, offsets and
+// neighbours stay in registers, and not across the reflection code (a face's
+// ratio is loaded when it is crossed); polygons with more faces hold more face
 // data per lane, and particles with internal energy more state, and get up
 // to 256.
 template <int DIM, int NV, class R, int FEAT>
-__global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 3 : 2)
+__global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 2)
     k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];
