@@ -7,8 +7,9 @@
  * notation; the cited equation numbers are the paper's.  Where the paper is
  * silent the reading used is stated at the function.  Parity unpinned: the
  * readings for reconstruction (MUSCL, van Leer), the equilibrium slope, the
- * upwind g0^h, boundary conditions and the Shakhov acceptance-rejection are
- * checked only through the invariant/limit pins and against the GPU path.
+ * upwind g0^h and boundary conditions are checked only through the
+ * invariant/limit pins and against the GPU path; the Shakhov
+ * acceptance-rejection is pinned statistically by the heat flux it must give.
  */
 #include "ugkwp_oracle.h"
 

@@ -540,3 +540,54 @@ def test_gas_at_rest_presses_its_own_pressure_on_diffuse_walls():
     for col in (3, 4, 5):
         mean = np.sum(surf[:, col] * L) / np.sum(L)
         assert abs(mean) < 0.05, (col, mean)
+
+
+def test_shakhov_sampling_carries_the_target_heat_flux():
+    """Eq. (4) with the heat flux of Eq. (5): the Shakhov target
+    f_M [1 + (1 - Pr) c.Q (c^2/RT - 5) / (5 p R T)] of density rho_s has the
+    heat flux (1 - Pr) Q rho_s / rho (Gaussian moments <c_x^2 c^2> = 5 (RT)^2
+    and <c_x^2 c^4> = 35 (RT)^3), its mass, momentum and energy are those of
+    f_M.  The middle cell of a closed 1D box holds retained particles with a
+    skewed velocity set of known Q (zero mean, the cell's temperature), so
+    W^h keeps the cell's U and T; the set drawn there by acceptance-rejection
+    must show that heat flux within four standard errors.  A flipped sign,
+    Pr in place of (1 - Pr), or Q tallied from the wrong velocity component
+    are eight or more standard errors away.  The polynomial's constant 5,
+    which keeps the factor free of momentum, cannot be seen here: with
+    another constant the factor adds a mean velocity of order (5 - k) Q,
+    the moment matching of the drawn set (R10) removes it, and the third
+    moments about the mean then come out the same to first order."""
+    Pr = 2.0 / 3.0
+    # Delta t = 0.8 / (2 * 3) and tau = mu / p = 13.3: about 1 % of the
+    # hydrodynamic part collides, so nearly half the cell is redrawn
+    m = wl.uniform1d([0.0, 1.0, 2.0, 3.0], rho=1.0, U=0.0, T=1.0, bc=wl.BC_SYMMETRY, mu_ref=13.3, Pr=Pr,
+                     n_ref=400000, seed=3)
+    o = oracle.Oracle(m)
+    rng = np.random.default_rng(17)
+    n = 20000
+    z = rng.standard_normal((n, 3))
+    c = z.copy()
+    c[:, 0] = z[:, 0] + 0.15 * (z[:, 0] ** 2 - 1.0)
+    c -= c.mean(axis=0)
+    mass = np.full(n, 0.5 / n)  # half of the cell's unit mass
+    c *= np.sqrt(1.5 * 0.5 / np.sum(mass * 0.5 * np.sum(c * c, axis=1)))
+    Q = np.sum(mass * c[:, 0] * 0.5 * np.sum(c * c, axis=1))  # per unit volume (Omega = 1)
+    assert Q > 0.15
+    pid = (1 << 44) | (1 << 20) | np.arange(n, dtype=np.int64)
+    o.set_particles(pid, np.ones(n, dtype=np.int32), mass, 1.0 + rng.random((n, 1)), c)
+    o.set_step(5)
+    o.step(1)
+    p = o.particles()
+    born = ((p["pid"] >> 44) == 5) & (((p["pid"] >> 20) & ((1 << 24) - 1)) == 1)
+    mb, ub = p["m"][born], p["u"][born]
+    assert born.sum() > 150000
+    rho_s = mb.sum()
+    h = ub[:, 0] * 0.5 * np.sum(ub * ub, axis=1)
+    q = np.sum(mb * h)
+    se = np.sqrt(np.sum(mb ** 2 * (h - q / rho_s) ** 2))
+    expect = (1.0 - Pr) * Q * rho_s / 1.0
+    assert abs(q - expect) < 4.0 * se, (q, expect, se)
+    assert abs(expect) > 8.0 * se
+    # the factor moves neither mass, momentum nor energy: the drawn set's
+    # velocities average to the cell's U = 0 and carry 3 R T / 2 per unit mass
+    assert abs(np.sum(mb * ub[:, 0])) < 1e-12 and abs(np.sum(mb * 0.5 * np.sum(ub * ub, axis=1)) / rho_s - 1.5) < 1e-12
