@@ -541,6 +541,71 @@ def cmd_eval(a):
             json.dump(out, f, indent=1)
 
 
+def _march(s, target, max_steps, chunk, tag):
+    """step_until in chunks with a progress line per chunk; returns
+    (converged, steps, seconds)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv, n = False, 0
+    while not conv and n < max_steps:
+        conv, n = s.step_until(target, min(chunk, max_steps - n))
+        print(f"    {tag}: step {n} r_avg {s.residual()[1]:.3e} {time.perf_counter() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    return conv, int(n), time.perf_counter() - t0
+
+
+def cmd_batched(a):
+    """Time to residual of several held-out cases: each case alone in plain
+    FP64 from the free stream (leg "f64"), against all of them in one batched
+    solve in the chosen precision from their warm starts (leg "batch-warm",
+    the warm starts' time included) or from the free stream ("batch-free").
+    A batch stops at the first step at which every case's r_avg is below the
+    target; a single case at its own."""
+    use_own_stream()
+    cases = [tuple(c) for c in draws(a.n_test, 4)[: a.n_cases]]
+    wls = [fine_case(Ma, Kn, Tw, n_ref=a.n_ref, seed=1) for (Ma, Kn, Tw) in cases]
+    out = dict(cases=[dict(Ma=Ma, Kn=Kn, Tw=Tw) for (Ma, Kn, Tw) in cases], n_ref=a.n_ref, target=a.target)
+    for leg in a.legs.split(","):
+        if leg == "f64":
+            per = []
+            for (Ma, Kn, Tw), wl in zip(cases, wls):
+                s = Solver(wl, stream=_stream().value)
+                try:
+                    conv, n, dt = _march(s, a.target, a.max_steps, a.chunk, f"f64 Ma {Ma:.2f}")
+                finally:
+                    s.close()
+                per.append(dict(converged=conv, steps=n, seconds=dt))
+            out[leg] = dict(precision="f64", start="free stream", cases=per,
+                            seconds=sum(r["seconds"] for r in per), converged=all(r["converged"] for r in per))
+        elif leg in ("batch-warm", "batch-free"):
+            tws = 0.0
+            batch = []
+            mlp = MLP.load(a.weights) if leg == "batch-warm" else None
+            for (Ma, Kn, Tw), wl in zip(cases, wls):
+                w = dict(wl)
+                if leg == "batch-warm":
+                    W0, info = warm_start(Ma, Kn, Tw, mlp, wl)
+                    w["W0"] = W0
+                    tws += info["seconds"]
+                batch.append(w)
+            s = Solver.batch(batch, stream=_stream().value, precision=a.precision)
+            try:
+                conv, n, dt = _march(s, a.target, a.max_steps, a.chunk, leg)
+                r_avg = [s.case_residual(k)[1] for k in range(len(batch))]
+            finally:
+                s.close()
+            out[leg] = dict(precision=a.precision, start="warm start" if leg == "batch-warm" else "free stream",
+                            converged=conv, steps=n, seconds=dt + tws, march_seconds=dt, warm_start_seconds=tws,
+                            case_r_avg=r_avg)
+        else:
+            raise SystemExit(f"unknown leg {leg}")
+        print(json.dumps({leg: out[leg]}), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2607_09552_amd.warmstart")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -577,9 +642,20 @@ def main(argv=None):
     e.add_argument("--reference", default="",
                    help="N0,N1: compare the wall means with a plain FP64 run's mean over steps N0..N1")
     e.add_argument("--out", default="")
+    b = sub.add_parser("batched", help="time to residual: cases alone in FP64 against one batched solve")
+    b.add_argument("--weights", default=WEIGHTS)
+    b.add_argument("--n-test", type=int, default=16)
+    b.add_argument("--n-cases", type=int, default=4)
+    b.add_argument("--n-ref", type=int, default=400)
+    b.add_argument("--precision", default="mixed")
+    b.add_argument("--legs", default="f64,batch-warm")
+    b.add_argument("--target", type=float, default=1e-6)
+    b.add_argument("--max-steps", type=int, default=200000)
+    b.add_argument("--chunk", type=int, default=10000)
+    b.add_argument("--out", default="")
     a = ap.parse_args(argv)
     sys.path.insert(0, ROOT)
-    {"data": cmd_data, "train": cmd_train, "eval": cmd_eval}[a.cmd](a)
+    {"data": cmd_data, "train": cmd_train, "eval": cmd_eval, "batched": cmd_batched}[a.cmd](a)
 
 
 if __name__ == "__main__":
