@@ -326,3 +326,45 @@ def test_fused_forward_matches_layers_and_reference():
     assert L.ugkwp_mlp_forward(vp(xb), M, 4, wd, wp, bp, vp(Y), None) == -1
     wd[2] = 256
     assert L.ugkwp_mlp_forward(vp(xb), M - 1, 4, wd, wp, bp, vp(Y), None) == -1
+
+
+def test_warm_start_end_to_end_and_batched_command(tmp_path):
+    """The whole warm start (coarse wave-particle solve, features, fused
+    network, decode) gives a valid fine field with a hot shock layer
+    (stagnation temperature T_0 = T_inf (1 + Ma^2/3) = 76 at Ma 15) and a
+    cold leeward side, which the fine solver takes as its initial state; the
+    batched time-to-residual command runs both legs on two held-out cases
+    (shortened) and reports every case."""
+    import torch
+    from paper_2607_09552_amd import warmstart as ws
+    ws.use_own_stream()
+    try:
+        _warm_start_checks(ws, tmp_path)
+    finally:
+        torch.cuda.synchronize()
+        torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def _warm_start_checks(ws, tmp_path):
+    import json
+    from paper_2607_09552_amd import Solver
+    wl = ws.fine_case(15.0, 0.01, 0.2, n_ref=20)
+    W0, info = ws.warm_start(15.0, 0.01, 0.2, wl=wl)
+    nf = ws.FINE[0] * ws.FINE[1]
+    assert W0.shape == (nf, 4) and np.all(np.isfinite(W0))
+    rho = W0[:, 0]
+    T = (W0[:, 3] - 0.5 * (W0[:, 1] ** 2 + W0[:, 2] ** 2) / rho) / (1.5 * rho)
+    assert np.all(rho > 0) and np.all(T > 0)
+    assert T.max() > 20.0 and T.min() < 1.0, (T.min(), T.max())
+    assert info["seconds"] > info["coarse_seconds"] > 0
+    s = Solver(wl, W0=W0, precision="mixed")
+    s.step(20)
+    assert np.all(np.isfinite(s.fields())) and s.residual()[2] == 20
+    s.close()
+    out = tmp_path / "batched.json"
+    ws.main(["batched", "--n-cases", "2", "--n-ref", "20", "--max-steps", "120", "--chunk", "60",
+             "--legs", "f64,batch-warm", "--out", str(out)])
+    r = json.loads(out.read_text())
+    assert [c["steps"] for c in r["f64"]["cases"]] == [120, 120]
+    assert r["batch-warm"]["steps"] == 120 and len(r["batch-warm"]["case_r_avg"]) == 2
+    assert r["batch-warm"]["warm_start_seconds"] > 0 and np.all(np.isfinite(r["batch-warm"]["case_r_avg"]))
