@@ -591,3 +591,48 @@ def test_shakhov_sampling_carries_the_target_heat_flux():
     # the factor moves neither mass, momentum nor energy: the drawn set's
     # velocities average to the cell's U = 0 and carry 3 R T / 2 per unit mass
     assert abs(np.sum(mb * ub[:, 0])) < 1e-12 and abs(np.sum(mb * 0.5 * np.sum(ub * ub, axis=1)) / rho_s - 1.5) < 1e-12
+
+
+def test_diffuse_wall_reemission_follows_the_wall_maxwellian():
+    """R13 (Sec. V.A, diffuse wall): a particle that reaches the wall leaves
+    it from the point of impact with the flux-weighted wall Maxwellian at
+    T_w -- normal speed Rayleigh distributed, P(v_n < v) = 1 - exp(-v^2 /
+    (2 R T_w)), tangential and z components N(0, R T_w) -- and keeps its
+    remaining time and mass.  20 000 particles sent at the wall of a
+    collisionless 1D box: the normal speeds pass a Kolmogorov-Smirnov test
+    against that law (the gas temperature, the wrong normal law or the
+    wrong sign fail it), the other components have mean 0 and variance
+    R T_w within four standard errors, and every particle still in the wall
+    cell sits exactly at v_n (dt - t_hit) from the wall."""
+    from scipy import stats
+    Tw = 0.5
+    m = wl.uniform1d([0.0, 1.0, 2.0, 3.0], rho=1.0, U=0.0, T=1.0, bc=(wl.BC_WALL_DIFFUSE, wl.BC_SYMMETRY),
+                     left=[Tw], right=[0.0], mu_ref=1e3, n_ref=20, seed=5)
+    o = oracle.Oracle(m)
+    dt = o.dt()[0]
+    rng = np.random.default_rng(23)
+    n = 20000
+    x0 = 0.001 + 0.009 * rng.random(n)
+    u = np.stack([-50.0 - 50.0 * rng.random(n), np.full(n, 0.3), np.full(n, -0.2)], axis=1)
+    mass = np.full(n, 1e-6)
+    pid = (1 << 44) | np.arange(n, dtype=np.int64)
+    o.set_particles(pid, np.zeros(n, dtype=np.int32), mass, x0[:, None], u)
+    o.set_step(3)
+    o.step(1)
+    p = o.particles()
+    mine = (p["pid"] >> 44) == 1
+    assert mine.sum() > n - 20  # tau = 1000 dt: a handful collide and leave
+    k = p["pid"][mine] & ((1 << 20) - 1)
+    v, x, cell = p["u"][mine], p["x"][mine, 0], p["cell"][mine]
+    assert np.all(v[:, 0] > 0) and np.all(p["m"][mine] == 1e-6)
+    ks = stats.kstest(v[:, 0], lambda s: 1.0 - np.exp(-s * s / (2.0 * Tw)))
+    assert ks.pvalue > 1e-3, ks
+    assert stats.kstest(v[:, 0], lambda s: 1.0 - np.exp(-s * s / 2.0)).pvalue < 1e-6
+    for c in (1, 2):
+        se_mean, se_var = math.sqrt(Tw / len(v)), Tw * math.sqrt(2.0 / len(v))
+        assert abs(v[:, c].mean()) < 4 * se_mean and abs(v[:, c].var() - Tw) < 4 * se_var
+    inside = cell == 0
+    assert inside.sum() > 0.9 * len(x)
+    t_hit = x0[k] / -u[k, 0]
+    want = v[:, 0] * (dt - t_hit)
+    assert np.allclose(x[inside], want[inside], rtol=1e-12, atol=1e-15)
