@@ -7,10 +7,11 @@
  * notation; the cited equation numbers are the paper's.  Where the paper is
  * silent the reading used is stated at the function.  Parity unpinned: the
  * readings for reconstruction (MUSCL, van Leer), the equilibrium slope, the
- * upwind g0^h, the far-field ghost slab and the positivity guard are checked
- * only through the invariant/limit pins and against the GPU path; the Shakhov
- * acceptance-rejection and the diffuse wall's re-emission are pinned
- * statistically by the distributions they must give.
+ * upwind g0^h and the positivity guard are checked only through the
+ * invariant/limit pins and against the GPU path; the Shakhov
+ * acceptance-rejection, the diffuse wall's re-emission and the far-field
+ * ghost slab are pinned statistically by the distributions and fluxes they
+ * must give.
  */
 #include "ugkwp_oracle.h"
 

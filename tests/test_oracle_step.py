@@ -636,3 +636,40 @@ def test_diffuse_wall_reemission_follows_the_wall_maxwellian():
     t_hit = x0[k] / -u[k, 0]
     want = v[:, 0] * (dt - t_hit)
     assert np.allclose(x[inside], want[inside], rtol=1e-12, atol=1e-15)
+
+
+def test_farfield_ghost_slab_injects_the_one_sided_flux():
+    """R12: the far-field ghost slab (depth dt_i (U_in + 6 sqrt(R T_g)),
+    sampled at rho_g e^{-dt_i/tau_g}, each particle flying straight for dt_i)
+    must inject, in expectation, the one-sided Maxwellian mass flux through
+    the face in one step: rho^hp s dt [U_n Phi(U_n/sigma) + sigma phi(U_n/sigma)]
+    (sigma = sqrt(R T_g), U_n the inward normal velocity), whatever the
+    tangential velocity.  One far-field face on the left of a 3 x 1 box of
+    unit squares, the other faces specular, a collisionless gas: the mass of
+    the ghost-born particles inside after one step matches it within four
+    standard errors (a slab cut at dt_i U_in, a lost thermal term or an
+    outward normal are many errors away)."""
+    from scipy import stats
+    box = wl.box2d([0.0, 1.0, 2.0, 3.0], [0.0, 1.0], wl.BC_SYMMETRY)
+    m = wl.uniform2d(box, rho=1.0, ux=0.5, uy=0.2, T=1.0, mu_ref=1e3, n_ref=200000, seed=9)
+    left = [b for b in range(len(m["bface_type"]))
+            if np.all(m["nodes"][m["bface_nodes"][b], 0] == 0.0)]
+    assert len(left) == 1
+    m["bface_type"] = m["bface_type"].copy()
+    m["bface_data"] = m["bface_data"].copy()
+    m["bface_type"][left[0]] = wl.BC_FARFIELD
+    m["bface_data"][left[0], :4] = [1.0, 0.5, 0.2, 1.0]
+    o = oracle.Oracle(m)
+    dt = o.dt()[0]
+    o.step(1)
+    p = o.particles()
+    birth = (p["pid"] >> 20) & ((1 << 24) - 1)
+    ghost = birth >= m["n_cells"]
+    mg = p["m"][ghost]
+    assert len(mg) > 5000 and np.all(p["u"][ghost, 0] > 0)
+    tau = 1e3  # mu_ref (T/T_ref)^omega / p with T = p = 1
+    Un, sig = 0.5, 1.0
+    want = math.exp(-dt / tau) * 1.0 * dt * (Un * stats.norm.cdf(Un / sig) + sig * stats.norm.pdf(Un / sig))
+    se = math.sqrt(np.sum(mg ** 2))
+    assert abs(mg.sum() - want) < 4.0 * se, (mg.sum(), want, se)
+    assert want > 25.0 * se
