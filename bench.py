@@ -103,10 +103,12 @@ def time_to_residual(a):
     import numpy as np
     import torch
     from paper_2607_09552_amd import Solver
-    w = workload(a.kn)
+    w = workload(a.kn) if a.workload == "cylinder" else workloads.flat_plate(seed=1)
     w["dt_source"] = {"initial": 0, "freestream": 1}[a.dt_source]
     W0, ws_info = None, None
     if a.warm_start:
+        if a.workload != "cylinder":
+            raise SystemExit("--warm-start: the warm-start network is trained on the cylinder")
         from paper_2607_09552_amd import warmstart as ws
         mlp = ws.MLP.load()
         torch.cuda.synchronize()
@@ -129,13 +131,16 @@ def time_to_residual(a):
     surf, cd = s.surface(1)
     start = ("learned warm start (coarse 40x30 UGKWP solve, BF16 MLP 32-256-256-256-32)" if a.warm_start
              else "uniform freestream")
+    name = (f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, Tw/Tinf 0.2 diffuse, N_ref 400, "
+            f"LTS CFL 0.8, {a.precision}, Philox seed 1" if a.workload == "cylinder" else
+            f"flat plate 300x200, Ma 10, Kn 0.0169, VHS omega 0.74, Pr 1, Tw/Tinf 1 diffuse, N_ref 300, "
+            f"LTS CFL 0.8, {a.precision}, Philox seed 1")
     out = {"metric": f"time-to-residual {a.ttr_target:g}", "value": elapsed if conv else None, "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "steps": int(n), "converged": bool(conv),
            "elapsed_s": elapsed, "march_s": march, "warm_start_s": ws_info["seconds"] if ws_info else 0.0,
            "ms_per_step": march / max(n, 1) * 1e3, "r_avg": ra, "r_inst": ri,
            "dtype": a.precision, "data": "synthetic",
-           "config": {"workload": f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
-                                  f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, {a.precision}, Philox seed 1",
+           "config": {"workload": name,
                       "start": start, "dt_from": a.dt_source, "rule": "first n >= 100 with r_avg < target"},
            "wall": {"Cd_mean": cd, "Cp_max": float(np.max(surf[:, 3])), "CF_absmax": float(np.max(np.abs(surf[:, 4]))),
                     "CQ_max": float(np.max(surf[:, 5]))}}
