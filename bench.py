@@ -83,7 +83,9 @@ def cpu_baseline(w, state, steps):
 
 
 def copy_probe(gib=1.0, reps=5):
-    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    """A plain device copy of known size, for scaling rocprofv3 byte counters,
+    then the same copies timed with HIP events: the HBM bandwidth a plain
+    stream reaches (bytes read + written per second)."""
     import torch
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -91,7 +93,15 @@ def copy_probe(gib=1.0, reps=5):
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps}))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps, "ms_per_copy": ms,
+                      "copy_GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}))
 
 
 def time_to_residual(a):
