@@ -491,7 +491,7 @@ def cmd_eval(a):
     use_own_stream()
     mlp = MLP.load(a.weights)
     out = []
-    cases = [(a.ma, a.kn, a.tw)] if a.ma else [tuple(c) for c in draws(a.n_test, 4)[: a.n_cases]]
+    cases = [(a.ma, a.kn, a.tw)] if a.ma else [tuple(c) for c in draws(a.n_test, 4)[a.skip: a.skip + a.n_cases]]
     n0, n1 = (int(x) for x in a.reference.split(",")) if a.reference else (0, 0)
     for (Ma, Kn, Tw) in cases:
         wl = fine_case(Ma, Kn, Tw, n_ref=a.n_ref, seed=1)
@@ -634,6 +634,7 @@ def main(argv=None):
     e.add_argument("--tw", type=float, default=0.2)
     e.add_argument("--n-test", type=int, default=16)
     e.add_argument("--n-cases", type=int, default=2)
+    e.add_argument("--skip", type=int, default=0, help="start after the first SKIP held-out cases")
     e.add_argument("--n-ref", type=int, default=400)
     e.add_argument("--precision", default="mixed")
     e.add_argument("--starts", default="free,warm")
