@@ -18,13 +18,37 @@ SRC = os.path.join(HERE, "ugkwp_oracle.c")
 OK, EINVAL, ENOMEM, EOVERFLOW, ENUMERIC = 0, -1, -2, -4, -5
 
 
-def build(quiet: bool = True) -> str:
-    """Compile the oracle with gcc: serial, FP64, no contraction, no fast-math."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-fPIC", "-shared",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+def build(quiet: bool = True, sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the oracle with gcc: serial, FP64, no contraction, no fast-math.
+
+    sanitize=True adds AddressSanitizer and UndefinedBehaviorSanitizer
+    (-fsanitize=address,undefined, frame pointers kept); such a build must be
+    loaded into a process started with the sanitizer runtimes preloaded
+    (LD_PRELOAD of libasan and libubsan, see sanitizer_env()).  `out` names
+    the library to write (default: the one lib() loads)."""
+    target = out or LIB
+    flags = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-fPIC", "-shared"]
+    if sanitize:
+        flags += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+    cmd = ["gcc", *flags, "-o", target + ".tmp", SRC, "-lm"]
     subprocess.run(cmd, check=True, capture_output=quiet)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(target + ".tmp", target)
+    return target
+
+
+def sanitizer_env() -> dict:
+    """Environment for a child process that loads a sanitize=True build:
+    LD_PRELOAD of gcc's ASan and UBSan runtimes, leak checking off (the
+    Python interpreter itself is not leak-clean), and the build's path in
+    UGKWP_ORACLE_LIB so that lib() loads it."""
+    def runtime(name):
+        r = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True, text=True, check=True)
+        return r.stdout.strip()
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = ":".join([runtime("libasan.so"), runtime("libubsan.so")])
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    return env
 
 
 class _Mesh(C.Structure):
@@ -58,9 +82,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("UGKWP_ORACLE_LIB", LIB)
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         dp, ip64, ip32, up64 = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)
         L.ref_init.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.POINTER(C.c_void_p)]
         L.ref_step.argtypes = [C.c_void_p, C.c_int32]
@@ -94,6 +119,18 @@ def lib():
         L.ref_flux_wall.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, dp]
         L.ref_track_one.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, dp, dp, dp, C.c_double,
                                     ip32, ip32]
+        L.ref_exact_sum.argtypes = [dp, C.c_int64]
+        L.ref_exact_sum.restype = C.c_double
+        L.ref_reconstruct.argtypes = [dp, C.c_double, dp, C.c_double, dp, C.c_double, C.c_int, dp, dp]
+        L.ref_reconstruct.restype = None
+        L.ref_face_values.argtypes = [C.c_void_p, C.c_int64, dp, dp, dp, dp, dp]
+        L.ref_face_geom.argtypes = [C.c_void_p, C.c_int64, dp]
+        L.ref_vacuum_guard.argtypes = [C.c_void_p, dp, C.c_double, dp]
+        L.ref_sample_deviation.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, dp, C.c_double, dp, dp]
+        L.ref_n_capped.argtypes = [C.c_void_p]
+        L.ref_n_capped.restype = C.c_int64
+        L.ref_get_history.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp]
+        L.ref_set_history.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -149,6 +186,19 @@ def flux_interior(WL, WR, dW0, WhL, WhR, dWhL, dWhR, dtL, tauL, dtR, tauR, K=1, 
     lib().ref_flux_interior(_p(WL), _p(WR), _p(dW0), _p(WhL), _p(WhR), _p(dWhL), _p(dWhR), dtL, tauL, dtR,
                             tauR, K, Pr, wave_only, _p(Feq), _p(Ffr))
     return Feq, Ffr
+
+
+def exact_sum(x):
+    x = _f64(x)
+    return lib().ref_exact_sum(_p(x), len(x))
+
+
+def reconstruct(Wfar, xfar, Wself, xself, Wother, xother, K=1):
+    Wfar = None if Wfar is None else _f64(Wfar)
+    Wself, Wother = _f64(Wself), _f64(Wother)
+    out, slope = np.zeros(4), np.zeros(4)
+    lib().ref_reconstruct(_p(Wfar), xfar, _p(Wself), xself, _p(Wother), xother, K, _p(out), _p(slope))
+    return out, slope
 
 
 def flux_wall(W, Wh, dt, tau, Tw, R=1.0, K=1, wave_only=0):
@@ -283,6 +333,51 @@ class Oracle:
         Sp = np.zeros((self.nc, self.nw))
         lib().ref_get_tally(self.h, _p(Sm), _p(Sp))
         return Sm, Sp
+
+    def face_values(self, fi):
+        """(W_L, W_R, slope_L, slope_R, dW0) of interior face fi, face frame."""
+        out = [np.zeros(4) for _ in range(5)]
+        self._check(lib().ref_face_values(self.h, fi, *[_p(a) for a in out]))
+        return out
+
+    def face_geom(self, fi):
+        """dict(L, R, LL, RR, mid=(x, y), n=(nx, ny)) of face fi."""
+        g = np.zeros(8)
+        self._check(lib().ref_face_geom(self.h, fi, _p(g)))
+        return dict(L=int(g[0]), R=int(g[1]), LL=int(g[2]), RR=int(g[3]), mid=g[4:6].copy(), n=g[6:8].copy())
+
+    def vacuum_guard(self, Sp, vol, Wn):
+        Sp, Wn = _f64(Sp), _f64(Wn).copy()
+        fired = lib().ref_vacuum_guard(self.h, _p(Sp), vol, _p(Wn))
+        return bool(fired), Wn
+
+    def sample_deviation(self, pid, step, Uh, Th, shak=None):
+        Uh = _f64(Uh)
+        shak = None if shak is None else _f64(shak)
+        z = np.zeros(3)
+        capped = lib().ref_sample_deviation(self.h, pid, step, _p(Uh), Th, _p(shak), _p(z))
+        return z, bool(capped)
+
+    def n_capped(self):
+        return int(lib().ref_n_capped(self.h))
+
+    def n_wall(self):
+        nw = C.c_int64()
+        lib().ref_surface(self.h, 0, None, 0, C.byref(nw), None)
+        return nw.value
+
+    def history(self):
+        nwl = self.n_wall()
+        h = dict(rho_prev=np.zeros(self.nc), rho_sum=np.zeros(self.nc), rho_mean_prev=np.zeros(self.nc),
+                 wlast=np.zeros(3 * nwl), wsum=np.zeros(3 * nwl), wema=np.zeros(3 * nwl), cd=np.zeros(3))
+        lib().ref_get_history(self.h, *[_p(h[k]) for k in ("rho_prev", "rho_sum", "rho_mean_prev", "wlast", "wsum",
+                                                               "wema", "cd")])
+        return h
+
+    def set_history(self, h):
+        keys = ("rho_prev", "rho_sum", "rho_mean_prev", "wlast", "wsum", "wema", "cd")
+        arrs = [None if h.get(k) is None else _f64(h[k]) for k in keys]
+        lib().ref_set_history(self.h, *[_p(a) for a in arrs])
 
     def face_flux(self):
         F = np.zeros((self.nf, self.nw))

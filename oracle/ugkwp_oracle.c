@@ -43,6 +43,15 @@ static int is_wall(int32_t ty) { return ty == REF_BC_WALL || ty == REF_BC_WALL_M
  * WALL_INTERNAL_CALL0 + h ceil(D/2) + j; birth uses calls j */
 #define WALL_INTERNAL_CALL0 256u
 
+/* accumulator of an exactly rounded sum (see xs_add) */
+typedef struct {
+  int n, cap;
+  double *p;      /* partials, increasing magnitude */
+  double inl[6];  /* inline storage for the first partials */
+  int nonfinite;  /* a term was inf or nan: the result is their plain sum */
+  double naive;
+} xsum;
+
 static const double TWO_PI = 6.283185307179586;
 static const double PI = 3.141592653589793;
 
@@ -88,6 +97,8 @@ struct ref_ctx {
   int64_t nwall;
   int64_t *wall_b;                 /* boundary face id of each wall face */
   double *wimp;                    /* per boundary face: particle impulse x,y and energy */
+  xsum *xwimp;                     /* their exact sums during a step */
+  int64_t n_capped;                /* Shakhov draws that took the 64-attempt fallback (last step) */
   double *wsurf_last, *wsurf_sum, *wsurf_ema; /* per wall face: p, tau, q */
   double cd_last, cd_sum, cd_ema;
   char err[256];
@@ -101,6 +112,112 @@ static int fail(ref_ctx *c, int code, const char *fmt, ...) {
     va_end(ap);
   }
   return code;
+}
+
+/* ======================================================================== */
+/* Exactly rounded sums                                                      */
+/* ======================================================================== */
+
+/* The tallies of Eqs. (24), (29)-(30) and the other sums over particles are
+ * plain sums; the oracle takes the FP64 value nearest to the exact sum (ties
+ * to even), so that the result does not depend on the order of the terms.
+ * Method: Shewchuk, "Adaptive precision floating-point arithmetic and fast
+ * robust geometric predicates" (1997): the running sum is kept exactly as a
+ * list of nonoverlapping partials of increasing magnitude, each new term is
+ * merged by error-free two-sums; the final rounding adds the partials from
+ * the top and settles an exact half-way case by the sign of the next
+ * partial below. */
+
+static void xs_init(xsum *s) {
+  s->n = 0;
+  s->cap = 6;
+  s->p = s->inl;
+  s->nonfinite = 0;
+  s->naive = 0.0;
+}
+
+static void xs_free(xsum *s) {
+  if (s->p != s->inl) free(s->p);
+  xs_init(s);
+}
+
+static void xs_add(xsum *s, double x) {
+  if (!isfinite(x) || s->nonfinite) {
+    if (!s->nonfinite) {
+      s->naive = 0.0;
+      for (int j = 0; j < s->n; ++j) s->naive += s->p[j];
+    }
+    s->nonfinite = 1;
+    s->naive += x;
+    return;
+  }
+  int i = 0;
+  for (int j = 0; j < s->n; ++j) {
+    double y = s->p[j];
+    if (fabs(x) < fabs(y)) {
+      double t = x;
+      x = y;
+      y = t;
+    }
+    double hi = x + y;
+    double lo = y - (hi - x);
+    if (lo != 0.0) s->p[i++] = lo;
+    x = hi;
+  }
+  if (i == s->cap) {
+    int ncap = 2 * s->cap;
+    double *q = malloc(sizeof(double) * (size_t)ncap);
+    if (!q) abort();
+    memcpy(q, s->p, sizeof(double) * (size_t)i);
+    if (s->p != s->inl) free(s->p);
+    s->p = q;
+    s->cap = ncap;
+  }
+  s->p[i++] = x;
+  s->n = i;
+}
+
+static double xs_round(const xsum *s) {
+  if (s->nonfinite) return s->naive;
+  int n = s->n;
+  if (n == 0) return 0.0;
+  double hi = s->p[--n], lo = 0.0;
+  while (n > 0) {
+    double x = hi, y = s->p[--n];
+    hi = x + y;
+    double yr = hi - x;
+    lo = y - yr;
+    if (lo != 0.0) break;
+  }
+  if (n > 0 && ((lo < 0.0 && s->p[n - 1] < 0.0) || (lo > 0.0 && s->p[n - 1] > 0.0))) {
+    double y = lo * 2.0;
+    double x = hi + y;
+    double yr = x - hi;
+    if (y == yr) hi = x;
+  }
+  return hi;
+}
+
+/* n accumulators in one block */
+static xsum *xs_array(int64_t n) {
+  xsum *a = calloc((size_t)(n ? n : 1), sizeof(xsum));
+  if (!a) abort();
+  for (int64_t k = 0; k < n; ++k) xs_init(&a[k]);
+  return a;
+}
+
+static void xs_array_free(xsum *a, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) xs_free(&a[k]);
+  free(a);
+}
+
+double ref_exact_sum(const double *x, int64_t n) {
+  xsum s;
+  xs_init(&s);
+  for (int64_t k = 0; k < n; ++k) xs_add(&s, x[k]);
+  double r = xs_round(&s);
+  xs_free(&s);
+  return r;
 }
 
 /* ======================================================================== */
@@ -750,6 +867,7 @@ int ref_init(const ref_mesh *m, const ref_params *par, const double *W0, ref_ctx
   c->Fs = xcalloc((size_t)(c->nf * nw), sizeof(double));
   c->count = xcalloc((size_t)nc, sizeof(int32_t));
   c->wimp = xcalloc((size_t)c->nb * 3, sizeof(double));
+  c->xwimp = xs_array(c->nb * 3);
   for (int64_t b = 0; b < c->nb; ++b) if (is_wall(c->btype[b])) c->nwall++;
   c->wall_b = xcalloc((size_t)c->nwall, sizeof(int64_t));
   c->wsurf_last = xcalloc((size_t)c->nwall * 3, sizeof(double));
@@ -796,6 +914,7 @@ void ref_free(ref_ctx *c) {
                   c->dt, c->ratio, c->rho_prev, c->rho_sum, c->rho_mean_prev, c->P, c->Sm, c->Sp,
                   c->Fs, c->count, c->wall_b, c->wimp, c->wsurf_last, c->wsurf_sum, c->wsurf_ema};
   for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; ++k) free(ptrs[k]);
+  if (c->xwimp) xs_array_free(c->xwimp, c->nb * 3);
   free(c);
 }
 
@@ -897,7 +1016,7 @@ static void gauss3(const ref_ctx *c, uint64_t pid, int64_t step, uint32_t purpos
  * acceptance-rejection against that Maxwellian: the correction factor uses the
  * cell's total U, T, p and the heat flux Q of Eq. (5) tallied from the
  * retained particles; deviations beyond 6 sqrt(R T^h) are rejected. */
-static void sample_deviation(const ref_ctx *c, uint64_t pid, int64_t step, const double Uh[2], double Th,
+static void sample_deviation(ref_ctx *c, uint64_t pid, int64_t step, const double Uh[2], double Th,
                              const double *shak /* NULL or {Ux, Uy, T, p, Qx, Qy} */, double z[3]) {
   if (!shak) {
     gauss3(c, pid, step, P_VEL, 0, z);
@@ -911,18 +1030,40 @@ static void sample_deviation(const ref_ctx *c, uint64_t pid, int64_t step, const
   double qn = sqrt(shak[4] * shak[4] + shak[5] * shak[5]);
   double w = cb * cb / RT - 5.0;
   double Bnd = 1.0 + (fabs(1.0 - c->p.Pr) * qn * cb * (w > 5.0 ? w : 5.0)) / (5.0 * shak[3] * RT);
+  /* Reading: at most 64 attempts.  If none is accepted, the particle takes
+   * the first attempt's draw that lies within c_max (so every sample is
+   * inside the truncated support of the target), or z = 0 if none does. */
+  int first_in = -1;
+  double zin[3] = {0.0, 0.0, 0.0};
   for (uint32_t att = 0; att < 64; ++att) {
     gauss3(c, pid, step, P_VEL, 2 * att, z);
     double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
     double ea, eb;
     draw2(c->p.seed, pid, step, P_SHAKHOV, att, &ea, &eb);
     if (dz > cmax) continue;
+    if (first_in < 0) {
+      first_in = (int)att;
+      for (int d = 0; d < 3; ++d) zin[d] = z[d];
+    }
     double cx = (Uh[0] + sig * z[0]) - shak[0], cy = (Uh[1] + sig * z[1]) - shak[1], cz = sig * z[2];
     double c2 = cx * cx + cy * cy + cz * cz;
     double cq = c->dim == 2 ? cx * shak[4] + cy * shak[5] : cx * shak[4];
     double phi = ((1.0 - c->p.Pr) * cq) / (5.0 * shak[3] * RT) * (c2 / RT - 5.0);
     if (ea * Bnd <= 1.0 + phi) return;
   }
+  c->n_capped++;
+  for (int d = 0; d < 3; ++d) z[d] = zin[d];
+}
+
+/* sample_deviation for test access; returns 1 if the 64-attempt fallback
+ * was taken */
+int ref_sample_deviation(ref_ctx *c, uint64_t pid, int64_t step, const double Uh[2], double Th, const double *shak,
+                         double z[3]) {
+  int64_t before = c->n_capped;
+  sample_deviation(c, pid, step, Uh, Th, shak, z);
+  int capped = c->n_capped != before;
+  c->n_capped = before;
+  return capped;
 }
 
 /* Tracking of one particle, Eq. (28) with crossing detection.
@@ -1011,8 +1152,8 @@ static int track(ref_ctx *c, particle *q, int64_t step, int32_t *ncross_out) {
       } else {
         q->u[0] = -q->u[0];
       }
-      c->wimp[3 * b + 0] += q->m * (ub[0] - q->u[0]);
-      c->wimp[3 * b + 1] += q->m * (ub[1] - q->u[1]);
+      xs_add(&c->xwimp[3 * b + 0], q->m * (ub[0] - q->u[0]));
+      xs_add(&c->xwimp[3 * b + 1], q->m * (ub[1] - q->u[1]));
       continue;
     }
     /* diffuse re-emission; internal energy from the wall temperature */
@@ -1035,9 +1176,9 @@ static int track(ref_ctx *c, particle *q, int64_t step, int32_t *ncross_out) {
     }
     double eb = 0.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
     double ea = 0.5 * (q->u[0] * q->u[0] + q->u[1] * q->u[1] + q->u[2] * q->u[2]);
-    c->wimp[3 * b + 0] += q->m * (ub[0] - q->u[0]);
-    c->wimp[3 * b + 1] += q->m * (ub[1] - q->u[1]);
-    c->wimp[3 * b + 2] += q->m * ((eb + eib) - (ea + q->ei));
+    xs_add(&c->xwimp[3 * b + 0], q->m * (ub[0] - q->u[0]));
+    xs_add(&c->xwimp[3 * b + 1], q->m * (ub[1] - q->u[1]));
+    xs_add(&c->xwimp[3 * b + 2], q->m * ((eb + eib) - (ea + q->ei)));
   }
 }
 
@@ -1121,6 +1262,92 @@ static void reconstruct(const double *Wfar, double xfar, const double *Wself, do
   }
 }
 
+/* Reading (the paper does not discuss positivity): an updated state Wn that
+ * is not a valid Maxwellian (a cell emptied into vacuum) is replaced by the
+ * content Sp / Omega of the particles that ended in the cell, Eq. (30), if
+ * that is a valid state, else by a vacuum floor state (rho = 1e-12 rho_inf
+ * at rest, T_inf).  Returns 1 if Wn was replaced. */
+int ref_vacuum_guard(const ref_ctx *c, const double *Sp, double vol, double *Wn) {
+  const int nw = c->nw;
+  if (prim_ok(prim(c, Wn))) return 0;
+  int ok = 0;
+  if (Sp[0] > 0.0) {
+    for (int q = 0; q < nw; ++q) Wn[q] = Sp[q] / vol;
+    ok = prim_ok(prim(c, Wn));
+  }
+  if (!ok) {
+    double rf = 1e-12 * c->p.rho_inf;
+    for (int q = 0; q < nw; ++q) Wn[q] = 0.0;
+    Wn[0] = rf;
+    Wn[nw - 1] = 0.5 * (double)c->N * rf * c->p.R * c->p.T_inf;
+  }
+  return 1;
+}
+
+/* Face values and slopes of one interior face fi (normal n from L to R) for
+ * the stored states of L, R and the cells LL, RR across their opposite faces
+ * (NULL if none): each side reconstructed by reconstruct(), and the
+ * equilibrium slope read as one central difference of the cell averages
+ * along n, dW0 = (W_R - W_L)/(xi_R - xi_L).  All in the face frame. */
+static void face_values(const ref_ctx *c, int64_t fi, const double *WLc, const double *WRc, const double *WLLc,
+                        const double *WRRc, double WLf[4], double WRf[4], double sl[4], double sr[4],
+                        double dW0[4]) {
+  const double n2[2] = {c->fn[2 * fi], c->fn[2 * fi + 1]};
+  int64_t L = c->fL[fi], R = c->fR[fi];
+  int64_t LL = opposite_cell(c, L, c->fkL[fi]);
+  int64_t RR = opposite_cell(c, R, c->fkR[fi]);
+  double xL = (c->cen[2 * L] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * L + 1] - c->fmid[2 * fi + 1]) * n2[1];
+  double xR = (c->cen[2 * R] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * R + 1] - c->fmid[2 * fi + 1]) * n2[1];
+  double wL[4], wR[4], wLL[4], wRR[4], xLL = 0, xRR = 0;
+  to_frame(c, WLc, n2, wL);
+  to_frame(c, WRc, n2, wR);
+  if (LL >= 0 && WLLc) {
+    to_frame(c, WLLc, n2, wLL);
+    xLL = (c->cen[2 * LL] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * LL + 1] - c->fmid[2 * fi + 1]) * n2[1];
+  }
+  if (RR >= 0 && WRRc) {
+    to_frame(c, WRRc, n2, wRR);
+    xRR = (c->cen[2 * RR] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * RR + 1] - c->fmid[2 * fi + 1]) * n2[1];
+  }
+  reconstruct(LL >= 0 && WLLc ? wLL : NULL, xLL, wL, xL, wR, xR, c->K, WLf, sl);
+  reconstruct(RR >= 0 && WRRc ? wRR : NULL, xRR, wR, xR, wL, xL, c->K, WRf, sr);
+  for (int q = 0; q < 4; ++q) dW0[q] = (wR[q] - wL[q]) / (xR - xL);
+}
+
+/* face_values of interior face fi from the current fields W (test access) */
+int ref_face_values(const ref_ctx *c, int64_t fi, double WLf[4], double WRf[4], double sl[4], double sr[4],
+                    double dW0[4]) {
+  if (fi < 0 || fi >= c->nf || c->fR[fi] < 0) return REF_EINVAL;
+  const int nw = c->nw;
+  int64_t L = c->fL[fi], R = c->fR[fi];
+  int64_t LL = opposite_cell(c, L, c->fkL[fi]);
+  int64_t RR = opposite_cell(c, R, c->fkR[fi]);
+  face_values(c, fi, c->W + L * nw, c->W + R * nw, LL >= 0 ? c->W + LL * nw : NULL, RR >= 0 ? c->W + RR * nw : NULL,
+              WLf, WRf, sl, sr, dW0);
+  return REF_OK;
+}
+
+/* geometry of face fi: out = {L, R (-(b+1) on the boundary), LL, RR (-1 if
+ * none), midpoint x, y, unit normal x, y (from L to R)} */
+int ref_face_geom(const ref_ctx *c, int64_t fi, double out[8]) {
+  if (fi < 0 || fi >= c->nf) return REF_EINVAL;
+  int64_t L = c->fL[fi], R = c->fR[fi];
+  out[0] = (double)L;
+  out[1] = (double)R;
+  out[2] = (double)opposite_cell(c, L, c->fkL[fi]);
+  out[3] = R >= 0 ? (double)opposite_cell(c, R, c->fkR[fi]) : -1.0;
+  out[4] = c->fmid[2 * fi];
+  out[5] = c->fmid[2 * fi + 1];
+  out[6] = c->fn[2 * fi];
+  out[7] = c->fn[2 * fi + 1];
+  return REF_OK;
+}
+
+void ref_reconstruct(const double *Wfar, double xfar, const double Wself[4], double xself, const double Wother[4],
+                     double xother, int K, double out[4], double slope[4]) {
+  reconstruct(Wfar, xfar, Wself, xself, Wother, xother, K, out, slope);
+}
+
 int ref_step(ref_ctx *c, int32_t n_steps) {
   if (!c) return REF_EINVAL;
   const int nw = c->nw, dim = c->dim, K = c->K;
@@ -1129,6 +1356,9 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
   cellstate *gs = xcalloc((size_t)nb, sizeof(cellstate));
   double *Qh = xcalloc((size_t)nc * 2, sizeof(double));
   double *Sret = xcalloc((size_t)(nc * nw), sizeof(double));
+  /* exact sums of the tallies W^p, W^{p,-}, W^{p,+} (times Omega) and of the
+   * retained particles' heat flux */
+  xsum *xret = xs_array(nc * nw), *xsm = xs_array(nc * nw), *xsp = xs_array(nc * nw), *xq = xs_array(nc * 2);
   int rc = REF_OK;
   for (int32_t it = 0; it < n_steps && rc == REF_OK; ++it) {
     const int64_t n = c->step;
@@ -1137,7 +1367,14 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
     memset(Sret, 0, sizeof(double) * (size_t)(nc * nw));
     memset(Qh, 0, sizeof(double) * (size_t)nc * 2);
     memset(c->wimp, 0, sizeof(double) * (size_t)nb * 3);
-    c->n_new = c->n_removed = c->n_exited = c->n_guard = 0;
+    for (int64_t k = 0; k < nc * nw; ++k) {
+      xs_free(&xret[k]);
+      xs_free(&xsm[k]);
+      xs_free(&xsp[k]);
+    }
+    for (int64_t k = 0; k < nc * 2; ++k) xs_free(&xq[k]);
+    for (int64_t k = 0; k < nb * 3; ++k) xs_free(&c->xwimp[k]);
+    c->n_new = c->n_removed = c->n_exited = c->n_guard = c->n_capped = 0;
 
     /* (1) cell state: tau = mu/p, x = dt/tau, E = e^{-x} (Sec. IV.B) */
     for (int64_t i = 0; i < nc; ++i) {
@@ -1156,15 +1393,17 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       particle *q = &c->P[k];
       double ps[4];
       psi_particle(c, q, ps);
-      for (int w = 0; w < nw; ++w) Sret[q->cell * nw + w] += ps[w];
+      for (int w = 0; w < nw; ++w) xs_add(&xret[q->cell * nw + w], ps[w]);
       if (c->p.Pr != 1.0) {
         prim_t s = prim(c, c->W + q->cell * nw);
         double cx = q->u[0] - s.ux, cy = q->u[1] - s.uy, cz = q->u[2];
         double h = 0.5 * (cx * cx + cy * cy + cz * cz) + q->ei;
-        Qh[2 * q->cell] += q->m * cx * h;
-        Qh[2 * q->cell + 1] += q->m * cy * h;
+        xs_add(&xq[2 * q->cell], q->m * cx * h);
+        xs_add(&xq[2 * q->cell + 1], q->m * cy * h);
       }
     }
+    for (int64_t k = 0; k < nc * nw; ++k) Sret[k] = xs_round(&xret[k]);
+    for (int64_t k = 0; k < nc * 2; ++k) Qh[k] = xs_round(&xq[k]);
     for (int64_t i = 0; i < nc; ++i) {
       for (int w = 0; w < nw; ++w) cs[i].Wh[w] = cs[i].W[w] - Sret[i * nw + w] / c->vol[i];
       prim_t h = prim(c, cs[i].Wh);
@@ -1262,7 +1501,9 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
        * scaled so that the set carries exactly the momentum and the thermal
        * energy (3 R T^h / 2 per unit mass) of W^hp. */
       int64_t first = c->np;
-      double zs[3] = {0.0, 0.0, 0.0}, es = 0.0;
+      xsum zs[3], es;
+      for (int d = 0; d < 3; ++d) xs_init(&zs[d]);
+      xs_init(&es);
       for (int64_t j = 0; j < N; ++j) {
         particle q;
         memset(&q, 0, sizeof q);
@@ -1273,10 +1514,10 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         q.t = c->dt[i];
         sample_position(c, i, q.pid, n, q.x);
         sample_deviation(c, q.pid, n, Uh, h.T, sp, q.u);
-        for (int d = 0; d < 3; ++d) zs[d] += q.u[d];
+        for (int d = 0; d < 3; ++d) xs_add(&zs[d], q.u[d]);
         if (c->p.D > 0) {
           q.ei = internal_eta(c, q.pid, n, 0);
-          es += q.ei;
+          xs_add(&es, q.ei);
         }
         if ((rc = push_particle(c, &q))) break;
         c->n_new++;
@@ -1285,16 +1526,24 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       double sig = sqrt(c->p.R * h.T);
       double zm[3] = {0.0, 0.0, 0.0}, alpha = 1.0;
       if (N >= 2) {
-        double S = 0.0;
-        for (int d = 0; d < 3; ++d) zm[d] = zs[d] / (double)N;
-        for (int64_t k = first; k < c->np; ++k)
-          for (int d = 0; d < 3; ++d) S += (c->P[k].u[d] - zm[d]) * (c->P[k].u[d] - zm[d]);
-        alpha = sqrt((3.0 * (double)N) / S);
+        /* S = sum_k |z_k - zbar|^2, each particle's squared norm rounded
+         * once, the sum exact */
+        xsum S;
+        xs_init(&S);
+        for (int d = 0; d < 3; ++d) zm[d] = xs_round(&zs[d]) / (double)N;
+        for (int64_t k = first; k < c->np; ++k) {
+          double a0 = c->P[k].u[0] - zm[0], a1 = c->P[k].u[1] - zm[1], a2 = c->P[k].u[2] - zm[2];
+          xs_add(&S, (a0 * a0 + a1 * a1) + a2 * a2);
+        }
+        alpha = sqrt((3.0 * (double)N) / xs_round(&S));
+        xs_free(&S);
       }
       /* the internal energies are scaled the same way to carry exactly
        * D R T^h / 2 per unit mass */
       double beta = 1.0;
-      if (N >= 2 && c->p.D > 0) beta = (0.5 * (double)c->p.D * (double)N) / es;
+      if (N >= 2 && c->p.D > 0) beta = (0.5 * (double)c->p.D * (double)N) / xs_round(&es);
+      for (int d = 0; d < 3; ++d) xs_free(&zs[d]);
+      xs_free(&es);
       for (int64_t k = first; k < c->np; ++k) {
         double *u = c->P[k].u;
         double w0 = (u[0] - zm[0]) * alpha, w1 = (u[1] - zm[1]) * alpha, w2 = (u[2] - zm[2]) * alpha;
@@ -1382,8 +1631,9 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       if (q->flags & F_GHOST) continue;
       double ps[4];
       psi_particle(c, q, ps);
-      for (int w = 0; w < nw; ++w) c->Sm[q->cell * nw + w] += ps[w];
+      for (int w = 0; w < nw; ++w) xs_add(&xsm[q->cell * nw + w], ps[w]);
     }
+    for (int64_t k = 0; k < nc * nw; ++k) c->Sm[k] = xs_round(&xsm[k]);
     /* (6) free transport with crossing scaling. */
     for (int64_t k = 0; k < c->np; ++k) {
       int r = track(c, &c->P[k], n, NULL);
@@ -1398,10 +1648,12 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
       if (q->flags & F_EXIT) { c->n_exited++; continue; }
       double ps[4];
       psi_particle(c, q, ps);
-      for (int w = 0; w < nw; ++w) c->Sp[q->cell * nw + w] += ps[w];
+      for (int w = 0; w < nw; ++w) xs_add(&xsp[q->cell * nw + w], ps[w]);
       if (q->flags & F_COLLIDE) { c->n_removed++; continue; }
       c->P[keep++] = *q;
     }
+    for (int64_t k = 0; k < nc * nw; ++k) c->Sp[k] = xs_round(&xsp[k]);
+    for (int64_t k = 0; k < nb * 3; ++k) c->wimp[k] = xs_round(&c->xwimp[k]);
     c->np = keep;
     qsort(c->P, (size_t)c->np, sizeof(particle), cmp_cell_pid);
     memset(c->count, 0, sizeof(int32_t) * (size_t)nc);
@@ -1417,26 +1669,21 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         double xR = (c->cen[2 * R] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * R + 1] - c->fmid[2 * fi + 1]) * n2[1];
         int64_t LL = opposite_cell(c, L, c->fkL[fi]);
         int64_t RR = opposite_cell(c, R, c->fkR[fi]);
-        double wL[4], wR[4], wLL[4], wRR[4], hL[4], hR[4], hLL[4], hRR[4];
+        double hL[4], hR[4], hLL[4], hRR[4];
         double xLL = 0, xRR = 0;
-        to_frame(c, cs[L].W, n2, wL);
-        to_frame(c, cs[R].W, n2, wR);
         to_frame(c, cs[L].Wh, n2, hL);
         to_frame(c, cs[R].Wh, n2, hR);
         if (LL >= 0) {
-          to_frame(c, cs[LL].W, n2, wLL);
           to_frame(c, cs[LL].Wh, n2, hLL);
           xLL = (c->cen[2 * LL] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * LL + 1] - c->fmid[2 * fi + 1]) * n2[1];
         }
         if (RR >= 0) {
-          to_frame(c, cs[RR].W, n2, wRR);
           to_frame(c, cs[RR].Wh, n2, hRR);
           xRR = (c->cen[2 * RR] - c->fmid[2 * fi]) * n2[0] + (c->cen[2 * RR + 1] - c->fmid[2 * fi + 1]) * n2[1];
         }
         double WLf[4], WRf[4], sl[4], sr[4], dW0[4];
-        reconstruct(LL >= 0 ? wLL : NULL, xLL, wL, xL, wR, xR, K, WLf, sl);
-        reconstruct(RR >= 0 ? wRR : NULL, xRR, wR, xR, wL, xL, K, WRf, sr);
-        for (int q = 0; q < 4; ++q) dW0[q] = (wR[q] - wL[q]) / (xR - xL);
+        face_values(c, fi, cs[L].W, cs[R].W, LL >= 0 ? cs[LL].W : NULL, RR >= 0 ? cs[RR].W : NULL, WLf, WRf, sl, sr,
+                    dW0);
         double HLf[4], HRf[4], shl[4], shr[4];
         const double *pHL = NULL, *pHR = NULL;
         if (cs[L].hvalid) {
@@ -1490,7 +1737,6 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
 
     /* (9) Eq. (53): W^{n+1} = W^n - dt_i/Omega_i sum_j F_j s_j + W^{fr,p}, with
      * W^{fr,p} = W^{p,+} - W^{p,-}, Eq. (29); fixed local face order. */
-    double num = 0.0, den = 0.0, num_avg = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
       double acc[4] = {0, 0, 0, 0};
       for (int64_t l = c->cptr[i]; l < c->cptr[i + 1]; ++l) {
@@ -1504,43 +1750,32 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
         double frp = c->Sp[i * nw + q] / c->vol[i] - c->Sm[i * nw + q] / c->vol[i];
         Wn[q] = (c->W[i * nw + q] - coef * acc[q]) + frp;
       }
-      /* Reading (the paper does not discuss positivity): an updated state that
-       * is not a valid Maxwellian (a cell emptied into vacuum) is replaced by
-       * the content of the particles that ended in it, or by a vacuum floor
-       * state (rho = 1e-12 rho_inf at rest, T_inf) if none did. */
-      prim_t s = prim(c, Wn);
-      if (!prim_ok(s)) {
-        c->n_guard++;
-        int ok = 0;
-        if (c->Sp[i * nw] > 0.0) {
-          for (int q = 0; q < nw; ++q) Wn[q] = c->Sp[i * nw + q] / c->vol[i];
-          ok = prim_ok(prim(c, Wn));
-        }
-        if (!ok) {
-          double rf = 1e-12 * c->p.rho_inf;
-          for (int q = 0; q < nw; ++q) Wn[q] = 0.0;
-          Wn[0] = rf;
-          Wn[nw - 1] = 0.5 * (double)c->N * rf * c->p.R * c->p.T_inf;
-        }
-      }
+      c->n_guard += ref_vacuum_guard(c, c->Sp + i * nw, c->vol[i], Wn);
       for (int q = 0; q < nw; ++q) c->W[i * nw + q] = Wn[q];
     }
     /* (10) residuals (reading: RMS over cell area of the density change, and of
      * the change of the running mean, relative to rho_inf) */
+    xsum num, den, num_avg;
+    xs_init(&num);
+    xs_init(&den);
+    xs_init(&num_avg);
     for (int64_t i = 0; i < nc; ++i) {
       double rho = c->W[i * nw];
       double d = rho - c->rho_prev[i];
-      num += c->vol[i] * d * d;
-      den += c->vol[i];
+      xs_add(&num, c->vol[i] * d * d);
+      xs_add(&den, c->vol[i]);
       c->rho_sum[i] += rho;
       double mean = c->rho_sum[i] / (double)(n + 1);
       double dm = n == 0 ? 0.0 : mean - c->rho_mean_prev[i];
-      num_avg += c->vol[i] * dm * dm;
+      xs_add(&num_avg, c->vol[i] * dm * dm);
       c->rho_mean_prev[i] = mean;
       c->rho_prev[i] = rho;
     }
-    c->r_inst = sqrt(num / den) / c->p.rho_inf;
-    c->r_avg = sqrt(num_avg / den) / c->p.rho_inf;
+    c->r_inst = sqrt(xs_round(&num) / xs_round(&den)) / c->p.rho_inf;
+    c->r_avg = sqrt(xs_round(&num_avg) / xs_round(&den)) / c->p.rho_inf;
+    xs_free(&num);
+    xs_free(&den);
+    xs_free(&num_avg);
 
     /* surface: wall pressure, shear and heat flux (wave + particle impulses) */
     double Uinf = sqrt(c->p.u_inf_x * c->p.u_inf_x + c->p.u_inf_y * c->p.u_inf_y);
@@ -1580,6 +1815,10 @@ int ref_step(ref_ctx *c, int32_t n_steps) {
   free(gs);
   free(Qh);
   free(Sret);
+  xs_array_free(xret, nc * nw);
+  xs_array_free(xsm, nc * nw);
+  xs_array_free(xsp, nc * nw);
+  xs_array_free(xq, nc * 2);
   return rc;
 }
 
@@ -1705,3 +1944,42 @@ int ref_get_face_flux(const ref_ctx *c, double *Fs) {
 int64_t ref_n_faces(const ref_ctx *c) { return c->nf; }
 int64_t ref_n_guard(const ref_ctx *c) { return c->n_guard; }
 void ref_set_step(ref_ctx *c, int64_t step) { c->step = step; }
+int64_t ref_n_capped(const ref_ctx *c) { return c->n_capped; }
+
+/* Averaging state behind the residuals and the surface means: per cell the
+ * last density, the running density sum and the last running mean; per wall
+ * face the last, summed and EMA values of (p, tau, q); C_d last, sum, EMA.
+ * Any pointer may be NULL. */
+int ref_get_history(const ref_ctx *c, double *rho_prev, double *rho_sum, double *rho_mean_prev, double *wlast,
+                    double *wsum, double *wema, double cd[3]) {
+  size_t nc = (size_t)c->nc, nw3 = (size_t)c->nwall * 3;
+  if (rho_prev) memcpy(rho_prev, c->rho_prev, nc * sizeof(double));
+  if (rho_sum) memcpy(rho_sum, c->rho_sum, nc * sizeof(double));
+  if (rho_mean_prev) memcpy(rho_mean_prev, c->rho_mean_prev, nc * sizeof(double));
+  if (wlast) memcpy(wlast, c->wsurf_last, nw3 * sizeof(double));
+  if (wsum) memcpy(wsum, c->wsurf_sum, nw3 * sizeof(double));
+  if (wema) memcpy(wema, c->wsurf_ema, nw3 * sizeof(double));
+  if (cd) {
+    cd[0] = c->cd_last;
+    cd[1] = c->cd_sum;
+    cd[2] = c->cd_ema;
+  }
+  return REF_OK;
+}
+
+int ref_set_history(ref_ctx *c, const double *rho_prev, const double *rho_sum, const double *rho_mean_prev,
+                    const double *wlast, const double *wsum, const double *wema, const double cd[3]) {
+  size_t nc = (size_t)c->nc, nw3 = (size_t)c->nwall * 3;
+  if (rho_prev) memcpy(c->rho_prev, rho_prev, nc * sizeof(double));
+  if (rho_sum) memcpy(c->rho_sum, rho_sum, nc * sizeof(double));
+  if (rho_mean_prev) memcpy(c->rho_mean_prev, rho_mean_prev, nc * sizeof(double));
+  if (wlast) memcpy(c->wsurf_last, wlast, nw3 * sizeof(double));
+  if (wsum) memcpy(c->wsurf_sum, wsum, nw3 * sizeof(double));
+  if (wema) memcpy(c->wsurf_ema, wema, nw3 * sizeof(double));
+  if (cd) {
+    c->cd_last = cd[0];
+    c->cd_sum = cd[1];
+    c->cd_ema = cd[2];
+  }
+  return REF_OK;
+}

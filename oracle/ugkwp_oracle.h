@@ -121,6 +121,31 @@ void ref_flux_wall(const double W[4], const double *Wh, double dt, double tau, d
    inside (cell_out), 1 if it left through a far-field/outflow face. */
 int ref_track_one(ref_ctx *c, uint64_t pid, int64_t step, int32_t cell, double x[2], double u[3],
                   double *m, double t, int32_t *cell_out, int32_t *n_cross);
+/* exactly rounded sum of x[0..n) (nearest, ties to even) */
+double ref_exact_sum(const double *x, int64_t n);
+/* reconstruction of one side of a face (Wfar NULL: first order) and the face
+   values/slopes of interior face fi from the current fields (face frame) */
+void ref_reconstruct(const double *Wfar, double xfar, const double Wself[4], double xself, const double Wother[4],
+                     double xother, int K, double out[4], double slope[4]);
+int ref_face_geom(const ref_ctx *c, int64_t fi, double out[8]);
+int ref_face_values(const ref_ctx *c, int64_t fi, double WLf[4], double WRf[4], double sl[4], double sr[4],
+                    double dW0[4]);
+/* vacuum guard on an updated state Wn [dim + 2] of a cell of volume vol with
+   post-transport particle tally Sp [dim + 2]; returns 1 if Wn was replaced */
+int ref_vacuum_guard(const ref_ctx *c, const double *Sp, double vol, double *Wn);
+/* deviation z of a new particle (Maxwellian, or Shakhov acceptance-rejection
+   when shak = {U_x, U_y, T, p, Q_x, Q_y} is given); returns 1 when no attempt
+   was accepted (then z is the first attempt within c_max, or 0) */
+int ref_sample_deviation(ref_ctx *c, uint64_t pid, int64_t step, const double Uh[2], double Th, const double *shak,
+                         double z[3]);
+/* Shakhov draws of the last step that took the 64-attempt fallback */
+int64_t ref_n_capped(const ref_ctx *c);
+/* averaging state (restart): rho_prev, rho_sum, rho_mean_prev [nc]; wall
+   faces' last, summed and EMA (p, tau, q) [nwall*3]; C_d last, sum, EMA */
+int ref_get_history(const ref_ctx *c, double *rho_prev, double *rho_sum, double *rho_mean_prev, double *wlast,
+                    double *wsum, double *wema, double cd[3]);
+int ref_set_history(ref_ctx *c, const double *rho_prev, const double *rho_sum, const double *rho_mean_prev,
+                    const double *wlast, const double *wsum, const double *wema, const double cd[3]);
 
 #ifdef __cplusplus
 }
