@@ -25,8 +25,16 @@
  *     library's own stream).  Getters synchronize that stream.
  *   - A context is not thread-safe; separate contexts are independent.
  *   - Every call returns UGKWP_OK or a negative error code;
- *     ugkwp_last_error() gives a text.  After an error from ugkwp_step the
- *     fields and particles are unspecified: free the context.
+ *     ugkwp_last_error() gives a text.  A step that fails (ENUMERIC,
+ *     EOVERFLOW) is not committed: the fields, the particle set, its tallies,
+ *     the running averages and the step counter stay those of the last
+ *     committed step, and the context can be used on (for instance saved,
+ *     or stepped again after a change of tuning).
+ *   - The particle tallies (Eqs. (24), (29)-(30)), the wall impulses and the
+ *     residual sums are exact fixed-point sums (every term cut into four
+ *     32-bit chunks of a window fixed at init) rounded once to FP64, so
+ *     every result is reproducible bit for bit from run to run, whatever
+ *     order the GPU's atomics take.
  *   - The library requires a gfx950 device; it has no CPU fallback.
  */
 #ifndef UGKWP_H
@@ -43,7 +51,8 @@ enum {
   UGKWP_EDEVICE = -3,   /* HIP runtime error or no usable device */
   UGKWP_EOVERFLOW = -4, /* particle capacity or a caller buffer too small */
   UGKWP_ENUMERIC = -5,  /* non-finite or invalid state, runaway tracking */
-  UGKWP_ESTATE = -6     /* call not valid in the current state */
+  UGKWP_ESTATE = -6,    /* call not valid in the current state */
+  UGKWP_EIO = -7        /* a checkpoint file could not be written or read */
 };
 
 enum { /* boundary face types */
@@ -167,10 +176,10 @@ int ugkwp_get_fields(ugkwp_ctx *ctx, double *W);
 int ugkwp_get_fields_device(ugkwp_ctx *ctx, void *d_W);
 /* Local time steps dt_i, [n_cells]. */
 int ugkwp_get_dt(ugkwp_ctx *ctx, double *dt);
-/* Retained particles per cell after the last step and step totals:
- * transported (retained + new + entered from ghosts), new, removed
- * (collided), exited, and cells reset by the vacuum guard.  Any pointer may
- * be NULL. */
+/* Retained particles per cell after the last committed step and that
+ * step's totals: transported (retained + new + entered from ghosts), new,
+ * removed (collided), exited, and cells reset by the vacuum guard.  Any
+ * pointer may be NULL. */
 int ugkwp_get_counts(ugkwp_ctx *ctx, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
                      int64_t *n_exited, int64_t *n_guard);
 /* Running sum over every committed step of the particles transported in it
@@ -188,15 +197,49 @@ int ugkwp_get_particles(ugkwp_ctx *ctx, int64_t cap, uint64_t *pid, int32_t *cel
  * be NULL: zero internal energy). */
 int ugkwp_set_particles(ugkwp_ctx *ctx, int64_t n, const uint64_t *pid, const int32_t *cell, const double *m,
                         const double *x, const double *u, const double *ei);
-/* Restart support: replace W ([n_cells*(dim+2)] host; the local time steps
- * stay those of the initial field, Eq. (33)) and the step counter that keys
- * the random numbers.  With ugkwp_set_particles this restores a state saved
- * with the getters. */
+/* Replace W ([n_cells*(dim+2)] host; the local time steps stay those of
+ * the initial field, Eq. (33)); the density of the last step (behind
+ * r_inst) is set to W's.  The running means are kept: ugkwp_set_history
+ * restores them. */
 int ugkwp_set_fields(ugkwp_ctx *ctx, const double *W);
+/* The step counter that keys the random numbers (0 <= step < 2^20). */
 int ugkwp_set_step(ugkwp_ctx *ctx, int64_t step);
-/* Last step's particle tallies sum_k m_k Psi_k before (W^{p,-} Omega) and
- * after (W^{p,+} Omega) transport, Eq. (30), [n_cells*(dim+2)] each. */
+/* Averaging state behind ugkwp_residual and the surface means (host
+ * arrays, each may be NULL): per cell the last density, the running sum of
+ * the density over the steps and its last running mean [n_cells]; per wall
+ * face the last, summed and EMA (p, tau, q) [n_wall*3]; per case
+ * {r_inst, r_avg, C_d last, C_d sum, C_d EMA, unused} [n_cases*6].  With
+ * ugkwp_set_fields, ugkwp_set_particles and ugkwp_set_step these restore a
+ * state taken with the getters exactly (ugkwp_save / ugkwp_load do all of
+ * it in one file). */
+int ugkwp_get_history(ugkwp_ctx *ctx, double *rho_prev, double *rho_sum, double *rho_mean_prev, double *wlast,
+                      double *wsum, double *wema, double *scal);
+int ugkwp_set_history(ugkwp_ctx *ctx, const double *rho_prev, const double *rho_sum, const double *rho_mean_prev,
+                      const double *wlast, const double *wsum, const double *wema, const double *scal);
+/* Checkpoint of the whole committed state to a file: fields, local time
+ * steps, the particle store exactly as held on the device, the averaging
+ * state, the step counter and the exact-summation windows (the file is
+ * written to path.tmp and renamed).  ugkwp_load restores it into a context
+ * created with the same mesh and parameters: a run continued from the file
+ * gives bit for bit the results of the uninterrupted run (the paper's runs
+ * last tens of thousands of steps with averaging windows, Sec. V).  Errors:
+ * EIO (file), EINVAL (the file does not match the context), ENOMEM. */
+int ugkwp_save(ugkwp_ctx *ctx, const char *path);
+int ugkwp_load(ugkwp_ctx *ctx, const char *path);
+/* Last committed step's particle tallies sum_k m_k Psi_k before
+ * (W^{p,-} Omega) and after (W^{p,+} Omega) transport, Eq. (30),
+ * [n_cells*(dim+2)] each. */
 int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
+/* Last committed step's time-averaged face fluxes times the face length,
+ * F_j s_j (Eqs. (49)-(50)), along each face's normal (outward of its first
+ * cell; faces numbered by first appearance over the cells' edges in order),
+ * [n_faces*(dim+2)] host; Fs may be NULL to query n_faces; EOVERFLOW if
+ * cap < n_faces. */
+int ugkwp_get_face_flux(ugkwp_ctx *ctx, double *Fs, int64_t cap, int64_t *n_faces);
+/* New particles of the last committed step whose Shakhov
+ * acceptance-rejection (Pr != 1) accepted none of its 64 attempts and took
+ * the first attempt inside the 6 sqrt(R T^h) cut instead. */
+int ugkwp_get_shakhov_fallbacks(ugkwp_ctx *ctx, int64_t *n_capped);
 
 /* Launch tuning (results do not depend on it).  batch_steps: steps enqueued
  * between two host synchronizations (1..1024); use_graph: replay captured
@@ -204,11 +247,13 @@ int ugkwp_get_tally(ugkwp_ctx *ctx, double *Sminus, double *Splus);
  * per-kernel timing is on); transport_block: threads per block of the
  * particle transport (64, 128 or 256); shakhov_lanes: lanes per new
  * particle that evaluate its first Shakhov acceptance-rejection attempts
- * together (1, 2, 4, 8 or 16).  ugkwp_get_tuning returns the
- * current values (defaults at init: 32, 1, 256, 4); ugkwp_set_tuning sets all
- * four (EINVAL if one is out of range). */
+ * together (1, 2, 4, 8 or 16); max_crossings: face crossings a particle
+ * may make in one step before the step fails as a runaway track (ENUMERIC,
+ * not committed; 1..10000).  ugkwp_get_tuning returns the current values
+ * (defaults at init: 32, 1, 256, 4, 10000); ugkwp_set_tuning sets all five
+ * (EINVAL if one is out of range). */
 typedef struct {
-  int32_t batch_steps, use_graph, transport_block, shakhov_lanes;
+  int32_t batch_steps, use_graph, transport_block, shakhov_lanes, max_crossings;
 } ugkwp_tuning;
 int ugkwp_set_tuning(ugkwp_ctx *ctx, const ugkwp_tuning *t);
 int ugkwp_get_tuning(ugkwp_ctx *ctx, ugkwp_tuning *t);

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libugkwp.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ENUMERIC, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6, -7
 BC_FARFIELD, BC_OUTFLOW, BC_WALL_DIFFUSE, BC_SYMMETRY = 1, 2, 3, 4
 
 # Every entry point declared in include/ugkwp.h and include/ugkwp_mlp.h.
@@ -24,6 +24,8 @@ ABI_SYMBOLS = (
     "ugkwp_get_fields_device", "ugkwp_get_dt", "ugkwp_get_counts", "ugkwp_get_work", "ugkwp_get_particles",
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
+    "ugkwp_get_face_flux", "ugkwp_get_history", "ugkwp_set_history", "ugkwp_save", "ugkwp_load",
+    "ugkwp_get_shakhov_fallbacks",
     "ugkwp_mlp_layer", "ugkwp_mlp_gemm_acc", "ugkwp_mlp_act_backward", "ugkwp_mlp_adam", "ugkwp_mlp_to_bf16",
     "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode", "ugkwp_mlp_pack", "ugkwp_mlp_forward",
 )
@@ -45,7 +47,7 @@ class _Mesh(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("batch_steps", C.c_int32), ("use_graph", C.c_int32), ("transport_block", C.c_int32),
-                ("shakhov_lanes", C.c_int32)]
+                ("shakhov_lanes", C.c_int32), ("max_crossings", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -106,6 +108,12 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.ugkwp_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.ugkwp_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_char_p), dp, i64p, dp, i32p]
+    L.ugkwp_get_face_flux.argtypes = [vp, dp, C.c_int64, i64p]
+    L.ugkwp_get_history.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    L.ugkwp_set_history.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    L.ugkwp_save.argtypes = [vp, C.c_char_p]
+    L.ugkwp_load.argtypes = [vp, C.c_char_p]
+    L.ugkwp_get_shakhov_fallbacks.argtypes = [vp, i64p]
     L.ugkwp_last_error.argtypes = [vp]
     L.ugkwp_last_error.restype = C.c_char_p
     L.ugkwp_free.argtypes = [vp]
@@ -323,12 +331,55 @@ class Solver:
         (the stagnation point, Sec. V.A), linearly interpolated between the
         centres of the two wall faces nearest to it; mode as ugkwp_surface
         (2: the EMA with alpha = 2/1001, the paper's convergence monitor;
-        interpolation and EMA commute)."""
+        interpolation and EMA commute).  A caller-side diagnostic: it
+        post-processes the library's per-face output of ugkwp_surface on the
+        host and is not part of the step."""
         out, _ = self.case_surface(case, mode) if self.ncase > 1 else self.surface(mode)
         d = np.hypot(out[:, 0] - point[0], out[:, 1] - point[1])
         a, b = np.argsort(d, kind="stable")[:2]
         wa = d[b] / (d[a] + d[b])
         return wa * out[a, 3] + (1.0 - wa) * out[b, 3], wa * out[a, 5] + (1.0 - wa) * out[b, 5]
+
+    def face_flux(self):
+        """Last committed step's F_j s_j per face [n_faces x (dim + 2)]."""
+        L = load_library()
+        nf = C.c_int64()
+        self._check(L.ugkwp_get_face_flux(self.h, None, 0, C.byref(nf)))
+        F = np.zeros((nf.value, self.nw))
+        self._check(L.ugkwp_get_face_flux(self.h, _ptr(F), nf.value, C.byref(nf)))
+        return F
+
+    def n_wall(self):
+        nw = C.c_int64()
+        load_library().ugkwp_surface(self.h, 0, None, 0, C.byref(nw), None)
+        return nw.value
+
+    _HIST = ("rho_prev", "rho_sum", "rho_mean_prev", "wlast", "wsum", "wema", "scal")
+
+    def history(self):
+        """Averaging state: per-cell last density, density sum and running
+        mean; per wall face last, summed and EMA (p, tau, q); per case the
+        scalar results (r_inst, r_avg, C_d last, sum, EMA, unused)."""
+        nwl = self.n_wall()
+        h = dict(rho_prev=np.zeros(self.nc), rho_sum=np.zeros(self.nc), rho_mean_prev=np.zeros(self.nc),
+                 wlast=np.zeros(3 * nwl), wsum=np.zeros(3 * nwl), wema=np.zeros(3 * nwl), scal=np.zeros(6 * self.ncase))
+        self._check(load_library().ugkwp_get_history(self.h, *[_ptr(h[k]) for k in self._HIST]))
+        return h
+
+    def set_history(self, h):
+        arrs = [None if h.get(k) is None else np.ascontiguousarray(h[k], dtype=np.float64) for k in self._HIST]
+        self._check(load_library().ugkwp_set_history(self.h, *[_ptr(a) for a in arrs]))
+
+    def save(self, path):
+        self._check(load_library().ugkwp_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._check(load_library().ugkwp_load(self.h, os.fsencode(path)))
+
+    def shakhov_fallbacks(self):
+        n = C.c_int64()
+        self._check(load_library().ugkwp_get_shakhov_fallbacks(self.h, C.byref(n)))
+        return n.value
 
     def tally(self):
         Sm = np.zeros((self.nc, self.nw))

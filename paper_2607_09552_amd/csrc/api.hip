@@ -66,8 +66,12 @@ struct ugkwp_ctx {
   // state
   State S{};
   int precision = 0;        // 0: FP64 store, 1: mixed (FP32 positions/velocities)
-  Store A{}, B{};           // FP64 store (precision 0)
-  Store32 A32{}, B32{};     // FP32 store (precision 1)
+  // particle stores: A the committed set of the current step, B the next
+  // committed set (written by the re-sort), T the transport's per-slot
+  // results (positions, masses, cells, changed velocities): a step that
+  // fails leaves A untouched
+  Store A{}, B{}, T{};         // FP64 store (precision 0)
+  Store32 A32{}, B32{}, T32{}; // FP32 store (precision 1)
   double2 *anchor = nullptr;
   float4 *lfn32 = nullptr;
   float2 *lda = nullptr;
@@ -77,7 +81,10 @@ struct ugkwp_ctx {
   std::vector<int64_t> h_case_cell, h_case_bface;  // [ncase + 1]
   std::vector<double> h_case_par;                  // [ncase * kCaseN]
   int *ccase = nullptr;
-  int64_t *case_cell = nullptr, *case_bface = nullptr;
+  int64_t *case_cell = nullptr, *case_bface = nullptr, *case_wall = nullptr;
+  std::vector<int64_t> h_case_wall;                // [ncase + 1] first wall face of each case
+  double *Sm_prev = nullptr, *Sp_prev = nullptr;   // W^{p,-}, W^{p,+} (times Omega) of the last committed step
+  int xw_exp = 0, xm_exp = 0, xr_exp = 0, xa_exp = 0;  // exact-summation window exponents E
   uint64_t *case_seed = nullptr;
   double *case_par = nullptr;
   int64_t cap = 0, n_ret = 0, step = 0;
@@ -91,7 +98,7 @@ struct ugkwp_ctx {
   // profiling
   bool prof = false, prof_all = false;
   // tuning
-  int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4;
+  int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4, max_crossings = 10000;
   // captured graph of two steps and the launch arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -134,6 +141,7 @@ struct ugkwp_ctx {
     g.case_bface = case_bface;
     g.case_seed = case_seed;
     g.case_par = case_par;
+    g.case_wall = case_wall;
     g.lfn32 = lfn32;
     g.lda = lda;
     return g;
@@ -141,6 +149,14 @@ struct ugkwp_ctx {
 };
 
 namespace {
+
+// Exact-summation window with top exponent E and NL 32-bit chunks.
+XWin make_window(int E, int NL) {
+  XWin w{};
+  w.down = std::ldexp(1.0, 32 - E);
+  for (int j = 0; j < NL; ++j) w.up[j] = std::ldexp(1.0, E - 32 * NL + 32 * j);
+  return w;
+}
 
 int set_err(ugkwp_ctx *c, int code, const char *fmt, ...) {
   if (c) {
@@ -495,7 +511,7 @@ int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
 }
 
 template <class R>
-int alloc_store(ugkwp_ctx *c, StoreT<R> &s, int64_t n) {
+int alloc_store(ugkwp_ctx *c, StoreT<R> &s, int64_t n, bool with_pid = true) {
   int rc = 0;
   rc |= dalloc(c, &s.x, n);
   if (c->dim == 2) rc |= dalloc(c, &s.y, n);
@@ -504,7 +520,7 @@ int alloc_store(ugkwp_ctx *c, StoreT<R> &s, int64_t n) {
   rc |= dalloc(c, &s.uz, n);
   if (c->P.D > 0) rc |= dalloc(c, &s.ei, n);
   rc |= dalloc(c, &s.m, n);
-  rc |= dalloc(c, &s.pid, n);
+  if (with_pid) rc |= dalloc(c, &s.pid, n);
   rc |= dalloc(c, &s.cell, n);
   return rc ? UGKWP_ENOMEM : UGKWP_OK;
 }
@@ -541,18 +557,21 @@ int copy_store(ugkwp_ctx *c, const StoreT<R> &from, const StoreT<R> &to, int64_t
 
 // Grow the particle buffers to hold at least `need` particles (retained kept).
 template <class R>
-int grow_stores(ugkwp_ctx *c, StoreT<R> &A, StoreT<R> &B, int64_t ncap) {
-  StoreT<R> A2{}, B2{};
+int grow_stores(ugkwp_ctx *c, StoreT<R> &A, StoreT<R> &B, StoreT<R> &T, int64_t ncap) {
+  StoreT<R> A2{}, B2{}, T2{};
   int rc = alloc_store(c, A2, ncap);
   if (!rc) rc = alloc_store(c, B2, ncap);
+  if (!rc) rc = alloc_store(c, T2, ncap, false);
   if (rc) return set_err(c, UGKWP_ENOMEM, "cannot grow particle store to %lld", (long long)ncap);
   rc = copy_store(c, A, A2, c->n_ret);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
   free_store(c, A);
   free_store(c, B);
+  free_store(c, T);
   A = A2;
   B = B2;
+  T = T2;
   return UGKWP_OK;
 }
 
@@ -561,7 +580,7 @@ int ensure_capacity(ugkwp_ctx *c, int64_t need) {
   const int64_t ncap = std::max<int64_t>(need + need / 4 + 1024, c->cap + c->cap / 2);
   if (ncap > (int64_t{1} << 31) - 256)
     return set_err(c, UGKWP_EOVERFLOW, "particle store of %lld exceeds 2^31", (long long)ncap);
-  const int rc = c->precision ? grow_stores(c, c->A32, c->B32, ncap) : grow_stores(c, c->A, c->B, ncap);
+  const int rc = c->precision ? grow_stores(c, c->A32, c->B32, c->T32, ncap) : grow_stores(c, c->A, c->B, c->T, ncap);
   if (rc) return rc;
   dfree(c, c->S.rank);
   dfree(c, c->S.tghost);
@@ -577,6 +596,9 @@ void swap_buffers(ugkwp_ctx *c) {
   std::swap(c->A, c->B);
   std::swap(c->A32, c->B32);
   std::swap(c->S.Sret, c->S.Sretn);
+  std::swap(c->S.Xret, c->S.Xretn);
+  std::swap(c->S.Sm, c->Sm_prev);
+  std::swap(c->S.Sp, c->Sp_prev);
   std::swap(c->S.roff, c->S.coff);
   std::swap(c->S.Mraw, c->S.Mrawn);
 }
@@ -603,37 +625,43 @@ struct Zeroer {
 // double-buffered pointers; after a halted batch it restores their parity.
 // The transport specialization for the context's features.
 template <int DIM, int NV, class R>
-void launch_transport(ugkwp_ctx *c, const Geo &g, const State &S, const StoreT<R> &A, dim3 gr, dim3 bl) {
+void launch_transport(ugkwp_ctx *c, const Geo &g, const State &S, const StoreT<R> &A, const StoreT<R> &T, dim3 gr,
+                      dim3 bl) {
   switch (c->feat) {
-    case 0: hipLaunchKernelGGL((k_transport<DIM, NV, R, 0>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
-    case kFeatEi: hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap); break;
+    case 0: hipLaunchKernelGGL((k_transport<DIM, NV, R, 0>), gr, bl, 0, c->stream, g, c->P, S, A, T, c->cap); break;
+    case kFeatEi:
+      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi>), gr, bl, 0, c->stream, g, c->P, S, A, T, c->cap);
+      break;
     case kFeatMaxwell:
-      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A, c->cap);
+      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A, T, c->cap);
       break;
     default:
-      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi | kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A,
+      hipLaunchKernelGGL((k_transport<DIM, NV, R, kFeatEi | kFeatMaxwell>), gr, bl, 0, c->stream, g, c->P, S, A, T,
                          c->cap);
       break;
   }
 }
 
+// Per-cell tally of the store s over the ranges of `off` (Pr != 1 also the
+// raw moments of the heat flux).
 template <int DIM, class R>
-int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
+void launch_tally(ugkwp_ctx *c, const Geo &g, const StoreT<R> &s, const int64_t *off, double *S, double *X,
+                  double *Sp, double *M) {
+  const dim3 gr(nblk(c->nc * 64, 256)), bl(256);
+  if (c->P.Pr != 1.0)
+    hipLaunchKernelGGL((k_cell_tally<DIM, R, true>), gr, bl, 0, c->stream, g, c->P, s, off, S, X, Sp, M, c->S.flags,
+                       c->S.halt);
+  else
+    hipLaunchKernelGGL((k_cell_tally<DIM, R, false>), gr, bl, 0, c->stream, g, c->P, s, off, S, X, Sp, M,
+                       c->S.flags, c->S.halt);
+}
+
+template <int DIM, class R>
+int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const StoreT<R> &T) {
   const int NW = DIM + 2;
   const Geo g = c->geo();
   State &S = c->S;
   const int64_t nc = c->nc, nb = c->nb;
-  {
-    Zeroer z;
-    z.add(S.Scol, nc * NW * 2);
-    z.add(S.count, nc);
-    z.add(S.wimp, std::max<int64_t>(nb, 1) * 3 * 2);
-    z.add(S.resid, 3 * 2 * c->ncase);
-    z.add(S.cdsum, 2 * c->ncase);
-    z.add(S.nghost, 2);
-    z.add(S.stats, kStatSlots * kStatN * 2);
-    z.launch(c);
-  }
   {
     ProfScope ps(c, kKCellPrep, 160.0 * nc);
     hipLaunchKernelGGL(k_cell_prep<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
@@ -645,6 +673,17 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
   int rc = scan(c, S.ncount, nc + nb, S.noff);
   if (rc) return rc;
   hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, c->stream, g, S, c->cap, c->cover, c->cover_new);
+  {
+    // the step's accumulators, cleared once the step is known to proceed
+    // (a halted step leaves the last committed step's values in place)
+    Zeroer z;
+    z.add(S.count, 2 * nc);
+    z.add(S.wimp, std::max<int64_t>(nb, 1) * 3 * kTallyLimbs * 2);
+    z.add(S.resid, 8 * 2 * c->ncase);
+    z.add(S.nghost, 2);
+    z.add(S.stats, kStatSlots * kStatN * 2);
+    z.launch(c);
+  }
   // bytes of one particle record: positions and velocities, mass, pid, cell
   const double rec = (DIM + 3) * static_cast<double>(sizeof(R)) + 20.0;
   // particle-parallel grids cover c->cover particles (c->cover_new new ones);
@@ -679,31 +718,31 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
     ProfScope ps(c, kKTransport, (rec + wr) * c->est_total);
     const dim3 gr(nblk(c->cover, c->transport_block)), bl(c->transport_block);
     if constexpr (DIM == 1) {
-      launch_transport<DIM, 2, R>(c, g, S, A, gr, bl);
+      launch_transport<DIM, 2, R>(c, g, S, A, T, gr, bl);
     } else {
       switch (c->NV) {
-        case 3: launch_transport<2, 3, R>(c, g, S, A, gr, bl); break;
-        case 4: launch_transport<2, 4, R>(c, g, S, A, gr, bl); break;
-        case 5: launch_transport<2, 5, R>(c, g, S, A, gr, bl); break;
-        case 6: launch_transport<2, 6, R>(c, g, S, A, gr, bl); break;
-        case 7: launch_transport<2, 7, R>(c, g, S, A, gr, bl); break;
-        default: launch_transport<2, 8, R>(c, g, S, A, gr, bl); break;
+        case 3: launch_transport<2, 3, R>(c, g, S, A, T, gr, bl); break;
+        case 4: launch_transport<2, 4, R>(c, g, S, A, T, gr, bl); break;
+        case 5: launch_transport<2, 5, R>(c, g, S, A, T, gr, bl); break;
+        case 6: launch_transport<2, 6, R>(c, g, S, A, T, gr, bl); break;
+        case 7: launch_transport<2, 7, R>(c, g, S, A, T, gr, bl); break;
+        default: launch_transport<2, 8, R>(c, g, S, A, T, gr, bl); break;
       }
     }
   }
-  rc = scan(c, S.count, nc, S.coff);
+  // kept particles per cell in count[0, nc), collided ones in count[nc, 2 nc)
+  rc = scan(c, S.count, 2 * nc, S.coff);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_copy64, dim3(nblk(nc, 256) > 1024 ? 1024 : nblk(nc, 256)), dim3(256), 0, c->stream, S.cursor,
-                     S.coff, nc);
+  hipLaunchKernelGGL(k_copy64, dim3(nblk(2 * nc, 256) > 1024 ? 1024 : nblk(2 * nc, 256)), dim3(256), 0, c->stream,
+                     S.cursor, S.coff, 2 * nc);
   {
     ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->est_kept);
-    hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(256), 0, c->stream, S, A, B, c->cap);
+    hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(256), 0, c->stream, S, A, T, B, c->cap);
   }
   {
     const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
-    ProfScope ps(c, kKCellTally, rd * c->est_kept + (16.0 + 8.0 * NW) * nc);
-    hipLaunchKernelGGL((k_cell_tally<DIM, R>), dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, B, S.coff,
-                       S.Sretn, S.Mrawn, c->P.Pr != 1.0 ? 1 : 0, S.halt);
+    ProfScope ps(c, kKCellTally, rd * c->est_kept + (16.0 + 8.0 * NW * 6) * nc);
+    launch_tally<DIM, R>(c, g, B, S.coff, S.Sretn, S.Xretn, S.Sp, S.Mrawn);
   }
   {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
@@ -726,8 +765,9 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B) {
 
 int enqueue(ugkwp_ctx *c) {
   if (c->precision)
-    return c->dim == 1 ? enqueue_step<1, float>(c, c->A32, c->B32) : enqueue_step<2, float>(c, c->A32, c->B32);
-  return c->dim == 1 ? enqueue_step<1, double>(c, c->A, c->B) : enqueue_step<2, double>(c, c->A, c->B);
+    return c->dim == 1 ? enqueue_step<1, float>(c, c->A32, c->B32, c->T32)
+                       : enqueue_step<2, float>(c, c->A32, c->B32, c->T32);
+  return c->dim == 1 ? enqueue_step<1, double>(c, c->A, c->B, c->T) : enqueue_step<2, double>(c, c->A, c->B, c->T);
 }
 
 int check_flags(ugkwp_ctx *c) {
@@ -736,7 +776,8 @@ int check_flags(ugkwp_ctx *c) {
   HIPCHK(hipStreamSynchronize(c->stream));
   if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state");
   if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking");
-  if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+  if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 particles in one cell");
+  if (flags & kFlagRange) return set_err(c, UGKWP_ENUMERIC, "a tally term outside its exact-summation window");
   return UGKWP_OK;
 }
 
@@ -915,34 +956,42 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   std::vector<double> W(W0, W0 + nc * nw);
   if ((rc = upload(c, &S.W, W))) return rc;
   const size_t ncw = nc * nw, nbw = std::max<int64_t>(nb, 1) * nw;
-  if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.tdt, nc) || dalloc(c, &S.E, nc) ||
-      dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) || dalloc(c, &S.Sm, ncw) ||
-      dalloc(c, &S.Sp, ncw) || dalloc(c, &S.Scol, ncw) || dalloc(c, &S.roff, nc + 1) || dalloc(c, &S.cursor, nc) || dalloc(c, &S.ar, nc * kArN) || dalloc(c, &S.Mraw, nc * 5) || dalloc(c, &S.Mrawn, nc * 5) || dalloc(c, &S.ncount, nc + nb) ||
+  const size_t nb1 = std::max<int64_t>(nb, 1), nwl1 = std::max<int64_t>(c->nwall, 1);
+  if (dalloc(c, &S.Wh, ncw) || dalloc(c, &S.dt, nc) || dalloc(c, &S.tau, nc) || dalloc(c, &S.tdt, nc) ||
+      dalloc(c, &S.E, nc) || dalloc(c, &S.hvalid, nc) || dalloc(c, &S.Sret, ncw) || dalloc(c, &S.Sretn, ncw) ||
+      dalloc(c, &S.Sm, ncw) || dalloc(c, &S.Sp, ncw) || dalloc(c, &c->Sm_prev, ncw) || dalloc(c, &c->Sp_prev, ncw) ||
+      dalloc(c, &S.Xret, ncw * kTallyLimbs) || dalloc(c, &S.Xretn, ncw * kTallyLimbs) ||
+      dalloc(c, &S.roff, 2 * nc + 1) || dalloc(c, &S.cursor, 2 * nc) || dalloc(c, &S.ar, nc * kArN) ||
+      dalloc(c, &S.Mraw, nc * 5) || dalloc(c, &S.Mrawn, nc * 5) || dalloc(c, &S.ncount, nc + nb) ||
       dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
-      dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, std::max<int64_t>(nb, 1)) ||
-      dalloc(c, &S.gdepth, std::max<int64_t>(nb, 1)) || dalloc(c, &S.ghvalid, std::max<int64_t>(nb, 1)) ||
-      dalloc(c, &S.nghost, 1) || dalloc(c, &S.count, nc) || dalloc(c, &S.coff, nc + 1) || dalloc(c, &S.Fs, c->nf * nw) ||
-      dalloc(c, &S.rho_prev, nc) || dalloc(c, &S.rho_sum, nc) || dalloc(c, &S.rho_mean_prev, nc) ||
-      dalloc(c, &S.resid, 3 * ncase) || dalloc(c, &S.wimp, std::max<int64_t>(nb, 1) * 3) ||
-      dalloc(c, &S.wlast, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.wsum, std::max<int64_t>(c->nwall, 1) * 3) ||
-      dalloc(c, &S.wema, std::max<int64_t>(c->nwall, 1) * 3) || dalloc(c, &S.cdsum, ncase) || dalloc(c, &S.scal, ncase * kScalN) ||
-      dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1) || dalloc(c, &S.halt, 1) ||
-      dalloc(c, &S.dstep, 1) || dalloc(c, &S.info, kInfoN))
+      dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, nb1) || dalloc(c, &S.gdepth, nb1) ||
+      dalloc(c, &S.ghvalid, nb1) || dalloc(c, &S.nghost, 1) || dalloc(c, &S.count, 2 * nc) ||
+      dalloc(c, &S.coff, 2 * nc + 1) || dalloc(c, &S.Fs, c->nf * nw) || dalloc(c, &S.rho_prev, nc) ||
+      dalloc(c, &S.rho_sum, nc) || dalloc(c, &S.rho_mean_prev, nc) || dalloc(c, &S.resid, 8 * ncase) ||
+      dalloc(c, &S.area, ncase) || dalloc(c, &S.wimp, nb1 * 3 * kTallyLimbs) || dalloc(c, &S.wlast, nwl1 * 3) ||
+      dalloc(c, &S.wsum, nwl1 * 3) || dalloc(c, &S.wema, nwl1 * 3) || dalloc(c, &S.fd, nwl1) ||
+      dalloc(c, &S.scal, ncase * kScalN) || dalloc(c, &S.stats, kStatSlots * kStatN) || dalloc(c, &S.flags, 1) ||
+      dalloc(c, &S.halt, 1) || dalloc(c, &S.dstep, 1) || dalloc(c, &S.info, kInfoN))
     return set_err(c, UGKWP_ENOMEM, "device allocation failed");
   S.nc_scatter = nc;
   HIPCHK(hipMemsetAsync(S.Sret, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Xret, 0, ncw * kTallyLimbs * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sm, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.Scol, 0, ncw * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.roff, 0, (nc + 1) * sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(c->Sm_prev, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(c->Sp_prev, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.roff, 0, (2 * nc + 1) * sizeof(int64_t), c->stream));
+  HIPCHK(hipMemsetAsync(S.coff, 0, (2 * nc + 1) * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.ar, 0, nc * kArN * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.Mraw, 0, nc * 5 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.count, 0, nc * sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(S.count, 0, 2 * nc * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_sum, 0, nc * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.rho_mean_prev, 0, nc * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.wsum, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.wlast, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(S.wema, 0, std::max<int64_t>(c->nwall, 1) * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wsum, 0, nwl1 * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wlast, 0, nwl1 * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wema, 0, nwl1 * 3 * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.wimp, 0, nb1 * 3 * kTallyLimbs * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.resid, 0, 8 * ncase * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.scal, 0, ncase * kScalN * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.stats, 0, kStatSlots * kStatN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, sizeof(int), c->stream));
@@ -950,6 +999,70 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   HIPCHK(hipMemsetAsync(S.dstep, 0, sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.info, 0, kInfoN * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.nghost, 0, sizeof(int64_t), c->stream));
+  // exact-summation windows (see XWin): E from bounds of the initial state,
+  // the far-field states and the geometry with generous headroom; a term
+  // beyond its window fails the step (ENUMERIC)
+  {
+    double content = 0.0, vmax = 0.0, rho_max = 0.0, area_max = 0.0;
+    const double R = par->R;
+    auto visit = [&](const double *Ws, double vol) {
+      const double rho = Ws[0];
+      double mom = 0.0;
+      for (int d = 0; d < c->dim; ++d) mom += Ws[1 + d] * Ws[1 + d];
+      mom = std::sqrt(mom);
+      const double E = Ws[nw - 1];
+      content = std::max(content, vol * (std::fabs(rho) + mom + std::fabs(E)));
+      rho_max = std::max(rho_max, std::fabs(rho));
+      if (rho > 0) {
+        const double U = mom / rho;
+        const double e = E - 0.5 * rho * U * U;
+        const double T = std::max(0.0, 2.0 * e / ((3.0 + par->D) * R * rho));
+        vmax = std::max(vmax, U + 15.0 * std::sqrt(R * T));
+      }
+    };
+    for (int64_t i = 0; i < nc; ++i) visit(W0 + i * nw, h.vol[i]);
+    for (int64_t b = 0; b < nb; ++b) {
+      const double *d = mesh->bface_data + 8 * b;
+      const int64_t i = h.bcell[b];
+      if (btype[b] == UGKWP_BC_FARFIELD) {
+        double Wg[4] = {d[0], d[0] * d[1], 0.0, 0.0};
+        if (c->dim == 2) Wg[2] = d[0] * d[2];
+        Wg[nw - 1] = 0.5 * d[0] * (d[1] * d[1] + (c->dim == 2 ? d[2] * d[2] : 0.0)) + 0.5 * (3.0 + par->D) * d[0] * R * d[3];
+        visit(Wg, h.vol[i]);
+      } else if (btype[b] == UGKWP_BC_WALL_DIFFUSE || btype[b] == UGKWP_BC_WALL_MAXWELL) {
+        vmax = std::max(vmax, 15.0 * std::sqrt(R * std::fabs(d[0])));
+      }
+    }
+    for (int k = 0; k < ncase; ++k) {
+      double a = 0.0;
+      for (int64_t i = case_cell[k]; i < case_cell[k + 1]; ++i) a += h.vol[i];
+      area_max = std::max(area_max, a);
+    }
+    if (!(content > 0.0) || !std::isfinite(content) || !std::isfinite(vmax))
+      return set_err(c, UGKWP_ENUMERIC, "invalid initial state");
+    auto expo = [](double v) { return static_cast<int>(std::ceil(std::log2(v))); };
+    c->xw_exp = expo(content) + 12;
+    c->xm_exp = c->xw_exp + expo(2.0 * std::max(vmax, 1.0)) + 2;
+    c->xr_exp = expo(area_max * std::max(rho_max, 1e-300) * std::max(rho_max, 1e-300)) + 25;
+    c->xa_exp = expo(area_max) + 1;
+    P.xw = make_window(c->xw_exp, kTallyLimbs);
+    P.xm = make_window(c->xm_exp, kTallyLimbs);
+    P.xr = make_window(c->xr_exp, 4);
+    P.max_cross = c->max_crossings;
+    // walls of each case (wall faces are numbered in boundary-face order)
+    c->h_case_wall.assign(ncase + 1, 0);
+    for (int k = 0; k < ncase; ++k) {
+      int64_t n = 0;
+      for (int64_t b = case_bface[k]; b < case_bface[k + 1]; ++b)
+        if (btype[b] == UGKWP_BC_WALL_DIFFUSE || btype[b] == UGKWP_BC_WALL_MAXWELL) ++n;
+      c->h_case_wall[k + 1] = c->h_case_wall[k] + n;
+    }
+    if ((rc = upload(c, &c->case_wall, c->h_case_wall))) return rc;
+    Geo ga = c->geo();
+    hipLaunchKernelGGL(k_case_area, dim3(nblk(ncase * 64, 256)), dim3(256), 0, c->stream, ga, S.area,
+                       make_window(c->xa_exp, 4));
+    HIPCHK(hipGetLastError());
+  }
   // rho_prev = initial density
   {
     std::vector<double> r(nc);
@@ -957,7 +1070,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
     HIPCHK(hipMemcpyAsync(S.rho_prev, r.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  if ((rc = reserve_scan(c, nc + nb))) return rc;
+  if ((rc = reserve_scan(c, std::max(2 * nc, nc + nb)))) return rc;
   void *pin = nullptr;
   HIPCHK(hipHostMalloc(&pin, 8 * sizeof(int64_t), hipHostMallocDefault));
   c->pinned = static_cast<int64_t *>(pin);
@@ -1128,7 +1241,8 @@ void drop_graph(ugkwp_ctx *c) {
 std::vector<int64_t> graph_key(const ugkwp_ctx *c) {
   return {reinterpret_cast<int64_t>(c->A.x), reinterpret_cast<int64_t>(c->B.x), reinterpret_cast<int64_t>(c->A32.x),
           reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.rank),
-          c->cap, c->cover, c->cover_new, c->transport_block, c->shakhov_lanes};
+          reinterpret_cast<int64_t>(c->T.x), reinterpret_cast<int64_t>(c->T32.x), c->cap, c->cover, c->cover_new,
+          c->transport_block, c->shakhov_lanes, c->P.max_cross, c->xw_exp, c->xm_exp, c->xr_exp};
 }
 
 // Captures two steps into a graph (the double-buffer swaps of two steps
@@ -1209,10 +1323,19 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
       continue;
     }
     if (halt) {
+      // the failed step was not committed: fields, particles, tallies,
+      // averages and the step counter are those of the last committed step,
+      // and the context can be used on
+      HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+      HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
       if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state at step %lld", (long long)c->step);
       if (flags & kFlagRunaway)
-        return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking at step %lld", (long long)(c->step - 1));
-      if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 new particles in one cell");
+        return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking at step %lld", (long long)c->step);
+      if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 particles in one cell");
+      if (flags & kFlagRange)
+        return set_err(c, UGKWP_ENUMERIC, "a tally term outside its exact-summation window at step %lld",
+                       (long long)c->step);
       return set_err(c, UGKWP_EDEVICE, "step halted (flags %d)", flags);
     }
     // room for the next batch
@@ -1354,18 +1477,29 @@ int ugkwp_get_dt(ugkwp_ctx *c, double *dt) {
 int ugkwp_get_counts(ugkwp_ctx *c, int32_t *count, int64_t *n_total, int64_t *n_new, int64_t *n_removed,
                      int64_t *n_exited, int64_t *n_guard) {
   if (!c) return UGKWP_EINVAL;
-  std::vector<int64_t> slots(kStatSlots * kStatN);
-  HIPCHK(hipMemcpyAsync(slots.data(), c->S.stats, slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  if (count) HIPCHK(hipMemcpyAsync(count, c->S.count, c->nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  // committed values only: the retained set's offsets and the last
+  // committed step's counts
+  int64_t info[kInfoN];
+  std::vector<int64_t> off(count ? c->nc + 1 : 0);
+  if (count) HIPCHK(hipMemcpyAsync(off.data(), c->S.roff, (c->nc + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(info, c->S.info, sizeof info, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (n_total) *n_total = c->last_total;
-  if (n_new) *n_new = c->last_new;
-  int64_t st[kStatN] = {0, 0, 0, 0};
-  for (int k = 0; k < kStatSlots; ++k)
-    for (int q = 0; q < kStatN; ++q) st[q] += slots[k * kStatN + q];
-  if (n_removed) *n_removed = st[kStatRemoved];
-  if (n_exited) *n_exited = st[kStatExited];
-  if (n_guard) *n_guard = st[kStatGuard];
+  if (count)
+    for (int64_t i = 0; i < c->nc; ++i) count[i] = static_cast<int32_t>(off[i + 1] - off[i]);
+  if (n_total) *n_total = info[kInfoTotal];
+  if (n_new) *n_new = info[kInfoNew];
+  if (n_removed) *n_removed = info[kInfoRemoved];
+  if (n_exited) *n_exited = info[kInfoExited];
+  if (n_guard) *n_guard = info[kInfoGuard];
+  return UGKWP_OK;
+}
+
+int ugkwp_get_shakhov_fallbacks(ugkwp_ctx *c, int64_t *n_capped) {
+  if (!c || !n_capped) return UGKWP_EINVAL;
+  int64_t info[kInfoN];
+  HIPCHK(hipMemcpyAsync(info, c->S.info, sizeof info, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *n_capped = info[kInfoCapped];
   return UGKWP_OK;
 }
 
@@ -1501,8 +1635,7 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
   std::vector<uint64_t> P(n);
   std::vector<int> C(n);
   std::vector<double> X(n), Y(n), U0(n), U1(n), U2(n), M(n), EI(n, 0.0);
-  std::vector<double> Sr(c->nc * c->nw, 0.0), Mr(c->nc * 5, 0.0);
-  std::vector<int> cnt(c->nc, 0);
+  std::vector<int64_t> ro(2 * c->nc + 1, 0);
   for (int64_t j = 0; j < n; ++j) {
     const int64_t k = order[j];
     P[j] = pid[k];
@@ -1514,64 +1647,331 @@ int ugkwp_set_particles(ugkwp_ctx *c, int64_t n, const uint64_t *pid, const int3
     U1[j] = u[3 * k + 1];
     U2[j] = u[3 * k + 2];
     if (ei && c->P.D > 0) EI[j] = ei[k];
-    if (c->precision) {  // the tallies see the velocities as stored
-      U0[j] = static_cast<float>(U0[j]);
-      U1[j] = static_cast<float>(U1[j]);
-      U2[j] = static_cast<float>(U2[j]);
-      EI[j] = static_cast<float>(EI[j]);
-    }
-    const double e = 0.5 * (U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j]) + EI[j];
-    const double q2 = U0[j] * U0[j] + U1[j] * U1[j] + U2[j] * U2[j];
-    const double q2i = q2 + 2.0 * EI[j];
-    double *mr = &Mr[C[j] * 5];
-    mr[0] += M[j] * U0[j] * q2i;
-    mr[1] += M[j] * U1[j] * q2i;
-    mr[2] += M[j] * U0[j] * U0[j];
-    mr[3] += M[j] * U0[j] * U1[j];
-    mr[4] += M[j] * U1[j] * U1[j];
-    double *sr = &Sr[C[j] * c->nw];
-    sr[0] += M[j];
-    sr[1] += M[j] * U0[j];
-    if (c->dim == 2) sr[2] += M[j] * U1[j];
-    sr[c->nw - 1] += M[j] * e;
-    cnt[C[j]]++;
+    ro[C[j] + 1]++;
   }
+  for (int64_t i = 0; i < c->nc; ++i) ro[i + 1] += ro[i];
+  for (int64_t i = c->nc + 1; i <= 2 * c->nc; ++i) ro[i] = n;  // no collided particles
   rc = c->precision ? write_store(c, c->A32, n, P, C, X, Y, U0, U1, U2, M, EI)
                     : write_store(c, c->A, n, P, C, X, Y, U0, U1, U2, M, EI);
   if (rc) return rc;
-  const hipMemcpyKind h2d = hipMemcpyHostToDevice;
-  HIPCHK(hipMemcpyAsync(c->S.Sret, Sr.data(), Sr.size() * 8, h2d, c->stream));
-  HIPCHK(hipMemcpyAsync(c->S.Mraw, Mr.data(), Mr.size() * 8, h2d, c->stream));
-  HIPCHK(hipMemcpyAsync(c->S.count, cnt.data(), cnt.size() * 4, h2d, c->stream));
-  std::vector<int64_t> ro(c->nc + 1, 0);
-  for (int64_t i = 0; i < c->nc; ++i) ro[i + 1] = ro[i] + cnt[i];
-  HIPCHK(hipMemcpyAsync(c->S.roff, ro.data(), ro.size() * 8, h2d, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpyAsync(c->S.roff, ro.data(), ro.size() * 8, hipMemcpyHostToDevice, c->stream));
+  // the retained tally W^p Omega (and the raw moments) from the store as the
+  // device holds it: the same exact sums a step computes
+  const Geo g = c->geo();
+  if (c->precision) {
+    if (c->dim == 1) launch_tally<1, float>(c, g, c->A32, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+    else launch_tally<2, float>(c, g, c->A32, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+  } else {
+    if (c->dim == 1) launch_tally<1, double>(c, g, c->A, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+    else launch_tally<2, double>(c, g, c->A, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+  }
+  HIPCHK(hipGetLastError());
   c->n_ret = n;
+  rc = check_flags(c);
+  if (rc) return rc;
   return UGKWP_OK;
 }
 
 int ugkwp_set_fields(ugkwp_ctx *c, const double *W) {
   if (!c || !W) return UGKWP_EINVAL;
-  HIPCHK(hipMemcpy(c->S.W, W, c->nc * c->nw * sizeof(double), hipMemcpyHostToDevice));
   std::vector<double> r(c->nc);
   for (int64_t i = 0; i < c->nc; ++i) r[i] = W[i * c->nw];
-  HIPCHK(hipMemcpy(c->S.rho_prev, r.data(), c->nc * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(c->S.W, W, c->nc * c->nw * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->S.rho_prev, r.data(), c->nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return UGKWP_OK;
 }
 
 int ugkwp_set_step(ugkwp_ctx *c, int64_t step) {
   if (!c || step < 0 || step >= (1 << 20)) return UGKWP_EINVAL;
-  HIPCHK(hipMemcpy(c->S.dstep, &step, sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(c->S.dstep, &step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   c->step = step;
   return UGKWP_OK;
+}
+
+int ugkwp_get_face_flux(ugkwp_ctx *c, double *Fs, int64_t cap, int64_t *n_faces) {
+  if (!c) return UGKWP_EINVAL;
+  if (n_faces) *n_faces = c->nf;
+  if (!Fs) return UGKWP_OK;
+  if (cap < c->nf) return set_err(c, UGKWP_EOVERFLOW, "face buffer too small");
+  HIPCHK(hipMemcpyAsync(Fs, c->S.Fs, c->nf * c->nw * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+int ugkwp_get_history(ugkwp_ctx *c, double *rho_prev, double *rho_sum, double *rho_mean_prev, double *wlast,
+                      double *wsum, double *wema, double *scal) {
+  if (!c) return UGKWP_EINVAL;
+  const size_t nc = c->nc * sizeof(double), nw3 = c->nwall * 3 * sizeof(double);
+  const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+  if (rho_prev) HIPCHK(hipMemcpyAsync(rho_prev, c->S.rho_prev, nc, d2h, c->stream));
+  if (rho_sum) HIPCHK(hipMemcpyAsync(rho_sum, c->S.rho_sum, nc, d2h, c->stream));
+  if (rho_mean_prev) HIPCHK(hipMemcpyAsync(rho_mean_prev, c->S.rho_mean_prev, nc, d2h, c->stream));
+  if (wlast && nw3) HIPCHK(hipMemcpyAsync(wlast, c->S.wlast, nw3, d2h, c->stream));
+  if (wsum && nw3) HIPCHK(hipMemcpyAsync(wsum, c->S.wsum, nw3, d2h, c->stream));
+  if (wema && nw3) HIPCHK(hipMemcpyAsync(wema, c->S.wema, nw3, d2h, c->stream));
+  if (scal) HIPCHK(hipMemcpyAsync(scal, c->S.scal, c->ncase * kScalN * sizeof(double), d2h, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (scal)
+    for (int k = 0; k < c->ncase; ++k) scal[k * kScalN + kScalTarget] = 0.0;
+  return UGKWP_OK;
+}
+
+int ugkwp_set_history(ugkwp_ctx *c, const double *rho_prev, const double *rho_sum, const double *rho_mean_prev,
+                      const double *wlast, const double *wsum, const double *wema, const double *scal) {
+  if (!c) return UGKWP_EINVAL;
+  const size_t nc = c->nc * sizeof(double), nw3 = c->nwall * 3 * sizeof(double);
+  const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+  std::vector<double> sc;
+  if (scal) {
+    sc.assign(scal, scal + c->ncase * kScalN);
+    for (int k = 0; k < c->ncase; ++k) sc[k * kScalN + kScalTarget] = 0.0;
+  }
+  if (rho_prev) HIPCHK(hipMemcpyAsync(c->S.rho_prev, rho_prev, nc, h2d, c->stream));
+  if (rho_sum) HIPCHK(hipMemcpyAsync(c->S.rho_sum, rho_sum, nc, h2d, c->stream));
+  if (rho_mean_prev) HIPCHK(hipMemcpyAsync(c->S.rho_mean_prev, rho_mean_prev, nc, h2d, c->stream));
+  if (wlast && nw3) HIPCHK(hipMemcpyAsync(c->S.wlast, wlast, nw3, h2d, c->stream));
+  if (wsum && nw3) HIPCHK(hipMemcpyAsync(c->S.wsum, wsum, nw3, h2d, c->stream));
+  if (wema && nw3) HIPCHK(hipMemcpyAsync(c->S.wema, wema, nw3, h2d, c->stream));
+  if (scal) HIPCHK(hipMemcpyAsync(c->S.scal, sc.data(), sc.size() * sizeof(double), h2d, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint file: a fixed header, then the arrays in this order (native
+// byte order): W, dt, rho_prev, rho_sum, rho_mean_prev, wlast, wsum, wema,
+// scal, info, and the committed particle store as the device holds it (its
+// order and, for the FP32 store, its cell-relative positions): x, (y), ux,
+// uy, uz, (ei) in the store's type, m, pid, cell.
+constexpr char kSaveMagic[8] = {'U', 'G', 'K', 'W', 'P', 'S', 'V', '1'};
+struct SaveHeader {
+  char magic[8];
+  int32_t version, dim, precision, D, ncase, xw, xm, xr;
+  int64_t nc, nb, nwall, nf, n_ret, step;
+  uint64_t seed;
+};
+
+struct File {
+  FILE *f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+
+template <class T>
+bool fput(FILE *f, const T *p, size_t n) {
+  return n == 0 || fwrite(p, sizeof(T), n, f) == n;
+}
+template <class T>
+bool fget(FILE *f, T *p, size_t n) {
+  return n == 0 || fread(p, sizeof(T), n, f) == n;
+}
+
+template <class T>
+int d2h(ugkwp_ctx *c, std::vector<T> &h, const T *d, size_t n) {
+  h.resize(n);
+  if (n) HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+  return UGKWP_OK;
+}
+template <class T>
+int h2d(ugkwp_ctx *c, T *d, const std::vector<T> &h) {
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return UGKWP_OK;
+}
+
+template <class R>
+int save_store(ugkwp_ctx *c, const StoreT<R> &s, FILE *f) {
+  const size_t n = c->n_ret;
+  std::vector<R> x, y, u0, u1, u2, ei;
+  std::vector<double> m;
+  std::vector<uint64_t> pid;
+  std::vector<int> cell;
+  d2h(c, x, s.x, n);
+  if (c->dim == 2) d2h(c, y, s.y, n);
+  d2h(c, u0, s.ux, n);
+  d2h(c, u1, s.uy, n);
+  d2h(c, u2, s.uz, n);
+  if (s.ei) d2h(c, ei, s.ei, n);
+  d2h(c, m, s.m, n);
+  d2h(c, pid, s.pid, n);
+  d2h(c, cell, s.cell, n);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  bool ok = fput(f, x.data(), n) && (c->dim != 2 || fput(f, y.data(), n)) && fput(f, u0.data(), n) &&
+            fput(f, u1.data(), n) && fput(f, u2.data(), n) && (!s.ei || fput(f, ei.data(), n)) &&
+            fput(f, m.data(), n) && fput(f, pid.data(), n) && fput(f, cell.data(), n);
+  return ok ? UGKWP_OK : set_err(c, UGKWP_EIO, "write failed");
+}
+
+template <class R>
+int load_store(ugkwp_ctx *c, const StoreT<R> &s, FILE *f, size_t n, std::vector<int> &cell) {
+  std::vector<R> x(n), y(c->dim == 2 ? n : 0), u0(n), u1(n), u2(n), ei(s.ei ? n : 0);
+  std::vector<double> m(n);
+  std::vector<uint64_t> pid(n);
+  cell.resize(n);
+  bool ok = fget(f, x.data(), n) && (c->dim != 2 || fget(f, y.data(), n)) && fget(f, u0.data(), n) &&
+            fget(f, u1.data(), n) && fget(f, u2.data(), n) && (!s.ei || fget(f, ei.data(), n)) &&
+            fget(f, m.data(), n) && fget(f, pid.data(), n) && fget(f, cell.data(), n);
+  if (!ok) return set_err(c, UGKWP_EIO, "checkpoint truncated");
+  for (size_t k = 0; k < n; ++k)
+    if (cell[k] < 0 || cell[k] >= c->nc || (k > 0 && cell[k] < cell[k - 1]))
+      return set_err(c, UGKWP_EINVAL, "checkpoint particle cells out of range or not sorted");
+  h2d(c, s.x, x);
+  if (c->dim == 2) h2d(c, s.y, y);
+  h2d(c, s.ux, u0);
+  h2d(c, s.uy, u1);
+  h2d(c, s.uz, u2);
+  if (s.ei) h2d(c, s.ei, ei);
+  h2d(c, s.m, m);
+  h2d(c, s.pid, pid);
+  h2d(c, s.cell, cell);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return UGKWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugkwp_save(ugkwp_ctx *c, const char *path) {
+  if (!c || !path) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  SaveHeader h{};
+  memcpy(h.magic, kSaveMagic, 8);
+  h.version = 1;
+  h.dim = c->dim;
+  h.precision = c->precision;
+  h.D = c->P.D;
+  h.ncase = c->ncase;
+  h.xw = c->xw_exp;
+  h.xm = c->xm_exp;
+  h.xr = c->xr_exp;
+  h.nc = c->nc;
+  h.nb = c->nb;
+  h.nwall = c->nwall;
+  h.nf = c->nf;
+  h.n_ret = c->n_ret;
+  h.step = c->step;
+  h.seed = c->P.seed;
+  const size_t nc = c->nc, nw3 = c->nwall * 3;
+  std::vector<double> W, dt, rp, rs, rm, wl, ws, we, sc;
+  std::vector<int64_t> info;
+  d2h(c, W, c->S.W, nc * c->nw);
+  d2h(c, dt, c->S.dt, nc);
+  d2h(c, rp, c->S.rho_prev, nc);
+  d2h(c, rs, c->S.rho_sum, nc);
+  d2h(c, rm, c->S.rho_mean_prev, nc);
+  d2h(c, wl, c->S.wlast, nw3);
+  d2h(c, ws, c->S.wsum, nw3);
+  d2h(c, we, c->S.wema, nw3);
+  d2h(c, sc, c->S.scal, c->ncase * kScalN);
+  d2h(c, info, c->S.info, kInfoN);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->ncase; ++k) sc[k * kScalN + kScalTarget] = 0.0;
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    File F;
+    F.f = fopen(tmp.c_str(), "wb");
+    if (!F.f) return set_err(c, UGKWP_EIO, "cannot open %s for writing", tmp.c_str());
+    bool ok = fput(F.f, &h, 1) && fput(F.f, W.data(), W.size()) && fput(F.f, dt.data(), nc) &&
+              fput(F.f, rp.data(), nc) && fput(F.f, rs.data(), nc) && fput(F.f, rm.data(), nc) &&
+              fput(F.f, wl.data(), nw3) && fput(F.f, ws.data(), nw3) && fput(F.f, we.data(), nw3) &&
+              fput(F.f, sc.data(), sc.size()) && fput(F.f, info.data(), info.size());
+    if (!ok) return set_err(c, UGKWP_EIO, "write failed");
+    const int rc = c->precision ? save_store(c, c->A32, F.f) : save_store(c, c->A, F.f);
+    if (rc) return rc;
+    if (fflush(F.f) != 0) return set_err(c, UGKWP_EIO, "write failed");
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return set_err(c, UGKWP_EIO, "cannot rename %s", tmp.c_str());
+  return UGKWP_OK;
+}
+
+int ugkwp_load(ugkwp_ctx *c, const char *path) {
+  if (!c || !path) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  File F;
+  F.f = fopen(path, "rb");
+  if (!F.f) return set_err(c, UGKWP_EIO, "cannot open %s", path);
+  SaveHeader h{};
+  if (!fget(F.f, &h, 1)) return set_err(c, UGKWP_EIO, "checkpoint truncated");
+  if (memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1) return set_err(c, UGKWP_EINVAL, "not a checkpoint");
+  if (h.dim != c->dim || h.precision != c->precision || h.D != c->P.D || h.ncase != c->ncase || h.nc != c->nc ||
+      h.nb != c->nb || h.nwall != c->nwall || h.nf != c->nf || h.n_ret < 0 || h.step < 0 || h.step >= (1 << 20))
+    return set_err(c, UGKWP_EINVAL, "checkpoint does not match this context's mesh and parameters");
+  const size_t nc = c->nc, nw3 = c->nwall * 3;
+  std::vector<double> W(nc * c->nw), dt(nc), rp(nc), rs(nc), rm(nc), wl(nw3), ws(nw3), we(nw3),
+      sc(c->ncase * kScalN);
+  std::vector<int64_t> info(kInfoN);
+  bool ok = fget(F.f, W.data(), W.size()) && fget(F.f, dt.data(), nc) && fget(F.f, rp.data(), nc) &&
+            fget(F.f, rs.data(), nc) && fget(F.f, rm.data(), nc) && fget(F.f, wl.data(), nw3) &&
+            fget(F.f, ws.data(), nw3) && fget(F.f, we.data(), nw3) && fget(F.f, sc.data(), sc.size()) &&
+            fget(F.f, info.data(), info.size());
+  if (!ok) return set_err(c, UGKWP_EIO, "checkpoint truncated");
+  for (size_t i = 0; i < nc; ++i)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return set_err(c, UGKWP_EINVAL, "checkpoint time steps invalid");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  int rc = ensure_capacity(c, h.n_ret);
+  if (rc) return rc;
+  std::vector<int> cell;
+  rc = c->precision ? load_store(c, c->A32, F.f, h.n_ret, cell) : load_store(c, c->A, F.f, h.n_ret, cell);
+  if (rc) return rc;
+  std::vector<int64_t> ro(2 * nc + 1, 0);
+  for (int v : cell) ro[v + 1]++;
+  for (size_t i = 0; i < nc; ++i) ro[i + 1] += ro[i];
+  for (size_t i = nc + 1; i <= 2 * nc; ++i) ro[i] = h.n_ret;
+  h2d(c, c->S.W, W);
+  h2d(c, c->S.dt, dt);
+  h2d(c, c->S.rho_prev, rp);
+  h2d(c, c->S.rho_sum, rs);
+  h2d(c, c->S.rho_mean_prev, rm);
+  if (nw3) {
+    h2d(c, c->S.wlast, wl);
+    h2d(c, c->S.wsum, ws);
+    h2d(c, c->S.wema, we);
+  }
+  h2d(c, c->S.scal, sc);
+  h2d(c, c->S.info, info);
+  h2d(c, c->S.roff, ro);
+  const int64_t step = h.step;
+  HIPCHK(hipMemcpyAsync(c->S.dstep, &step, sizeof step, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+  c->xw_exp = h.xw;
+  c->xm_exp = h.xm;
+  c->xr_exp = h.xr;
+  c->P.xw = make_window(h.xw, kTallyLimbs);
+  c->P.xm = make_window(h.xm, kTallyLimbs);
+  c->P.xr = make_window(h.xr, 4);
+  // crossing ratios (and the FP32 tables) from the restored time steps
+  Geo g = c->geo();
+  hipLaunchKernelGGL(k_init_ratio, dim3(nblk(c->nc * c->NV, 256)), dim3(256), 0, c->stream, g, c->S.dt, c->lfn);
+  if (c->precision)
+    hipLaunchKernelGGL(k_init_mixed, dim3(nblk(c->nc * c->NV, 256)), dim3(256), 0, c->stream, g, c->lfn32, c->lda);
+  c->n_ret = h.n_ret;
+  c->step = h.step;
+  if (c->precision) {
+    if (c->dim == 1) launch_tally<1, float>(c, g, c->A32, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+    else launch_tally<2, float>(c, g, c->A32, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+  } else {
+    if (c->dim == 1) launch_tally<1, double>(c, g, c->A, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+    else launch_tally<2, double>(c, g, c->A, c->S.roff, c->S.Sret, c->S.Xret, nullptr, c->S.Mraw);
+  }
+  HIPCHK(hipGetLastError());
+  rc = check_flags(c);
+  if (rc) return rc;
+  return sync_counts(c);
 }
 
 int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
   if (!c) return UGKWP_EINVAL;
   const size_t bytes = c->nc * c->nw * sizeof(double);
-  if (Sminus) HIPCHK(hipMemcpyAsync(Sminus, c->S.Sm, bytes, hipMemcpyDeviceToHost, c->stream));
-  if (Splus) HIPCHK(hipMemcpyAsync(Splus, c->S.Sp, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (Sminus) HIPCHK(hipMemcpyAsync(Sminus, c->Sm_prev, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (Splus) HIPCHK(hipMemcpyAsync(Splus, c->Sp_prev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return UGKWP_OK;
 }
@@ -1579,13 +1979,17 @@ int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
 int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
   if (!c || !t) return UGKWP_EINVAL;
   if (t->batch_steps < 1 || t->batch_steps > 1024 || (t->use_graph != 0 && t->use_graph != 1) ||
-      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) || (t->shakhov_lanes != 1 && t->shakhov_lanes != 2 && t->shakhov_lanes != 4 &&
-       t->shakhov_lanes != 8 && t->shakhov_lanes != 16))
+      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) ||
+      (t->shakhov_lanes != 1 && t->shakhov_lanes != 2 && t->shakhov_lanes != 4 && t->shakhov_lanes != 8 &&
+       t->shakhov_lanes != 16) ||
+      t->max_crossings < 1 || t->max_crossings > 10000)
     return set_err(c, UGKWP_EINVAL, "tuning value out of range");
   c->batch_steps = t->batch_steps;
   c->use_graph = t->use_graph;
   c->transport_block = t->transport_block;
   c->shakhov_lanes = t->shakhov_lanes;
+  c->max_crossings = t->max_crossings;
+  c->P.max_cross = t->max_crossings;
   return UGKWP_OK;
 }
 
@@ -1595,6 +1999,7 @@ int ugkwp_get_tuning(ugkwp_ctx *c, ugkwp_tuning *t) {
   t->use_graph = c->use_graph;
   t->transport_block = c->transport_block;
   t->shakhov_lanes = c->shakhov_lanes;
+  t->max_crossings = c->max_crossings;
   return UGKWP_OK;
 }
 

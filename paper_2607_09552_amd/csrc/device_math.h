@@ -410,6 +410,119 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63u); }
 
+// ---------------------------------------------------------------------------
+// Order-independent sums.  The particle tallies of Eqs. (24), (29)-(30), the
+// wall impulses and the residual sums are accumulated in fixed point: a term
+// v is cut into NL 32-bit chunks of a window [2^(E - 32 NL), 2^E),
+//   v = sum_j c_j 2^(E - 32 NL + 32 j),  c_j integer, |c_j| < 2^32,
+// each chunk held in an FP64 value (bits of v below the window are dropped).
+// Sums of up to 2^20 chunks stay below 2^52 and are exact in FP64, so a
+// chunk total does not depend on the order in which the terms arrive
+// (lane-strided loops, wavefront trees or atomics).  The total is rounded
+// once to the FP64 value nearest the window's exact sum (ties to even).
+// Each accumulated quantity has its own window E, fixed at init.  The
+// tallies use NL = 6: a 192-bit window keeps every particle term of any cell
+// (particle masses span some 30 decades between a stagnation layer and a
+// near-vacuum wake) exact to far below an ulp of its cell's content, so the
+// rounded tally is that of the exact sum; the others use NL = 4.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLimbs = 6;
+struct XWin {
+  double down;           // 2^(32 - E): scales a term so that its top chunk is the integer part
+  double up[kMaxLimbs];  // 2^(E - 32 NL + 32 j): weight of chunk j
+};
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kTwoM32 = 1.0 / 4294967296.0;
+
+// Chunks of v in window w; returns false if |v| >= 2^E or v is not finite.
+template <int NL>
+__device__ __forceinline__ bool xs_split(double v, const XWin &w, double c[NL]) {
+  double t = v * w.down;
+  const bool ok = fabs(t) < kTwo32;
+#pragma unroll
+  for (int j = NL - 1; j > 0; --j) {
+    c[j] = trunc(t);
+    t = (t - c[j]) * kTwo32;
+  }
+  c[0] = trunc(t);
+  return ok;
+}
+
+// Carry-normalizes chunk totals L (|L_j| < 2^52): L_0..L_{NL-2} in
+// [0, 2^32), the sign in L_{NL-1}.  Exact.
+template <int NL>
+__device__ __forceinline__ void xs_normalize(double L[NL]) {
+#pragma unroll
+  for (int j = 0; j < NL - 1; ++j) {
+    const double cy = floor(L[j] * kTwoM32);
+    L[j] = L[j] - cy * kTwo32;
+    L[j + 1] = L[j + 1] + cy;
+  }
+}
+
+// The FP64 value nearest sum_j L_j 2^(E - 32 NL + 32 j) (ties to even).
+// After normalization the nonzero chunks are nonoverlapping partials of
+// increasing magnitude; they are added from the top, and an exact half-way
+// case is settled by the sign of the next partial below (the final step of
+// Shewchuk's exactly rounded summation, 1997).
+template <int NL>
+__device__ __forceinline__ double xs_round(const double Lin[NL], const XWin &w) {
+  double L[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) L[j] = Lin[j];
+  xs_normalize<NL>(L);
+  double p[NL];
+  int n = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j)
+    if (L[j] != 0.0) p[n++] = L[j] * w.up[j];
+  if (n == 0) return 0.0;
+  double hi = p[--n], lo = 0.0;
+  while (n > 0) {
+    const double x = hi, y = p[--n];
+    hi = x + y;
+    const double yr = hi - x;
+    lo = y - yr;
+    if (lo != 0.0) break;
+  }
+  if (n > 0 && ((lo < 0.0 && p[n - 1] < 0.0) || (lo > 0.0 && p[n - 1] > 0.0))) {
+    const double y = lo * 2.0;
+    const double x = hi + y;
+    const double yr = x - hi;
+    if (y == yr) hi = x;
+  }
+  return hi;
+}
+
+// One halving exchange: lanes with bit `o` set keep v[H..2H), the others
+// v[0..H), each adding its partner's copy; the kept half moves to v[0..H).
+template <int H, int P>
+__device__ __forceinline__ void spread_step(double (&v)[P], int o, bool hi) {
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double send = hi ? v[j] : v[j + H];
+    const double keep = hi ? v[j + H] : v[j];
+    v[j] = keep + __shfl_xor(send, o, 64);
+  }
+  if constexpr (H > 1) spread_step<H / 2>(v, o >> 1, (lane_id() & (o >> 1)) != 0);
+}
+
+template <int P>
+__device__ __forceinline__ double wave_sum_spread(double (&v)[P]) {
+  static_assert(P >= 2 && P <= 64 && (P & (P - 1)) == 0, "P: a power of two in [2, 64]");
+  spread_step<P / 2>(v, 32, (lane_id() & 32) != 0);
+  // the remaining exchanges are plain sums
+#pragma unroll
+  for (int o = 32 / (P / 2) / 2; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+  return v[0];
+}
+
+template <int P>
+__host__ __device__ constexpr int spread_shift() {
+  return P == 64 ? 0 : P == 32 ? 1 : P == 16 ? 2 : P == 8 ? 3 : P == 4 ? 4 : P == 2 ? 5 : 6;
+}
+
 __device__ __forceinline__ int popc_below(uint64_t mask) {
   const int l = lane_id();
   const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -11,13 +11,19 @@ constexpr int kPad = INT32_MIN;      // padding local face (cells with fewer fac
 constexpr int kNoFace = INT32_MIN;   // lface entry of a padding local face
 constexpr int kScanBlock = 1024;
 constexpr int kMaxCross = 10000;
+constexpr int kTallyLimbs = 6;  // chunks of the exact particle tallies (a 192-bit window)
 
 // kBcMaxwell: wall with accommodation alpha (data T_w, alpha), Sec. V.B
 enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4, kBcMaxwell = 6 };
 // kFlagConverged is not an error: the step that reached the residual target
 // (scal[kScalTarget] > 0) is done and later steps are skipped
-enum : int { kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16, kFlagConverged = 32 };
-enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatN = 4 };
+// kFlagRange: a term fell outside its exact-summation window (see XWin)
+enum : int {
+  kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16, kFlagConverged = 32,
+  kFlagRange = 64
+};
+// kStatCapped: new particles whose Shakhov acceptance-rejection ran out of attempts
+enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatCapped = 3, kStatN = 4 };
 // Step statistics are spread over kStatSlots copies (slot = block id mod
 // kStatSlots) so that the per-wave counter updates do not serialize on one
 // address; readers sum the slots.
@@ -60,6 +66,7 @@ struct Geo {
   const int64_t *case_bface;  // [ncase + 1] first boundary face of each case
   const uint64_t *case_seed;  // [ncase] Philox seed of each case
   const double *case_par;     // [ncase * kCaseN] per-case gas and reference values
+  const int64_t *case_wall;   // [ncase + 1] first wall face of each case
   // mixed precision only (particle positions relative to a cell anchor):
   const double2 *anchor; // [nc] anchor of each cell (its centroid)
   const float4 *lfn32;   // [nc*NV] normal (x, y), offset n.(v_k - anchor) (z), crossing ratio (w)
@@ -77,6 +84,11 @@ struct Params {
   int wave_only;  // E = 0: no particles, the waves carry all of g^h
   uint64_t seed;
   double rho_inf, u_inf_x, u_inf_y, U_inf, T_inf, L_ref;
+  int max_cross;  // crossings per particle and step before the step fails as a runaway
+  // exact-summation windows: particle tallies and wall impulses (xw), raw
+  // moments of the heat flux (xm), kTallyLimbs chunks each; residual sums
+  // (xr), four chunks
+  XWin xw, xm, xr;
 };
 
 // Per-step and persistent state (device pointers).
@@ -84,7 +96,8 @@ struct State {
   double *W, *Wh, *dt, *tau, *E;
   double2 *tdt;                         // [nc] (tau, dt) for the transport
   int *hvalid;
-  double *Sret, *Sretn, *Sm, *Sp, *Scol;  // tallies sum_k m_k Psi_k [nc*NW]
+  double *Sret, *Sretn, *Sm, *Sp;       // tallies sum_k m_k Psi_k [nc*NW]: retained (W^p Omega), W^{p,-}, W^{p,+}
+  double *Xret, *Xretn;                 // [nc*NW*kTallyLimbs] the retained tally as normalized exact chunks (window xw)
   double *ar;                           // [nc*kArN] Shakhov acceptance-rejection table (Pr != 1)
   double *Mraw, *Mrawn;                 // [nc*5] sum m u_a |u|^2 (a = x, y), sum m u_x u_x, u_x u_y, u_y u_y
   int64_t *roff;                        // [nc + 1] offsets of the retained (sorted) store
@@ -95,17 +108,18 @@ struct State {
   int *ghvalid;                         // [nb]
   int64_t *nghost;                      // entered ghost particles this step
   double *tghost;                       // remaining time of entered ghost particles
-  int *count;                           // [nc] kept particles per cell
-  int64_t *coff;                        // [nc + 1] exclusive scan of count
-  int *rank;                            // [cap] 0 kept, -1 removed or left
-  int64_t *cursor;                      // [nc] slot cursor of the scatter
+  int *count;                           // [2 nc] particles ending in each cell: kept (c), collided (nc + c)
+  int64_t *coff;                        // [2 nc + 1] exclusive scan of count
+  int *rank;                            // [cap] per transported slot: -1 left or unused, else kRank* bits
+  int64_t *cursor;                      // [2 nc] slot cursor of the scatter
   int64_t nc_scatter;                   // number of cells (for kernels without Geo)
   double *Fs;                           // [nf*NW] time-averaged face flux times s_j
   double *rho_prev, *rho_sum, *rho_mean_prev;
-  double *resid;                        // [ncase*3] residual sums
-  double *wimp;                         // [nb*3] particle impulse x, y and energy at walls
+  double *resid;                        // [ncase*2*4] chunks of the residual sums (window xr)
+  double *area;                         // [ncase] area of each case (exact sum of the cell volumes)
+  double *wimp;                         // [nb*3*kTallyLimbs] chunks of the particle impulse x, y and energy at walls (window xw)
   double *wlast, *wsum, *wema;          // [nwall*3] p, tau, q
-  double *cdsum;                        // [ncase] drag of the step
+  double *fd;                           // [nwall] drag force of each wall face in the step
   double *scal;                         // [ncase*kScalN] per case (the target in case 0's slot)
   int64_t *stats;                       // [kStatSlots * kStatN]
   int *flags;
@@ -113,7 +127,15 @@ struct State {
   int64_t *dstep;                       // step counter (keys the random numbers)
   int64_t *info;                        // [kInfoN] counts of the last committed step and running sums
 };
-enum : int { kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, kInfoN };
+// info: counts of the last committed step (total, new, removed, exited,
+// guarded, Shakhov fallbacks), its recorded bounds, and the running work sum
+enum : int {
+  kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, kInfoRemoved, kInfoExited, kInfoGuard, kInfoCapped,
+  kInfoN
+};
+// transport outcome of a slot (rank): bit 0 collided (Eq. (51)), bit 1 the
+// velocity changed at a wall or symmetry face
+enum : int { kRankCollided = 1, kRankReflected = 2 };
 
 // Particle store, structure of arrays.  R = double: global positions (the
 // FP64 path); R = float: positions relative to the cell's anchor and FP32
@@ -145,10 +167,12 @@ template <int DIM, class R> __global__ void k_sample_ghosts(Geo, Params, State, 
 // code for the optional features (their registers would cost occupancy).
 enum : int { kFeatEi = 1, kFeatMaxwell = 2 };  // particles carry |xi|^2 / 2; Maxwell wall faces exist
 template <int DIM, int NV, class R, int FEAT>
-__global__ void k_transport(Geo, Params, State, StoreT<R>, int64_t);
-template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, int64_t);
-template <int DIM, class R>
-__global__ void k_cell_tally(Geo, StoreT<R>, const int64_t *, double *, double *, int, const int *);
+__global__ void k_transport(Geo, Params, State, StoreT<R>, StoreT<R>, int64_t);
+template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, StoreT<R>, int64_t);
+template <int DIM, class R, bool RAW>
+__global__ void k_cell_tally(Geo, Params, StoreT<R>, const int64_t *, double *, double *, double *, double *, int *,
+                             const int *);
+__global__ void k_case_area(Geo, double *, XWin);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State);
 template <int DIM> __global__ void k_surface(Geo, Params, State);

@@ -5,6 +5,8 @@
 // The pre-transport set is [retained | new from cells | entered from ghosts].
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace ugk {
 
 // ---------------------------------------------------------------------------
@@ -455,15 +457,16 @@ __device__ __forceinline__ void sample_position(const Geo &g, int64_t cell, uint
 
 // One acceptance-rejection attempt `att` for the Shakhov target (Eq. (4))
 // against the Maxwellian of W^h (table a of the cell, from cell_prep):
-// draws z (calls 2 att, 2 att + 1), rejects beyond 6 sigma, else accepts
-// with probability (1 + phi) / B.  z is set even when rejected.
+// draws z (calls 2 att, 2 att + 1); returns 0 if the deviation lies beyond
+// the 6 sigma cut, 1 if inside but rejected, 2 if accepted (probability
+// (1 + phi) / B).  z is set in every case.
 template <int DIM>
-__device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a, uint64_t seed, uint64_t pid,
-                                                int64_t step, uint32_t att, double z[3]) {
+__device__ __forceinline__ int shakhov_attempt(const Params &p, const double *a, uint64_t seed, uint64_t pid,
+                                               int64_t step, uint32_t att, double z[3]) {
   gauss3(seed, pid, step, kVel, 2 * att, z);
   const double sig = a[kArSig];
   const double dz = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]) * sig;
-  if (dz > a[kArCmax]) return false;
+  if (dz > a[kArCmax]) return 0;
   double ea, eb;
   rng2(seed, pid, step, kShakhov, att, ea, eb);
   const double RT = a[kArRT];
@@ -472,7 +475,7 @@ __device__ __forceinline__ bool shakhov_attempt(const Params &p, const double *a
   const double c2 = cx * cx + cy * cy + cz * cz;
   const double cq = DIM == 2 ? cx * a[kArQx] + cy * a[kArQy] : cx * a[kArQx];
   const double phi = ((1.0 - p.Pr) * cq) / (5.0 * a[kArP] * RT) * (c2 / RT - 5.0);
-  return ea * a[kArBnd] <= 1.0 + phi;
+  return ea * a[kArBnd] <= 1.0 + phi ? 2 : 1;
 }
 
 // Draw pass: one thread per new particle of the interior cells.  The birth
@@ -512,6 +515,7 @@ __device__ __forceinline__ void sample_draw_one(const Geo &g, const Params &p, c
   out.pid[o] = pid;
   out.cell[o] = static_cast<int>(i);
   out.m[o] = st.mnew[i];
+  (void)NW;
 }
 
 template <int DIM, class R>
@@ -523,7 +527,9 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
 }
 
 // Shakhov deviations of the new particles (Pr != 1).  The result is that of
-// the sequential rule: the lowest accepted attempt of 0..63, else attempt 63.
+// the sequential rule: the lowest accepted attempt of 0..63; if none is
+// accepted (a fallback, counted), the lowest attempt inside the 6 sigma cut,
+// or z = 0 if there is none.
 // An attempt is a long dependent chain (Philox, logarithms, sine/cosine) and
 // the number of attempts varies widely (about the acceptance bound B; all
 // 64 in near-vacuum cells where B is huge), so work is spread over lanes:
@@ -556,12 +562,18 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     cell = out.cell[n_ret + kp];
     seed = case_seed(g, p, case_of(g, cell));
   }
+  int ncapped = 0;
   // phase 1
   {
     double z[3] = {0.0, 0.0, 0.0};
-    const bool acc = act && shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step,
-                                                 static_cast<uint32_t>(s1), z);
-    const uint64_t seg = (__ballot(acc) >> (g1 * K1)) & (K1 == 64 ? ~0ull : ((1ull << K1) - 1ull));
+    const int res = act ? shakhov_attempt<DIM>(p, st.ar + static_cast<int64_t>(cell) * kArN, seed, pid, step,
+                                               static_cast<uint32_t>(s1), z)
+                        : 0;
+    const uint64_t gmask = K1 == 64 ? ~0ull : ((1ull << K1) - 1ull);
+    const uint64_t seg = (__ballot(res == 2) >> (g1 * K1)) & gmask;
+    const uint64_t segin = (__ballot(res >= 1) >> (g1 * K1)) & gmask;
+    // lowest attempt inside the cut so far (phase 1 attempt = lane in group)
+    const int first_in = segin ? __ffsll(static_cast<long long>(segin)) - 1 : -1;
     if (act && seg != 0 && s1 == __ffsll(static_cast<long long>(seg)) - 1) {
       const int64_t o = n_ret + kp;
       out.ux[o] = static_cast<R>(z[0]);
@@ -587,23 +599,37 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
       const uint64_t gseed = __shfl(seed, sv, 64);
       const int gcell = __shfl(cell, sv, 64);
       const int64_t gk = __shfl(kp, sv, 64);
+      int gin = __shfl(first_in, sv, 64);
       const double *tab = st.ar + static_cast<int64_t>(gcell) * kArN;
       bool gdone = src < 0;
       uint32_t a = static_cast<uint32_t>(K1);
       while (__ballot(!gdone)) {
         const uint32_t att = a + static_cast<uint32_t>(sl);
         double w[3] = {0.0, 0.0, 0.0};
-        bool ok = false;
-        if (!gdone && att < 64) ok = shakhov_attempt<DIM>(p, tab, gseed, gpid, step, att, w);
-        const uint64_t sg = (__ballot(ok) >> (grp * L)) & segm;
+        int res2 = 0;
+        if (!gdone && att < 64) res2 = shakhov_attempt<DIM>(p, tab, gseed, gpid, step, att, w);
+        const uint64_t sg = (__ballot(res2 == 2) >> (grp * L)) & segm;
+        const uint64_t sgin = (__ballot(res2 >= 1) >> (grp * L)) & segm;
         if (!gdone) {
-          if (sg != 0 || a + static_cast<uint32_t>(L) >= 64) {
-            const int wr = sg != 0 ? __ffsll(static_cast<long long>(sg)) - 1 : static_cast<int>(63 - a);
-            if (sl == wr) {
+          if (gin < 0 && sgin != 0) gin = static_cast<int>(a) + __ffsll(static_cast<long long>(sgin)) - 1;
+          if (sg != 0) {
+            if (sl == __ffsll(static_cast<long long>(sg)) - 1) {
               const int64_t d = n_ret + gk;
               out.ux[d] = static_cast<R>(w[0]);
               out.uy[d] = static_cast<R>(w[1]);
               out.uz[d] = static_cast<R>(w[2]);
+            }
+            gdone = true;
+          } else if (a + static_cast<uint32_t>(L) >= 64) {
+            // no attempt accepted: the first draw inside the cut, else 0
+            if (sl == 0) {
+              double zf[3] = {0.0, 0.0, 0.0};
+              if (gin >= 0) gauss3(gseed, gpid, step, kVel, 2 * static_cast<uint32_t>(gin), zf);
+              const int64_t d = n_ret + gk;
+              out.ux[d] = static_cast<R>(zf[0]);
+              out.uy[d] = static_cast<R>(zf[1]);
+              out.uz[d] = static_cast<R>(zf[2]);
+              ++ncapped;
             }
             gdone = true;
           } else {
@@ -613,13 +639,24 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
       }
     }
   }
+  const uint64_t mc = __ballot(ncapped > 0);
+  if (mc) {
+    // at most one capped particle per lane per round; sum the lanes' counts
+    int tot = ncapped;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if (lane == 0)
+      atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[(blockIdx.x % kStatSlots) * kStatN + kStatCapped]),
+                static_cast<unsigned long long>(tot));
+  }
 }
 
 // Moment-matching pass: one wavefront per cell over its new particles.  For
 // N >= 2 the deviations are shifted to zero mean and scaled so that the set
 // carries exactly the momentum and thermal energy of W^hp (Eq. (25)):
 // u = U^h + sqrt(R T^h) ((z - zbar) alpha), alpha = sqrt(3 N / sum |z - zbar|^2).
-// Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)).
+// Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)), rounded
+// once from the exact chunks of both.
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   constexpr int NW = DIM + 2;
@@ -628,9 +665,12 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
   const int64_t n_ret = st.roff[g.nc];
   const int lane = lane_id();
   const int N = n_ret + st.noff[i] + st.ncount[i] <= cap ? st.ncount[i] : 0;
-  double snew[NW];
+  // chunks of the new set's tally: value q * kTallyLimbs + j = chunk j of component q
+  constexpr int NLT = kTallyLimbs;
+  double xc[32];
 #pragma unroll
-  for (int q = 0; q < NW; ++q) snew[q] = 0.0;
+  for (int q = 0; q < 32; ++q) xc[q] = 0.0;
+  bool ok = true;
   if (N > 0) {
     const int64_t base = n_ret + st.noff[i];
     const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
@@ -675,17 +715,33 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       }
       const double u0 = r0, u1 = r1, u2 = r2;
       const double en = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2) + ei;
-      snew[0] += mk;
-      snew[1] += mk * u0;
-      if (DIM == 2) snew[2] += mk * u1;
-      snew[NW - 1] += mk * en;
+      double t[NW];
+      t[0] = mk;
+      t[1] = mk * u0;
+      if (DIM == 2) t[2] = mk * u1;
+      t[NW - 1] = mk * en;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        double c[NLT];
+        ok = xs_split<NLT>(t[q], p.xw, c) && ok;
+#pragma unroll
+        for (int jj = 0; jj < NLT; ++jj) xc[q * NLT + jj] += c[jj];
+      }
     }
   }
+  if (__ballot(!ok) && lane == 0) atomicOr(st.flags, kFlagRange);
+  // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
+  const double tot = wave_sum_spread<32>(xc);
+  double L[NLT];
 #pragma unroll
-  for (int q = 0; q < NW; ++q) snew[q] = wave_sum(snew[q]);
-  if (lane == 0) {
+  for (int jj = 0; jj < NLT; ++jj) L[jj] = __shfl(tot, (lane + 2 * jj) & 63, 64);
+  const int v = lane >> 1;
+  const int q = v / NLT;
+  if ((lane & 1) == 0 && v % NLT == 0 && q < NW) {
+    const double *xr = st.Xret + (i * NW + q) * NLT;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) st.Sm[i * NW + q] = st.Sret[i * NW + q] + snew[q];
+    for (int jj = 0; jj < NLT; ++jj) L[jj] += xr[jj];
+    st.Sm[i * NW + q] = xs_round<NLT>(L, p.xw);
   }
 }
 
@@ -795,10 +851,28 @@ __device__ __forceinline__ typename Face<R>::type load_face(const Geo &g, int64_
   else return g.lfn[l];
 }
 
+// Particle impulse on a wall face: exact chunks (window xw) of
+// m (u_before - u_after) (x, y) and of the energy given up, added
+// atomically (order-independent).
+__device__ __forceinline__ void wall_impulse(const Params &p, const State &st, int bf, double ix, double iy, double ie) {
+  constexpr int NLT = kTallyLimbs;
+  const double v[3] = {ix, iy, ie};
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double c[NLT];
+    ok = xs_split<NLT>(v[q], p.xw, c) && ok;
+#pragma unroll
+    for (int j = 0; j < NLT; ++j)
+      if (c[j] != 0.0) atomicAdd(&st.wimp[(3 * bf + q) * NLT + j], c[j]);
+  }
+  if (!ok) atomicOr(st.flags, kFlagRange);
+}
+
 template <int DIM, int NV, class R, int FEAT>
 __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, const State &st, const StoreT<R> &s,
-                                              int64_t n_ret, int64_t gbase, int64_t n_total, int64_t step,
-                                              int64_t k) {
+                                              const StoreT<R> &tw, int64_t n_ret, int64_t gbase, int64_t n_total,
+                                              int64_t step, int64_t k) {
   constexpr int NW = DIM + 2;
   constexpr bool F32 = IsF32<R>::value;
   using F4 = typename Face<R>::type;
@@ -870,8 +944,10 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
         if (DIM == 2) y = y + u1 * t;
         break;
       }
-      if (++ncross > kMaxCross) {
+      if (++ncross > p.max_cross) {
+        // the step fails: later kernels of the step (and of the batch) skip
         atomicOr(st.flags, kFlagRunaway);
+        atomicOr(st.halt, 1);
         break;
       }
       x = x + u0 * best;
@@ -942,8 +1018,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
           u0 = -u0;
         }
         const double c0 = u0, c1 = u1;
-        atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
-        atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
+        wall_impulse(p, st, bf, m * (b0 - c0), m * (b1 - c1), 0.0);
         load_cell(cell);
         continue;
       }
@@ -969,8 +1044,6 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       const double c0 = u0, c1 = u1, c2 = u2;
       const double eb = 0.5 * (b0 * b0 + b1 * b1 + b2 * b2);
       const double ea = 0.5 * (c0 * c0 + c1 * c1 + c2 * c2);
-      atomicAdd(&st.wimp[3 * bf + 0], m * (b0 - c0));
-      atomicAdd(&st.wimp[3 * bf + 1], m * (b1 - c1));
       if constexpr ((FEAT & kFeatEi) != 0) {
         // internal energy from the wall temperature (draws of this hit)
         const double eib = ei;
@@ -979,46 +1052,38 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
                                          kWallInternalCall0 + static_cast<uint32_t>((hits - 1) * ((p.D + 1) / 2)),
                                          p.D));
         const double eia = ei;
-        atomicAdd(&st.wimp[3 * bf + 2], m * ((eb + eib) - (ea + eia)));
+        wall_impulse(p, st, bf, m * (b0 - c0), m * (b1 - c1), m * ((eb + eib) - (ea + eia)));
       } else {
-        atomicAdd(&st.wimp[3 * bf + 2], m * (eb - ea));
+        wall_impulse(p, st, bf, m * (b0 - c0), m * (b1 - c1), m * (eb - ea));
       }
       load_cell(cell);
     }
-    s.x[k] = x;
-    if (DIM == 2) s.y[k] = y;
+    // results go to the work store: the committed store stays as it was
+    // until the step is complete
+    tw.x[k] = x;
+    if (DIM == 2) tw.y[k] = y;
     if (reflected) {
-      s.ux[k] = u0;
-      s.uy[k] = u1;
-      s.uz[k] = u2;
-      if constexpr ((FEAT & kFeatEi) != 0) s.ei[k] = ei;
+      tw.ux[k] = u0;
+      tw.uy[k] = u1;
+      tw.uz[k] = u2;
+      if constexpr ((FEAT & kFeatEi) != 0) tw.ei[k] = ei;
     }
-    s.m[k] = m;
-    s.cell[k] = cell;
+    tw.m[k] = m;
+    tw.cell[k] = cell;
+    if (!exited) st.rank[k] = (collide ? kRankCollided : 0) | (reflected ? kRankReflected : 0);
+    else st.rank[k] = -1;
   }
   const bool inside = active && !exited;
-  const bool keep = inside && !collide;
-  // collided particles end their flight here (Eq. (51)) and are dropped after
-  // the tally; their share of W^{p,+} (Eq. (30)) is added directly
-  if (inside && collide) {
-    const double v0 = u0, v1 = u1, v2 = u2;
-    double en = 0.5 * (v0 * v0 + v1 * v1 + v2 * v2);
-    if constexpr ((FEAT & kFeatEi) != 0) en = en + static_cast<double>(ei);
-    double *S = st.Scol + static_cast<int64_t>(cell) * NW;
-    atomicAdd(&S[0], m);
-    atomicAdd(&S[1], m * v0);
-    if (DIM == 2) atomicAdd(&S[2], m * v1);
-    atomicAdd(&S[NW - 1], m * en);
-  }
-  // histogram of the kept particles per destination cell (one atomic per
-  // group, no return value needed)
+  // histogram of the particles ending inside per destination: kept ones in
+  // bin `cell`, collided ones (Eq. (51): they end their flight here, enter
+  // W^{p,+} of Eq. (30) and are then dropped) in bin nc + cell; one atomic
+  // per group, no return value needed
   {
-    const int key = keep ? cell : -1;
+    const int key = inside ? (collide ? static_cast<int>(g.nc) + cell : cell) : -1;
     int leader;
     const uint64_t grp = wave_group(key, leader);
     if (key >= 0 && lane_id() == leader) atomicAdd(&st.count[key], __popcll(grp));
   }
-  if (active) st.rank[k] = keep ? 0 : -1;
   // step statistics
   const uint64_t me = __ballot(active && exited), mr = __ballot(inside && collide);
   if (lane_id() == 0) {
@@ -1039,7 +1104,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
 // to 256.
 template <int DIM, int NV, class R, int FEAT>
 __global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 2)
-    k_transport(Geo g, Params p, State st, StoreT<R> s, int64_t cap) {
+    k_transport(Geo g, Params p, State st, StoreT<R> s, StoreT<R> tw, int64_t cap) {
   if (*st.halt) return;
   const int64_t n_ret = st.roff[g.nc];
   const int64_t gbase = n_ret + st.noff[g.nc];
@@ -1049,23 +1114,32 @@ __global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 
   // the grid covers the store capacity, which bounds every step's set
   const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
   if (base >= n_total) return;  // block-uniform: whole wavefronts take part in the grouping
-  transport_one<DIM, NV, R, FEAT>(g, p, st, s, n_ret, gbase, n_total, step, base + threadIdx.x);
+  transport_one<DIM, NV, R, FEAT>(g, p, st, s, tw, n_ret, gbase, n_total, step, base + threadIdx.x);
 }
 
-// Re-sort (counting sort, scatter pass): cursor[c] starts at the exclusive
-// scan of the kept counts; each wavefront claims contiguous slots for its
-// lanes of equal destination with one atomic per group, all groups of the
-// wave in the same instruction.
+// Re-sort (counting sort, scatter pass) into the next committed store b:
+// cursor[c] starts at the exclusive scan of the counts; each wavefront
+// claims contiguous slots for its lanes of equal destination with one atomic
+// per group, all groups of the wave in the same instruction.  Kept
+// particles go to [off[c], off[c+1]) (the next step's retained set, sorted
+// by cell); collided ones to [off[nc+c], off[nc+c+1]) after all kept ones,
+// with only what the tally reads (mass, velocity, internal energy).
+// Positions, masses and cells come from the transport's work store tw,
+// velocities from tw where the transport changed them, else from a.
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R> b, int64_t cap) {
+__global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R> tw, StoreT<R> b, int64_t cap) {
   if (*st.halt) return;
-  const int64_t nt = st.roff[st.nc_scatter] + st.noff[st.nc_scatter] + *st.nghost;
+  const int64_t ncs = st.nc_scatter;
+  const int64_t nt = st.roff[ncs] + st.noff[ncs] + *st.nghost;
   const int64_t n_total = nt < cap ? nt : cap;
   const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
   if (base >= n_total) return;  // block-uniform
   const int64_t k = base + threadIdx.x;
-  const bool live = k < n_total && st.rank[k] >= 0;
-  const int c = live ? a.cell[k] : -1;
+  const int rk = k < n_total ? st.rank[k] : -1;
+  const bool live = rk >= 0;
+  const int cell = live ? tw.cell[k] : 0;
+  const bool col = live && (rk & kRankCollided) != 0;
+  const int c = live ? (col ? static_cast<int>(ncs) + cell : cell) : -1;
   int leader;
   const uint64_t grp = wave_group(c, leader);
   unsigned long long bs = 0;
@@ -1074,69 +1148,131 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
   bs = __shfl(bs, leader >= 0 ? leader : lane_id(), 64);
   if (!live) return;
   const int64_t d = static_cast<int64_t>(bs) + popc_below(grp);
-  b.x[d] = a.x[k];
-  if (DIM == 2) b.y[d] = a.y[k];
-  b.ux[d] = a.ux[k];
-  b.uy[d] = a.uy[k];
-  b.uz[d] = a.uz[k];
-  if (a.ei) b.ei[d] = a.ei[k];
-  b.m[d] = a.m[k];
+  const StoreT<R> &uv = (rk & kRankReflected) ? tw : a;
+  b.ux[d] = uv.ux[k];
+  b.uy[d] = uv.uy[k];
+  b.uz[d] = uv.uz[k];
+  if (a.ei) b.ei[d] = uv.ei[k];
+  b.m[d] = tw.m[k];
+  if (col) return;
+  b.x[d] = tw.x[k];
+  if (DIM == 2) b.y[d] = tw.y[k];
   b.pid[d] = a.pid[k];
-  b.cell[d] = c;
+  b.cell[d] = cell;
 }
 
-// Per-cell tally of the retained (kept) particles after the re-sort, one
-// wavefront per cell over its contiguous range [off[c], off[c+1]):
-// S[c] = sum_k m_k Psi_k (the next step's W^p Omega, Eq. (24), and the kept
-// part of W^{p,+} Omega, Eq. (30)).  With Pr != 1 also the raw moments
-// sum m u_a |u|^2 and sum m u_a u_b that give the heat flux of Eq. (5) once
-// the next step's U is known.  Lane-strided partial sums in a fixed order,
-// then one butterfly per value: no atomics.
-template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_cell_tally(Geo g, StoreT<R> s, const int64_t *__restrict__ off,
-                                                    double *__restrict__ S, double *__restrict__ M, int raw,
-                                                    const int *__restrict__ halt) {
-  constexpr int NW = DIM + 2;
-  const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (c >= g.nc || *halt) return;
-  const int64_t a = off[c], b = off[c + 1];
-  double v[NW], r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < NW; ++q) v[q] = 0.0;
-#pragma unroll 4
+// Per-cell tally after the re-sort, one wavefront per cell over its kept
+// range [off[c], off[c+1]) and collided range [off[nc+c], off[nc+c+1]):
+//   S[c]  = round(sum over kept of m_k Psi_k): the next step's W^p Omega
+//           (Eq. (24)); X[c] its exact chunks (normalized);
+//   Sp[c] = round(sum over kept and collided): W^{p,+} Omega (Eq. (30));
+//   with Pr != 1 the raw moments sum m u_a (|u|^2 + 2 e_i) and
+//   sum m u_a u_b that give the heat flux of Eq. (5) once the next step's
+//   U is known.
+// Every sum is exact (fixed-point chunks, see XWin), so it does not depend on
+// the order of the particles within a cell, which the scatter's atomics
+// leave open.  Also used at restart (empty collided ranges, Sp = null).
+// Adds the chunks of m Psi of the particles in [a, b) to xw at offset AT
+// and, with RAW, the chunks of their raw moments to xr (kTallyLimbs chunks
+// per quantity).
+template <int DIM, bool RAW, int AT, int PW, int PR, class R>
+__device__ __forceinline__ void tally_range(const Params &p, const StoreT<R> &s, int64_t a, int64_t b,
+                                            double (&xw)[PW], double (&xr)[PR], bool &ok) {
+  constexpr int NW = DIM + 2, NLT = kTallyLimbs;
   for (int64_t k = a + lane_id(); k < b; k += 64) {
     const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
     const double ei = s.ei ? static_cast<double>(s.ei[k]) : 0.0;
     const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
-    v[0] += m;
-    v[1] += m * u0;
-    if (DIM == 2) v[2] += m * u1;
-    v[NW - 1] += m * (0.5 * q2 + ei);
-    if (raw) {
-      // sum m u_a (|u|^2 + 2 e_i): with the energy tally it gives the heat
-      // flux of Eq. (5) including the internal part
+    double t[NW];
+    t[0] = m;
+    t[1] = m * u0;
+    if (DIM == 2) t[2] = m * u1;
+    t[NW - 1] = m * (0.5 * q2 + ei);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      double ch[NLT];
+      ok = xs_split<NLT>(t[q], p.xw, ch) && ok;
+#pragma unroll
+      for (int j = 0; j < NLT; ++j) xw[AT + NLT * q + j] += ch[j];
+    }
+    if constexpr (RAW) {
       const double q2i = q2 + 2.0 * ei;
-      r[0] += m * u0 * q2i;
-      r[1] += m * u1 * q2i;
-      r[2] += m * u0 * u0;
-      r[3] += m * u0 * u1;
-      r[4] += m * u1 * u1;
+      const double r[5] = {m * u0 * q2i, m * u1 * q2i, m * u0 * u0, m * u0 * u1, m * u1 * u1};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        double ch[NLT];
+        ok = xs_split<NLT>(r[q], p.xm, ch) && ok;
+#pragma unroll
+        for (int j = 0; j < NLT; ++j) xr[NLT * q + j] += ch[j];
+      }
     }
   }
+}
+
+template <int DIM, bool RAW, class R>
+__device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const StoreT<R> &s, const int64_t *off,
+                                           double *S, double *X, double *Sp, double *M, int *flags, int64_t c) {
+  constexpr int NW = DIM + 2, NLT = kTallyLimbs;
+  constexpr int PR = RAW ? 32 : 2;
+  const int lane = lane_id();
+  const int64_t a = off[c], b = off[c + 1], ca = off[g.nc + c], cb = off[g.nc + c + 1];
+  bool ok = (b - a) + (cb - ca) <= (int64_t{1} << 20);
+  // xw value NLT q + j: chunk j of component q (kept particles, then in a
+  // second pass the collided ones); xr value NLT r + j: chunk j of raw moment r
+  double xw[32], xr[PR];
 #pragma unroll
-  for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
-  if (raw) {
+  for (int v = 0; v < 32; ++v) xw[v] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) r[q] = wave_sum(r[q]);
+  for (int v = 0; v < PR; ++v) xr[v] = 0.0;
+  tally_range<DIM, RAW, 0>(p, s, a, b, xw, xr, ok);
+  // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
+  const double tk = wave_sum_spread<32>(xw);
+  double L[NLT], C[NLT];
+#pragma unroll
+  for (int j = 0; j < NLT; ++j) L[j] = __shfl(tk, (lane + 2 * j) & 63, 64);
+  if (Sp) {
+#pragma unroll
+    for (int v = 0; v < 32; ++v) xw[v] = 0.0;
+    tally_range<DIM, false, 0>(p, s, ca, cb, xw, xr, ok);
+    const double tc = wave_sum_spread<32>(xw);
+#pragma unroll
+    for (int j = 0; j < NLT; ++j) C[j] = __shfl(tc, (lane + 2 * j) & 63, 64);
   }
-  if (lane_id() == 0) {
+  if (__ballot(!ok) && lane == 0) atomicOr(flags, kFlagRange);
+  const int v = lane >> 1, q = v / NLT;
+  if ((lane & 1) == 0 && v % NLT == 0 && q < NW) {
+    xs_normalize<NLT>(L);
 #pragma unroll
-    for (int q = 0; q < NW; ++q) S[c * NW + q] = v[q];
-    if (raw) {
+    for (int j = 0; j < NLT; ++j) X[(c * NW + q) * NLT + j] = L[j];
+    S[c * NW + q] = xs_round<NLT>(L, p.xw);
+    if (Sp) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) M[c * 5 + q] = r[q];
+      for (int j = 0; j < NLT; ++j) C[j] += L[j];
+      Sp[c * NW + q] = xs_round<NLT>(C, p.xw);
     }
   }
+  if constexpr (RAW) {
+    // lane l holds the total of xr value l >> 1; lane 2 NLT r gathers moment r
+    const double tr = wave_sum_spread<32>(xr);
+    double Lr[NLT];
+#pragma unroll
+    for (int j = 0; j < NLT; ++j) Lr[j] = __shfl(tr, (lane + 2 * j) & 63, 64);
+    const int r = v / NLT;
+    if ((lane & 1) == 0 && v % NLT == 0 && r < 5) M[c * 5 + r] = xs_round<NLT>(Lr, p.xm);
+  }
+}
+
+// RAW: also the raw moments (Pr != 1).
+template <int DIM, class R, bool RAW>
+__global__ void __launch_bounds__(256, RAW ? 2 : 4) k_cell_tally(Geo g, Params p, StoreT<R> s,
+                                                                 const int64_t *__restrict__ off,
+                                                                 double *__restrict__ S, double *__restrict__ X,
+                                                                 double *__restrict__ Sp, double *__restrict__ M,
+                                                                 int *__restrict__ flags,
+                                                                 const int *__restrict__ halt) {
+  const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  if (c >= g.nc || *halt) return;  // whole wavefront
+  cell_tally<DIM, RAW>(g, p, s, off, S, X, Sp, M, flags, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1227,15 +1363,15 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
 // with W^{fr,p} = W^{p,+} - W^{p,-} (Eq. (29)); faces in fixed local order.
 // Invalid results (a cell emptied into vacuum) take the content of the
 // particles that ended in the cell, or a vacuum floor state.
-// Also the residual sums and the running mean of the density.
-// ---------------------------------------------------------------------------
+// Also the residual sums (exact chunks, per case) and the running mean of
+// the density.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   if (*st.halt) return;
   const int64_t step = *st.dstep;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  double r[3] = {0.0, 0.0, 0.0};
+  double r[2] = {0.0, 0.0};
   bool guarded = false;
   if (i < g.nc) {
     double acc[NW];
@@ -1255,9 +1391,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
     double Wn[NW];
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
-      const double sp = st.Sretn[i * NW + q] + st.Scol[i * NW + q];
-      st.Sp[i * NW + q] = sp;
-      const double frp = sp / vol - st.Sm[i * NW + q] / vol;
+      const double frp = st.Sp[i * NW + q] / vol - st.Sm[i * NW + q] / vol;
       Wn[q] = (st.W[i * NW + q] - coef * acc[q]) + frp;
     }
     const Prim<DIM> s = prim<DIM>(Wn, p.NR);
@@ -1283,49 +1417,47 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
     const double rho = Wn[0];
     const double d = rho - st.rho_prev[i];
     r[0] = vol * d * d;
-    r[1] = vol;
     const double sum = st.rho_sum[i] + rho;
     st.rho_sum[i] = sum;
     const double mean = sum / static_cast<double>(step + 1);
     const double dm = step == 0 ? 0.0 : mean - st.rho_mean_prev[i];
-    r[2] = vol * dm * dm;
+    r[1] = vol * dm * dm;
     st.rho_mean_prev[i] = mean;
     st.rho_prev[i] = rho;
   }
+  const int lane = lane_id();
   const uint64_t gm = __ballot(guarded);
-  if (lane_id() == 0 && gm)
+  if (lane == 0 && gm)
     atomicAdd(reinterpret_cast<unsigned long long *>(&st.stats[(blockIdx.x % kStatSlots) * kStatN + kStatGuard]),
               static_cast<unsigned long long>(__popcll(gm)));
-  if (!g.ccase) {
+  double rc[2][4];
+  bool ok = true;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) r[q] = wave_sum(r[q]);
-    if (lane_id() == 0) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[q], r[q]);
-    }
-    return;
-  }
-  // a batch: the sums go to the case of each cell (the cells of a case are
+  for (int q = 0; q < 2; ++q) ok = xs_split<4>(r[q], p.xr, rc[q]) && ok;
+  if (__ballot(!ok) && lane == 0) atomicOr(st.flags, kFlagRange);
+  // the sums go to the case of each cell (the cells of a case are
   // contiguous, so a wavefront holds one or two cases)
-  const int key = i < g.nc ? g.ccase[i] : -1;
+  const int key = i < g.nc ? case_of(g, i) : -1;
   uint64_t todo = __ballot(key >= 0);
   while (todo) {
     const int l = __ffsll(static_cast<long long>(todo)) - 1;
     const int cs = __builtin_amdgcn_readlane(key, l);
     const bool in = key == cs;
-    double v[3];
+    double v[8];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) v[q] = wave_sum(in ? r[q] : 0.0);
-    if (lane_id() == l) {
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&st.resid[3 * cs + q], v[q]);
-    }
+      for (int j = 0; j < 4; ++j) v[4 * q + j] = in ? rc[q][j] : 0.0;
+    // lane 8 w holds the total of chunk value w = 4 q + j
+    const double tot = wave_sum_spread<8>(v);
+    if ((lane & 7) == 0 && tot != 0.0) atomicAdd(&st.resid[8 * cs + (lane >> 3)], tot);
     todo &= ~__ballot(in);
   }
 }
 
 // a10: wall pressure, shear and heat flux (wave + particle impulses per unit
-// area and time), their running sum and EMA (2/1001), and the drag sum.
+// area and time), their running sum and EMA (2/1001), and the drag force of
+// each wall face (summed per case in a fixed order by k_finish).
 template <int DIM>
 __global__ void k_surface(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
@@ -1342,17 +1474,20 @@ __global__ void k_surface(Geo g, Params p, State st) {
   double Fl[NW];
 #pragma unroll
   for (int q = 0; q < NW; ++q) Fl[q] = st.Fs[static_cast<int64_t>(f) * NW + q] / s;
+  double imp[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) imp[q] = xs_round<kTallyLimbs>(st.wimp + (3 * b + q) * kTallyLimbs, p.xw);
   const double nx = fl.x, ny = DIM == 2 ? fl.y : 0.0;
   const double mx = Fl[1], my = DIM == 2 ? Fl[2] : 0.0, eF = Fl[DIM + 1];
   const double sdt = s * st.dt[i];
-  const double px = mx + st.wimp[3 * b] / sdt, py = my + (DIM == 2 ? st.wimp[3 * b + 1] / sdt : 0.0);
+  const double px = mx + imp[0] / sdt, py = my + (DIM == 2 ? imp[1] / sdt : 0.0);
   double v[3];
   v[0] = px * nx + py * ny;
   v[1] = py * nx - px * ny;
-  v[2] = eF + st.wimp[3 * b + 2] / sdt;
+  v[2] = eF + imp[2] / sdt;
   const int cs = case_of(g, i);
   const double ex = case_val(g, cs, kCaseEx, p.u_inf_x / p.U_inf), ey = case_val(g, cs, kCaseEy, p.u_inf_y / p.U_inf);
-  atomicAdd(&st.cdsum[cs], (px * ex + py * ey) * s);
+  st.fd[w] = (px * ex + py * ey) * s;
   constexpr double a = 2.0 / 1001.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -1362,29 +1497,33 @@ __global__ void k_surface(Geo g, Params p, State st) {
   }
 }
 
-// scalar bookkeeping after a step: residuals, C_d (last, sum, EMA), the
-// step's particle counts, then the step counter advances (the step is
-// committed).  A runaway track halts later steps.
-// Bookkeeping after a step: per case the residuals and C_d (last, sum,
-// EMA), one thread per case; then the step's particle counts, and the step
-// counter advances (the step is committed).  A runaway track halts later
-// steps; so does meeting the residual target (every case's r_avg, r_inst in
-// wave-only runs, below it).
+// Bookkeeping after a step: per case (one thread each) the residuals from
+// their exact chunks and the case's area, C_d from the wall faces' drag
+// summed in wall order (last, sum, EMA); then the step's particle counts
+// (the statistics slots summed), and the step counter advances (the step is
+// committed).  Meeting the residual target (every case's r_avg, r_inst in
+// wave-only runs, below it) halts later steps.
 __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
   __shared__ int all_below;
+  __shared__ int64_t stat_sum[kStatN];
   if (blockIdx.x != 0 || *st.halt) return;
   const int64_t step = *st.dstep;
   const double tgt = st.scal[kScalTarget];
   if (threadIdx.x == 0) all_below = 1;
+  if (threadIdx.x < kStatN) stat_sum[threadIdx.x] = 0;
   __syncthreads();
   for (int cs = threadIdx.x; cs < g.ncase; cs += blockDim.x) {
     double *sc = st.scal + cs * kScalN;
     const double rho_inf = case_val(g, cs, kCaseRho, p.rho_inf);
     const double U = case_val(g, cs, kCaseU, p.U_inf), L = case_val(g, cs, kCaseL, p.L_ref);
-    const double *rs = st.resid + 3 * cs;
-    sc[kScalRinst] = sqrt(rs[0] / rs[1]) / rho_inf;
-    sc[kScalRavg] = sqrt(rs[2] / rs[1]) / rho_inf;
-    const double cd = st.cdsum[cs] / (0.5 * rho_inf * U * U * L);
+    const double *rs = st.resid + 8 * cs;
+    const double area = st.area[cs];
+    sc[kScalRinst] = sqrt(xs_round<4>(rs, p.xr) / area) / rho_inf;
+    sc[kScalRavg] = sqrt(xs_round<4>(rs + 4, p.xr) / area) / rho_inf;
+    double fsum = 0.0;
+    const int64_t w0 = g.case_wall ? g.case_wall[cs] : 0, w1 = g.case_wall ? g.case_wall[cs + 1] : g.nwall;
+    for (int64_t w = w0; w < w1; ++w) fsum += st.fd[w];
+    const double cd = fsum / (0.5 * rho_inf * U * U * L);
     constexpr double a = 2.0 / 1001.0;
     sc[kScalCdLast] = cd;
     sc[kScalCdSum] += cd;
@@ -1393,6 +1532,9 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
     // floors the instantaneous one); wave-only runs have no noise
     if (!((p.wave_only ? sc[kScalRinst] : sc[kScalRavg]) < tgt)) atomicAnd(&all_below, 0);
   }
+  for (int k = threadIdx.x; k < kStatSlots * kStatN; k += blockDim.x)
+    if (st.stats[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&stat_sum[k % kStatN]),
+                               static_cast<unsigned long long>(st.stats[k]));
   __syncthreads();
   if (threadIdx.x != 0) return;
   const int64_t nnew = st.noff[nc] + *st.nghost;
@@ -1400,13 +1542,35 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
   st.info[kInfoTotal] = ntot;
   st.info[kInfoNew] = nnew;
   st.info[kInfoSumTotal] += ntot;
+  st.info[kInfoRemoved] = stat_sum[kStatRemoved];
+  st.info[kInfoExited] = stat_sum[kStatExited];
+  st.info[kInfoGuard] = stat_sum[kStatGuard];
+  st.info[kInfoCapped] = stat_sum[kStatCapped];
   *st.dstep = step + 1;
-  if (*st.flags & kFlagRunaway) *st.halt = 1;
   // convergence test: the first step n >= 100 with the residual below the target
   if (tgt > 0.0 && step + 1 >= 100 && all_below) {
     *st.flags |= kFlagConverged;
     *st.halt = 1;
   }
+}
+
+// Area of each case: the exact sum of its cell volumes (one wavefront per case).
+__global__ void k_case_area(Geo g, double *__restrict__ area, XWin w) {
+  const int cs = (blockIdx.x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) >> 6;
+  if (cs >= g.ncase) return;
+  const int64_t c0 = g.ccase ? g.case_cell[cs] : 0, c1 = g.ccase ? g.case_cell[cs + 1] : g.nc;
+  double xc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = c0 + lane_id(); i < c1; i += 64) {
+    double ch[4];
+    xs_split<4>(g.vol[i], w, ch);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xc[j] += ch[j];
+  }
+  const double tot = wave_sum_spread<4>(xc);
+  double L[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) L[j] = __shfl(tot, 16 * j, 64);
+  if (lane_id() == 0) area[cs] = xs_round<4>(L, w);
 }
 
 // After the count scan, before anything of the step is modified: halt if a
@@ -1461,14 +1625,17 @@ UGK_INST(2)
   template __global__ void k_sample_match<D, R>(Geo, Params, State, StoreT<R>, int64_t);                 \
   template __global__ void k_sample_shakhov<D, R>(Geo, Params, State, StoreT<R>, int64_t, uint32_t);     \
   template __global__ void k_sample_ghosts<D, R>(Geo, Params, State, StoreT<R>, int64_t);                \
-  template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, int64_t);                        \
-  template __global__ void k_cell_tally<D, R>(Geo, StoreT<R>, const int64_t *, double *, double *, int,  \
-                                              const int *);
+  template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, StoreT<R>, int64_t);             \
+  template __global__ void k_cell_tally<D, R, false>(Geo, Params, StoreT<R>, const int64_t *, double *,     \
+                                                     double *, double *, double *, int *, const int *);    \
+  template __global__ void k_cell_tally<D, R, true>(Geo, Params, StoreT<R>, const int64_t *, double *,      \
+                                                    double *, double *, double *, int *, const int *);
 UGK_INST_P(1, double)
 UGK_INST_P(2, double)
 UGK_INST_P(1, float)
 UGK_INST_P(2, float)
-#define UGK_INST_T(D, N, R, F) template __global__ void k_transport<D, N, R, F>(Geo, Params, State, StoreT<R>, int64_t);
+#define UGK_INST_T(D, N, R, F) \
+  template __global__ void k_transport<D, N, R, F>(Geo, Params, State, StoreT<R>, StoreT<R>, int64_t);
 #define UGK_INST_TF(D, N, R) UGK_INST_T(D, N, R, 0) UGK_INST_T(D, N, R, 1) UGK_INST_T(D, N, R, 2) UGK_INST_T(D, N, R, 3)
 UGK_INST_TF(1, 2, double)
 UGK_INST_TF(1, 2, float)

@@ -11,11 +11,13 @@ several 256-thread blocks with ragged tails:
   within 1e-12 of each component's scale (max |rho|, max |rho U| as a vector
   norm, max |rho E|);
 - free-running runs of many steps: particle identities, cells and counts
-  bit-exact at every checkpoint; fields within DRIFT.  The fields of the two
-  runs separate slowly because W^h = W - W^p (Eq. (24)) and the hydrodynamic
-  temperature cancel catastrophically in particle-dominated and hypersonic
-  cells, which amplifies last-bit differences of order-dependent sums
-  (GPU atomics) and of libm vs device transcendentals.
+  bit-exact at every checkpoint; fields within DRIFT.  Both sides take the
+  tallies as exactly rounded sums, so they agree bit for bit where the
+  particles do; the fields of the two runs still separate slowly, because
+  the device's and the host library's transcendentals (exp, log, erfc,
+  sin/cos, pow) differ in the last bit now and then, and W^h = W - W^p
+  (Eq. (24)) and the hydrodynamic temperature cancel catastrophically in
+  particle-dominated and hypersonic cells.
 """
 import numpy as np
 import pytest
@@ -27,6 +29,15 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 DRIFT = 1e-10
+# 2D free runs over more than eight steps (batch to step 12, graph replays
+# to step 17).  Both sides take identical integer decisions and exactly
+# rounded tallies, so what still separates their fields is the last bit of
+# the transcendental functions (the device library's exp, log, erfc, pow,
+# sin/cos against the host's), amplified by the cancellation in
+# W^h = W - W^p; measured: 1.1e-10 at step 12 (Ma 10 case of the batch) and
+# 1.2e-10 at step 17 (Ma 15 cylinder).  From a common state every stage
+# agrees to TOL (tests/test_gpu_exact.py).
+DRIFT_LONG = 1e-9
 
 
 def _solver(w, **kw):
@@ -41,6 +52,11 @@ def _field_err(a, b):
     if b.shape[1] == 4:
         scale[1] = scale[2] = np.sqrt(b[:, 1] ** 2 + b[:, 2] ** 2).max()
     scale[scale == 0] = 1.0
+    return np.max(np.abs(a - b).max(axis=0) / scale)
+
+
+def _tally_err(a, b, floor):
+    scale = np.maximum(np.abs(b).max(axis=0), floor)
     return np.max(np.abs(a - b).max(axis=0) / scale)
 
 
@@ -66,6 +82,7 @@ def compare(g, r, tag="", tol=TOL):
     assert np.array_equal(cg, cr), f"{tag}: per-cell counts differ"
     for k in ("total", "new", "removed", "exited", "guard"):
         assert ig[k] == ir[k], f"{tag}: {k} {ig[k]} vs {ir[k]}"
+    assert g.shakhov_fallbacks() == r.n_capped(), f"{tag}: Shakhov fallbacks differ"
     # A particle mass m = rho^h e^{-x} Omega / N inherits the cancellation of
     # W^h = W - W^p (Eq. (24)), amplified further where a cell empties into
     # vacuum; the masses' aggregate is held to the field bar through the
@@ -84,11 +101,15 @@ def compare(g, r, tag="", tol=TOL):
         assert de <= (1e-10 if tol <= TOL else 1e-6), f"{tag}: internal energy error {de:.3e}"
     e = _field_err(g.fields(), Wr)
     assert e <= tol, f"{tag}: field error {e:.3e}"
-    # tallies enter the update as S / Omega next to W: compare on W's scale
+    # tallies on their own scale (per component, the largest |S| of the
+    # domain); from a common state they are exactly rounded sums of equal
+    # terms on both sides.  The scale is floored at 1e-40 of the largest cell
+    # content: the device's fixed-point window drops terms far below that
+    # (the e^{-10^9}-mass particles of the continuum limit)
     Smg, Spg = g.tally()
     Smr, Spr = r.tally()
-    v = r.vol[:, None]
-    et = max(_field_err(Wr + Smg / v, Wr + Smr / v), _field_err(Wr + Spg / v, Wr + Spr / v))
+    floor = 1e-40 * np.max(np.abs(Wr).sum(axis=1) * r.vol)
+    et = max(_tally_err(Smg, Smr, floor), _tally_err(Spg, Spr, floor))
     assert et <= tol, f"{tag}: tallies differ by {et:.3e}"
     return e
 
@@ -363,27 +384,25 @@ def _compare_case(g, k, r, pg, W, cnt, tag, tol):
 
 def test_batch_cases_equal_single_case_oracle():
     """Three uneven cylinders (sizes, Ma, Kn, T_w and seeds differ) in one
-    batch.  Free run: each case's particle ids, cells and per-cell counts
-    equal those of the oracle running the case alone, fields within DRIFT,
-    wall quantities and residuals within 1e-8 (free-running fields separate
-    through the conditioning of W^h = W - W^p, and the floating-point atomics
-    of the transport add in a different order on every run: about 1e-10 by
-    step 8 in the Ma 10 case, so the free run is compared up to step 4).  Then
-    one step from the batch's state at step 8 (loaded into a fresh batch and,
-    case by case, into fresh oracles) to the strict bar."""
+    batch.  Free run over 12 steps: each case's particle ids, cells and
+    per-cell counts equal those of the oracle running the case alone, fields
+    within DRIFT to step 8 and DRIFT_LONG at step 12, wall quantities and
+    residuals within 1e-8.  Then one step
+    from the batch's state at step 12 (loaded into a fresh batch and, case
+    by case, into fresh oracles) to the strict bar."""
     from paper_2607_09552_amd import Solver
     cases = _batch_cases()
     g = Solver.batch(cases)
     refs = [oracle.Oracle(w) for w in cases]
     done = 0
-    for n in (1, 4):
+    for n in (1, 4, 8, 12):
         g.step(n - done)
         for r in refs:
             r.step(n - done)
         done = n
         W, pg, cnt = g.fields(), g.particles(), g.counts()[0]
         for k, r in enumerate(refs):
-            _compare_case(g, k, r, pg, W, cnt, (n, k), DRIFT)
+            _compare_case(g, k, r, pg, W, cnt, (n, k), DRIFT if n <= 8 else DRIFT_LONG)
             sg, cdg = g.case_surface(k, 1)
             sr, cdr = r.surface(1)
             assert np.allclose(sg, sr, rtol=1e-8, atol=1e-8 * np.abs(sr).max()), (n, k)
@@ -391,13 +410,12 @@ def test_batch_cases_equal_single_case_oracle():
             ig, ag = g.case_residual(k)
             ir, ar_, _ = r.residual()
             assert abs(ig - ir) <= 1e-8 * ir and abs(ag - ar_) <= 1e-8 * ar_, (n, k)
-    g.step(8 - done)
     # strict: one step from a common state
     W, pg = g.fields(), g.particles()
     g2 = Solver.batch(cases)
     g2.set_fields(W)
     g2.set_particles(pg["pid"], pg["cell"], pg["m"], pg["x"], pg["u"], pg["ei"])
-    g2.set_step(8)
+    g2.set_step(12)
     ors = []
     for k, w in enumerate(cases):
         c0, nck, _, _ = g.case_range(k)
@@ -407,7 +425,7 @@ def test_batch_cases_equal_single_case_oracle():
         r.set_fields(W[c0:c0 + nck])
         r.set_particles(pg["pid"][sel], pg["cell"][sel] - c0, pg["m"][sel], pg["x"][sel], pg["u"][sel],
                         pg["ei"][sel])
-        r.set_step(8)
+        r.set_step(12)
         r.step(1)
         ors.append(r)
     g2.step(1)
@@ -416,9 +434,8 @@ def test_batch_cases_equal_single_case_oracle():
     for k, r in enumerate(ors):
         sel, order, c0, nck = _compare_case(g2, k, r, pg2, W2, cnt2, ("common", k), TOL)
         Smr, Spr = r.tally()
-        Wr = r.fields()
-        v = r.vol[:, None]
-        et = max(_field_err(Wr + Smg[c0:c0 + nck] / v, Wr + Smr / v), _field_err(Wr + Spg[c0:c0 + nck] / v, Wr + Spr / v))
+        floor = 1e-40 * np.max(np.abs(r.fields()).sum(axis=1) * r.vol)
+        et = max(_tally_err(Smg[c0:c0 + nck], Smr, floor), _tally_err(Spg[c0:c0 + nck], Spr, floor))
         assert et <= TOL, ("common tallies", k, et)
 
 
@@ -448,21 +465,15 @@ def test_graph_replays_match_the_oracle():
     r2 = oracle.Oracle(w2)
     r2.vol = cell_volumes(w2)
     done = 0
-    for n in (2, 4):
+    for n in (2, 4, 9, 17):
         g2.step(n - done)
         r2.step(n - done)
         done = n
-        compare(g2, r2, f"graph with growth, step {n}", DRIFT)
-    # The free runs' fields drift apart with the order of the GPU's atomic
-    # sums (this Ma 15 case has reached 1.2e-10 by step 10 and 4.9e-11 by
-    # step 6, depending on the launch sequence), so they are compared up to
-    # step 4 only.  The strict
-    # bar is taken from a common state: the graph run's state at step 10 (past
-    # the first, most violent steps of the impulsive start, where two steps
-    # amplify last-bit differences to 2.5e-12) loaded into a fresh graph-mode
-    # context, whose small store grows on loading, and the oracle, then one
-    # two-step graph replay.
-    g2.step(6)
+        compare(g2, r2, f"graph with growth, step {n}", DRIFT if n <= 8 else DRIFT_LONG)
+    # The strict bar is taken from a common state: the graph run's state at
+    # step 17 (past the first, most violent steps of the impulsive start)
+    # loaded into a fresh graph-mode context, whose small store grows on
+    # loading, and the oracle, then one two-step graph replay.
     W, p = g2.fields(), g2.particles()
     g3 = _solver(w2, particle_capacity=5000)
     g3.set_tuning(use_graph=1, batch_steps=2)
@@ -471,10 +482,10 @@ def test_graph_replays_match_the_oracle():
     for s in (g3, r3):
         s.set_fields(W)
         s.set_particles(p["pid"], p["cell"], p["m"], p["x"], p["u"], p["ei"])
-        s.set_step(10)
+        s.set_step(17)
     g3.step(2)
     r3.step(2)
-    e = compare(g3, r3, "two graph steps from the state at step 10", TOL)
+    e = compare(g3, r3, "two graph steps from the state at step 17", TOL)
     print(f"graph, two steps from a common state: field error {e:.3e}")
 
 
