@@ -186,7 +186,8 @@ int ugkwp_get_counts(ugkwp_ctx *ctx, int32_t *count, int64_t *n_total, int64_t *
  * (the n_total of ugkwp_get_counts, summed): the work counter behind the
  * particle-update rate.  Starts at 0 at init. */
 int ugkwp_get_work(ugkwp_ctx *ctx, int64_t *n_transported);
-/* Retained particles sorted by pid: pid = step << 44 | birth cell << 20 | j
+/* Retained particles sorted by pid (then by cell: each case of a batch
+ * numbers its particles on its own): pid = step << 44 | birth cell << 20 | j
  * (birth cell >= n_cells marks a boundary face), cell, mass, position
  * [n*dim], velocity [n*3], internal energy per unit mass |xi|^2 / 2 [n]
  * (0 when D = 0).  Pointers may be NULL; *n is set even when cap is too
@@ -207,7 +208,8 @@ int ugkwp_set_step(ugkwp_ctx *ctx, int64_t step);
 /* Averaging state behind ugkwp_residual and the surface means (host
  * arrays, each may be NULL): per cell the last density, the running sum of
  * the density over the steps and its last running mean [n_cells]; per wall
- * face the last, summed and EMA (p, tau, q) [n_wall*3]; per case
+ * face (all wall faces of a batch, case after case) the last, summed and EMA
+ * (p, tau, q) [n_wall*3]; per case
  * {r_inst, r_avg, C_d last, C_d sum, C_d EMA, unused} [n_cases*6].  With
  * ugkwp_set_fields, ugkwp_set_particles and ugkwp_set_step these restore a
  * state taken with the getters exactly (ugkwp_save / ugkwp_load do all of

@@ -350,6 +350,9 @@ class Solver:
         return F
 
     def n_wall(self):
+        """Wall faces of the context (of every case of a batch)."""
+        if self.ncase > 1:
+            return sum(self.case_range(k)[3] for k in range(self.ncase))
         nw = C.c_int64()
         load_library().ugkwp_surface(self.h, 0, None, 0, C.byref(nw), None)
         return nw.value

@@ -1599,7 +1599,8 @@ int ugkwp_get_particles(ugkwp_ctx *c, int64_t cap, uint64_t *pid, int32_t *cell,
   if (rc) return rc;
   std::vector<int64_t> order(np);
   for (int64_t k = 0; k < np; ++k) order[k] = k;
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return P[a] < P[b]; });
+  // by pid, then cell: the cases of a batch number their particles each on their own
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return P[a] != P[b] ? P[a] < P[b] : C[a] < C[b]; });
   for (int64_t j = 0; j < np; ++j) {
     const int64_t k = order[j];
     if (pid) pid[j] = P[k];

@@ -202,6 +202,15 @@ def _scaled_err(a, b, scale=None):
     return float(np.max(np.abs(a - b).max(axis=0) / s))
 
 
+def _tally_err(a, b):
+    """A tally S = sum m Psi on its own scale: max |S_rho|, max |S_E| and,
+    for momentum, max sqrt(2 |S_rho| |S_E|), the bound of sum m |u|."""
+    nw = b.shape[1]
+    scale = np.abs(b).max(axis=0)
+    scale[1:nw - 1] = np.sqrt(2.0 * np.abs(b[:, 0]) * np.abs(b[:, nw - 1])).max()
+    return _scaled_err(a, b, scale)
+
+
 def common_state_stage_parity(w, n, tag):
     """Run the GPU to step n, load fields, particles, step counter and the
     averaging state into a fresh GPU context and the oracle, take one step
@@ -233,8 +242,8 @@ def common_state_stage_parity(w, n, tag):
     errs["dW"] = _scaled_err(Wg - W, Wr - W)
     Smg, Spg = g.tally()
     Smr, Spr = r.tally()
-    errs["W^{p,-}"] = _scaled_err(Smg, Smr)
-    errs["W^{p,+}"] = _scaled_err(Spg, Spr)
+    errs["W^{p,-}"] = _tally_err(Smg, Smr)
+    errs["W^{p,+}"] = _tally_err(Spg, Spr)
     ig, ag, _ = g.residual()
     ir, ar, _ = r.residual()
     errs["r_inst"] = abs(ig - ir) / ir

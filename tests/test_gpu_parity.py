@@ -56,7 +56,14 @@ def _field_err(a, b):
 
 
 def _tally_err(a, b, floor):
-    scale = np.maximum(np.abs(b).max(axis=0), floor)
+    """max |a - b| per component of a tally S = sum m Psi over the tally's
+    own scale: max |S_rho|, max |S_E|, and for the momentum components
+    max sqrt(2 |S_rho| |S_E|), the bound of sum m |u| (Cauchy-Schwarz), since
+    a momentum tally may cancel to rounding noise (floored as described)."""
+    nw = b.shape[1]
+    scale = np.abs(b).max(axis=0)
+    scale[1:nw - 1] = np.sqrt(2.0 * np.abs(b[:, 0]) * np.abs(b[:, nw - 1])).max()
+    scale = np.maximum(scale, floor)
     return np.max(np.abs(a - b).max(axis=0) / scale)
 
 
@@ -101,11 +108,10 @@ def compare(g, r, tag="", tol=TOL):
         assert de <= (1e-10 if tol <= TOL else 1e-6), f"{tag}: internal energy error {de:.3e}"
     e = _field_err(g.fields(), Wr)
     assert e <= tol, f"{tag}: field error {e:.3e}"
-    # tallies on their own scale (per component, the largest |S| of the
-    # domain); from a common state they are exactly rounded sums of equal
-    # terms on both sides.  The scale is floored at 1e-40 of the largest cell
-    # content: the device's fixed-point window drops terms far below that
-    # (the e^{-10^9}-mass particles of the continuum limit)
+    # tallies on their own scale (see _tally_err); from a common state they
+    # are exactly rounded sums of equal terms on both sides.  The scale is
+    # floored at 1e-40 of the largest cell content: the device's fixed-point
+    # window drops terms far below that
     Smg, Spg = g.tally()
     Smr, Spr = r.tally()
     floor = 1e-40 * np.max(np.abs(Wr).sum(axis=1) * r.vol)
