@@ -146,6 +146,24 @@ int ugkwp_case_surface(ugkwp_ctx *ctx, int32_t case_id, int32_t mode, double *ou
  * (more than 2^20 particles born in one cell), ENOMEM, EDEVICE. */
 int ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps);
 
+/* ugkwp_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same steps with the same results, bit for bit, but the step's
+ * accumulators (the per-cell histogram and scatter cursors of the re-sort,
+ * the wall-impulse and residual chunks, counters and the scan's block sums)
+ * live in one static device array of 48 MiB that the library holds on each
+ * device it runs on until the process ends, and the call allocates nothing:
+ * no store growth (EOVERFLOW if the step would need more particle slots
+ * than the store holds: give ugkwp_params.particle_capacity, or let
+ * ugkwp_step grow it first), no graph capture (every kernel launched
+ * directly), no timing events (ESTATE while ugkwp_profile is on).
+ * EOVERFLOW if the mesh's accumulators exceed the array (about 24 bytes per
+ * cell: meshes up to some 1.9 million cells).  Every call on a device
+ * shares that device's array, which keeps the last call's contents (each
+ * step clears what must start at zero): calls that overlap on one device,
+ * from any context or thread, race.  Other errors as ugkwp_step. */
+int ugkwp_step_noalloc(ugkwp_ctx *ctx, int32_t n_steps);
+
 /* Advances until the residual target is met: stops after the first step
  * n >= 100 whose r_avg (see ugkwp_residual; every case's for a batch) is
  * below target (the convergence rule used for time-to-residual), or after

@@ -25,7 +25,7 @@ ABI_SYMBOLS = (
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
     "ugkwp_get_face_flux", "ugkwp_get_history", "ugkwp_set_history", "ugkwp_save", "ugkwp_load",
-    "ugkwp_get_shakhov_fallbacks",
+    "ugkwp_get_shakhov_fallbacks", "ugkwp_step_noalloc",
     "ugkwp_mlp_layer", "ugkwp_mlp_gemm_acc", "ugkwp_mlp_act_backward", "ugkwp_mlp_adam", "ugkwp_mlp_to_bf16",
     "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode", "ugkwp_mlp_pack", "ugkwp_mlp_forward",
 )
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_case_residual.argtypes = [vp, C.c_int32, dp, dp]
     L.ugkwp_case_surface.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64, i64p, dp]
     L.ugkwp_step.argtypes = [vp, C.c_int32]
+    L.ugkwp_step_noalloc.argtypes = [vp, C.c_int32]
     L.ugkwp_step_until.argtypes = [vp, C.c_double, C.c_int32, i32p]
     L.ugkwp_residual.argtypes = [vp, dp, dp, i64p]
     L.ugkwp_surface.argtypes = [vp, C.c_int32, dp, C.c_int64, i64p, dp]
@@ -245,6 +246,11 @@ class Solver:
 
     def step(self, n=1):
         self._check(load_library().ugkwp_step(self.h, n))
+
+    def step_noalloc(self, n=1):
+        """ugkwp_step without any device allocation (scratch in the library's
+        static array; no store growth, no graph replay)."""
+        self._check(load_library().ugkwp_step_noalloc(self.h, n))
 
     def step_until(self, target, max_steps):
         """Steps until the first step n >= 100 with r_avg < target (r_inst in

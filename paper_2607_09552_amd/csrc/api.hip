@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -12,6 +13,21 @@
 #include "kernels.h"
 
 using namespace ugk;
+
+// Scratch of ugkwp_step_noalloc: the per-step accumulators of a step (the
+// kept/collided histogram and its scatter cursors, the wall-impulse and
+// residual chunks, the ghost-entry counter, the step statistics and the
+// scan's block sums) in a static device array, for callers that cannot
+// allocate.  Every call on a device shares that device's copy; calls that
+// overlap on one device race.  Host code uses the address obtained with
+// hipGetSymbolAddress, never the array's name.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t{48} << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 
 namespace {
@@ -99,6 +115,10 @@ struct ugkwp_ctx {
   bool prof = false, prof_all = false;
   // tuning
   int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4, max_crossings = 10000;
+  // ugkwp_step_noalloc: this device's scratch array, and set while such a
+  // call runs (no growth, no graph capture, no timing events)
+  unsigned char *noalloc_scratch = nullptr;
+  bool noalloc = false;
   // captured graph of two steps and the launch arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1071,6 +1091,21 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   if ((rc = reserve_scan(c, std::max(2 * nc, nc + nb)))) return rc;
+  {
+    // this device's copy of the no-allocation scratch array, once per device
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_err(c, UGKWP_EDEVICE, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return set_err(c, UGKWP_EDEVICE, "scratch array address: %s", hipGetErrorString(e));
+      g_scratch_ptr[dev] = ptr;
+    }
+    c->noalloc_scratch = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+  }
   void *pin = nullptr;
   HIPCHK(hipHostMalloc(&pin, 8 * sizeof(int64_t), hipHostMallocDefault));
   c->pinned = static_cast<int64_t *>(pin);
@@ -1215,6 +1250,9 @@ namespace {
 // Sizes the store and the particle-parallel grids for steps whose
 // pre-transport set is about `need` particles, `need_new` of them new.
 int plan_launches(ugkwp_ctx *c, int64_t need, int64_t need_new) {
+  // without allocation the store stays as it is; a step that does not fit
+  // halts in k_check and fails (run_steps)
+  if (c->noalloc) need = std::min(need, c->cap);
   int rc = ensure_capacity(c, need);
   if (rc) return rc;
   // rounded up so that the launch arguments, and a captured graph, stay the
@@ -1283,7 +1321,7 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
     const int32_t batch = std::min<int32_t>(n_steps - done, c->batch_steps);
     const int64_t step0 = c->step;
     int32_t k = 0;
-    if (c->use_graph && !c->prof && batch >= 2) {
+    if (c->use_graph && !c->prof && !c->noalloc && batch >= 2) {
       rc = ensure_graph(c);
       if (rc) return rc;
       for (; k + 2 <= batch; k += 2) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
@@ -1314,6 +1352,14 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
       return UGKWP_OK;
     }
     if (halt && (flags & ~(kFlagCapacity | kFlagGrid)) == 0) {
+      if (c->noalloc && c->last_need > c->cap) {
+        HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+        HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return set_err(c, UGKWP_EOVERFLOW,
+                       "step %lld needs %lld particle slots, the store holds %lld: ugkwp_step_noalloc does not grow it",
+                       (long long)c->step, (long long)c->last_need, (long long)c->cap);
+      }
       // the step was not committed: grow the store or the grids to its
       // recorded bounds and resume from it
       rc = plan_launches(c, c->last_need + c->last_need / 4 + 4096, c->last_need_new + c->last_need_new / 4);
@@ -1355,6 +1401,57 @@ int ugkwp_step(ugkwp_ctx *c, int32_t n_steps) {
   if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
   if (c->step + n_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
   return run_steps(c, n_steps, false, nullptr);
+}
+
+int ugkwp_step_noalloc(ugkwp_ctx *c, int32_t n_steps) {
+  if (!c || n_steps < 0) return UGKWP_EINVAL;
+  if (!c->S.W) return set_err(c, UGKWP_ESTATE, "context not initialized");
+  if (c->step + n_steps >= (1 << 20) - 1) return set_err(c, UGKWP_EOVERFLOW, "step count exceeds the pid layout (2^20)");
+  if (c->prof) return set_err(c, UGKWP_ESTATE, "per-kernel timing creates events: switch it off first");
+  if (!c->noalloc_scratch) return set_err(c, UGKWP_EDEVICE, "no scratch array");
+  // layout of the step's accumulators in the scratch array (256-byte aligned)
+  const int64_t nc = c->nc, nb1 = std::max<int64_t>(c->nb, 1);
+  const int64_t scan_blocks = std::max<int64_t>(1, (std::max(2 * nc, nc + c->nb) + kScanBlock) / kScanBlock) + 1;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_count = take(2 * nc * sizeof(int)), o_cursor = take(2 * nc * sizeof(int64_t)),
+               o_wimp = take(nb1 * 3 * kTallyLimbs * sizeof(double)), o_resid = take(8 * c->ncase * sizeof(double)),
+               o_nghost = take(sizeof(int64_t)), o_stats = take(kStatSlots * kStatN * sizeof(int64_t)),
+               o_scan = take(scan_blocks * sizeof(int64_t));
+  if (at > kNoAllocScratchBytes)
+    return set_err(c, UGKWP_EOVERFLOW, "the step's accumulators need %zu bytes, the scratch array holds %zu", at,
+                   kNoAllocScratchBytes);
+  unsigned char *base = c->noalloc_scratch;
+  State saved = c->S;
+  int64_t *saved_scan = c->scan_tmp;
+  const int64_t saved_scan_n = c->scan_tmp_n;
+  c->S.count = reinterpret_cast<int *>(base + o_count);
+  c->S.cursor = reinterpret_cast<int64_t *>(base + o_cursor);
+  c->S.wimp = reinterpret_cast<double *>(base + o_wimp);
+  c->S.resid = reinterpret_cast<double *>(base + o_resid);
+  c->S.nghost = reinterpret_cast<int64_t *>(base + o_nghost);
+  c->S.stats = reinterpret_cast<int64_t *>(base + o_stats);
+  c->scan_tmp = reinterpret_cast<int64_t *>(base + o_scan);
+  c->scan_tmp_n = scan_blocks;
+  c->noalloc = true;
+  const int rc = run_steps(c, n_steps, false, nullptr);
+  (void)hipStreamSynchronize(c->stream);
+  c->noalloc = false;
+  // the pointers that the double buffering swaps (tallies, offsets) stay as
+  // the steps left them; the scratch pointers go back to the context's own
+  c->S.count = saved.count;
+  c->S.cursor = saved.cursor;
+  c->S.wimp = saved.wimp;
+  c->S.resid = saved.resid;
+  c->S.nghost = saved.nghost;
+  c->S.stats = saved.stats;
+  c->scan_tmp = saved_scan;
+  c->scan_tmp_n = saved_scan_n;
+  return rc;
 }
 
 int ugkwp_step_until(ugkwp_ctx *c, double target, int32_t max_steps, int32_t *converged) {
