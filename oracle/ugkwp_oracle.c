@@ -5,13 +5,15 @@
  *
  * Every step follows the paper (arXiv 2607.09552) in its own order and
  * notation; the cited equation numbers are the paper's.  Where the paper is
- * silent the reading used is stated at the function.  Parity unpinned: the
- * readings for reconstruction (MUSCL, van Leer), the equilibrium slope, the
- * upwind g0^h and the positivity guard are checked only through the
- * invariant/limit pins and against the GPU path; the Shakhov
+ * silent the reading used is stated at the function.  Pins: the
+ * reconstruction (MUSCL, van Leer) and the equilibrium slope by exactness on
+ * linear fields over graded meshes, the positivity guard branch by branch,
+ * the whole step by an independent literal GTS step (equal time steps), the
+ * collisionless limit by free-molecular wall fluxes on a plate, the Shakhov
  * acceptance-rejection, the diffuse wall's re-emission and the far-field
- * ghost slab are pinned statistically by the distributions and fluxes they
- * must give.
+ * ghost slab statistically by the distributions and fluxes they must give.
+ * Parity unpinned: the upwind reading of g0^h in Eq. (50), checked only
+ * through those pins and against the GPU path.
  */
 #include "ugkwp_oracle.h"
 
