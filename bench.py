@@ -26,19 +26,20 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# 2D transport: reads a particle record (x, y, u_x, u_y, u_z, m, pid, cell:
-# 60 B in FP64, 40 B with FP32 positions and velocities) and writes x, y, m,
-# the cell and the keep flag (32 B, 24 B)
-TRANSPORT_BYTES = {"f64": 92.0, "mixed": 64.0}
+# Algorithmic bytes of one particle update: read and write one particle
+# record (2D: x, y, u_x, u_y, u_z, m, pid, cell = 60 B in FP64; 40 B with
+# FP32 cell-relative positions and velocities).  The transport, the kernel
+# that moves every particle, is held against it per launch.
+TRANSPORT_BYTES = {"f64": 120.0, "mixed": 80.0}
 TRANSPORT_BYTES_PER_PARTICLE = TRANSPORT_BYTES["f64"]
-TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "transport_cylinder_traffic.json"),
-                 "mixed": os.path.join(ROOT, "profiles", "transport_cylinder_mixed_traffic.json")}
+TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "step_traffic_cylinder.json"),
+                 "mixed": os.path.join(ROOT, "profiles", "step_traffic_cylinder_mixed.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2607_09552_amd", "csrc", "kernels.hip")
 
 
-def workload(kn=0.01):
+def workload(kn=0.01, lts=1):
     return workloads.cylinder(n_theta=200, n_r=150, Ma=15.0, Kn=kn, omega=0.81, Pr=2.0 / 3.0, Tw=0.2, n_ref=400,
-                              lts=1, seed=1)
+                              lts=lts, seed=1)
 
 
 def kernel_sha():
@@ -46,10 +47,12 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_particle(precision="f64"):
-    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading)
-    per particle of a transport launch, from the committed rocprofv3 counter
-    summary if it was taken on the current kernel source; else None."""
+def measured_traffic(precision="f64"):
+    """HBM bytes per transported particle (FETCH_SIZE + WRITE_SIZE, each
+    scaled by what the counter reads for the library's streaming copy of
+    known size), per kernel and for the whole step, from the committed
+    rocprofv3 counter summary if it was taken on the current kernel source;
+    else None."""
     try:
         with open(TRAFFIC_FILES[precision]) as f:
             t = json.load(f)
@@ -57,7 +60,41 @@ def traffic_per_particle(precision="f64"):
         return None
     if t.get("kernel_sha") != kernel_sha():
         return None
-    return t.get("bytes_per_particle")
+    return t
+
+
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"host_cpu": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def oracle_shock(steps=2000):
+    """The oracle over the whole 1D shock run (100 cells, N_ref 200, LTS,
+    FP64, seed 1): particle updates/s and cell-steps/s on one core."""
+    import oracle
+    w = workloads.shock1d()
+    o = oracle.Oracle(w)
+    n_upd = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(1)
+        n_upd += o.counts()[1]["total"]
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"workload": "1D Ma 3 shock, 100 cells, N_ref 200, LTS, FP64", "steps": steps, "seconds": dt,
+            "particle_updates_per_s": n_upd / dt, "cell_steps_per_s": w["n_cells"] * steps / dt}
 
 
 def cpu_baseline(w, state, steps):
@@ -77,20 +114,33 @@ def cpu_baseline(w, state, steps):
         n_upd += o.counts()[1]["total"]
     dt = time.perf_counter() - t0
     o.close()
-    return dict(value=n_upd / dt, unit="particle updates/s", cores=1, kind="oracle",
-                sample=f"{steps} steps of the same cylinder workload from the GPU state after step {step0} "
-                       f"({len(p['pid'])} retained particles), {n_upd} particle updates in {dt:.1f} s, 1 thread")
+    out = dict(value=n_upd / dt, unit="particle updates/s", cores=1, kind="oracle",
+               sample=f"{steps} steps of the same cylinder workload from the GPU state after step {step0} "
+                      f"({len(p['pid'])} retained particles), {n_upd} particle updates in {dt:.1f} s, 1 thread",
+               cell_steps_per_s=w["n_cells"] * steps / dt)
+    out.update(host_info())
+    out["shock1d_full_run"] = oracle_shock()
+    return out
 
 
 def copy_probe(gib=1.0, reps=5):
-    """A plain device copy of known size, for scaling rocprofv3 byte counters,
-    then the same copies timed with HIP events: the HBM bandwidth a plain
-    stream reaches (bytes read + written per second)."""
+    """The library's streaming copy (k_stream_copy) of known size, for
+    scaling rocprofv3 byte counters and as the attainable HBM rate (bytes
+    read + written per second), over a few grid sizes; torch's copy_ beside
+    it for comparison."""
     import torch
+    from paper_2607_09552_amd import stream_copy
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(reps):
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    runs = {}
+    for blocks in (0, 4 * cus, 16 * cus, 32 * cus, (n * 8 // 16 + 255) // 256):
+        ms = stream_copy(b, a, reps=reps, blocks=blocks)
+        runs[str(blocks)] = {"ms_per_copy": ms, "GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}
+    assert torch.equal(a, b)
+    for _ in range(2):
         b.copy_(a)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -100,8 +150,10 @@ def copy_probe(gib=1.0, reps=5):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps, "ms_per_copy": ms,
-                      "copy_GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}))
+    best = max(v["GBps"] for v in runs.values())
+    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "reps": reps, "compute_units": cus,
+                      "stream_copy_by_grid": runs, "stream_copy_best_GBps": best,
+                      "torch_copy_GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}))
 
 
 def time_to_residual(a):
@@ -299,6 +351,8 @@ def main():
                     help="N > 0: N uneven cylinder cases (80x60 to 240x180, Ma 5-20, Kn 0.005-0.2, N_ref 200) "
                          "in one batched solve")
     ap.add_argument("--kn", type=float, default=0.01)
+    ap.add_argument("--gts", action="store_true",
+                    help="global time step (Eq. (34)) on the cylinder: per-step throughput at a step cap")
     ap.add_argument("--workload", choices=("cylinder", "plate"), default="cylinder",
                     help="plate: the Ma 10 flat plate (300x200, N_ref 300) instead of the cylinder")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -351,7 +405,10 @@ def main():
     if a.batch:
         batch_bench(a)
         return
-    w = workload(a.kn) if a.workload == "cylinder" else workloads.flat_plate(seed=1)
+    w = workload(a.kn, lts=0 if a.gts else 1) if a.workload == "cylinder" else workloads.flat_plate(seed=1)
+    if a.gts and a.workload != "cylinder":
+        print("--gts applies to the cylinder", file=sys.stderr)
+        sys.exit(2)
     s = Solver(w, precision=a.precision)
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
     s.step(a.warmup)
@@ -385,8 +442,11 @@ def main():
     # particles one launch transports on average over the timed steps
     bytes_per_launch = TRANSPORT_BYTES[a.precision] * n_upd / max(tr["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tpp = traffic_per_particle(a.precision) if a.workload == "cylinder" else None  # counters taken on the cylinder
-    traffic = None if tpp is None else tpp * n_upd / max(tr["launches"], 1)
+    # counters taken on the LTS cylinder at this precision
+    mt = measured_traffic(a.precision) if (a.workload == "cylinder" and not a.gts) else None
+    traffic = None
+    if mt is not None and "transport" in mt["kernels"]:
+        traffic = mt["kernels"]["transport"]["bytes_per_particle"] * n_upd / max(tr["launches"], 1)
     kern = {k: dict(ms_per_launch=round(v["ms"] / max(v["launches"], 1), 5),
                     GBs=round(v["bytes"] / max(v["ms"], 1e-12) * 1e-6, 1) if v["ms"] > 0 else None)
             for k, v in breakdown.items() if v["launches"] > 0}
@@ -409,7 +469,8 @@ def main():
         "dtype": "f64" if a.precision == "f64" else "f32 particles, f64 cells",
         "data": "synthetic",
         "config": {"workload": (f"cylinder O-grid 200x150, Ma 15, Kn {a.kn}, VHS omega 0.81, Pr 2/3, "
-                                f"Tw/Tinf 0.2 diffuse, N_ref 400, LTS CFL 0.8, " if a.workload == "cylinder" else
+                                f"Tw/Tinf 0.2 diffuse, N_ref 400, {'GTS' if a.gts else 'LTS'} CFL 0.8, "
+                                if a.workload == "cylinder" else
                                 "flat plate 300x200, Ma 10, Kn 0.0169, VHS omega 0.74, Pr 1, Tw/Tinf 1 diffuse, "
                                 "N_ref 300, LTS CFL 0.8, ")
                                + f"{'FP64' if a.precision == 'f64' else 'FP32 particle push'}, Philox seed 1",
@@ -423,9 +484,11 @@ def main():
                           "achieved": step_bytes / (elapsed / a.steps) / 1e9,
                           "frac": step_bytes / (elapsed / a.steps) / 1e9 / HBM_PEAK_GBS,
                           "bytes_per_step": step_bytes,
-                          "model": f"{rec2:.0f} B per particle update (read + write one record) + 400 B per cell"},
+                          "model": f"{rec2:.0f} B per particle update (read + write one record) + 400 B per cell",
+                          "measured_bytes_per_particle": None if mt is None else mt["step_bytes_per_particle"]},
         "kernels": kern,
         "kernels_note": f"per-kernel breakdown from {nb} further steps with events around every kernel",
+        "residual_at_end": dict(zip(("r_inst", "r_avg", "step"), s.residual())),
     }
     if not a.no_cpu and a.precision == "f64":
         out["cpu_baseline"] = cpu_baseline(w, state, a.cpu_steps)

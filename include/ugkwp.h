@@ -31,10 +31,11 @@
  *     committed step, and the context can be used on (for instance saved,
  *     or stepped again after a change of tuning).
  *   - The particle tallies (Eqs. (24), (29)-(30)), the wall impulses and the
- *     residual sums are exact fixed-point sums (every term cut into four
- *     32-bit chunks of a window fixed at init) rounded once to FP64, so
- *     every result is reproducible bit for bit from run to run, whatever
- *     order the GPU's atomics take.
+ *     residual sums are exact fixed-point sums (every term cut into 32-bit
+ *     chunks of a window fixed at init: six for tallies and wall impulses,
+ *     four for the residual sums) rounded once to FP64, so every result is
+ *     reproducible bit for bit from run to run, whatever order the GPU's
+ *     atomics take.
  *   - The library requires a gfx950 device; it has no CPU fallback.
  */
 #ifndef UGKWP_H
@@ -286,6 +287,20 @@ int ugkwp_get_tuning(ugkwp_ctx *ctx, ugkwp_tuning *t);
 int ugkwp_profile(ugkwp_ctx *ctx, int32_t enable);
 int ugkwp_profile_read(ugkwp_ctx *ctx, int32_t cap, const char **names, double *ms, int64_t *launches,
                        double *bytes, int32_t *n);
+
+/* Bandwidth reference, outside the step: copies `bytes` bytes from device
+ * buffer src to device buffer dst with the library's streaming kernel
+ * (16-byte loads and stores, four per thread in flight, grid-stride), once
+ * untimed and then `reps` times back to back on `stream` (NULL = the null
+ * stream), and stores the mean milliseconds per copy, from HIP events, in
+ * *ms_per_copy.  blocks = 0 launches 8 workgroups of 256 threads per compute
+ * unit; any other value sets the grid.  Both pointers 16-byte aligned, bytes
+ * a positive multiple of 16, regions disjoint, reps >= 1, else UGKWP_EINVAL;
+ * a HIP failure gives UGKWP_EDEVICE (no context, so no error text).  It moves
+ * 2 * bytes per copy through HBM: the rate the step's kernels are held
+ * against beside the datasheet peak. */
+int ugkwp_stream_copy(void *dst, const void *src, int64_t bytes, int32_t reps, int32_t blocks, void *stream,
+                      double *ms_per_copy);
 
 const char *ugkwp_last_error(const ugkwp_ctx *ctx);
 void ugkwp_free(ugkwp_ctx *ctx);

@@ -25,7 +25,7 @@ ABI_SYMBOLS = (
     "ugkwp_set_particles", "ugkwp_set_fields", "ugkwp_set_step", "ugkwp_get_tally", "ugkwp_profile", "ugkwp_profile_read",
     "ugkwp_set_tuning", "ugkwp_get_tuning", "ugkwp_last_error", "ugkwp_free",
     "ugkwp_get_face_flux", "ugkwp_get_history", "ugkwp_set_history", "ugkwp_save", "ugkwp_load",
-    "ugkwp_get_shakhov_fallbacks", "ugkwp_step_noalloc",
+    "ugkwp_get_shakhov_fallbacks", "ugkwp_step_noalloc", "ugkwp_stream_copy",
     "ugkwp_mlp_layer", "ugkwp_mlp_gemm_acc", "ugkwp_mlp_act_backward", "ugkwp_mlp_adam", "ugkwp_mlp_to_bf16",
     "ugkwp_mlp_mse_grad", "ugkwp_ws_features", "ugkwp_ws_decode", "ugkwp_mlp_pack", "ugkwp_mlp_forward",
 )
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     L.ugkwp_save.argtypes = [vp, C.c_char_p]
     L.ugkwp_load.argtypes = [vp, C.c_char_p]
     L.ugkwp_get_shakhov_fallbacks.argtypes = [vp, i64p]
+    L.ugkwp_stream_copy.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, dp]
     L.ugkwp_last_error.argtypes = [vp]
     L.ugkwp_last_error.restype = C.c_char_p
     L.ugkwp_free.argtypes = [vp]
@@ -140,6 +141,23 @@ def _ptr(a, t=C.c_double):
 
 def _vp(a):
     return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def stream_copy(dst, src, reps=5, blocks=0):
+    """Copies torch device tensor src into dst (same byte size) with the
+    library's streaming kernel on torch's current stream; returns the mean
+    milliseconds per copy (ugkwp_stream_copy)."""
+    import torch
+    L = load_library()
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("stream_copy: two device tensors of the same byte size")
+    ms = C.c_double()
+    rc = L.ugkwp_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, reps, blocks,
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(ms))
+    if rc != 0:
+        raise UgkwpError(rc, "ugkwp_stream_copy failed")
+    return ms.value
 
 
 class Solver:

@@ -2117,6 +2117,50 @@ int ugkwp_profile(ugkwp_ctx *c, int32_t enable) {
   return UGKWP_OK;
 }
 
+int ugkwp_stream_copy(void *dst, const void *src, int64_t bytes, int32_t reps, int32_t blocks, void *stream,
+                      double *ms_per_copy) {
+  const auto ad = reinterpret_cast<uintptr_t>(dst), as = reinterpret_cast<uintptr_t>(src);
+  if (!dst || !src || bytes <= 0 || (bytes & 15) || (ad & 15) || (as & 15) || reps < 1 || blocks < 0 ||
+      !ms_per_copy)
+    return UGKWP_EINVAL;
+  if ((ad < as + static_cast<uintptr_t>(bytes)) && (as < ad + static_cast<uintptr_t>(bytes))) return UGKWP_EINVAL;
+  const int64_t n = bytes / 16;
+  int grid = blocks;
+  if (grid == 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return UGKWP_EDEVICE;
+    grid = 8 * cus;
+  }
+  const int64_t need = (n + 255) / 256;
+  if (grid > need) grid = static_cast<int>(need);
+  auto st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return UGKWP_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return UGKWP_EDEVICE;
+  }
+  bool ok = true;
+  auto *d = static_cast<uint4 *>(dst);
+  const auto *sp = static_cast<const uint4 *>(src);
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, d, sp, n);  // warm-up
+  ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+  for (int r = 0; ok && r < reps; ++r) {
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, d, sp, n);
+    ok = hipGetLastError() == hipSuccess;
+  }
+  float ms = 0.0f;
+  ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok) return UGKWP_EDEVICE;
+  *ms_per_copy = static_cast<double>(ms) / reps;
+  return UGKWP_OK;
+}
+
 int ugkwp_profile_read(ugkwp_ctx *c, int32_t cap, const char **names, double *ms, int64_t *launches, double *bytes,
                        int32_t *n) {
   if (!c) return UGKWP_EINVAL;

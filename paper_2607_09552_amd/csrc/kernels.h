@@ -186,6 +186,7 @@ struct ZeroList {
   int count;
 };
 __global__ void k_zero_many(ZeroList, const int *);
+__global__ void k_stream_copy(uint4 *, const uint4 *, int64_t);
 __global__ void k_copy64(int64_t *, const int64_t *, int64_t);
 
 }  // namespace ugk

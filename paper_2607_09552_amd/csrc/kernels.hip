@@ -1172,30 +1172,31 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
 // Every sum is exact (fixed-point chunks, see XWin), so it does not depend on
 // the order of the particles within a cell, which the scatter's atomics
 // leave open.  Also used at restart (empty collided ranges, Sp = null).
-// Adds the chunks of m Psi of the particles in [a, b) to xw at offset AT
-// and, with RAW, the chunks of their raw moments to xr (kTallyLimbs chunks
-// per quantity).
-template <int DIM, bool RAW, int AT, int PW, int PR, class R>
+// Adds the exact chunks of the particles in [a, b) to xc: of m Psi (RAW
+// false) or of the raw moments of the heat flux (RAW true), kTallyLimbs
+// chunks per quantity (value kTallyLimbs q + j = chunk j of quantity q).
+template <int DIM, bool RAW, class R>
 __device__ __forceinline__ void tally_range(const Params &p, const StoreT<R> &s, int64_t a, int64_t b,
-                                            double (&xw)[PW], double (&xr)[PR], bool &ok) {
+                                            double (&xc)[32], bool &ok) {
   constexpr int NW = DIM + 2, NLT = kTallyLimbs;
   for (int64_t k = a + lane_id(); k < b; k += 64) {
     const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
     const double ei = s.ei ? static_cast<double>(s.ei[k]) : 0.0;
     const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
-    double t[NW];
-    t[0] = m;
-    t[1] = m * u0;
-    if (DIM == 2) t[2] = m * u1;
-    t[NW - 1] = m * (0.5 * q2 + ei);
+    if constexpr (!RAW) {
+      double t[NW];
+      t[0] = m;
+      t[1] = m * u0;
+      if (DIM == 2) t[2] = m * u1;
+      t[NW - 1] = m * (0.5 * q2 + ei);
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      double ch[NLT];
-      ok = xs_split<NLT>(t[q], p.xw, ch) && ok;
+      for (int q = 0; q < NW; ++q) {
+        double ch[NLT];
+        ok = xs_split<NLT>(t[q], p.xw, ch) && ok;
 #pragma unroll
-      for (int j = 0; j < NLT; ++j) xw[AT + NLT * q + j] += ch[j];
-    }
-    if constexpr (RAW) {
+        for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
+      }
+    } else {
       const double q2i = q2 + 2.0 * ei;
       const double r[5] = {m * u0 * q2i, m * u1 * q2i, m * u0 * u0, m * u0 * u1, m * u1 * u1};
 #pragma unroll
@@ -1203,73 +1204,73 @@ __device__ __forceinline__ void tally_range(const Params &p, const StoreT<R> &s,
         double ch[NLT];
         ok = xs_split<NLT>(r[q], p.xm, ch) && ok;
 #pragma unroll
-        for (int j = 0; j < NLT; ++j) xr[NLT * q + j] += ch[j];
+        for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
       }
     }
   }
+}
+
+// Chunk totals of one tally pass over [a, b): on return, lane 2 NLT q holds
+// the NLT chunk totals of quantity q in L.
+template <int DIM, bool RAW, class R>
+__device__ __forceinline__ void tally_pass(const Params &p, const StoreT<R> &s, int64_t a, int64_t b,
+                                           double (&L)[kTallyLimbs], bool &ok) {
+  double xc[32];
+#pragma unroll
+  for (int v = 0; v < 32; ++v) xc[v] = 0.0;
+  tally_range<DIM, RAW>(p, s, a, b, xc, ok);
+  // lane l holds the total of value l >> 1
+  const double t = wave_sum_spread<32>(xc);
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < kTallyLimbs; ++j) L[j] = __shfl(t, (lane + 2 * j) & 63, 64);
 }
 
 template <int DIM, bool RAW, class R>
 __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const StoreT<R> &s, const int64_t *off,
                                            double *S, double *X, double *Sp, double *M, int *flags, int64_t c) {
   constexpr int NW = DIM + 2, NLT = kTallyLimbs;
-  constexpr int PR = RAW ? 32 : 2;
   const int lane = lane_id();
   const int64_t a = off[c], b = off[c + 1], ca = off[g.nc + c], cb = off[g.nc + c + 1];
   bool ok = (b - a) + (cb - ca) <= (int64_t{1} << 20);
-  // xw value NLT q + j: chunk j of component q (kept particles, then in a
-  // second pass the collided ones); xr value NLT r + j: chunk j of raw moment r
-  double xw[32], xr[PR];
-#pragma unroll
-  for (int v = 0; v < 32; ++v) xw[v] = 0.0;
-#pragma unroll
-  for (int v = 0; v < PR; ++v) xr[v] = 0.0;
-  tally_range<DIM, RAW, 0>(p, s, a, b, xw, xr, ok);
-  // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
-  const double tk = wave_sum_spread<32>(xw);
-  double L[NLT], C[NLT];
-#pragma unroll
-  for (int j = 0; j < NLT; ++j) L[j] = __shfl(tk, (lane + 2 * j) & 63, 64);
-  if (Sp) {
-#pragma unroll
-    for (int v = 0; v < 32; ++v) xw[v] = 0.0;
-    tally_range<DIM, false, 0>(p, s, ca, cb, xw, xr, ok);
-    const double tc = wave_sum_spread<32>(xw);
-#pragma unroll
-    for (int j = 0; j < NLT; ++j) C[j] = __shfl(tc, (lane + 2 * j) & 63, 64);
-  }
-  if (__ballot(!ok) && lane == 0) atomicOr(flags, kFlagRange);
   const int v = lane >> 1, q = v / NLT;
-  if ((lane & 1) == 0 && v % NLT == 0 && q < NW) {
-    xs_normalize<NLT>(L);
-#pragma unroll
-    for (int j = 0; j < NLT; ++j) X[(c * NW + q) * NLT + j] = L[j];
+  const bool writer = (lane & 1) == 0 && v % NLT == 0;
+  // kept particles: the next step's W^p Omega
+  double L[NLT];
+  tally_pass<DIM, false>(p, s, a, b, L, ok);
+  if (writer && q < NW) {
     S[c * NW + q] = xs_round<NLT>(L, p.xw);
-    if (Sp) {
+    double Ln[NLT];
 #pragma unroll
-      for (int j = 0; j < NLT; ++j) C[j] += L[j];
-      Sp[c * NW + q] = xs_round<NLT>(C, p.xw);
-    }
+    for (int j = 0; j < NLT; ++j) Ln[j] = L[j];
+    xs_normalize<NLT>(Ln);
+#pragma unroll
+    for (int j = 0; j < NLT; ++j) X[(c * NW + q) * NLT + j] = Ln[j];
   }
   if constexpr (RAW) {
-    // lane l holds the total of xr value l >> 1; lane 2 NLT r gathers moment r
-    const double tr = wave_sum_spread<32>(xr);
+    // raw moments of the kept particles
     double Lr[NLT];
-#pragma unroll
-    for (int j = 0; j < NLT; ++j) Lr[j] = __shfl(tr, (lane + 2 * j) & 63, 64);
-    const int r = v / NLT;
-    if ((lane & 1) == 0 && v % NLT == 0 && r < 5) M[c * 5 + r] = xs_round<NLT>(Lr, p.xm);
+    tally_pass<DIM, true>(p, s, a, b, Lr, ok);
+    if (writer && q < 5) M[c * 5 + q] = xs_round<NLT>(Lr, p.xm);
   }
+  if (Sp) {
+    // collided particles: W^{p,+} Omega is the exact sum over both sets
+    double C[NLT];
+    tally_pass<DIM, false>(p, s, ca, cb, C, ok);
+#pragma unroll
+    for (int j = 0; j < NLT; ++j) C[j] += L[j];
+    if (writer && q < NW) Sp[c * NW + q] = xs_round<NLT>(C, p.xw);
+  }
+  if (__ballot(!ok) && lane == 0) atomicOr(flags, kFlagRange);
 }
 
 // RAW: also the raw moments (Pr != 1).
 template <int DIM, class R, bool RAW>
-__global__ void __launch_bounds__(256, RAW ? 2 : 4) k_cell_tally(Geo g, Params p, StoreT<R> s,
-                                                                 const int64_t *__restrict__ off,
-                                                                 double *__restrict__ S, double *__restrict__ X,
-                                                                 double *__restrict__ Sp, double *__restrict__ M,
-                                                                 int *__restrict__ flags,
-                                                                 const int *__restrict__ halt) {
+__global__ void __launch_bounds__(256) k_cell_tally(Geo g, Params p, StoreT<R> s, const int64_t *__restrict__ off,
+                                                    double *__restrict__ S, double *__restrict__ X,
+                                                    double *__restrict__ Sp,
+                                                    double *__restrict__ M, int *__restrict__ flags,
+                                                    const int *__restrict__ halt) {
   const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (c >= g.nc || *halt) return;  // whole wavefront
   cell_tally<DIM, RAW>(g, p, s, off, S, X, Sp, M, flags, c);
@@ -1601,6 +1602,23 @@ __global__ void k_zero_many(ZeroList L, const int *__restrict__ halt) {
     uint32_t *p = L.p[b];
     for (int64_t i = i0; i < L.n[b]; i += stride) p[i] = 0u;
   }
+}
+
+// Streaming copy of n 16-byte elements: the attainable HBM rate that the
+// step's kernels are compared with.  Each thread moves four elements per
+// iteration (all four loads issued before the stores).
+__global__ void __launch_bounds__(256) k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                     int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ src, int64_t n) {

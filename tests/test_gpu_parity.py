@@ -188,6 +188,17 @@ def test_shock1d_gts_parity():
     run_pair(w, [1, 5, 40], tol=TOL)
 
 
+def test_cylinder_gts_parity():
+    """The coarse O-grid cylinder with one global time step (Eq. (34),
+    lts = 0: every cell at the smallest Delta t_i, no crossing scaled), free
+    running and one step from common states."""
+    w = wl.cylinder(n_theta=40, n_r=30, n_ref=50, Pr=1.0, lts=0)
+    g, r, _ = run_pair(w, [1, 2, 4, 8])
+    dt = g.dt()
+    assert np.all(dt == dt[0])
+    common_state_steps(w, [0, 5, 11])
+
+
 def test_cylinder_small_parity():
     """Coarse O-grid cylinder (Ma 15, cold diffuse wall, far field), through
     the impulsive start where the vacuum guard acts."""
