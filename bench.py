@@ -411,8 +411,13 @@ def main():
         sys.exit(2)
     s = Solver(w, precision=a.precision)
     print(f"# warmup {a.warmup} steps", file=sys.stderr, flush=True)
-    s.step(a.warmup)
-    torch.cuda.synchronize()
+    done = 0
+    while done < a.warmup:
+        k = min(500, a.warmup - done)
+        s.step(k)
+        done += k
+        torch.cuda.synchronize()
+        print(f"# warmup step {done}", file=sys.stderr, flush=True)
     # timed region: HIP events around the transport launches only (events
     # around every kernel would slow the step measurably)
     s.profile(True, transport_only=True)

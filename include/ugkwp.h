@@ -29,7 +29,11 @@
  *     EOVERFLOW) is not committed: the fields, the particle set, its tallies,
  *     the running averages and the step counter stay those of the last
  *     committed step, and the context can be used on (for instance saved,
- *     or stepped again after a change of tuning).
+ *     or stepped again after a change of tuning).  One exception: a
+ *     residual term outside its summation window (a one-step density change
+ *     some 2^12 times the initial maximum density) is found after the
+ *     fields were updated; that step stays committed and the call returns
+ *     ENUMERIC after it.
  *   - The particle tallies (Eqs. (24), (29)-(30)), the wall impulses and the
  *     residual sums are exact fixed-point sums (every term cut into 32-bit
  *     chunks of a window fixed at init: six for tallies and wall impulses,

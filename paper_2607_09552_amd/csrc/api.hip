@@ -516,7 +516,7 @@ int reserve_scan(ugkwp_ctx *c, int64_t n) {
   return UGKWP_OK;
 }
 
-int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
+int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out, int64_t *copy = nullptr) {
   const int64_t nblocks = std::max<int64_t>(1, (n + kScanBlock) / kScanBlock);
   if (nblocks + 1 > c->scan_tmp_n) return set_err(c, UGKWP_EDEVICE, "scan of %lld values exceeds its reserve", (long long)n);
   ProfScope ps(c, kKScan, 12.0 * static_cast<double>(n));
@@ -525,7 +525,7 @@ int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out) {
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, c->stream, c->scan_tmp, nblocks,
                      c->scan_tmp + nblocks, c->S.halt);
   hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, c->stream, out, n, c->scan_tmp,
-                     c->scan_tmp + nblocks, c->S.halt);
+                     c->scan_tmp + nblocks, c->S.halt, copy);
   HIPCHK(hipGetLastError());
   return UGKWP_OK;
 }
@@ -751,10 +751,9 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
     }
   }
   // kept particles per cell in count[0, nc), collided ones in count[nc, 2 nc)
-  rc = scan(c, S.count, 2 * nc, S.coff);
+  // the scan also sets the scatter's cursors to the offsets
+  rc = scan(c, S.count, 2 * nc, S.coff, S.cursor);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_copy64, dim3(nblk(2 * nc, 256) > 1024 ? 1024 : nblk(2 * nc, 256)), dim3(256), 0, c->stream,
-                     S.cursor, S.coff, 2 * nc);
   {
     ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->est_kept);
     hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(256), 0, c->stream, S, A, T, B, c->cap);
@@ -776,8 +775,8 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
     ProfScope ps(c, kKSurface, 150.0 * c->nwall);
     hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S);
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(std::min(1024, (c->ncase + 63) / 64 * 64)), 0, c->stream, g, c->P, S,
-                     nc);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(std::max(256, std::min(1024, (c->ncase + 63) / 64 * 64))), 0,
+                     c->stream, g, c->P, S, nc);
   HIPCHK(hipGetLastError());
   swap_buffers(c);
   return UGKWP_OK;
@@ -794,6 +793,12 @@ int check_flags(ugkwp_ctx *c) {
   int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, c->S.flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (flags) {
+    // the error is reported here; later steps start clean
+    HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+    HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
   if (flags & kFlagInvalid) return set_err(c, UGKWP_ENUMERIC, "invalid cell state");
   if (flags & kFlagRunaway) return set_err(c, UGKWP_ENUMERIC, "runaway particle tracking");
   if (flags & kFlagOverflow) return set_err(c, UGKWP_EOVERFLOW, "more than 2^20 particles in one cell");
@@ -1343,6 +1348,15 @@ int run_steps(ugkwp_ctx *c, int32_t n_steps, bool until, int32_t *converged) {
     const int halt = static_cast<int>(c->pinned[1] & 0xffffffff), flags = static_cast<int>(c->pinned[2] & 0xffffffff);
     rc = sync_counts(c);
     if (rc) return rc;
+    if (flags & kFlagResidRange) {
+      // a residual term outside its window: that step updated the fields and
+      // is committed (later steps of the batch halted before changing anything)
+      HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));
+      HIPCHK(hipMemsetAsync(c->S.flags, 0, sizeof(int), c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return set_err(c, UGKWP_ENUMERIC, "a residual term outside its exact-summation window at step %lld",
+                     (long long)(c->step - 1));
+    }
     if (halt && until && flags == kFlagConverged) {
       // the step that met the target is done; the rest of the batch was skipped
       HIPCHK(hipMemsetAsync(c->S.halt, 0, sizeof(int), c->stream));

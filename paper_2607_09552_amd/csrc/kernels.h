@@ -17,10 +17,13 @@ constexpr int kTallyLimbs = 6;  // chunks of the exact particle tallies (a 192-b
 enum : int { kBcFarfield = 1, kBcOutflow = 2, kBcWall = 3, kBcSymmetry = 4, kBcMaxwell = 6 };
 // kFlagConverged is not an error: the step that reached the residual target
 // (scal[kScalTarget] > 0) is done and later steps are skipped
-// kFlagRange: a term fell outside its exact-summation window (see XWin)
+// kFlagRange: a particle term fell outside its exact-summation window (see
+// XWin); the step halts before anything is committed
+// kFlagResidRange: a residual term fell outside its window; the fields are
+// already updated, so the step is committed and the call stops after it
 enum : int {
   kFlagInvalid = 1, kFlagRunaway = 2, kFlagOverflow = 4, kFlagCapacity = 8, kFlagGrid = 16, kFlagConverged = 32,
-  kFlagRange = 64
+  kFlagRange = 64, kFlagResidRange = 128
 };
 // kStatCapped: new particles whose Shakhov acceptance-rejection ran out of attempts
 enum : int { kStatExited = 0, kStatRemoved = 1, kStatGuard = 2, kStatCapped = 3, kStatN = 4 };
@@ -158,7 +161,7 @@ template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
 template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
 __global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *, const int *);
 __global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
-__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *);
+__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *, int64_t *);
 template <int DIM, class R> __global__ void k_sample_draw(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_match(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t, uint32_t);
@@ -171,7 +174,7 @@ __global__ void k_transport(Geo, Params, State, StoreT<R>, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_scatter(State, StoreT<R>, StoreT<R>, StoreT<R>, int64_t);
 template <int DIM, class R, bool RAW>
 __global__ void k_cell_tally(Geo, Params, StoreT<R>, const int64_t *, double *, double *, double *, double *, int *,
-                             const int *);
+                             int *);
 __global__ void k_case_area(Geo, double *, XWin);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
 template <int DIM> __global__ void k_update(Geo, Params, State);
@@ -187,6 +190,5 @@ struct ZeroList {
 };
 __global__ void k_zero_many(ZeroList, const int *);
 __global__ void k_stream_copy(uint4 *, const uint4 *, int64_t);
-__global__ void k_copy64(int64_t *, const int64_t *, int64_t);
 
 }  // namespace ugk

@@ -405,11 +405,17 @@ __global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__r
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Also copies the first n results to out2 when given (the scatter's cursors).
 __global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ bsum,
-                           const int64_t *__restrict__ total, const int *__restrict__ halt) {
+                           const int64_t *__restrict__ total, const int *__restrict__ halt,
+                           int64_t *__restrict__ out2) {
   if (*halt) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
-  if (i < n) out[i] += bsum[blockIdx.x];
+  if (i < n) {
+    const int64_t v = out[i] + bsum[blockIdx.x];
+    out[i] = v;
+    if (out2) out2[i] = v;
+  }
   if (i == n) out[n] = *total;
 }
 
@@ -537,9 +543,10 @@ __global__ void __launch_bounds__(256) k_sample_draw(Geo g, Params p, State st, 
 //     parameter in {1, 2, 4, 8, 16}); the K lanes of a particle evaluate
 //     attempts 0..K-1 at once and keep the lowest accepted one;
 //  2. the particles not yet accepted are finished in the same way with L
-//     lanes each on attempts K, K + L, ...: four at a time with L = 16, or
-//     with L = 32 or 64 when only two or one remain (near-vacuum particles,
-//     which need every attempt, then take one or two rounds).
+//     lanes each on attempts K, K + L, ...: L = 64 / n rounded down to a
+//     power of two for n remaining particles, at least 8, so that up to
+//     eight remaining particles share one round, and a lone near-vacuum
+//     particle, which needs every attempt, gets all 64 lanes.
 // More lanes per particle means more wavefronts in flight to hide latency.
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State st, StoreT<R> out, int64_t cap,
@@ -586,7 +593,10 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
     uint64_t hard = open;
     while (hard) {
       const int nh = __popcll(hard);
-      const int L = nh == 1 ? 64 : nh == 2 ? 32 : 16;  // lanes per particle (uniform)
+      // lanes per particle (uniform): 64 / nh rounded down to a power of
+      // two, at least 8 (a round of many particles with few lanes each
+      // would idle lanes on the slowest ones)
+      const int L = nh == 1 ? 64 : nh == 2 ? 32 : nh <= 4 ? 16 : 8;
       const int grp = lane / L, sl = lane % L;
       const uint64_t segm = L == 64 ? ~0ull : ((1ull << L) - 1ull);
       // this group's particle: the grp-th remaining one, if any
@@ -729,7 +739,10 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       }
     }
   }
-  if (__ballot(!ok) && lane == 0) atomicOr(st.flags, kFlagRange);
+  if (__ballot(!ok) && lane == 0) {
+    atomicOr(st.flags, kFlagRange);
+    atomicOr(st.halt, 1);
+  }
   // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
   const double tot = wave_sum_spread<32>(xc);
   double L[NLT];
@@ -866,7 +879,10 @@ __device__ __forceinline__ void wall_impulse(const Params &p, const State &st, i
     for (int j = 0; j < NLT; ++j)
       if (c[j] != 0.0) atomicAdd(&st.wimp[(3 * bf + q) * NLT + j], c[j]);
   }
-  if (!ok) atomicOr(st.flags, kFlagRange);
+  if (!ok) {
+    atomicOr(st.flags, kFlagRange);
+    atomicOr(st.halt, 1);
+  }
 }
 
 template <int DIM, int NV, class R, int FEAT>
@@ -1172,41 +1188,63 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
 // Every sum is exact (fixed-point chunks, see XWin), so it does not depend on
 // the order of the particles within a cell, which the scatter's atomics
 // leave open.  Also used at restart (empty collided ranges, Sp = null).
+
+// Adds the exact chunks of one particle's m Psi (RAW false) or raw moments
+// (RAW true) to xc.
+template <int DIM, bool RAW>
+__device__ __forceinline__ void tally_one(const Params &p, double m, double u0, double u1, double u2, double ei,
+                                          double (&xc)[32], bool &ok) {
+  constexpr int NW = DIM + 2, NLT = kTallyLimbs;
+  const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
+  if constexpr (!RAW) {
+    double t[NW];
+    t[0] = m;
+    t[1] = m * u0;
+    if (DIM == 2) t[2] = m * u1;
+    t[NW - 1] = m * (0.5 * q2 + ei);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      double ch[NLT];
+      ok = xs_split<NLT>(t[q], p.xw, ch) && ok;
+#pragma unroll
+      for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
+    }
+  } else {
+    const double q2i = q2 + 2.0 * ei;
+    const double r[5] = {m * u0 * q2i, m * u1 * q2i, m * u0 * u0, m * u0 * u1, m * u1 * u1};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      double ch[NLT];
+      ok = xs_split<NLT>(r[q], p.xm, ch) && ok;
+#pragma unroll
+      for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
+    }
+  }
+}
+
 // Adds the exact chunks of the particles in [a, b) to xc: of m Psi (RAW
 // false) or of the raw moments of the heat flux (RAW true), kTallyLimbs
 // chunks per quantity (value kTallyLimbs q + j = chunk j of quantity q).
+// Two particles per lane and iteration, both loaded before either is split
+// (a missing second one has m = 0 and adds zero chunks).
 template <int DIM, bool RAW, class R>
 __device__ __forceinline__ void tally_range(const Params &p, const StoreT<R> &s, int64_t a, int64_t b,
                                             double (&xc)[32], bool &ok) {
-  constexpr int NW = DIM + 2, NLT = kTallyLimbs;
-  for (int64_t k = a + lane_id(); k < b; k += 64) {
+  for (int64_t k = a + lane_id(); k < b; k += 128) {
+    const int64_t k2 = k + 64;
+    const bool two = k2 < b;
     const double m = s.m[k], u0 = s.ux[k], u1 = s.uy[k], u2 = s.uz[k];
     const double ei = s.ei ? static_cast<double>(s.ei[k]) : 0.0;
-    const double q2 = u0 * u0 + u1 * u1 + u2 * u2;
-    if constexpr (!RAW) {
-      double t[NW];
-      t[0] = m;
-      t[1] = m * u0;
-      if (DIM == 2) t[2] = m * u1;
-      t[NW - 1] = m * (0.5 * q2 + ei);
-#pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        double ch[NLT];
-        ok = xs_split<NLT>(t[q], p.xw, ch) && ok;
-#pragma unroll
-        for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
-      }
-    } else {
-      const double q2i = q2 + 2.0 * ei;
-      const double r[5] = {m * u0 * q2i, m * u1 * q2i, m * u0 * u0, m * u0 * u1, m * u1 * u1};
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        double ch[NLT];
-        ok = xs_split<NLT>(r[q], p.xm, ch) && ok;
-#pragma unroll
-        for (int j = 0; j < NLT; ++j) xc[NLT * q + j] += ch[j];
-      }
+    double m2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0, ej = 0.0;
+    if (two) {
+      m2 = s.m[k2];
+      v0 = s.ux[k2];
+      v1 = s.uy[k2];
+      v2 = s.uz[k2];
+      if (s.ei) ej = s.ei[k2];
     }
+    tally_one<DIM, RAW>(p, m, u0, u1, u2, ei, xc, ok);
+    tally_one<DIM, RAW>(p, m2, v0, v1, v2, ej, xc, ok);
   }
 }
 
@@ -1228,7 +1266,8 @@ __device__ __forceinline__ void tally_pass(const Params &p, const StoreT<R> &s, 
 
 template <int DIM, bool RAW, class R>
 __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const StoreT<R> &s, const int64_t *off,
-                                           double *S, double *X, double *Sp, double *M, int *flags, int64_t c) {
+                                           double *S, double *X, double *Sp, double *M, int *flags, int *halt,
+                                           int64_t c) {
   constexpr int NW = DIM + 2, NLT = kTallyLimbs;
   const int lane = lane_id();
   const int64_t a = off[c], b = off[c + 1], ca = off[g.nc + c], cb = off[g.nc + c + 1];
@@ -1261,7 +1300,10 @@ __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const 
     for (int j = 0; j < NLT; ++j) C[j] += L[j];
     if (writer && q < NW) Sp[c * NW + q] = xs_round<NLT>(C, p.xw);
   }
-  if (__ballot(!ok) && lane == 0) atomicOr(flags, kFlagRange);
+  if (__ballot(!ok) && lane == 0) {
+    atomicOr(flags, kFlagRange);
+    atomicOr(halt, 1);
+  }
 }
 
 // RAW: also the raw moments (Pr != 1).
@@ -1270,10 +1312,10 @@ __global__ void __launch_bounds__(256) k_cell_tally(Geo g, Params p, StoreT<R> s
                                                     double *__restrict__ S, double *__restrict__ X,
                                                     double *__restrict__ Sp,
                                                     double *__restrict__ M, int *__restrict__ flags,
-                                                    const int *__restrict__ halt) {
+                                                    int *__restrict__ halt) {
   const int64_t c = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (c >= g.nc || *halt) return;  // whole wavefront
-  cell_tally<DIM, RAW>(g, p, s, off, S, X, Sp, M, flags, c);
+  cell_tally<DIM, RAW>(g, p, s, off, S, X, Sp, M, flags, halt, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1435,7 +1477,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
   bool ok = true;
 #pragma unroll
   for (int q = 0; q < 2; ++q) ok = xs_split<4>(r[q], p.xr, rc[q]) && ok;
-  if (__ballot(!ok) && lane == 0) atomicOr(st.flags, kFlagRange);
+  if (__ballot(!ok) && lane == 0) atomicOr(st.flags, kFlagResidRange);
   // the sums go to the case of each cell (the cells of a case are
   // contiguous, so a wavefront holds one or two cases)
   const int key = i < g.nc ? case_of(g, i) : -1;
@@ -1521,9 +1563,19 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
     const double area = st.area[cs];
     sc[kScalRinst] = sqrt(xs_round<4>(rs, p.xr) / area) / rho_inf;
     sc[kScalRavg] = sqrt(xs_round<4>(rs + 4, p.xr) / area) / rho_inf;
+    // the drag sums the wall faces in order; 32 loads are issued
+    // together before their sequential additions
     double fsum = 0.0;
     const int64_t w0 = g.case_wall ? g.case_wall[cs] : 0, w1 = g.case_wall ? g.case_wall[cs + 1] : g.nwall;
-    for (int64_t w = w0; w < w1; ++w) fsum += st.fd[w];
+    int64_t w = w0;
+    for (; w + 32 <= w1; w += 32) {
+      double v[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v[j] = st.fd[w + j];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) fsum += v[j];
+    }
+    for (; w < w1; ++w) fsum += st.fd[w];
     const double cd = fsum / (0.5 * rho_inf * U * U * L);
     constexpr double a = 2.0 / 1001.0;
     sc[kScalCdLast] = cd;
@@ -1533,9 +1585,14 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
     // floors the instantaneous one); wave-only runs have no noise
     if (!((p.wave_only ? sc[kScalRinst] : sc[kScalRavg]) < tgt)) atomicAnd(&all_below, 0);
   }
-  for (int k = threadIdx.x; k < kStatSlots * kStatN; k += blockDim.x)
-    if (st.stats[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&stat_sum[k % kStatN]),
-                               static_cast<unsigned long long>(st.stats[k]));
+  {
+    // blockDim.x is a multiple of kStatN: a thread's slots hold one statistic
+    int64_t loc = 0;
+#pragma unroll 4
+    for (int k = threadIdx.x; k < kStatSlots * kStatN; k += blockDim.x) loc += st.stats[k];
+    if (loc) atomicAdd(reinterpret_cast<unsigned long long *>(&stat_sum[threadIdx.x % kStatN]),
+                       static_cast<unsigned long long>(loc));
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
   const int64_t nnew = st.noff[nc] + *st.nghost;
@@ -1621,11 +1678,6 @@ __global__ void __launch_bounds__(256) k_stream_copy(uint4 *__restrict__ dst, co
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
-__global__ void k_copy64(int64_t *__restrict__ dst, const int64_t *__restrict__ src, int64_t n) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------------------
 // explicit instantiations
 // ---------------------------------------------------------------------------
@@ -1645,9 +1697,9 @@ UGK_INST(2)
   template __global__ void k_sample_ghosts<D, R>(Geo, Params, State, StoreT<R>, int64_t);                \
   template __global__ void k_scatter<D, R>(State, StoreT<R>, StoreT<R>, StoreT<R>, int64_t);             \
   template __global__ void k_cell_tally<D, R, false>(Geo, Params, StoreT<R>, const int64_t *, double *,     \
-                                                     double *, double *, double *, int *, const int *);    \
+                                                     double *, double *, double *, int *, int *);          \
   template __global__ void k_cell_tally<D, R, true>(Geo, Params, StoreT<R>, const int64_t *, double *,      \
-                                                    double *, double *, double *, int *, const int *);
+                                                    double *, double *, double *, int *, int *);
 UGK_INST_P(1, double)
 UGK_INST_P(2, double)
 UGK_INST_P(1, float)

@@ -368,3 +368,53 @@ def _warm_start_checks(ws, tmp_path):
     assert [c["steps"] for c in r["f64"]["cases"]] == [120, 120]
     assert r["batch-warm"]["steps"] == 120 and len(r["batch-warm"]["case_r_avg"]) == 2
     assert r["batch-warm"]["warm_start_seconds"] > 0 and np.all(np.isfinite(r["batch-warm"]["case_r_avg"]))
+
+
+def test_network_beats_the_upsampled_coarse_field_on_held_out_draws():
+    """What the trained network gains: for the first three held-out draws
+    (never trained on), the fine solve's steady field (200 x 150, N_ref 100,
+    mixed precision, mean over 4000 steps after 4000 as for the training
+    targets, seeds of their own) is
+    computed here, and the network's field must be closer to it than the
+    bilinearly upsampled coarse field it starts from: RMS error of every
+    normalized primitive (ln rho, u/U, v/U, ln T) smaller on every draw, and
+    on average at most half the upsampled error.  Untrained or wrongly
+    applied weights (a correction with the wrong sign, outputs in another
+    order) fail it."""
+    import torch
+    from paper_2607_09552_amd import warmstart as ws
+    ws.use_own_stream()
+    try:
+        _network_gain_checks(ws)
+    finally:
+        torch.cuda.synchronize()
+        torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def _network_gain_checks(ws):
+    import torch
+    from paper_2607_09552_amd import Solver
+    cases = [tuple(c) for c in ws.draws(16, 4)[:3]]
+    Wc, _ = ws.coarse_solve(cases)
+    wls = [ws.fine_case(*c, n_ref=100, seed=7000 + k) for k, c in enumerate(cases)]
+    s = Solver.batch(wls, stream=ws._stream().value, precision="mixed", tuned=False)
+    try:
+        Wm = ws.averaged_fields(s, 4000, 4000, 10).cpu().numpy()
+        ranges = [s.case_range(k)[:2] for k in range(len(cases))]
+    finally:
+        s.close()
+    mlp = ws.MLP.load()
+    nf = ws.FINE[0] * ws.FINE[1]
+    rows = nf + (-nf) % 32
+    e_up, e_nn = [], []
+    for k, c in enumerate(cases):
+        c0, n = ranges[k]
+        target = ws._norm_prim(Wm[c0:c0 + n], wls[k])
+        X16, _, P32 = ws.features(Wc[k], ws.ws_case(wls[k], *c), rows, XT=False)
+        Y = mlp.infer(X16, rows)[:nf, :4].float().cpu().numpy()
+        P = P32.cpu().numpy().astype(np.float64)
+        e_up.append(np.sqrt(np.mean((target - P) ** 2, axis=0)))
+        e_nn.append(np.sqrt(np.mean((target - P - Y) ** 2, axis=0)))
+    e_up, e_nn = np.array(e_up), np.array(e_nn)
+    assert np.all(e_nn < e_up), (e_up, e_nn)
+    assert np.all(e_nn.mean(0) < 0.5 * e_up.mean(0)), (e_up.mean(0), e_nn.mean(0))
