@@ -522,10 +522,8 @@ int scan(ugkwp_ctx *c, const int *in, int64_t n, int64_t *out, int64_t *copy = n
   ProfScope ps(c, kKScan, 12.0 * static_cast<double>(n));
   hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanBlock), 0, c->stream, in, n, out, c->scan_tmp,
                      c->S.halt);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, c->stream, c->scan_tmp, nblocks,
-                     c->scan_tmp + nblocks, c->S.halt);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, c->stream, out, n, c->scan_tmp,
-                     c->scan_tmp + nblocks, c->S.halt, copy);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, c->stream, out, n, c->scan_tmp, c->S.halt,
+                     copy);
   HIPCHK(hipGetLastError());
   return UGKWP_OK;
 }

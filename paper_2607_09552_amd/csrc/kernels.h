@@ -160,8 +160,7 @@ __global__ void k_init_mixed(Geo, float4 *, float2 *);
 template <int DIM> __global__ void k_cell_prep(Geo, Params, State);
 template <int DIM> __global__ void k_ghost_prep(Geo, Params, State);
 __global__ void k_scan_blocks(const int *, int64_t, int64_t *, int64_t *, const int *);
-__global__ void k_scan_sums(int64_t *, int64_t, int64_t *, const int *);
-__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int64_t *, const int *, int64_t *);
+__global__ void k_scan_add(int64_t *, int64_t, const int64_t *, const int *, int64_t *);
 template <int DIM, class R> __global__ void k_sample_draw(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_match(Geo, Params, State, StoreT<R>, int64_t);
 template <int DIM, class R> __global__ void k_sample_shakhov(Geo, Params, State, StoreT<R>, int64_t, uint32_t);

@@ -345,8 +345,9 @@ __global__ void k_ghost_prep(Geo g, Params p, State st) {
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of int counts into int64 offsets (three-phase: block sums,
-// one-block scan of the sums, add).  kScanBlock elements per block.
+// Exclusive scan of int counts into int64 offsets in two launches: block
+// scans with their sums, then an add pass in which every block sums the block
+// sums before it.  kScanBlock elements per block.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t &total) {
   // sh: blockDim.x entries; Hillis-Steele on wavefront sums
@@ -389,34 +390,25 @@ __global__ void k_scan_blocks(const int *__restrict__ in, int64_t n, int64_t *__
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total,
-                            const int *__restrict__ halt) {
-  __shared__ int64_t sh[kScanBlock / 64 + 1];
-  if (*halt) return;
-  int64_t carry = 0;
-  for (int64_t base = 0; base < nb; base += kScanBlock) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = i < nb ? bsum[i] : 0;
-    int64_t t;
-    const int64_t r = block_excl_scan(v, sh, t);
-    if (i < nb) bsum[i] = r + carry;
-    carry += t;
-  }
-  if (threadIdx.x == 0) *total = carry;
-}
 
-// Also copies the first n results to out2 when given (the scatter's cursors).
+// Adds to each block's scan the sum of the block sums before it (each block
+// sums them itself: there are few) and writes the total to out[n].  Also
+// copies the first n results to out2 when given (the scatter's cursors).
 __global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ bsum,
-                           const int64_t *__restrict__ total, const int *__restrict__ halt,
-                           int64_t *__restrict__ out2) {
-  if (*halt) return;
+                           const int *__restrict__ halt, int64_t *__restrict__ out2) {
+  __shared__ int64_t sh[kScanBlock / 64 + 1];
+  if (*halt) return;  // uniform: nothing changes halt during the scan
+  int64_t part = 0;
+  for (int64_t k = threadIdx.x; k < static_cast<int64_t>(blockIdx.x); k += blockDim.x) part += bsum[k];
+  int64_t carry;
+  (void)block_excl_scan(part, sh, carry);
   const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
   if (i < n) {
-    const int64_t v = out[i] + bsum[blockIdx.x];
+    const int64_t v = out[i] + carry;
     out[i] = v;
     if (out2) out2[i] = v;
   }
-  if (i == n) out[n] = *total;
+  if (i == n) out[n] = carry + bsum[blockIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -672,25 +664,38 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
   constexpr int NW = DIM + 2;
   const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   if (i >= g.nc || *st.halt) return;  // whole wavefront
-  const int64_t n_ret = st.roff[g.nc];
+  constexpr int NLT = kTallyLimbs;
   const int lane = lane_id();
+  const int v = lane >> 1;
+  const int q = v / NLT;
+  const bool writer = (lane & 1) == 0 && v % NLT == 0 && q < NW;
+  // the retained tally's exact chunks, loaded early (independent of the rest)
+  double xr[NLT];
+#pragma unroll
+  for (int jj = 0; jj < NLT; ++jj) xr[jj] = writer ? st.Xret[(i * NW + q) * NLT + jj] : 0.0;
+  const int64_t n_ret = st.roff[g.nc];
   const int N = n_ret + st.noff[i] + st.ncount[i] <= cap ? st.ncount[i] : 0;
   // chunks of the new set's tally: value q * kTallyLimbs + j = chunk j of component q
-  constexpr int NLT = kTallyLimbs;
   double xc[32];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) xc[q] = 0.0;
+  for (int k = 0; k < 32; ++k) xc[k] = 0.0;
   bool ok = true;
   if (N > 0) {
     const int64_t base = n_ret + st.noff[i];
     const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
     const double sig = sqrt(p.R * h.T);
     const double mk = st.mnew[i];
+    // the first 64 particles' deviations stay in registers across the passes
+    const bool own = lane < N;
+    const double z0 = own ? static_cast<double>(out.ux[base + lane]) : 0.0;
+    const double z1 = own ? static_cast<double>(out.uy[base + lane]) : 0.0;
+    const double z2 = own ? static_cast<double>(out.uz[base + lane]) : 0.0;
+    const double e0 = own && out.ei ? static_cast<double>(out.ei[base + lane]) : 0.0;
     double zm[3] = {0.0, 0.0, 0.0};
     double alpha = 1.0, beta = 1.0;
     if (N >= 2) {
-      double zs[3] = {0.0, 0.0, 0.0}, es = 0.0;
-      for (int j = lane; j < N; j += 64) {
+      double zs[3] = {z0, z1, z2}, es = e0;
+      for (int j = lane + 64; j < N; j += 64) {
         zs[0] += out.ux[base + j];
         zs[1] += out.uy[base + j];
         zs[2] += out.uz[base + j];
@@ -701,7 +706,11 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       // the internal energies are scaled to carry exactly D R T^h / 2 per unit mass
       if (out.ei) beta = (0.5 * static_cast<double>(p.D) * static_cast<double>(N)) / wave_sum(es);
       double S = 0.0;
-      for (int j = lane; j < N; j += 64) {
+      if (own) {
+        const double a0 = z0 - zm[0], a1 = z1 - zm[1], a2 = z2 - zm[2];
+        S = a0 * a0 + a1 * a1 + a2 * a2;
+      }
+      for (int j = lane + 64; j < N; j += 64) {
         const double a0 = out.ux[base + j] - zm[0], a1 = out.uy[base + j] - zm[1], a2 = out.uz[base + j] - zm[2];
         S += a0 * a0 + a1 * a1 + a2 * a2;
       }
@@ -710,8 +719,11 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
     }
     for (int j = lane; j < N; j += 64) {
       const int64_t k = base + j;
-      const double w0 = (out.ux[k] - zm[0]) * alpha, w1 = (out.uy[k] - zm[1]) * alpha,
-                   w2 = (out.uz[k] - zm[2]) * alpha;
+      const bool first = j == lane;
+      const double y0 = first ? z0 : static_cast<double>(out.ux[k]);
+      const double y1 = first ? z1 : static_cast<double>(out.uy[k]);
+      const double y2 = first ? z2 : static_cast<double>(out.uz[k]);
+      const double w0 = (y0 - zm[0]) * alpha, w1 = (y1 - zm[1]) * alpha, w2 = (y2 - zm[2]) * alpha;
       // the stored velocities (rounded in the FP32 store) enter the tally
       const R r0 = static_cast<R>(h.ux + sig * w0), r1 = static_cast<R>(h.uy + sig * w1), r2 = static_cast<R>(sig * w2);
       out.ux[k] = r0;
@@ -719,7 +731,8 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       out.uz[k] = r2;
       double ei = 0.0;
       if (out.ei) {
-        const R re = static_cast<R>((p.R * h.T) * (beta * static_cast<double>(out.ei[k])));
+        const double y3 = first ? e0 : static_cast<double>(out.ei[k]);
+        const R re = static_cast<R>((p.R * h.T) * (beta * y3));
         out.ei[k] = re;
         ei = re;
       }
@@ -731,11 +744,11 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       if (DIM == 2) t[2] = mk * u1;
       t[NW - 1] = mk * en;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        double c[NLT];
-        ok = xs_split<NLT>(t[q], p.xw, c) && ok;
+      for (int c = 0; c < NW; ++c) {
+        double ch[NLT];
+        ok = xs_split<NLT>(t[c], p.xw, ch) && ok;
 #pragma unroll
-        for (int jj = 0; jj < NLT; ++jj) xc[q * NLT + jj] += c[jj];
+        for (int jj = 0; jj < NLT; ++jj) xc[c * NLT + jj] += ch[jj];
       }
     }
   }
@@ -743,19 +756,17 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
     atomicOr(st.flags, kFlagRange);
     atomicOr(st.halt, 1);
   }
-  // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
-  const double tot = wave_sum_spread<32>(xc);
   double L[NLT];
+  if (N > 0) {
+    // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
+    const double tot = wave_sum_spread<32>(xc);
 #pragma unroll
-  for (int jj = 0; jj < NLT; ++jj) L[jj] = __shfl(tot, (lane + 2 * jj) & 63, 64);
-  const int v = lane >> 1;
-  const int q = v / NLT;
-  if ((lane & 1) == 0 && v % NLT == 0 && q < NW) {
-    const double *xr = st.Xret + (i * NW + q) * NLT;
+    for (int jj = 0; jj < NLT; ++jj) L[jj] = __shfl(tot, (lane + 2 * jj) & 63, 64) + xr[jj];
+  } else {
 #pragma unroll
-    for (int jj = 0; jj < NLT; ++jj) L[jj] += xr[jj];
-    st.Sm[i * NW + q] = xs_round<NLT>(L, p.xw);
+    for (int jj = 0; jj < NLT; ++jj) L[jj] = xr[jj];
   }
+  if (writer) st.Sm[i * NW + q] = xs_round<NLT>(L, p.xw);
 }
 
 // Ghost injection: one wavefront per far-field/outflow face samples its slab;
@@ -1225,11 +1236,19 @@ __device__ __forceinline__ void tally_one(const Params &p, double m, double u0, 
 // Adds the exact chunks of the particles in [a, b) to xc: of m Psi (RAW
 // false) or of the raw moments of the heat flux (RAW true), kTallyLimbs
 // chunks per quantity (value kTallyLimbs q + j = chunk j of quantity q).
-// Two particles per lane and iteration, both loaded before either is split
-// (a missing second one has m = 0 and adds zero chunks).
+// Two particles per lane and iteration for m Psi, both loaded before either
+// is split (a missing second one has m = 0 and adds zero chunks); one for
+// the raw moments, whose five quantities leave no registers for a second.
 template <int DIM, bool RAW, class R>
 __device__ __forceinline__ void tally_range(const Params &p, const StoreT<R> &s, int64_t a, int64_t b,
                                             double (&xc)[32], bool &ok) {
+  if constexpr (RAW) {
+    for (int64_t k = a + lane_id(); k < b; k += 64) {
+      const double ei = s.ei ? static_cast<double>(s.ei[k]) : 0.0;
+      tally_one<DIM, RAW>(p, s.m[k], s.ux[k], s.uy[k], s.uz[k], ei, xc, ok);
+    }
+    return;
+  }
   for (int64_t k = a + lane_id(); k < b; k += 128) {
     const int64_t k2 = k + 64;
     const bool two = k2 < b;
@@ -1274,6 +1293,12 @@ __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const 
   bool ok = (b - a) + (cb - ca) <= (int64_t{1} << 20);
   const int v = lane >> 1, q = v / NLT;
   const bool writer = (lane & 1) == 0 && v % NLT == 0;
+  if constexpr (RAW) {
+    // raw moments of the kept particles (first, while nothing else is live)
+    double Lr[NLT];
+    tally_pass<DIM, true>(p, s, a, b, Lr, ok);
+    if (writer && q < 5) M[c * 5 + q] = xs_round<NLT>(Lr, p.xm);
+  }
   // kept particles: the next step's W^p Omega
   double L[NLT];
   tally_pass<DIM, false>(p, s, a, b, L, ok);
@@ -1285,12 +1310,6 @@ __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const 
     xs_normalize<NLT>(Ln);
 #pragma unroll
     for (int j = 0; j < NLT; ++j) X[(c * NW + q) * NLT + j] = Ln[j];
-  }
-  if constexpr (RAW) {
-    // raw moments of the kept particles
-    double Lr[NLT];
-    tally_pass<DIM, true>(p, s, a, b, Lr, ok);
-    if (writer && q < 5) M[c * 5 + q] = xs_round<NLT>(Lr, p.xm);
   }
   if (Sp) {
     // collided particles: W^{p,+} Omega is the exact sum over both sets
@@ -1308,7 +1327,7 @@ __device__ __forceinline__ void cell_tally(const Geo &g, const Params &p, const 
 
 // RAW: also the raw moments (Pr != 1).
 template <int DIM, class R, bool RAW>
-__global__ void __launch_bounds__(256) k_cell_tally(Geo g, Params p, StoreT<R> s, const int64_t *__restrict__ off,
+__global__ void __launch_bounds__(256, 4) k_cell_tally(Geo g, Params p, StoreT<R> s, const int64_t *__restrict__ off,
                                                     double *__restrict__ S, double *__restrict__ X,
                                                     double *__restrict__ Sp,
                                                     double *__restrict__ M, int *__restrict__ flags,
