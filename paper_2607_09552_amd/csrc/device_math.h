@@ -256,11 +256,14 @@ __device__ __forceinline__ void microslope(const double W[4], const double dW[4]
 // Interior-face time-averaged flux, face frame: equilibrium part Eq. (49)
 // with W0 from Eq. (17), a from the continuous normal slope dW0, A from
 // Eq. (22); free-transport wave part Eq. (50) read upwind (left hydrodynamic
-// state for u_n > 0, right for u_n < 0); a side with Wh == nullptr adds none.
-__device__ __forceinline__ void flux_interior(const double WL[4], const double WR[4], const double dW0[4],
-                                              const double *WhL, const double *WhR, const double dWhL[4],
-                                              const double dWhR[4], double dtL, double tauL, double dtR,
-                                              double tauR, int K, double Pr, int wave_only, double F[4]) {
+// state for u_n > 0, right for u_n < 0); a side whose flag hasL / hasR is
+// false adds none.  (Flags rather than null pointers keep the arrays in
+// registers.)
+__device__ __forceinline__ void flux_interior(const double (&WL)[4], const double (&WR)[4], const double (&dW0)[4],
+                                              bool hasL, const double (&WhL)[4], bool hasR, const double (&WhR)[4],
+                                              const double (&dWhL)[4], const double (&dWhR)[4], double dtL,
+                                              double tauL, double dtR, double tauR, int K, double Pr, int wave_only,
+                                              double (&F)[4]) {
   const FState sL = fstate(WL, K), sR = fstate(WR, K);
   Mom m;
   double pL[4], pR[4], W0[4];
@@ -309,7 +312,7 @@ __device__ __forceinline__ void flux_interior(const double WL[4], const double W
     }
   }
   double Ffr[4] = {0.0, 0.0, 0.0, 0.0};
-  if (WhL) {
+  if (hasL) {
     const FState h = fstate(WhL, K);
     double ah[4], g1[4], ga[4];
     microslope(WhL, dWhL, K, 1.0, ah);
@@ -319,7 +322,7 @@ __device__ __forceinline__ void flux_interior(const double WL[4], const double W
 #pragma unroll
     for (int q = 0; q < 4; ++q) Ffr[q] += h.rho * (cL.f0 * g1[q] + cL.f1 * ga[q]);
   }
-  if (WhR) {
+  if (hasR) {
     const FState h = fstate(WhR, K);
     double ah[4], g1[4], ga[4];
     microslope(WhR, dWhR, K, 1.0, ah);
@@ -336,8 +339,8 @@ __device__ __forceinline__ void flux_interior(const double WL[4], const double W
 // Diffuse isothermal wall, first order: outgoing half (into the wall)
 // abar g(W) + (dbar - E) g(W^h); reflected half: wall Maxwellian at rest and
 // T_w with the density that makes the net wave mass flux zero.
-__device__ __forceinline__ void flux_wall(const double W[4], const double *Wh, double dt, double tau, double Tw,
-                                          double R, int K, int wave_only, double F[4]) {
+__device__ __forceinline__ void flux_wall(const double (&W)[4], bool hasWh, const double (&Wh)[4], double dt,
+                                          double tau, double Tw, double R, int K, int wave_only, double (&F)[4]) {
   Coef co = time_coef(dt, tau);
   if (wave_only) {
     co.f0 = co.d;
@@ -350,7 +353,7 @@ __device__ __forceinline__ void flux_wall(const double W[4], const double *Wh, d
   psi_mom(m, 1, 0, 0, t);
 #pragma unroll
   for (int q = 0; q < 4; ++q) F[q] = s.rho * co.a * t[q];
-  if (Wh) {
+  if (hasWh) {
     const FState h = fstate(Wh, K);
     moments(m, h.U, h.V, h.lam, K, +1);
     psi_mom(m, 1, 0, 0, t);
@@ -373,16 +376,16 @@ __device__ __forceinline__ double van_leer(double a, double b) {
 
 // Face value along the normal line (face at xi = 0): limited slope from the
 // far neighbour and the other side; first order if there is no far neighbour
-// or the limited value is not a valid Maxwellian.
-__device__ __forceinline__ void reconstruct(const double *Wfar, double xfar, const double Wself[4], double xself,
-                                            const double Wother[4], double xother, double out[4],
-                                            double slope[4]) {
+// (has_far false) or the limited value is not a valid Maxwellian.
+__device__ __forceinline__ void reconstruct(bool has_far, const double (&Wfar)[4], double xfar,
+                                            const double (&Wself)[4], double xself, const double (&Wother)[4],
+                                            double xother, double (&out)[4], double (&slope)[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     out[q] = Wself[q];
     slope[q] = 0.0;
   }
-  if (!Wfar) return;
+  if (!has_far) return;
   double v[4], s[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

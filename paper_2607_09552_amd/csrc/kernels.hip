@@ -1145,22 +1145,37 @@ __global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 
 }
 
 // Re-sort (counting sort, scatter pass) into the next committed store b:
-// cursor[c] starts at the exclusive scan of the counts; each wavefront
-// claims contiguous slots for its lanes of equal destination with one atomic
-// per group, all groups of the wave in the same instruction.  Kept
-// particles go to [off[c], off[c+1]) (the next step's retained set, sorted
-// by cell); collided ones to [off[nc+c], off[nc+c+1]) after all kept ones,
-// with only what the tally reads (mass, velocity, internal energy).
-// Positions, masses and cells come from the transport's work store tw,
-// velocities from tw where the transport changed them, else from a.
+// cursor[c] starts at the exclusive scan of the counts.  A workgroup claims
+// contiguous slots for all its particles of one destination with one atomic:
+// each wavefront groups its lanes by destination, the group leaders enter
+// the destination in a workgroup table in LDS (open addressing over 256
+// entries, so every workgroup of 256 particles fits) and take their group's
+// offset within the workgroup's run, and one thread per destination then
+// claims the run.  Longer runs than per-wavefront claims mean fewer partly
+// written lines.  Kept particles go to [off[c], off[c+1]) (the next step's
+// retained set, sorted by cell); collided ones to [off[nc+c], off[nc+c+1])
+// after all kept ones, with only what the tally reads (mass, velocity,
+// internal energy).  Positions, masses and cells come from the transport's
+// work store tw, velocities from tw where the transport changed them, else
+// from a.  The order within a destination is left open (the tallies are
+// exact sums).
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R> tw, StoreT<R> b, int64_t cap) {
+  constexpr int kSlots = 256;
+  __shared__ int skey[kSlots];
+  __shared__ int scnt[kSlots];
+  __shared__ unsigned long long sbase[kSlots];
   if (*st.halt) return;
   const int64_t ncs = st.nc_scatter;
   const int64_t nt = st.roff[ncs] + st.noff[ncs] + *st.nghost;
   const int64_t n_total = nt < cap ? nt : cap;
   const int64_t base = blockIdx.x * static_cast<int64_t>(blockDim.x);
   if (base >= n_total) return;  // block-uniform
+  for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+    skey[t] = -1;
+    scnt[t] = 0;
+  }
+  __syncthreads();
   const int64_t k = base + threadIdx.x;
   const int rk = k < n_total ? st.rank[k] : -1;
   const bool live = rk >= 0;
@@ -1169,12 +1184,29 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
   const int c = live ? (col ? static_cast<int>(ncs) + cell : cell) : -1;
   int leader;
   const uint64_t grp = wave_group(c, leader);
-  unsigned long long bs = 0;
-  if (live && lane_id() == leader)
-    bs = atomicAdd(reinterpret_cast<unsigned long long *>(&st.cursor[c]), static_cast<unsigned long long>(__popcll(grp)));
-  bs = __shfl(bs, leader >= 0 ? leader : lane_id(), 64);
+  int slot = 0, off = 0;
+  if (live && lane_id() == leader) {
+    slot = static_cast<int>((static_cast<uint32_t>(c) * 2654435761u) >> 24);
+    for (;;) {
+      const int old = atomicCAS(&skey[slot], -1, c);
+      if (old == -1 || old == c) break;
+      slot = (slot + 1) & (kSlots - 1);
+    }
+    off = atomicAdd(&scnt[slot], __popcll(grp));
+  }
+  const int src = leader >= 0 ? leader : lane_id();
+  slot = __shfl(slot, src, 64);
+  off = __shfl(off, src, 64);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+    const int key = skey[t];
+    if (key >= 0)
+      sbase[t] = atomicAdd(reinterpret_cast<unsigned long long *>(&st.cursor[key]),
+                           static_cast<unsigned long long>(scnt[t]));
+  }
+  __syncthreads();
   if (!live) return;
-  const int64_t d = static_cast<int64_t>(bs) + popc_below(grp);
+  const int64_t d = static_cast<int64_t>(sbase[slot]) + off + popc_below(grp);
   const StoreT<R> &uv = (rk & kRankReflected) ? tw : a;
   b.ux[d] = uv.ux[k];
   b.uy[d] = uv.uy[k];
@@ -1342,7 +1374,7 @@ __global__ void __launch_bounds__(256, 4) k_cell_tally(Geo g, Params p, StoreT<R
 // stored as F_j s_j along the face normal (outward of the face's L cell).
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
+__global__ void __launch_bounds__(256, 3) k_face_flux(Geo g, Params p, State st) {
   constexpr int NW = DIM + 2;
   const int64_t fi = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (fi >= g.nf || *st.halt) return;
@@ -1357,7 +1389,7 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
   const bool hvL = st.hvalid[L] != 0;
   if (R >= 0) {
     const int LL = g.fLL[fi], RR = g.fRR[fi];
-    double wR[4], hR[4], wLL[4], hLL[4], wRR[4], hRR[4];
+    double wR[4], hR[4], wLL[4] = {0, 0, 0, 0}, hLL[4] = {0, 0, 0, 0}, wRR[4] = {0, 0, 0, 0}, hRR[4] = {0, 0, 0, 0};
     to_frame<DIM>(st.W + static_cast<int64_t>(R) * NW, n.x, n.y, wR);
     to_frame<DIM>(st.Wh + static_cast<int64_t>(R) * NW, n.x, n.y, hR);
     const bool hvR = st.hvalid[R] != 0;
@@ -1370,29 +1402,26 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
       to_frame<DIM>(st.Wh + static_cast<int64_t>(RR) * NW, n.x, n.y, hRR);
     }
     double WLf[4], WRf[4], sl[4], sr[4], dW0[4];
-    reconstruct(LL >= 0 ? wLL : nullptr, xi.x, wL, xi.y, wR, xi.z, WLf, sl);
-    reconstruct(RR >= 0 ? wRR : nullptr, xi.w, wR, xi.z, wL, xi.y, WRf, sr);
+    reconstruct(LL >= 0, wLL, xi.x, wL, xi.y, wR, xi.z, WLf, sl);
+    reconstruct(RR >= 0, wRR, xi.w, wR, xi.z, wL, xi.y, WRf, sr);
 #pragma unroll
     for (int q = 0; q < 4; ++q) dW0[q] = (wR[q] - wL[q]) / (xi.z - xi.y);
-    double HLf[4], HRf[4], shl[4] = {0, 0, 0, 0}, shr[4] = {0, 0, 0, 0};
-    const double *pHL = nullptr, *pHR = nullptr;
+    double HLf[4] = {0, 0, 0, 0}, HRf[4] = {0, 0, 0, 0}, shl[4] = {0, 0, 0, 0}, shr[4] = {0, 0, 0, 0};
     if (hvL) {
       const bool okf = LL >= 0 && st.hvalid[LL] != 0 && hvR;
-      reconstruct(okf ? hLL : nullptr, xi.x, hL, xi.y, hR, xi.z, HLf, shl);
-      pHL = HLf;
+      reconstruct(okf, hLL, xi.x, hL, xi.y, hR, xi.z, HLf, shl);
     }
     if (hvR) {
       const bool okf = RR >= 0 && st.hvalid[RR] != 0 && hvL;
-      reconstruct(okf ? hRR : nullptr, xi.w, hR, xi.z, hL, xi.y, HRf, shr);
-      pHR = HRf;
+      reconstruct(okf, hRR, xi.w, hR, xi.z, hL, xi.y, HRf, shr);
     }
-    flux_interior(WLf, WRf, dW0, pHL, pHR, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr,
+    flux_interior(WLf, WRf, dW0, hvL, HLf, hvR, HRf, shl, shr, st.dt[L], st.tau[L], st.dt[R], st.tau[R], K, p.Pr,
                   p.wave_only, F);
   } else {
     const int b = -R - 1;
     const int ty = g.btype[b];
     if (ty == kBcWall) {
-      flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, F);
+      flux_wall(wL, hvL, hL, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, F);
     } else {
       double wG[4], hG[4], dW0[4];
       const double z[4] = {0, 0, 0, 0};
@@ -1400,13 +1429,13 @@ __global__ void __launch_bounds__(256) k_face_flux(Geo g, Params p, State st) {
       to_frame<DIM>(st.gWh + static_cast<int64_t>(b) * NW, n.x, n.y, hG);
 #pragma unroll
       for (int q = 0; q < 4; ++q) dW0[q] = (wG[q] - wL[q]) / (-2.0 * xi.y);
-      flux_interior(wL, wG, dW0, hvL ? hL : nullptr, st.ghvalid[b] ? hG : nullptr, z, z, st.dt[L], st.tau[L],
+      flux_interior(wL, wG, dW0, hvL, hL, st.ghvalid[b] != 0, hG, z, z, st.dt[L], st.tau[L],
                     st.dt[L], st.gtau[b], K, p.Pr, p.wave_only, F);
       if (ty == kBcMaxwell) {
         // alpha times the diffuse wall's flux plus (1 - alpha) times the
         // mirror-state (specular) flux
         double Fd[4];
-        flux_wall(wL, hvL ? hL : nullptr, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, Fd);
+        flux_wall(wL, hvL, hL, st.dt[L], st.tau[L], g.bdata[8 * b], p.R, K, p.wave_only, Fd);
         const double a = g.bdata[8 * b + 1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) F[q] = a * Fd[q] + (1.0 - a) * F[q];

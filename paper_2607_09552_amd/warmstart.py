@@ -495,7 +495,10 @@ def cmd_eval(a):
     n0, n1 = (int(x) for x in a.reference.split(",")) if a.reference else (0, 0)
     for (Ma, Kn, Tw) in cases:
         wl = fine_case(Ma, Kn, Tw, n_ref=a.n_ref, seed=1)
-        res = dict(Ma=Ma, Kn=Kn, Tw=Tw, n_ref=a.n_ref, precision=a.precision)
+        # time steps from the freestream for every run (the reference and the
+        # free-stream leg have them anyway): all runs share one steady state
+        wl["dt_source"] = {"initial": 0, "freestream": 1}[a.dt_source]
+        res = dict(Ma=Ma, Kn=Kn, Tw=Tw, n_ref=a.n_ref, precision=a.precision, dt_source=a.dt_source)
         ref = None
         if n1 > n0 > 0:
             # the wall coefficients' mean over steps n0 < n <= n1 of a plain
@@ -503,15 +506,18 @@ def cmd_eval(a):
             s = Solver(wl, stream=_stream().value)
             try:
                 s.step(n0)
-                m0 = s.surface(1)[0][:, 3:6].copy()
+                sf0, cdr0 = s.surface(1)
+                m0 = sf0[:, 3:6].copy()
                 t0 = time.perf_counter()
                 for k in range(n0, n1, 10000):
                     s.step(min(10000, n1 - k))
                     print(f"  reference: {min(k + 10000, n1)} steps {time.perf_counter() - t0:.1f} s", flush=True)
-                m1 = s.surface(1)[0][:, 3:6].copy()
+                sf1, cdr1 = s.surface(1)
+                m1 = sf1[:, 3:6].copy()
             finally:
                 s.close()
             ref = (n1 * m1 - n0 * m0) / (n1 - n0)
+            ref_cd = (n1 * cdr1 - n0 * cdr0) / (n1 - n0)
             res["reference"] = dict(steps=[n0, n1], precision="f64", start="free stream")
         for start in a.starts.split(","):
             W0, info = (None, dict(seconds=0.0)) if start == "free" else warm_start(Ma, Kn, Tw, mlp, wl)
@@ -523,15 +529,32 @@ def cmd_eval(a):
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 surf, cd = s.surface(1)
+                win = None
+                if a.window > 0:
+                    # means over a fixed window of steps after convergence,
+                    # from the running means: (n1 M1 - n0 M0) / (n1 - n0)
+                    n0c, m0c = int(steps), surf[:, 3:6].copy()
+                    s.step(a.window)
+                    s1, cd1 = s.surface(1)
+                    n1c = n0c + a.window
+                    win = ((n1c * s1[:, 3:6] - n0c * m0c) / a.window, (n1c * cd1 - n0c * cd) / a.window)
             finally:
                 s.close()
             res[start] = dict(converged=conv, steps=int(steps), seconds=dt, start_seconds=info["seconds"],
                               cd_mean=cd)
+            if win is not None:
+                res[start]["window"] = dict(steps=a.window, cd=float(win[1]))
             if ref is not None:
                 # relative L2 over the wall faces of the running means at convergence
                 d = np.linalg.norm(surf[:, 3:6] - ref, axis=0) / np.linalg.norm(ref, axis=0)
                 res[start].update(dCp=float(d[0]), dCF=float(d[1]), dCQ=float(d[2]))
                 print(f"    wall means vs reference: dCp {d[0]:.3e} dCF {d[1]:.3e} dCQ {d[2]:.3e}", flush=True)
+                if win is not None:
+                    dw = np.linalg.norm(win[0] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+                    res[start]["window"].update(dCp=float(dw[0]), dCF=float(dw[1]), dCQ=float(dw[2]),
+                                                dCd=float(abs(win[1] - ref_cd) / abs(ref_cd)))
+                    print(f"    window of {a.window} steps vs reference: dCp {dw[0]:.3e} dCF {dw[1]:.3e} "
+                          f"dCQ {dw[2]:.3e} dCd {res[start]['window']['dCd']:.3e}", flush=True)
             del W0
             print(f"  Ma {Ma:.2f} Kn {Kn:.4f} Tw {Tw:.3f} {start}: converged {conv} steps {steps} {dt:.1f} s "
                   f"(+{info['seconds']:.2f} s start) C_d {cd:.4f}", flush=True)
@@ -643,6 +666,10 @@ def main(argv=None):
     e.add_argument("--reference", default="",
                    help="N0,N1: compare the wall means with a plain FP64 run's mean over steps N0..N1")
     e.add_argument("--out", default="")
+    e.add_argument("--window", type=int, default=0,
+                   help="after convergence, compare the wall means over this many further steps")
+    e.add_argument("--dt-source", choices=("initial", "freestream"), default="initial",
+                   help="time steps of every run from its initial field (Eq. (33)) or from the freestream")
     b = sub.add_parser("batched", help="time to residual: cases alone in FP64 against one batched solve")
     b.add_argument("--weights", default=WEIGHTS)
     b.add_argument("--n-test", type=int, default=16)
