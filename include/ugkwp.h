@@ -120,8 +120,11 @@ typedef struct {
  * steps dt_i from W0 (Eq. (33); from the freestream when dt_source = 1),
  * fixed for the whole run; the particle set
  * starts empty (W^p = 0, Sec. III.C).  W0 is [n_cells*(dim+2)] host memory.
+ * Sizes: fewer than 2^28 cells in a context (2^24 cells plus boundary
+ * faces per case, the particle ids' layout).
  * Errors: EINVAL (mesh not matching its boundary list, non-convex or
- * clockwise cell, bad parameters), ENUMERIC (invalid W0), EDEVICE, ENOMEM. */
+ * clockwise cell, bad parameters, sizes), ENUMERIC (invalid W0), EDEVICE,
+ * ENOMEM. */
 int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double *W0, ugkwp_ctx **out);
 
 /* A batch of independent cases in one context: the cases' meshes are joined

@@ -600,11 +600,9 @@ int ensure_capacity(ugkwp_ctx *c, int64_t need) {
     return set_err(c, UGKWP_EOVERFLOW, "particle store of %lld exceeds 2^31", (long long)ncap);
   const int rc = c->precision ? grow_stores(c, c->A32, c->B32, c->T32, ncap) : grow_stores(c, c->A, c->B, c->T, ncap);
   if (rc) return rc;
-  dfree(c, c->S.rank);
   dfree(c, c->S.tghost);
-  c->S.rank = nullptr;
   c->S.tghost = nullptr;
-  if (dalloc(c, &c->S.rank, ncap) || dalloc(c, &c->S.tghost, ncap))
+  if (dalloc(c, &c->S.tghost, ncap))
     return set_err(c, UGKWP_ENOMEM, "cannot grow particle work arrays");
   c->cap = ncap;
   return UGKWP_OK;
@@ -876,6 +874,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   if (mesh->dim != 1 && mesh->dim != 2) return set_err(c, UGKWP_EINVAL, "dim must be 1 or 2");
   if (mesh->n_cells <= 0 || mesh->n_cells >= (int64_t{1} << 31) - 1 - mesh->n_bfaces)
     return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces must be in [1, 2^31)");
+  if (mesh->n_cells > kCodeCell) return set_err(c, UGKWP_EINVAL, "a context holds fewer than 2^28 cells");
   for (int k = 0; k < ncase; ++k)
     if ((case_cell[k + 1] - case_cell[k]) + (case_bface[k + 1] - case_bface[k]) >= (1 << 24) - 1)
       return set_err(c, UGKWP_EINVAL, "n_cells + n_bfaces of a case must be below 2^24");
@@ -1281,7 +1280,7 @@ void drop_graph(ugkwp_ctx *c) {
 // change when the store grows), capacity, grid coverage and tuning.
 std::vector<int64_t> graph_key(const ugkwp_ctx *c) {
   return {reinterpret_cast<int64_t>(c->A.x), reinterpret_cast<int64_t>(c->B.x), reinterpret_cast<int64_t>(c->A32.x),
-          reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.rank),
+          reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.tghost),
           reinterpret_cast<int64_t>(c->T.x), reinterpret_cast<int64_t>(c->T32.x), c->cap, c->cover, c->cover_new,
           c->transport_block, c->shakhov_lanes, c->P.max_cross, c->xw_exp, c->xm_exp, c->xr_exp};
 }

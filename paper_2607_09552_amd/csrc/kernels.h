@@ -113,7 +113,6 @@ struct State {
   double *tghost;                       // remaining time of entered ghost particles
   int *count;                           // [2 nc] particles ending in each cell: kept (c), collided (nc + c)
   int64_t *coff;                        // [2 nc + 1] exclusive scan of count
-  int *rank;                            // [cap] per transported slot: -1 left or unused, else kRank* bits
   int64_t *cursor;                      // [2 nc] slot cursor of the scatter
   int64_t nc_scatter;                   // number of cells (for kernels without Geo)
   double *Fs;                           // [nf*NW] time-averaged face flux times s_j
@@ -136,9 +135,16 @@ enum : int {
   kInfoTotal = 0, kInfoNew, kInfoNeed, kInfoSumTotal, kInfoNeedNew, kInfoRemoved, kInfoExited, kInfoGuard, kInfoCapped,
   kInfoN
 };
-// transport outcome of a slot (rank): bit 0 collided (Eq. (51)), bit 1 the
-// velocity changed at a wall or symmetry face
-enum : int { kRankCollided = 1, kRankReflected = 2 };
+// Transport outcome of a slot, held in the work store's cell entry: -1 when
+// the particle left the domain; else the cell in the low 28 bits, with bit
+// 30 set when it collided (Eq. (51)), bit 29 when a wall or symmetry face
+// changed its velocity and bit 28 when it crossed into another cell (its
+// mass changed, Eq. (41)); the scatter reads the velocity and the mass from
+// the work store only when they changed.  A context holds fewer than 2^28
+// cells.
+enum : int {
+  kCodeCollided = 1 << 30, kCodeReflected = 1 << 29, kCodeMoved = 1 << 28, kCodeCell = (1 << 28) - 1
+};
 
 // Particle store, structure of arrays.  R = double: global positions (the
 // FP64 path); R = float: positions relative to the cell's anchor and FP32

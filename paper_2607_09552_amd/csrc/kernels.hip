@@ -949,6 +949,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       t = static_cast<R>(st.tghost[k - gbase]);
     }
     bool reflected = false;
+    bool moved = false;
     int ncross = 0, hits = 0;
     for (;;) {
       R best = static_cast<R>(INFINITY);
@@ -989,6 +990,7 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
           nb = nbr[kk];
         }
       if (nb >= 0) {
+        moved = true;
         const int64_t l = static_cast<int64_t>(cell) * NV + kb;
         load_cell(nb);
         if constexpr (F32) {
@@ -1095,10 +1097,10 @@ __device__ __forceinline__ void transport_one(const Geo &g, const Params &p, con
       tw.uz[k] = u2;
       if constexpr ((FEAT & kFeatEi) != 0) tw.ei[k] = ei;
     }
-    tw.m[k] = m;
-    tw.cell[k] = cell;
-    if (!exited) st.rank[k] = (collide ? kRankCollided : 0) | (reflected ? kRankReflected : 0);
-    else st.rank[k] = -1;
+    if (moved) tw.m[k] = m;
+    tw.cell[k] = exited ? -1
+                        : (cell | (collide ? kCodeCollided : 0) | (reflected ? kCodeReflected : 0) |
+                           (moved ? kCodeMoved : 0));
   }
   const bool inside = active && !exited;
   // histogram of the particles ending inside per destination: kept ones in
@@ -1155,10 +1157,10 @@ __global__ void __launch_bounds__(256, (NV <= 4 && (FEAT & kFeatEi) == 0) ? 4 : 
 // written lines.  Kept particles go to [off[c], off[c+1]) (the next step's
 // retained set, sorted by cell); collided ones to [off[nc+c], off[nc+c+1])
 // after all kept ones, with only what the tally reads (mass, velocity,
-// internal energy).  Positions, masses and cells come from the transport's
-// work store tw, velocities from tw where the transport changed them, else
-// from a.  The order within a destination is left open (the tallies are
-// exact sums).
+// internal energy).  Positions and cells come from the transport's work
+// store tw, velocities and masses from tw where the transport changed them
+// (the slot's outcome code says which), else from a.  The order within a
+// destination is left open (the tallies are exact sums).
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R> tw, StoreT<R> b, int64_t cap) {
   constexpr int kSlots = 256;
@@ -1177,10 +1179,10 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
   }
   __syncthreads();
   const int64_t k = base + threadIdx.x;
-  const int rk = k < n_total ? st.rank[k] : -1;
-  const bool live = rk >= 0;
-  const int cell = live ? tw.cell[k] : 0;
-  const bool col = live && (rk & kRankCollided) != 0;
+  const int code = k < n_total ? tw.cell[k] : -1;
+  const bool live = code >= 0;
+  const int cell = live ? (code & kCodeCell) : 0;
+  const bool col = live && (code & kCodeCollided) != 0;
   const int c = live ? (col ? static_cast<int>(ncs) + cell : cell) : -1;
   int leader;
   const uint64_t grp = wave_group(c, leader);
@@ -1207,12 +1209,13 @@ __global__ void __launch_bounds__(256) k_scatter(State st, StoreT<R> a, StoreT<R
   __syncthreads();
   if (!live) return;
   const int64_t d = static_cast<int64_t>(sbase[slot]) + off + popc_below(grp);
-  const StoreT<R> &uv = (rk & kRankReflected) ? tw : a;
+  const StoreT<R> &uv = (code & kCodeReflected) ? tw : a;
+  const StoreT<R> &um = (code & kCodeMoved) ? tw : a;
   b.ux[d] = uv.ux[k];
   b.uy[d] = uv.uy[k];
   b.uz[d] = uv.uz[k];
   if (a.ei) b.ei[d] = uv.ei[k];
-  b.m[d] = tw.m[k];
+  b.m[d] = um.m[k];
   if (col) return;
   b.x[d] = tw.x[k];
   if (DIM == 2) b.y[d] = tw.y[k];
