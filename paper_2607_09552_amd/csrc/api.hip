@@ -720,7 +720,7 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
   }
   {
     ProfScope ps(c, kKSampleMatch, 48.0 * c->est_new + (8.0 * 2 * NW + 24.0) * nc);
-    hipLaunchKernelGGL((k_sample_match<DIM, R>), dim3(nblk(nc * 64, 256)), dim3(256), 0, c->stream, g, c->P, S, A,
+    hipLaunchKernelGGL((k_sample_match<DIM, R>), dim3(nblk(nc * 16, 256)), dim3(256), 0, c->stream, g, c->P, S, A,
                        c->cap);
   }
   if (nb > 0) {

@@ -653,22 +653,58 @@ __global__ void __launch_bounds__(256) k_sample_shakhov(Geo g, Params p, State s
   }
 }
 
-// Moment-matching pass: one wavefront per cell over its new particles.  For
+// Moment-matching pass: sixteen lanes per cell (four cells per wavefront:
+// a cell draws about twenty new particles in the benchmark flow) over its
+// new particles.  For
 // N >= 2 the deviations are shifted to zero mean and scaled so that the set
 // carries exactly the momentum and thermal energy of W^hp (Eq. (25)):
 // u = U^h + sqrt(R T^h) ((z - zbar) alpha), alpha = sqrt(3 N / sum |z - zbar|^2).
 // Also W^{p,-} Omega = W^p Omega + the new set's tally (Eq. (30)), rounded
-// once from the exact chunks of both.
+// once from the exact chunks of both.  Every reduction stays within the
+// cell's sixteen lanes (exchanges at distance 8, 4, 2, 1).
+constexpr int kMatchLanes = 16;
+
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int o = kMatchLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One halving exchange at distance O: of 2H values, a lane keeps the half
+// its bit O selects and adds the partner's copy of it.
+template <int H, int O>
+__device__ __forceinline__ void seg_halve(double (&v)[32]) {
+  const bool hi = (lane_id() & O) != 0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double send = hi ? v[j] : v[j + H];
+    const double keep = hi ? v[j + H] : v[j];
+    v[j] = keep + __shfl_xor(send, O, 64);
+  }
+}
+
+// Totals of 32 values over a cell's sixteen lanes: on return, lane r of the
+// segment holds the totals of values 2r (in v[0]) and 2r + 1 (in v[1]).
+__device__ __forceinline__ void seg_spread32(double (&v)[32]) {
+  seg_halve<16, 8>(v);
+  seg_halve<8, 4>(v);
+  seg_halve<4, 2>(v);
+  seg_halve<2, 1>(v);
+}
+
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st, StoreT<R> out, int64_t cap) {
   constexpr int NW = DIM + 2;
-  const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  if (i >= g.nc || *st.halt) return;  // whole wavefront
   constexpr int NLT = kTallyLimbs;
-  const int lane = lane_id();
-  const int v = lane >> 1;
-  const int q = v / NLT;
-  const bool writer = (lane & 1) == 0 && v % NLT == 0 && q < NW;
+  static_assert(NLT == 6 && NW * NLT <= 32, "the writer layout assumes six chunks per component");
+  const int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kMatchLanes;
+  // a segment (one cell) returns as a whole; reductions stay inside segments
+  if (i >= g.nc || *st.halt) return;
+  const int sl = lane_id() % kMatchLanes;
+  // component q is gathered by segment lane 3 q (its chunks sit at lanes 3 q,
+  // 3 q + 1 and 3 q + 2, two each)
+  const int q = sl / 3;
+  const bool writer = sl % 3 == 0 && q < NW;
   // the retained tally's exact chunks, loaded early (independent of the rest)
   double xr[NLT];
 #pragma unroll
@@ -685,41 +721,41 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
     const Prim<DIM> h = prim<DIM>(st.Wh + i * NW, p.NR);
     const double sig = sqrt(p.R * h.T);
     const double mk = st.mnew[i];
-    // the first 64 particles' deviations stay in registers across the passes
-    const bool own = lane < N;
-    const double z0 = own ? static_cast<double>(out.ux[base + lane]) : 0.0;
-    const double z1 = own ? static_cast<double>(out.uy[base + lane]) : 0.0;
-    const double z2 = own ? static_cast<double>(out.uz[base + lane]) : 0.0;
-    const double e0 = own && out.ei ? static_cast<double>(out.ei[base + lane]) : 0.0;
+    // the first sixteen particles' deviations stay in registers across the passes
+    const bool own = sl < N;
+    const double z0 = own ? static_cast<double>(out.ux[base + sl]) : 0.0;
+    const double z1 = own ? static_cast<double>(out.uy[base + sl]) : 0.0;
+    const double z2 = own ? static_cast<double>(out.uz[base + sl]) : 0.0;
+    const double e0 = own && out.ei ? static_cast<double>(out.ei[base + sl]) : 0.0;
     double zm[3] = {0.0, 0.0, 0.0};
     double alpha = 1.0, beta = 1.0;
     if (N >= 2) {
       double zs[3] = {z0, z1, z2}, es = e0;
-      for (int j = lane + 64; j < N; j += 64) {
+      for (int j = sl + kMatchLanes; j < N; j += kMatchLanes) {
         zs[0] += out.ux[base + j];
         zs[1] += out.uy[base + j];
         zs[2] += out.uz[base + j];
         if (out.ei) es += out.ei[base + j];
       }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) zm[d] = wave_sum(zs[d]) / static_cast<double>(N);
+      for (int d = 0; d < 3; ++d) zm[d] = seg_sum(zs[d]) / static_cast<double>(N);
       // the internal energies are scaled to carry exactly D R T^h / 2 per unit mass
-      if (out.ei) beta = (0.5 * static_cast<double>(p.D) * static_cast<double>(N)) / wave_sum(es);
+      if (out.ei) beta = (0.5 * static_cast<double>(p.D) * static_cast<double>(N)) / seg_sum(es);
       double S = 0.0;
       if (own) {
         const double a0 = z0 - zm[0], a1 = z1 - zm[1], a2 = z2 - zm[2];
         S = a0 * a0 + a1 * a1 + a2 * a2;
       }
-      for (int j = lane + 64; j < N; j += 64) {
+      for (int j = sl + kMatchLanes; j < N; j += kMatchLanes) {
         const double a0 = out.ux[base + j] - zm[0], a1 = out.uy[base + j] - zm[1], a2 = out.uz[base + j] - zm[2];
         S += a0 * a0 + a1 * a1 + a2 * a2;
       }
-      S = wave_sum(S);
+      S = seg_sum(S);
       alpha = sqrt((3.0 * static_cast<double>(N)) / S);
     }
-    for (int j = lane; j < N; j += 64) {
+    for (int j = sl; j < N; j += kMatchLanes) {
       const int64_t k = base + j;
-      const bool first = j == lane;
+      const bool first = j == sl;
       const double y0 = first ? z0 : static_cast<double>(out.ux[k]);
       const double y1 = first ? z1 : static_cast<double>(out.uy[k]);
       const double y2 = first ? z2 : static_cast<double>(out.uz[k]);
@@ -752,16 +788,21 @@ __global__ void __launch_bounds__(256) k_sample_match(Geo g, Params p, State st,
       }
     }
   }
-  if (__ballot(!ok) && lane == 0) {
+  if (!ok) {
     atomicOr(st.flags, kFlagRange);
     atomicOr(st.halt, 1);
   }
   double L[NLT];
   if (N > 0) {
-    // lane l holds the total of value l >> 1; lane 2 NLT q gathers component q
-    const double tot = wave_sum_spread<32>(xc);
-#pragma unroll
-    for (int jj = 0; jj < NLT; ++jj) L[jj] = __shfl(tot, (lane + 2 * jj) & 63, 64) + xr[jj];
+    seg_spread32(xc);
+    const double b0 = __shfl(xc[0], lane_id() + 1, 64), b1 = __shfl(xc[1], lane_id() + 1, 64);
+    const double c0 = __shfl(xc[0], lane_id() + 2, 64), c1 = __shfl(xc[1], lane_id() + 2, 64);
+    L[0] = xc[0] + xr[0];
+    L[1] = xc[1] + xr[1];
+    L[2] = b0 + xr[2];
+    L[3] = b1 + xr[3];
+    L[4] = c0 + xr[4];
+    L[5] = c1 + xr[5];
   } else {
 #pragma unroll
     for (int jj = 0; jj < NLT; ++jj) L[jj] = xr[jj];
