@@ -22,7 +22,9 @@ Training fits the corrections to time-averaged steady fields of full UGKWP
 runs of sampled cases (mean squared error, Adam).  Every arithmetic step of
 inference and training runs in the library's kernels (dense layers on the
 BF16 matrix cores); torch only holds device memory and clears gradient
-buffers.
+buffers.  Data preparation (the time averages of the solver's fields that
+become the targets and the coarse input, the held-out error figures) is
+host numpy.
 
 Command line (GPU): ``python -m paper_2607_09552_amd.warmstart data|train|eval``.
 """
@@ -132,18 +134,20 @@ def cylinder_ws_case(Ma, Kn, Tw):
 
 
 def averaged_fields(s, transient, average, every, log=None):
-    """Device mean of the conservative fields of solver s over `average`
-    steps (sampled every `every`) after `transient` steps."""
+    """Mean of the conservative fields of solver s over `average` steps
+    (sampled every `every`) after `transient` steps, summed on the host
+    (data preparation, not the network's arithmetic) and returned as a
+    device tensor for the feature kernel."""
     import torch
     s.step(transient)
-    acc = torch.zeros((s.nc, s.nw), dtype=torch.float64, device="cuda")
+    acc = np.zeros((s.nc, s.nw), dtype=np.float64)
     n = max(1, average // every)
     for k in range(n):
         s.step(every)
-        acc += s.fields_device()
+        acc += s.fields()
         if log and (k + 1) % max(1, n // 4) == 0:
             log(f"averaged {(k + 1) * every} steps")
-    return acc / n
+    return torch.tensor(acc / n, device="cuda")
 
 
 def coarse_solve(cases, transient=COARSE_TRANSIENT, average=COARSE_AVERAGE, every=COARSE_EVERY):
