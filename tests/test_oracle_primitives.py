@@ -20,6 +20,7 @@ import pytest
 from scipy import integrate
 
 import oracle
+import workloads as wl
 from tests import quadrature as Q
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -274,7 +275,15 @@ def test_wall_flux_zero_mass_and_quadrature():
 
 
 def test_lts_counterexample_values():
-    """Sec. IV.A: the printed 4/3 vs 3/2 of Eq. (46)."""
+    """Sec. IV.A, Eq. (46): with time steps that vary from step to step,
+    stepwise proportional mass scaling breaks the multi-step flux balance
+    (the printed example: 4/3 against 3/2); with fixed local time steps (the
+    method's, Eq. (33), R22) the oracle's crossings keep it exactly.  A
+    stream of particles leaves cell L across the face into R during M = 2
+    steps of the fixed steps: the transported mass per unit time,
+    sum m / (M dt), is the same on both sides (Eq. (45)), and replaying the
+    same crossings with the printed time-varying steps gives the printed
+    imbalance."""
     from fractions import Fraction as Fr
     vals = {}
     for line in open(os.path.join(GOLD, "lts_counterexample.txt")):
@@ -288,6 +297,30 @@ def test_lts_counterexample_values():
     lhs = sum(dR) / sum(dL)
     rhs = sum(r / l for r, l in zip(dR, dL)) / M
     assert lhs == Fr(vals["lhs"][0]) and rhs == Fr(vals["rhs"][0]) and lhs != rhs
+    # fixed steps: two cells of widths 1 and 2 (dt_R = 2 dt_L by Eq. (33) in
+    # a uniform state); each step the same set of particles leaves L into R
+    m = wl.uniform1d(np.array([0.0, 1.0, 3.0]), U=0.0, bc=wl.BC_SYMMETRY)
+    o = oracle.Oracle(m)
+    dt = o.dt()
+    assert dt[1] == 2.0 * dt[0]
+    rng = np.random.default_rng(7)
+    sent, got = Fr(0), Fr(0)
+    for step in range(M):
+        for k in range(50):
+            m0 = float(rng.uniform(0.5, 1.5))
+            x0 = float(rng.uniform(0.6, 0.99))
+            u = np.array([float(rng.uniform(0.5, 2.0)) / dt[0], 0.0, 0.0])
+            r = o.track_one(1000 * step + k, step, 0, [x0], u, m0, dt[0])
+            assert r["rc"] == 0 and r["cell"] == 1
+            sent += Fr(m0)
+            got += Fr(r["m"])
+    # the transported mass per unit time is the same on both sides
+    assert abs(float(got / (M * Fr(dt[1])) - sent / (M * Fr(dt[0])))) <= 1e-15 * float(sent / (M * Fr(dt[0])))
+    # the same crossings under the printed time-varying steps: stepwise
+    # scaling by dt_R,l / dt_L,l leaves the two sides unequal by 4/3 : 3/2
+    per_step = sent / M
+    got_v = sum(per_step * r / l for r, l in zip(dR, dL))
+    assert (got_v / sum(dR)) / (sent / sum(dL)) == rhs / lhs
 
 
 def test_vacuum_interface_carries_no_equilibrium_flux():
