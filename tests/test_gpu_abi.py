@@ -111,3 +111,31 @@ def test_init_checks():
     c["bface_type"][0] = 9
     with pytest.raises(UgkwpError, match="unknown type"):
         Solver(c)
+
+
+def test_stream_copy_copies_and_checks_its_arguments():
+    """ugkwp_stream_copy (the bandwidth reference): the copy equals its
+    source for the default grid, a small grid (grid-stride loop and its
+    tail) and one element per thread; misaligned, overlapping, empty or
+    odd-sized requests are refused with EINVAL before anything runs."""
+    import torch
+    from paper_2607_09552_amd import load_library, stream_copy
+    L = load_library()
+    n = (1 << 20) + 3  # 16-byte elements: a ragged tail for every grid
+    a = torch.arange(2 * n, dtype=torch.float64, device="cuda")
+    for blocks in (0, 7, (n + 255) // 256):
+        b = torch.full_like(a, -1.0)
+        ms = stream_copy(b, a, reps=2, blocks=blocks)
+        torch.cuda.synchronize()
+        assert ms > 0 and torch.equal(a, b), blocks
+    out = C.c_double()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    other = torch.empty_like(a)
+    pa, pb = a.data_ptr(), other.data_ptr()
+    EINVAL = -1
+    assert L.ugkwp_stream_copy(C.c_void_p(pb), C.c_void_p(pa), 0, 1, 0, st, C.byref(out)) == EINVAL
+    assert L.ugkwp_stream_copy(C.c_void_p(pb), C.c_void_p(pa), 24, 1, 0, st, C.byref(out)) == EINVAL
+    assert L.ugkwp_stream_copy(C.c_void_p(pb + 8), C.c_void_p(pa), 32, 1, 0, st, C.byref(out)) == EINVAL
+    assert L.ugkwp_stream_copy(C.c_void_p(pa + 16), C.c_void_p(pa), 64, 1, 0, st, C.byref(out)) == EINVAL
+    assert L.ugkwp_stream_copy(C.c_void_p(pb), C.c_void_p(pa), 32, 0, 0, st, C.byref(out)) == EINVAL
+    assert L.ugkwp_stream_copy(None, C.c_void_p(pa), 32, 1, 0, st, C.byref(out)) == EINVAL
