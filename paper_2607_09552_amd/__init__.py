@@ -47,7 +47,8 @@ class _Mesh(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("batch_steps", C.c_int32), ("use_graph", C.c_int32), ("transport_block", C.c_int32),
-                ("shakhov_lanes", C.c_int32), ("max_crossings", C.c_int32)]
+                ("shakhov_lanes", C.c_int32), ("max_crossings", C.c_int32), ("scatter_block", C.c_int32),
+                ("tally_block", C.c_int32), ("flux_block", C.c_int32)]
 
 
 class _Params(C.Structure):

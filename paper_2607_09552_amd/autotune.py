@@ -1,5 +1,6 @@
 """Launch-tuning sweep on the GPU (gfx950): steps per host synchronization,
-graph replay, transport block size and the lanes per particle of the
+graph replay, the block sizes of the transport, the re-sort's scatter, the
+per-cell tally and the face fluxes, and the lanes per particle of the
 Shakhov sampler's first phase (ugkwp_set_tuning; results do not depend on
 them).
 
@@ -28,6 +29,9 @@ SPACE = {
     "use_graph": [0, 1],
     "transport_block": [64, 128, 256],
     "shakhov_lanes": [1, 2, 4, 8, 16],
+    "scatter_block": [64, 128, 256],
+    "tally_block": [64, 128, 256],
+    "flux_block": [64, 128, 256],
 }
 
 

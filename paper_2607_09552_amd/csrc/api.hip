@@ -115,6 +115,7 @@ struct ugkwp_ctx {
   bool prof = false, prof_all = false;
   // tuning
   int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4, max_crossings = 10000;
+  int32_t scatter_block = 256, tally_block = 256, flux_block = 256;
   // ugkwp_step_noalloc: this device's scratch array, and set while such a
   // call runs (no growth, no graph capture, no timing events)
   unsigned char *noalloc_scratch = nullptr;
@@ -663,7 +664,7 @@ void launch_transport(ugkwp_ctx *c, const Geo &g, const State &S, const StoreT<R
 template <int DIM, class R>
 void launch_tally(ugkwp_ctx *c, const Geo &g, const StoreT<R> &s, const int64_t *off, double *S, double *X,
                   double *Sp, double *M) {
-  const dim3 gr(nblk(c->nc * 64, 256)), bl(256);
+  const dim3 gr(nblk(c->nc * 64, c->tally_block)), bl(c->tally_block);
   if (c->P.Pr != 1.0)
     hipLaunchKernelGGL((k_cell_tally<DIM, R, true>), gr, bl, 0, c->stream, g, c->P, s, off, S, X, Sp, M, c->S.flags,
                        c->S.halt);
@@ -705,7 +706,7 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
   // particle-parallel grids cover c->cover particles (c->cover_new new ones);
   // a step whose counts exceed them halts in k_check and is redone with
   // larger grids.  Blocks past the step's count return at once.
-  const unsigned gcap = static_cast<unsigned>(nblk(c->cover, 256));
+  const unsigned gcap = static_cast<unsigned>(nblk(c->cover, c->scatter_block));
   const unsigned gnew = static_cast<unsigned>(nblk(c->cover_new, 256));
   {
     ProfScope ps(c, kKSampleCells, rec * c->est_new);
@@ -752,7 +753,7 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
   if (rc) return rc;
   {
     ProfScope ps(c, kKScatter, (2.0 * rec + 4.0) * c->est_kept);
-    hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(256), 0, c->stream, S, A, T, B, c->cap);
+    hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(gcap), dim3(c->scatter_block), 0, c->stream, S, A, T, B, c->cap);
   }
   {
     const double rd = 8.0 * NW;  // m and the velocity components of a kept particle
@@ -761,7 +762,8 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
   }
   {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
-    hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, 256)), dim3(256), 0, c->stream, g, c->P, S);
+    hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, c->flux_block)), dim3(c->flux_block), 0, c->stream, g,
+                       c->P, S);
   }
   {
     ProfScope ps(c, kKUpdate, 350.0 * nc);
@@ -1282,7 +1284,8 @@ std::vector<int64_t> graph_key(const ugkwp_ctx *c) {
   return {reinterpret_cast<int64_t>(c->A.x), reinterpret_cast<int64_t>(c->B.x), reinterpret_cast<int64_t>(c->A32.x),
           reinterpret_cast<int64_t>(c->B32.x), reinterpret_cast<int64_t>(c->S.Sret), reinterpret_cast<int64_t>(c->S.tghost),
           reinterpret_cast<int64_t>(c->T.x), reinterpret_cast<int64_t>(c->T32.x), c->cap, c->cover, c->cover_new,
-          c->transport_block, c->shakhov_lanes, c->P.max_cross, c->xw_exp, c->xm_exp, c->xr_exp};
+          c->transport_block, c->shakhov_lanes, c->P.max_cross, c->xw_exp, c->xm_exp, c->xr_exp,
+          c->scatter_block, c->tally_block, c->flux_block};
 }
 
 // Captures two steps into a graph (the double-buffer swaps of two steps
@@ -2085,10 +2088,13 @@ int ugkwp_get_tally(ugkwp_ctx *c, double *Sminus, double *Splus) {
   return UGKWP_OK;
 }
 
+static bool block_ok(int32_t b) { return b == 64 || b == 128 || b == 256; }
+
 int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
   if (!c || !t) return UGKWP_EINVAL;
   if (t->batch_steps < 1 || t->batch_steps > 1024 || (t->use_graph != 0 && t->use_graph != 1) ||
-      (t->transport_block != 64 && t->transport_block != 128 && t->transport_block != 256) ||
+      !block_ok(t->transport_block) || !block_ok(t->scatter_block) || !block_ok(t->tally_block) ||
+      !block_ok(t->flux_block) ||
       (t->shakhov_lanes != 1 && t->shakhov_lanes != 2 && t->shakhov_lanes != 4 && t->shakhov_lanes != 8 &&
        t->shakhov_lanes != 16) ||
       t->max_crossings < 1 || t->max_crossings > 10000)
@@ -2099,6 +2105,9 @@ int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
   c->shakhov_lanes = t->shakhov_lanes;
   c->max_crossings = t->max_crossings;
   c->P.max_cross = t->max_crossings;
+  c->scatter_block = t->scatter_block;
+  c->tally_block = t->tally_block;
+  c->flux_block = t->flux_block;
   return UGKWP_OK;
 }
 
@@ -2109,6 +2118,9 @@ int ugkwp_get_tuning(ugkwp_ctx *c, ugkwp_tuning *t) {
   t->transport_block = c->transport_block;
   t->shakhov_lanes = c->shakhov_lanes;
   t->max_crossings = c->max_crossings;
+  t->scatter_block = c->scatter_block;
+  t->tally_block = c->tally_block;
+  t->flux_block = c->flux_block;
   return UGKWP_OK;
 }
 

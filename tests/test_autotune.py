@@ -7,7 +7,8 @@ from paper_2607_09552_amd import autotune
 
 class _Fake:
     def __init__(self):
-        self.cfg = dict(batch_steps=32, use_graph=1, transport_block=256, shakhov_lanes=4)
+        self.cfg = dict(batch_steps=32, use_graph=1, transport_block=256, shakhov_lanes=4, scatter_block=256,
+                        tally_block=256, flux_block=256)
         self.t = 0.0
         self.n = 0
 
@@ -24,7 +25,8 @@ class _Fake:
     def step(self, k):
         c = self.cfg
         cost = 1.0 + 0.01 * abs(c["batch_steps"] - 16) + 0.05 * (1 - c["use_graph"]) \
-            + 0.02 * (c["transport_block"] != 128) + 0.03 * abs(c["shakhov_lanes"] - 8) / 4
+            + 0.02 * (c["transport_block"] != 128) + 0.03 * abs(c["shakhov_lanes"] - 8) / 4 \
+            + 0.02 * (c["scatter_block"] != 128) + 0.015 * (c["tally_block"] != 64) + 0.01 * (c["flux_block"] != 256)
         self.t += k * cost * (1.0 + 1e-4 * self.n / 1000.0)  # the flow slowly gets more expensive
         self.n += k * 1000
 
@@ -32,7 +34,8 @@ class _Fake:
 def test_sweep_finds_the_cheapest_settings_despite_drift():
     f = _Fake()
     best, table = autotune.sweep(f, rounds=5, steps=16, log=lambda m: None, clock=lambda: f.t, sync=lambda: None)
-    assert best == dict(batch_steps=16, use_graph=1, transport_block=128, shakhov_lanes=8)
+    assert best == dict(batch_steps=16, use_graph=1, transport_block=128, shakhov_lanes=8, scatter_block=128,
+                        tally_block=64, flux_block=256)
     assert f.cfg == best
     assert len(table) >= 4
 

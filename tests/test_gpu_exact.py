@@ -66,14 +66,15 @@ def _cylinder(**kw):
 def test_same_seed_runs_are_bit_identical(precision):
     """Two independent runs of the 40 x 30 Ma 15 cylinder (Shakhov, Pr 2/3:
     raw-moment tallies too) over 200 steps, one with graph replays and one
-    with eager launches and another transport block: every field, particle,
+    with eager launches and other block shapes: every field, particle,
     tally, face flux, wall quantity and residual identical (FP64 and the
     mixed-precision store)."""
     w = _cylinder()
     a = _solver(w, precision=precision)
     b = _solver(w, precision=precision)
     a.set_tuning(use_graph=1, batch_steps=16)
-    b.set_tuning(use_graph=0, batch_steps=7, transport_block=128, shakhov_lanes=8)
+    b.set_tuning(use_graph=0, batch_steps=7, transport_block=128, shakhov_lanes=8, scatter_block=64,
+                 tally_block=128, flux_block=64)
     for n in (1, 50, 200):
         a.step(n - a.residual()[2])
         b.step(n - b.residual()[2])
