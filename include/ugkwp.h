@@ -277,11 +277,12 @@ int ugkwp_get_shakhov_fallbacks(ugkwp_ctx *ctx, int64_t *n_capped);
  * particle that evaluate its first Shakhov acceptance-rejection attempts
  * together (1, 2, 4, 8 or 16); max_crossings: face crossings a particle
  * may make in one step before the step fails as a runaway track (ENUMERIC,
- * not committed; 1..10000); scatter_block, tally_block, flux_block: threads
- * per block of the re-sort's scatter (its slot claims are per block), of
- * the per-cell tally (one wavefront per cell) and of the face fluxes (one
- * thread per face), each 64, 128 or 256.  ugkwp_get_tuning returns the
- * current values (defaults at init: 32, 1, 256, 4, 10000, 256, 256, 256);
+ * not committed; 1..10000); scatter_block: threads per block of the
+ * re-sort's scatter (its slot claims are per block; 64, 128, 256 or 512);
+ * tally_block, flux_block: threads per block of the per-cell tally (one
+ * wavefront per cell) and of the face fluxes (one thread per face), each
+ * 64, 128 or 256.  ugkwp_get_tuning returns the current values (defaults at
+ * init: 32, 1, 256, 4, 10000, 512, 256, 256);
  * ugkwp_set_tuning sets all eight (EINVAL if one is out of range).  None of
  * them changes a result. */
 typedef struct {

@@ -29,7 +29,7 @@ SPACE = {
     "use_graph": [0, 1],
     "transport_block": [64, 128, 256],
     "shakhov_lanes": [1, 2, 4, 8, 16],
-    "scatter_block": [64, 128, 256],
+    "scatter_block": [128, 256, 512],
     "tally_block": [64, 128, 256],
     "flux_block": [64, 128, 256],
 }

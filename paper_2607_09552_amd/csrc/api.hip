@@ -115,7 +115,7 @@ struct ugkwp_ctx {
   bool prof = false, prof_all = false;
   // tuning
   int32_t batch_steps = 32, use_graph = 1, transport_block = 256, shakhov_lanes = 4, max_crossings = 10000;
-  int32_t scatter_block = 256, tally_block = 256, flux_block = 256;
+  int32_t scatter_block = 512, tally_block = 256, flux_block = 256;
   // ugkwp_step_noalloc: this device's scratch array, and set while such a
   // call runs (no growth, no graph capture, no timing events)
   unsigned char *noalloc_scratch = nullptr;
@@ -2093,7 +2093,8 @@ static bool block_ok(int32_t b) { return b == 64 || b == 128 || b == 256; }
 int ugkwp_set_tuning(ugkwp_ctx *c, const ugkwp_tuning *t) {
   if (!c || !t) return UGKWP_EINVAL;
   if (t->batch_steps < 1 || t->batch_steps > 1024 || (t->use_graph != 0 && t->use_graph != 1) ||
-      !block_ok(t->transport_block) || !block_ok(t->scatter_block) || !block_ok(t->tally_block) ||
+      !block_ok(t->transport_block) || !(block_ok(t->scatter_block) || t->scatter_block == 512) ||
+      !block_ok(t->tally_block) ||
       !block_ok(t->flux_block) ||
       (t->shakhov_lanes != 1 && t->shakhov_lanes != 2 && t->shakhov_lanes != 4 && t->shakhov_lanes != 8 &&
        t->shakhov_lanes != 16) ||

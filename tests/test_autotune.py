@@ -7,7 +7,7 @@ from paper_2607_09552_amd import autotune
 
 class _Fake:
     def __init__(self):
-        self.cfg = dict(batch_steps=32, use_graph=1, transport_block=256, shakhov_lanes=4, scatter_block=256,
+        self.cfg = dict(batch_steps=32, use_graph=1, transport_block=256, shakhov_lanes=4, scatter_block=512,
                         tally_block=256, flux_block=256)
         self.t = 0.0
         self.n = 0

@@ -54,9 +54,9 @@ def test_argument_checks_leave_the_context_usable():
     assert L.ugkwp_set_tuning(h, C.byref(t)) == EINVAL
     assert "out of range" in _msg(L, h)
     good = dict(batch_steps=8, use_graph=0, transport_block=256, shakhov_lanes=4, max_crossings=100,
-                scatter_block=256, tally_block=256, flux_block=256)
+                scatter_block=512, tally_block=256, flux_block=256)
     for knob in ("scatter_block", "tally_block", "flux_block"):
-        for bad in (0, 32, 96, 512):
+        for bad in (0, 32, 96, 1024) + ((512,) if knob != "scatter_block" else ()):
             t = _Tuning(**dict(good, **{knob: bad}))
             assert L.ugkwp_set_tuning(h, C.byref(t)) == EINVAL, (knob, bad)
     # none of it changed anything: both contexts give the same steps
