@@ -40,6 +40,24 @@ def test_sweep_finds_the_cheapest_settings_despite_drift():
     assert len(table) >= 4
 
 
+class _FakeFlat(_Fake):
+    """Only two settings matter: a transport block of 128 saves 2 %, a tally
+    block of 64 saves 0.1 % (less than the sweep's noise threshold)."""
+
+    def step(self, k):
+        c = self.cfg
+        cost = 1.0 - 0.02 * (c["transport_block"] == 128) - 0.001 * (c["tally_block"] == 64)
+        self.t += k * cost
+        self.n += k * 1000
+
+
+def test_sweep_keeps_the_current_value_within_the_noise():
+    f = _FakeFlat()
+    best, _ = autotune.sweep(f, rounds=5, steps=16, log=lambda m: None, clock=lambda: f.t, sync=lambda: None)
+    assert best["transport_block"] == 128
+    assert best["tally_block"] == 256 and best == dict(f.tuning())
+
+
 def test_load_tuning_missing_file(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "TUNING_FILE", str(tmp_path / "none.json"))
     assert autotune.load_tuning("cylinder") is None
