@@ -63,6 +63,9 @@ struct ugkwp_ctx {
   int lts = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // side stream of the face fluxes (they overlap the re-sort) and its fork / join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   // host copies needed by getters
   std::vector<double> h_face_mid;  // [nf*2]
@@ -673,6 +676,11 @@ void launch_tally(ugkwp_ctx *c, const Geo &g, const StoreT<R> &s, const int64_t 
                        c->S.flags, c->S.halt);
 }
 
+template <int DIM>
+void launch_face_flux(ugkwp_ctx *c, const Geo &g, const State &S, hipStream_t st) {
+  hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, c->flux_block)), dim3(c->flux_block), 0, st, g, c->P, S);
+}
+
 template <int DIM, class R>
 int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const StoreT<R> &T) {
   const int NW = DIM + 2;
@@ -747,6 +755,17 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
       }
     }
   }
+  // The face fluxes need only the cell states of the step's start: they run
+  // on the side stream beside the re-sort, which leaves most of the device's
+  // registers free (with per-kernel timing on, in order on the library
+  // stream instead).
+  const bool side = !c->prof;
+  if (side) {
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    launch_face_flux<DIM>(c, g, S, c->side);
+    HIPCHK(hipEventRecord(c->ev_join, c->side));
+  }
   // kept particles per cell in count[0, nc), collided ones in count[nc, 2 nc)
   // the scan also sets the scatter's cursors to the offsets
   rc = scan(c, S.count, 2 * nc, S.coff, S.cursor);
@@ -760,10 +779,11 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
     ProfScope ps(c, kKCellTally, rd * c->est_kept + (16.0 + 8.0 * NW * 6) * nc);
     launch_tally<DIM, R>(c, g, B, S.coff, S.Sretn, S.Xretn, S.Sp, S.Mrawn);
   }
-  {
+  if (side) {
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  } else {
     ProfScope ps(c, kKFaceFlux, 408.0 * c->nf);
-    hipLaunchKernelGGL(k_face_flux<DIM>, dim3(nblk(c->nf, c->flux_block)), dim3(c->flux_block), 0, c->stream, g,
-                       c->P, S);
+    launch_face_flux<DIM>(c, g, S, c->stream);
   }
   {
     ProfScope ps(c, kKUpdate, 350.0 * nc);
@@ -919,6 +939,9 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->own_stream = true;
   }
+  HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   for (int64_t b = 0; b < mesh->n_bfaces; ++b)
     if ((mesh->bface_type[b] < 1 || mesh->bface_type[b] > 4) && mesh->bface_type[b] != UGKWP_BC_WALL_MAXWELL)
       return set_err(c, UGKWP_EINVAL, "boundary face %lld has unknown type", (long long)b);
@@ -2213,6 +2236,10 @@ void ugkwp_free(ugkwp_ctx *c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
