@@ -70,31 +70,84 @@ __device__ __forceinline__ f32x16 tile_mma(const uint16_t *__restrict__ A, int64
   return acc;
 }
 
+// NB adjacent 32 x 32 tiles of C in one row band: one A fragment per k step
+// serves NB matrix-core operations (register blocking); the k loop is
+// unrolled so that later steps' loads are in flight during the current
+// step's operations.  Each tile's operations run in the same k order as in
+// tile_mma, so the results are the same bit for bit.
+template <int NB, int KC>
+__device__ __forceinline__ void tile_mma_nb(const uint16_t *__restrict__ A, int64_t lda,
+                                            const uint16_t *__restrict__ B, int64_t ldb, int64_t row0, int64_t col0,
+                                            int64_t Kr, f32x16 (&acc)[NB]) {
+  // KC > 0: K known at compile time, the loop unrolled completely (all
+  // operand loads can be issued ahead of the matrix-core operations)
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const uint16_t *pa = A + (row0 + r) * lda + 8 * h;
+  const uint16_t *pb = B + (col0 + r) * ldb + 8 * h;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = f32x16{};
+  auto step = [&](int64_t k) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(pa + k);
+    bf16x8 b[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(pb + 32 * j * ldb + k);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[j], acc[j], 0, 0, 0);
+  };
+  if constexpr (KC > 0) {
+    // every operand fragment first, then the operations
+    bf16x8 a[KC / 16], b[KC / 16][NB];
+#pragma unroll
+    for (int q = 0; q < KC / 16; ++q) {
+      a[q] = *reinterpret_cast<const bf16x8 *>(pa + 16 * q);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) b[q][j] = *reinterpret_cast<const bf16x8 *>(pb + 32 * j * ldb + 16 * q);
+    }
+    // keep the scheduler from sinking the loads back between the operations
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < KC / 16; ++q) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q], b[q][j], acc[j], 0, 0, 0);
+    }
+  } else {
+#pragma unroll 4
+    for (int64_t k = 0; k < Kr; k += 16) step(k);
+  }
+}
+
 // Layer: Z = A B^T + bias; with act, Y = GELU(Z) else Y = Z.  Writes Z (FP32,
 // optional), Y as FP32 (optional), as BF16 (optional) and as transposed BF16
-// [N x M] (optional).  Grid: (M / 32) x (N / 32) wavefronts, 4 per block.
-__global__ void __launch_bounds__(256) k_layer(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+// [N x M] (optional).  Grid: (M / 32) x (N / (32 NB)) wavefronts, 4 per
+// block; a wavefront takes NB adjacent column tiles.
+template <int NB, int KC>
+__global__ void __launch_bounds__(256, 2) k_layer(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                const float *__restrict__ bias, int64_t M, int64_t N, int64_t K,
                                                int act, float *__restrict__ Z, float *__restrict__ Y32,
                                                uint16_t *__restrict__ Y16, uint16_t *__restrict__ YT16) {
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-  const int64_t tiles_n = N / 32;
+  const int64_t tiles_n = N / (32 * NB);
   if (wave >= (M / 32) * tiles_n) return;
-  const int64_t row0 = (wave / tiles_n) * 32, col0 = (wave % tiles_n) * 32;
-  const f32x16 acc = tile_mma(A, K, B, K, row0, col0, 0, K);
+  const int64_t row0 = (wave / tiles_n) * 32, col00 = (wave % tiles_n) * 32 * NB;
+  f32x16 acc[NB];
+  tile_mma_nb<NB, KC>(A, K, B, K, row0, col00, K, acc);
   const int lane = threadIdx.x & 63;
-  const int64_t col = col0 + (lane & 31);
-  const float bc = bias ? bias[col] : 0.0f;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int64_t row = row0 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
-    const float z = acc[i] + bc;
-    const float y = act ? gelu(z) : z;
-    if (Z) Z[row * N + col] = z;
-    if (Y32) Y32[row * N + col] = y;
-    const uint16_t yb = f2bf(y);
-    if (Y16) Y16[row * N + col] = yb;
-    if (YT16) YT16[col * M + row] = yb;
+  for (int j = 0; j < NB; ++j) {
+    const int64_t col = col00 + 32 * j + (lane & 31);
+    const float bc = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t row = row0 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
+      const float z = acc[j][i] + bc;
+      const float y = act ? gelu(z) : z;
+      if (Z) Z[row * N + col] = z;
+      if (Y32) Y32[row * N + col] = y;
+      const uint16_t yb = f2bf(y);
+      if (Y16) Y16[row * N + col] = yb;
+      if (YT16) YT16[col * M + row] = yb;
+    }
   }
 }
 
@@ -495,9 +548,23 @@ extern "C" {
 int ugkwp_mlp_layer(const uint16_t *A, const uint16_t *B, const float *bias, int64_t M, int64_t N, int64_t K,
                     int32_t act, float *Z, float *Y32, uint16_t *Y16, uint16_t *YT16, void *stream) {
   if (!A || !B || M <= 0 || N <= 0 || K <= 0 || M % 32 || N % 32 || K % 16) return -1;
-  const int64_t waves = (M / 32) * (N / 32);
-  hipLaunchKernelGGL(k_layer, dim3(static_cast<unsigned>(blocks_for_waves(waves))), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), A, B, bias, M, N, K, act, Z, Y32, Y16, YT16);
+  // two column tiles per wavefront where N allows it; the network's inner
+  // sizes (K = 32, 256) with the k loop unrolled completely
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = N % 64 == 0 ? 2 : 1;
+  const unsigned blocks = static_cast<unsigned>(blocks_for_waves((M / 32) * (N / (32 * nb))));
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, A, B, bias, M, N, K, act, Z, Y32, Y16, YT16);
+  };
+  if (nb == 2) {
+    if (K == 256) go(k_layer<2, 256>);
+    else if (K == 32) go(k_layer<2, 32>);
+    else go(k_layer<2, 0>);
+  } else {
+    if (K == 256) go(k_layer<1, 256>);
+    else if (K == 32) go(k_layer<1, 32>);
+    else go(k_layer<1, 0>);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
