@@ -22,7 +22,12 @@
  *   - Ownership: every input array is copied at init; the caller keeps it.
  *     Outputs go to caller buffers (host unless the name says device).
  *   - All GPU work is ordered on the stream given at init (NULL = the
- *     library's own stream).  Getters synchronize that stream.
+ *     library's own stream).  Within a step, the face fluxes run on a side
+ *     stream that the context creates (default priority); it waits on an
+ *     event of the given stream and the given stream waits on it before
+ *     the update, so work enqueued later on the given stream, its
+ *     synchronization and graph capture of it include the side work.
+ *     Getters synchronize the given stream.
  *   - A context is not thread-safe; separate contexts are independent.
  *   - Every call returns UGKWP_OK or a negative error code;
  *     ugkwp_last_error() gives a text.  A step that fails (ENUMERIC,
