@@ -103,6 +103,7 @@ struct ugkwp_ctx {
   int64_t *case_cell = nullptr, *case_bface = nullptr, *case_wall = nullptr;
   std::vector<int64_t> h_case_wall;                // [ncase + 1] first wall face of each case
   double *Sm_prev = nullptr, *Sp_prev = nullptr;   // W^{p,-}, W^{p,+} (times Omega) of the last committed step
+  double *Fs_prev = nullptr;  // F_j s_j of the last committed step (a step writes S.Fs)
   int xw_exp = 0, xm_exp = 0, xr_exp = 0, xa_exp = 0;  // exact-summation window exponents E
   uint64_t *case_seed = nullptr;
   double *case_par = nullptr;
@@ -619,6 +620,7 @@ void swap_buffers(ugkwp_ctx *c) {
   std::swap(c->S.Xret, c->S.Xretn);
   std::swap(c->S.Sm, c->Sm_prev);
   std::swap(c->S.Sp, c->Sp_prev);
+  std::swap(c->S.Fs, c->Fs_prev);
   std::swap(c->S.roff, c->S.coff);
   std::swap(c->S.Mraw, c->S.Mrawn);
 }
@@ -1013,7 +1015,7 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
       dalloc(c, &S.noff, nc + nb + 1) || dalloc(c, &S.mnew, nc + nb) || dalloc(c, &S.gW, nbw) ||
       dalloc(c, &S.gWh, nbw) || dalloc(c, &S.gtau, nb1) || dalloc(c, &S.gdepth, nb1) ||
       dalloc(c, &S.ghvalid, nb1) || dalloc(c, &S.nghost, 1) || dalloc(c, &S.count, 2 * nc) ||
-      dalloc(c, &S.coff, 2 * nc + 1) || dalloc(c, &S.Fs, c->nf * nw) || dalloc(c, &S.rho_prev, nc) ||
+      dalloc(c, &S.coff, 2 * nc + 1) || dalloc(c, &S.Fs, c->nf * nw) || dalloc(c, &c->Fs_prev, c->nf * nw) || dalloc(c, &S.rho_prev, nc) ||
       dalloc(c, &S.rho_sum, nc) || dalloc(c, &S.rho_mean_prev, nc) || dalloc(c, &S.resid, 8 * ncase) ||
       dalloc(c, &S.area, ncase) || dalloc(c, &S.wimp, nb1 * 3 * kTallyLimbs) || dalloc(c, &S.wlast, nwl1 * 3) ||
       dalloc(c, &S.wsum, nwl1 * 3) || dalloc(c, &S.wema, nwl1 * 3) || dalloc(c, &S.fd, nwl1) ||
@@ -1027,6 +1029,8 @@ int init_impl(ugkwp_ctx *c, const ugkwp_mesh *mesh, const ugkwp_params *par, con
   HIPCHK(hipMemsetAsync(S.Sp, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(c->Sm_prev, 0, ncw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(c->Sp_prev, 0, ncw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(S.Fs, 0, c->nf * nw * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(c->Fs_prev, 0, c->nf * nw * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(S.roff, 0, (2 * nc + 1) * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.coff, 0, (2 * nc + 1) * sizeof(int64_t), c->stream));
   HIPCHK(hipMemsetAsync(S.ar, 0, nc * kArN * sizeof(double), c->stream));
@@ -1830,7 +1834,7 @@ int ugkwp_get_face_flux(ugkwp_ctx *c, double *Fs, int64_t cap, int64_t *n_faces)
   if (n_faces) *n_faces = c->nf;
   if (!Fs) return UGKWP_OK;
   if (cap < c->nf) return set_err(c, UGKWP_EOVERFLOW, "face buffer too small");
-  HIPCHK(hipMemcpyAsync(Fs, c->S.Fs, c->nf * c->nw * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(Fs, c->Fs_prev, c->nf * c->nw * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return UGKWP_OK;
 }
