@@ -1253,15 +1253,17 @@ __global__ void __launch_bounds__(512) k_scatter(State st, StoreT<R> a, StoreT<R
   const int64_t d = static_cast<int64_t>(sbase[slot]) + off + popc_below(grp);
   const StoreT<R> &uv = (code & kCodeReflected) ? tw : a;
   const StoreT<R> &um = (code & kCodeMoved) ? tw : a;
-  b.ux[d] = uv.ux[k];
-  b.uy[d] = uv.uy[k];
-  b.uz[d] = uv.uz[k];
-  if (a.ei) b.ei[d] = uv.ei[k];
-  b.m[d] = um.m[k];
+  // the sources are read once: non-temporal loads (the scatter 302 -> 283 us
+  // on the 200x150 cylinder; the tally that follows lost 10 of them)
+  b.ux[d] = __builtin_nontemporal_load(&uv.ux[k]);
+  b.uy[d] = __builtin_nontemporal_load(&uv.uy[k]);
+  b.uz[d] = __builtin_nontemporal_load(&uv.uz[k]);
+  if (a.ei) b.ei[d] = __builtin_nontemporal_load(&uv.ei[k]);
+  b.m[d] = __builtin_nontemporal_load(&um.m[k]);
   if (col) return;
-  b.x[d] = tw.x[k];
-  if (DIM == 2) b.y[d] = tw.y[k];
-  b.pid[d] = a.pid[k];
+  b.x[d] = __builtin_nontemporal_load(&tw.x[k]);
+  if (DIM == 2) b.y[d] = __builtin_nontemporal_load(&tw.y[k]);
+  b.pid[d] = __builtin_nontemporal_load(&a.pid[k]);
   b.cell[d] = cell;
 }
 
