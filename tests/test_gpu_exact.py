@@ -81,6 +81,22 @@ def test_same_seed_runs_are_bit_identical(precision):
         _assert_identical(_state(a), _state(b), f"step {n}")
 
 
+def test_side_stream_matches_the_serial_order():
+    """The face fluxes on the side stream beside the re-sort (graph replays)
+    and in order on the library stream (per-kernel timing on, eager
+    launches): identical states after 60 steps."""
+    w = _cylinder()
+    a = _solver(w)
+    b = _solver(w)
+    a.set_tuning(use_graph=1, batch_steps=16)
+    b.profile(True)
+    for n in (1, 60):
+        a.step(n - a.residual()[2])
+        b.step(n - b.residual()[2])
+        _assert_identical(_state(a), _state(b), f"step {n}")
+    b.profile(False)
+
+
 def test_batch_is_reproducible():
     """The same for a batch of uneven cases (per-case residual and drag sums)."""
     from paper_2607_09552_amd import Solver
