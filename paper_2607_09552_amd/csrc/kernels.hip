@@ -1650,7 +1650,39 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
   if (threadIdx.x == 0) all_below = 1;
   if (threadIdx.x < kStatN) stat_sum[threadIdx.x] = 0;
   __syncthreads();
-  for (int cs = threadIdx.x; cs < g.ncase; cs += blockDim.x) {
+  // The drag of a case sums its wall faces' terms in wall order.  For each
+  // group of blockDim.x cases the block stages the group's terms in LDS,
+  // a chunk at a time with every load in flight together, and each case's
+  // thread adds its range in order from LDS (the same additions in the same
+  // order as one thread walking the array).
+  constexpr int kChunk = 2048;
+  __shared__ double sfd[kChunk];
+  for (int cs0 = 0; cs0 < g.ncase; cs0 += static_cast<int>(blockDim.x)) {
+    const int cs = cs0 + static_cast<int>(threadIdx.x);
+    const bool has = cs < g.ncase;
+    const int cl = (cs0 + static_cast<int>(blockDim.x) < g.ncase ? cs0 + static_cast<int>(blockDim.x) : g.ncase);
+    const int64_t gw0 = g.case_wall ? g.case_wall[cs0] : 0, gw1 = g.case_wall ? g.case_wall[cl] : g.nwall;
+    const int64_t w0 = has && g.case_wall ? g.case_wall[cs] : 0;
+    const int64_t w1 = has ? (g.case_wall ? g.case_wall[cs + 1] : g.nwall) : 0;
+    double fsum = 0.0;
+    for (int64_t c0 = gw0; c0 < gw1; c0 += kChunk) {
+      const int64_t c1 = c0 + kChunk < gw1 ? c0 + kChunk : gw1;
+      for (int64_t w = c0 + threadIdx.x; w < c1; w += blockDim.x) sfd[w - c0] = st.fd[w];
+      __syncthreads();
+      const int64_t a0 = w0 > c0 ? w0 : c0, a1 = w1 < c1 ? w1 : c1;
+      // 32 values read ahead of their in-order additions
+      int64_t w = a0;
+      for (; w + 32 <= a1; w += 32) {
+        double v[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = sfd[w - c0 + j];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) fsum += v[j];
+      }
+      for (; w < a1; ++w) fsum += sfd[w - c0];
+      __syncthreads();
+    }
+    if (!has) continue;
     double *sc = st.scal + cs * kScalN;
     const double rho_inf = case_val(g, cs, kCaseRho, p.rho_inf);
     const double U = case_val(g, cs, kCaseU, p.U_inf), L = case_val(g, cs, kCaseL, p.L_ref);
@@ -1658,19 +1690,6 @@ __global__ void k_finish(Geo g, Params p, State st, int64_t nc) {
     const double area = st.area[cs];
     sc[kScalRinst] = sqrt(xs_round<4>(rs, p.xr) / area) / rho_inf;
     sc[kScalRavg] = sqrt(xs_round<4>(rs + 4, p.xr) / area) / rho_inf;
-    // the drag sums the wall faces in order; 32 loads are issued
-    // together before their sequential additions
-    double fsum = 0.0;
-    const int64_t w0 = g.case_wall ? g.case_wall[cs] : 0, w1 = g.case_wall ? g.case_wall[cs + 1] : g.nwall;
-    int64_t w = w0;
-    for (; w + 32 <= w1; w += 32) {
-      double v[32];
-#pragma unroll
-      for (int j = 0; j < 32; ++j) v[j] = st.fd[w + j];
-#pragma unroll
-      for (int j = 0; j < 32; ++j) fsum += v[j];
-    }
-    for (; w < w1; ++w) fsum += st.fd[w];
     const double cd = fsum / (0.5 * rho_inf * U * U * L);
     constexpr double a = 2.0 / 1001.0;
     sc[kScalCdLast] = cd;
