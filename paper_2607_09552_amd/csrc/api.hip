@@ -788,12 +788,11 @@ int enqueue_step(ugkwp_ctx *c, const StoreT<R> &A, const StoreT<R> &B, const Sto
     launch_face_flux<DIM>(c, g, S, c->stream);
   }
   {
-    ProfScope ps(c, kKUpdate, 350.0 * nc);
-    hipLaunchKernelGGL(k_update<DIM>, dim3(nblk(nc, 256)), dim3(256), 0, c->stream, g, c->P, S);
-  }
-  if (c->nwall > 0) {
-    ProfScope ps(c, kKSurface, 150.0 * c->nwall);
-    hipLaunchKernelGGL(k_surface<DIM>, dim3(nblk(c->nwall, 256)), dim3(256), 0, c->stream, g, c->P, S);
+    // the cells' update, and the wall quantities in workgroups after them
+    ProfScope ps(c, kKUpdate, 350.0 * nc + 150.0 * c->nwall);
+    const int64_t ub = nblk(nc, 256);
+    hipLaunchKernelGGL(k_update<DIM>, dim3(static_cast<unsigned>(ub + nblk(c->nwall, 256))), dim3(256), 0, c->stream,
+                       g, c->P, S, ub);
   }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(std::max(256, std::min(1024, (c->ncase + 63) / 64 * 64))), 0,
                      c->stream, g, c->P, S, nc);

@@ -182,8 +182,7 @@ __global__ void k_cell_tally(Geo, Params, StoreT<R>, const int64_t *, double *, 
                              int *);
 __global__ void k_case_area(Geo, double *, XWin);
 template <int DIM> __global__ void k_face_flux(Geo, Params, State);
-template <int DIM> __global__ void k_update(Geo, Params, State);
-template <int DIM> __global__ void k_surface(Geo, Params, State);
+template <int DIM> __global__ void k_update(Geo, Params, State, int64_t);
 __global__ void k_finish(Geo, Params, State, int64_t);
 __global__ void k_check(Geo, State, int64_t, int64_t, int64_t);
 // Up to kZeroMax buffers cleared by one launch (32-bit words each).

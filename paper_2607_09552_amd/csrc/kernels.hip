@@ -1503,10 +1503,19 @@ __global__ void __launch_bounds__(256, 3) k_face_flux(Geo g, Params p, State st)
 // particles that ended in the cell, or a vacuum floor state.
 // Also the residual sums (exact chunks, per case) and the running mean of
 // the density.
+// Workgroups from `ublocks` on compute the wall quantities (surface_one)
+// instead: one launch for both.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
+__device__ __forceinline__ void surface_one(const Geo &g, const Params &p, const State &st, int64_t w);
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st, int64_t ublocks) {
   constexpr int NW = DIM + 2;
   if (*st.halt) return;
+  if (blockIdx.x >= ublocks) {  // whole workgroups
+    surface_one<DIM>(g, p, st, (blockIdx.x - ublocks) * static_cast<int64_t>(blockDim.x) + threadIdx.x);
+    return;
+  }
   const int64_t step = *st.dstep;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   double r[2] = {0.0, 0.0};
@@ -1595,12 +1604,13 @@ __global__ void __launch_bounds__(256) k_update(Geo g, Params p, State st) {
 
 // a10: wall pressure, shear and heat flux (wave + particle impulses per unit
 // area and time), their running sum and EMA (2/1001), and the drag force of
-// each wall face (summed per case in a fixed order by k_finish).
+// each wall face w (summed per case in a fixed order by k_finish).  Run by
+// extra workgroups of k_update (it needs only the face fluxes, the wall
+// impulses and dt).
 template <int DIM>
-__global__ void k_surface(Geo g, Params p, State st) {
+__device__ __forceinline__ void surface_one(const Geo &g, const Params &p, const State &st, int64_t w) {
   constexpr int NW = DIM + 2;
-  const int64_t w = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (w >= g.nwall || *st.halt) return;
+  if (w >= g.nwall) return;
   const int64_t step = *st.dstep;
   const int b = g.wall_b[w];
   const int i = g.bcell[b];
@@ -1800,8 +1810,7 @@ __global__ void __launch_bounds__(256) k_stream_copy(uint4 *__restrict__ dst, co
   template __global__ void k_cell_prep<D>(Geo, Params, State);                                           \
   template __global__ void k_ghost_prep<D>(Geo, Params, State);                                          \
   template __global__ void k_face_flux<D>(Geo, Params, State);                                           \
-  template __global__ void k_update<D>(Geo, Params, State);                                              \
-  template __global__ void k_surface<D>(Geo, Params, State);
+  template __global__ void k_update<D>(Geo, Params, State, int64_t);
 UGK_INST(1)
 UGK_INST(2)
 #define UGK_INST_P(D, R)                                                                                  \
