@@ -55,3 +55,38 @@ def test_library_exports_no_other_c_symbols():
     syms = {ln.split()[-1] for ln in out.splitlines() if ln.split() and ln.split()[1] in "TW"}
     c_syms = {x for x in syms if not x.startswith("_")}
     assert c_syms == set(declared_functions()), sorted(c_syms ^ set(declared_functions()))
+
+
+def _struct_fields(header, name):
+    """Field names, in order, of `typedef struct { ... } name;` in a header."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", header)).read(), flags=re.S)
+    end = re.search(r"\}\s*" + name + r"\s*;", src).start()
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:  # "int32_t a, b, c" -> a, b, c
+            names = decl.split(None, 1)[1]
+            fields += [f.strip() for f in names.split(",")]
+    return fields
+
+
+def test_tuning_struct_matches_the_binding():
+    """The ctypes layout of ugkwp_tuning follows the header field for field
+    (all int32_t), so a field added on one side only is caught here."""
+    import paper_2607_09552_amd as pkg
+    fields = _struct_fields("ugkwp.h", "ugkwp_tuning")
+    assert fields == [n for n, _ in pkg._Tuning._fields_]
+    assert all(t is ctypes.c_int32 for _, t in pkg._Tuning._fields_)
+
+
+def test_recorded_tuning_uses_known_fields():
+    """Every setting in the recorded tuning table is a field of ugkwp_tuning."""
+    import json
+    import paper_2607_09552_amd as pkg
+    from paper_2607_09552_amd import autotune
+    known = {n for n, _ in pkg._Tuning._fields_}
+    data = json.load(open(autotune.TUNING_FILE))
+    for name, rec in data.items():
+        assert set(rec["best"]) <= known, (name, set(rec["best"]) - known)
+    assert set(autotune.SPACE) <= known
