@@ -58,26 +58,33 @@ def test_library_exports_no_other_c_symbols():
 
 
 def _struct_fields(header, name):
-    """Field names, in order, of `typedef struct { ... } name;` in a header."""
+    """(field, ctypes type) pairs, in order, of `typedef struct { ... } name;`
+    in a header (pointers as c_void_p)."""
     src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", header)).read(), flags=re.S)
     end = re.search(r"\}\s*" + name + r"\s*;", src).start()
     body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64,
+             "double": ctypes.c_double}
     fields = []
     for decl in body.split(";"):
-        decl = decl.strip()
-        if decl:  # "int32_t a, b, c" -> a, b, c
-            names = decl.split(None, 1)[1]
-            fields += [f.strip() for f in names.split(",")]
+        m = re.match(r"\s*(?:const\s+)?(\w+)\s+(.*\S)", decl, flags=re.S)
+        if not m:
+            continue
+        for d in m.group(2).split(","):
+            d = d.strip()
+            fields.append((d.lstrip("*").strip(), ctypes.c_void_p if d.startswith("*") else ctype[m.group(1)]))
     return fields
 
 
-def test_tuning_struct_matches_the_binding():
-    """The ctypes layout of ugkwp_tuning follows the header field for field
-    (all int32_t), so a field added on one side only is caught here."""
+@pytest.mark.parametrize("header, struct, cls", [("ugkwp.h", "ugkwp_tuning", "_Tuning"),
+                                                 ("ugkwp.h", "ugkwp_params", "_Params"),
+                                                 ("ugkwp.h", "ugkwp_mesh", "_Mesh"),
+                                                 ("ugkwp_mlp.h", "ugkwp_ws_case", "WsCase")])
+def test_structs_match_the_binding(header, struct, cls):
+    """The binding's ctypes layouts follow the headers field for field and
+    type for type, so a field added or retyped on one side only is caught."""
     import paper_2607_09552_amd as pkg
-    fields = _struct_fields("ugkwp.h", "ugkwp_tuning")
-    assert fields == [n for n, _ in pkg._Tuning._fields_]
-    assert all(t is ctypes.c_int32 for _, t in pkg._Tuning._fields_)
+    assert _struct_fields(header, struct) == list(getattr(pkg, cls)._fields_)
 
 
 def test_recorded_tuning_uses_known_fields():
