@@ -11,9 +11,9 @@
  * the whole step by an independent literal GTS step (equal time steps), the
  * collisionless limit by free-molecular wall fluxes on a plate, the Shakhov
  * acceptance-rejection, the diffuse wall's re-emission and the far-field
- * ghost slab statistically by the distributions and fluxes they must give.
- * Parity unpinned: the upwind reading of g0^h in Eq. (50), checked only
- * through those pins and against the GPU path.
+ * ghost slab statistically by the distributions and fluxes they must give,
+ * the upwind g0^h of Eq. (50) by the collisionless transport of the
+ * piecewise initial reconstruction, integrated by quadrature in t and u.
  */
 #include "ugkwp_oracle.h"
 

@@ -7,7 +7,9 @@
   paper's epsilon_alpha(t), Eq. (13), over [0, dt] (Eq. (16), Eq. (48));
 - half-range moments, microslopes (Eqs. (20), (22)) and the time-averaged
   fluxes (Eqs. (49), (50)) against brute-force velocity-space quadrature;
-- the GTS form, Eqs. (23), (31), as the equal-step special case.
+- the GTS form, Eqs. (23), (31), as the equal-step special case;
+- the upwind g_0^h of Eq. (50) against the collisionless transport of the
+  piecewise initial reconstruction.
 """
 import math
 import os
@@ -18,6 +20,7 @@ import mpmath
 import numpy as np
 import pytest
 from scipy import integrate
+from scipy.special import roots_hermite, roots_legendre
 
 import oracle
 import workloads as wl
@@ -255,6 +258,79 @@ def test_equal_steps_recover_gts_flux():
         Ffg += (dd - dt * E) * Q.moment(Wh, K, half, power=1)
     assert np.allclose(dt * Feq, Fg, rtol=1e-10, atol=1e-12)
     assert np.allclose(dt * Ffr, Ffg, rtol=1e-10, atol=1e-12)
+
+
+def _free_transport_flux(Wh, dWh, dt, tau, K, pick="transport"):
+    """The wave's free-transport flux through a face at x = 0 from its definition.
+
+    The hydrodynamic part of the initial distribution is one function of the
+    normal coordinate x: g_L (1 + a_L x) for x < 0 and g_R (1 + a_R x) for
+    x > 0, g_s the Maxwellian of W^h_s and a_s its microslope (Eq. (20)).
+    Collisionless transport carries it unchanged along u: the face sees
+    f(0, t, u) = g^h_0(-u_n t, u), so the piece is chosen by the sign of the
+    departure point x0 = -u_n t, not by a rule on u.  The wave keeps the part
+    that neither collides nor is sampled as a collisionless particle, weight
+    e^{-t/tau} - e^{-dt/tau} (the coefficients of Eq. (50)), averaged over the
+    step.  Plain Gauss quadrature in t, u_n (split at 0), u_t and xi (K = 1).
+    pick="swapped" and "central" evaluate the two other readings: the piece
+    opposite to the departure point, and the mean of the two pieces."""
+    assert K == 1
+    xt, wt = roots_legendre(24)
+    t = 0.5 * dt * (xt + 1.0)
+    wtt = 0.5 * dt * wt * (np.exp(-t / tau) - math.exp(-dt / tau)) / dt
+    sides = []
+    for W, dW in zip(Wh, dWh):
+        rho, U, V, lam = Q.state(W, K)
+        sides.append((rho, U, V, lam, Q.solve_slope(W, dW, K)))
+    span = max(abs(s[1]) for s in sides) + 16.0 * max(math.sqrt(0.5 / s[3]) for s in sides)
+    xl, wl = roots_legendre(200)
+    un = np.concatenate([0.5 * span * (xl - 1.0), 0.5 * span * (xl + 1.0)])
+    wun = np.concatenate([0.5 * span * wl, 0.5 * span * wl])
+    xh, wh = roots_hermite(24)
+    F = np.zeros(4)
+    for ti, wti in zip(t, wtt):
+        x0 = -un * ti
+        piece = []
+        for rho, U, V, lam, a in sides:
+            UN, UT, XI2 = np.meshgrid(un, V + xh / math.sqrt(lam), (xh / math.sqrt(lam)) ** 2, indexing="ij")
+            w = (wh / math.sqrt(math.pi))[None, :, None] * (wh / math.sqrt(math.pi))[None, None, :]
+            gn = rho * math.sqrt(lam / math.pi) * np.exp(-lam * (un - U) ** 2)
+            f = gn[:, None, None] * (1.0 + Q.poly(a)(UN, UT, XI2) * x0[:, None, None])
+            piece.append(np.sum(UN * Q.psi(UN, UT, XI2) * f * w, axis=(2, 3)))
+        if pick == "transport":
+            h = np.where(x0 < 0.0, piece[0], piece[1])
+        elif pick == "swapped":
+            h = np.where(x0 < 0.0, piece[1], piece[0])
+        else:
+            h = 0.5 * (piece[0] + piece[1])
+        F += wti * np.sum(h * wun, axis=1)
+    return F
+
+
+@pytest.mark.parametrize("case,x", [(0, 0.3), (1, 1.0), (2, 4.0)])
+def test_free_transport_wave_flux_is_upwind(case, x):
+    """Eq. (50)'s g_0^h on the two sides of a face: with equal steps and
+    relaxation times on both sides the wave's free-transport flux must equal
+    the collisionless transport of the piecewise initial reconstruction, which
+    reads the left piece for u_n > 0 and the right one for u_n < 0.  The two
+    other readings (sides swapped, or their mean) miss by orders of magnitude
+    more than the quadrature error."""
+    K = 1
+    rng = np.random.default_rng(300 + case)
+    WL, WR = _rand_state(rng, K), _rand_state(rng, K)
+    WhL = WL * rng.uniform(0.2, 0.9)
+    WhR = WR * rng.uniform(0.2, 0.9)
+    dWhL = rng.normal(size=4) * 0.3 * np.abs(WhL)
+    dWhR = rng.normal(size=4) * 0.3 * np.abs(WhR)
+    tau = 0.05
+    dt = x * tau
+    _, Ffr = oracle.flux_interior(WL, WR, (WR - WL), WhL, WhR, dWhL, dWhR, dt, tau, dt, tau, K, 1.0)
+    ref = _free_transport_flux((WhL, WhR), (dWhL, dWhR), dt, tau, K)
+    s = np.abs(ref).max()
+    assert np.allclose(Ffr, ref, rtol=1e-10, atol=1e-10 * s), (Ffr, ref)
+    for other in ("swapped", "central"):
+        alt = _free_transport_flux((WhL, WhR), (dWhL, dWhR), dt, tau, K, pick=other)
+        assert np.abs(alt - ref).max() > 1e-3 * s, other
 
 
 def test_wall_flux_zero_mass_and_quadrature():
