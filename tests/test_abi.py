@@ -97,3 +97,33 @@ def test_recorded_tuning_uses_known_fields():
     for name, rec in data.items():
         assert set(rec["best"]) <= known, (name, set(rec["best"]) - known)
     assert set(autotune.SPACE) <= known
+
+
+def _enum_values(path, prefix):
+    """NAME -> value of the `PREFIX_NAME = value` enumerators in a header."""
+    src = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b" + prefix + r"_(\w+)\s*=\s*(-?\d+)", src)}
+
+
+def test_codes_match_the_header():
+    """The status and boundary-type codes the binding, the workload builders
+    and the oracle use are the values include/ugkwp.h gives them: a workload
+    built once feeds both the library and the oracle."""
+    import paper_2607_09552_amd as pkg
+    import workloads
+    lib = _enum_values(os.path.join(ROOT, "include", "ugkwp.h"), "UGKWP")
+    ref = _enum_values(os.path.join(ROOT, "oracle", "ugkwp_oracle.h"), "REF")
+    status = ("OK", "EINVAL", "ENOMEM", "EDEVICE", "EOVERFLOW", "ENUMERIC", "ESTATE", "EIO")
+    assert {k: lib[k] for k in status} == {k: getattr(pkg, k) for k in status}
+    assert len(set(lib[k] for k in status)) == len(status)
+    for k in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "ENUMERIC"):
+        assert ref[k] == lib[k], k
+    bc = {k: v for k, v in lib.items() if k.startswith("BC_")}
+    assert set(bc) == {"BC_FARFIELD", "BC_OUTFLOW", "BC_WALL_DIFFUSE", "BC_SYMMETRY", "BC_WALL_MAXWELL"}
+    for k, v in bc.items():
+        assert getattr(workloads, k) == v, k
+        if hasattr(pkg, k):
+            assert getattr(pkg, k) == v, k
+    assert ref["BC_WALL"] == bc["BC_WALL_DIFFUSE"]
+    for k in ("BC_FARFIELD", "BC_OUTFLOW", "BC_SYMMETRY", "BC_WALL_MAXWELL"):
+        assert ref[k] == bc[k], k
