@@ -129,7 +129,10 @@ typedef struct {
  * faces per case, the particle ids' layout).
  * Errors: EINVAL (mesh not matching its boundary list, non-convex or
  * clockwise cell, bad parameters, sizes), ENUMERIC (invalid W0), EDEVICE,
- * ENOMEM. */
+ * ENOMEM.  On an error *out still holds a context (NULL only when out is
+ * NULL or the context itself could not be allocated): ugkwp_last_error()
+ * on it says why, and the caller frees it with ugkwp_free; no other call
+ * may use it.  Arguments are checked before any device call. */
 int ugkwp_init(const ugkwp_mesh *mesh, const ugkwp_params *params, const double *W0, ugkwp_ctx **out);
 
 /* A batch of independent cases in one context: the cases' meshes are joined

@@ -1,10 +1,12 @@
 """The C ABI library loads and exports every entry point include/*.h
-declares (no compute calls: this runs without a GPU)."""
+declares, its structs, codes and argument checks agree with the binding
+(no compute calls: this runs without a GPU)."""
 import ctypes
 import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -127,3 +129,72 @@ def test_codes_match_the_header():
     assert ref["BC_WALL"] == bc["BC_WALL_DIFFUSE"]
     for k in ("BC_FARFIELD", "BC_OUTFLOW", "BC_SYMMETRY", "BC_WALL_MAXWELL"):
         assert ref[k] == bc[k], k
+
+
+def _ctx_entry_points():
+    """Entry points of include/ugkwp.h whose first argument is the context."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "ugkwp.h")).read(), flags=re.S)
+    return re.findall(r"\bint\s+(ugkwp_\w+)\s*\(\s*(?:const\s+)?ugkwp_ctx\s*\*", src)
+
+
+def test_entry_points_reject_a_null_context():
+    """Every call on a context returns EINVAL for a null one, before any
+    device call (so this runs without a GPU); the binding declares the
+    argument types of each."""
+    import paper_2607_09552_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.fail("libugkwp.so is not built (run __graft_entry__.build())")
+    L = pkg.load_library()
+    names = _ctx_entry_points()
+    assert len(names) >= 25 and "ugkwp_step_noalloc" in names
+    ints = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64)
+    for n in names:
+        f = getattr(L, n)
+        assert f.argtypes is not None, n
+        args = [0.0 if t is ctypes.c_double else 0 if t in ints else None for t in f.argtypes]
+        assert f(*args) == pkg.EINVAL, n
+    assert L.ugkwp_last_error(None) == b"no context"
+    L.ugkwp_free(None)
+    assert L.ugkwp_stream_copy(None, None, 0, 1, 0, None, None) == pkg.EINVAL
+
+
+def test_init_rejects_bad_arguments_before_any_device_call():
+    """ugkwp_init and ugkwp_init_batch check their arguments on the host:
+    the error comes back with a context that says why and frees without a
+    device."""
+    import paper_2607_09552_amd as pkg
+    import workloads
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.fail("libugkwp.so is not built (run __graft_entry__.build())")
+    L = pkg.load_library()
+    assert L.ugkwp_init(None, None, None, None) == pkg.EINVAL
+
+    def fails(rc, h, text):
+        assert rc == pkg.EINVAL and h.value
+        msg = L.ugkwp_last_error(h).decode()
+        L.ugkwp_free(h)
+        assert text in msg, msg
+
+    h = ctypes.c_void_p()
+    fails(L.ugkwp_init(None, None, None, ctypes.byref(h)), h, "null argument")
+    s = pkg.Solver.__new__(pkg.Solver)
+    s._keep = []
+    m, p, W = s._marshal(workloads.shock1d(n_half=8), None, None, 0, "f64")
+    Wp = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for field, bad in (("cfl", 0.0), ("n_ref", 0), ("R", -1.0), ("dt_source", 2)):
+        good = getattr(p, field)
+        setattr(p, field, bad)
+        fails(L.ugkwp_init(ctypes.byref(m), ctypes.byref(p), Wp, ctypes.byref(h)), h, "invalid parameters")
+        setattr(p, field, good)
+    m.dim = 3
+    fails(L.ugkwp_init(ctypes.byref(m), ctypes.byref(p), Wp, ctypes.byref(h)), h, "dim must be 1 or 2")
+
+    box = workloads.box2d(np.linspace(0.0, 1.0, 5), np.linspace(0.0, 1.0, 4))
+    cases = [workloads.uniform2d(box), workloads.uniform2d(box, cfl=0.5)]
+    ms, ps = (pkg._Mesh * 2)(), (pkg._Params * 2)()
+    ws = (ctypes.POINTER(ctypes.c_double) * 2)()
+    for k, w in enumerate(cases):
+        ms[k], ps[k], Wk = s._marshal(w, None, None, 0, "f64")
+        ws[k] = Wk.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fails(L.ugkwp_init_batch(0, ms, ps, ws, ctypes.byref(h)), h, "no case")
+    fails(L.ugkwp_init_batch(2, ms, ps, ws, ctypes.byref(h)), h, "must equal case 0's")
