@@ -172,7 +172,9 @@ class Solver:
     def __init__(self, wl, W0=None, stream=None, particle_capacity=0, precision="f64", batch=None, tuned=True):
         L = load_library()
         self._keep = []
-        self.wl, self.batch = wl, batch  # the workloads, for host-side diagnostics
+        # the workload(s), for host-side diagnostics: `cases` is the batch's
+        # list of workloads (None for one case; `batch` is the constructor)
+        self.wl, self.cases = wl, batch
         if batch is None:
             m, p, W = self._marshal(wl, W0, stream, particle_capacity, precision)
             self.dim, self.nc, self.ncase = int(wl["dim"]), int(wl["n_cells"]), 1

@@ -33,8 +33,8 @@ def _volumes(w):
 def cell_volumes(solver):
     """Cell volumes (areas in 2D, lengths in 1D) from the solver's workload(s),
     in the context's cell order (a batch's cases one after another)."""
-    if solver.batch is not None:
-        return np.concatenate([_volumes(w) for w in solver.batch])
+    if solver.cases is not None:
+        return np.concatenate([_volumes(w) for w in solver.cases])
     return _volumes(solver.wl)
 
 
