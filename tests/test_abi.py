@@ -198,3 +198,44 @@ def test_init_rejects_bad_arguments_before_any_device_call():
         ws[k] = Wk.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     fails(L.ugkwp_init_batch(0, ms, ps, ws, ctypes.byref(h)), h, "no case")
     fails(L.ugkwp_init_batch(2, ms, ps, ws, ctypes.byref(h)), h, "must equal case 0's")
+
+
+def _prototypes():
+    """(return type, name, [ctypes type per argument]) of every function the
+    headers declare; pointers as c_void_p."""
+    scalar = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64,
+              "double": ctypes.c_double, "float": ctypes.c_float}
+    out = []
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for ret, name, args in re.findall(r"\b(int|void|const\s+char\s*\*)\s*(ugkwp_\w+)\s*\(([^)]*)\)\s*;", src):
+            types = []
+            for a in (x.strip() for x in args.split(",") if x.strip()):
+                if "*" in a:
+                    types.append(ctypes.c_void_p)
+                else:
+                    types.append(scalar[re.sub(r"\bconst\b", "", a).split()[0]])
+            out.append((ret, name, types))
+    return out
+
+
+def test_every_entry_point_rejects_null_arguments():
+    """With null pointers and zero sizes every entry point of both headers
+    returns EINVAL (-1) from its host-side checks, before any device call."""
+    import paper_2607_09552_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.fail("libugkwp.so is not built (run __graft_entry__.build())")
+    pkg.load_library()  # torch's HIP runtime first, as the binding loads it
+    lib = ctypes.CDLL(pkg.LIB_PATH)  # own handle: argument types set here stay here
+    protos = _prototypes()
+    assert {n for _, n, _ in protos} == set(declared_functions())
+    checked = 0
+    for ret, name, types in protos:
+        if ret != "int":
+            continue
+        f = getattr(lib, name)
+        f.argtypes, f.restype = types, ctypes.c_int
+        args = [None if t is ctypes.c_void_p else t(0) for t in types]
+        assert f(*args) == pkg.EINVAL, name
+        checked += 1
+    assert checked >= 40
