@@ -1,7 +1,5 @@
 """The tuning sweep's selection logic, on a stand-in solver whose step cost
 is a known function of the settings plus a drift (no GPU)."""
-import pytest
-
 from paper_2607_09552_amd import autotune
 
 

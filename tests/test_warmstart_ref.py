@@ -3,7 +3,6 @@ closed forms, textbook values, finite differences and library routines."""
 import math
 
 import numpy as np
-import pytest
 import torch
 
 from oracle import warmstart_ref as ref
