@@ -140,10 +140,11 @@ def test_half_range_moments_quadrature(U, lam):
             else:
                 a, b = U - 40 * sig, U + 40 * sig
             pts = [U] if a < U < b else None
-            ref = integrate.quad(f, a, b, args=(k,), points=pts, epsabs=0, epsrel=1e-13, limit=400)[0]
             # relative accuracy, floored at 1e-14 of the full-range absolute moment
-            # (far half-range tails of a fast drift cancel in the recursion)
+            # (far half-range tails of a fast drift cancel in the recursion; odd
+            # moments of a Maxwellian at rest are exactly zero)
             full = integrate.quad(lambda u: abs(f(u, k)), U - 40 * sig, U + 40 * sig, points=[U], limit=400)[0]
+            ref = integrate.quad(f, a, b, args=(k,), points=pts, epsabs=1e-16 * full, epsrel=1e-13, limit=400)[0]
             assert abs(M[k] - ref) <= 1e-12 * abs(ref) + 1e-14 * full, (sign, k, M[k], ref)
 
 
