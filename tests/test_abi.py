@@ -239,3 +239,24 @@ def test_every_entry_point_rejects_null_arguments():
         assert f(*args) == pkg.EINVAL, name
         checked += 1
     assert checked >= 40
+
+
+def test_tuning_values_within_the_library_ranges():
+    """Every recorded best setting and every value the tuner sweeps is one
+    ugkwp_set_tuning accepts (block sizes 64, 128 or 256, the re-sort also
+    512; Shakhov lanes 1 to 16 in powers of two; 1 to 1024 steps per batch;
+    graph on or off; 1 to 10000 crossings), so a sweep never stops on an
+    EINVAL and a recorded table always loads."""
+    import json
+    from paper_2607_09552_amd import autotune
+    ok = {"transport_block": {64, 128, 256}, "tally_block": {64, 128, 256}, "flux_block": {64, 128, 256},
+          "scatter_block": {64, 128, 256, 512}, "shakhov_lanes": {1, 2, 4, 8, 16}, "use_graph": {0, 1},
+          "batch_steps": set(range(1, 1025)), "max_crossings": set(range(1, 10001))}
+    for name, values in autotune.SPACE.items():
+        assert set(values) <= ok[name], name
+    for case, rec in json.load(open(autotune.TUNING_FILE)).items():
+        for name, v in rec["best"].items():
+            assert v in ok[name], (case, name, v)
+        for key in rec.get("seconds_per_update", {}):
+            for name, v in json.loads(key).items():
+                assert v in ok[name], (case, name, v)
